@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the Active Flux step on one MI355X: DOF-updates/s, FP32-bulk vs FP64.
+
+Workload: the isentropic vortex (strength 5, centre (5,5), background (1,1,1,1), gamma 1.4)
+on a periodic 4096 x 4096 grid of [0,10]^2, Algorithm 1 with the correction term, CFL 0.3,
+time step computed on the device before every step.  A step is one pass of the whole hot path
+(point values at the intermediate and new time levels, Simpson fluxes, conservative update,
+time-step reduction).  One DOF-update is one DOF site (cell average, corner, x- or y-edge
+midpoint; a 4-vector) advanced one full step: 4 N^2 sites per step on a periodic grid.
+
+Inputs are generated on the host and copied to HBM before the timed region.  The timed region
+runs `--steps` steps with HIP events around every kernel on the library's stream (the events
+give both the step time and the average duration of the dominant kernel for the roofline).
+
+Prints one JSON line.  Only N=1 is supported: the run uses one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s per step, FP32-bulk vs FP64 on 1 GPU at stated L1 error"
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X vector FP32 (published)
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
+
+# ------------------------------------------------------------------------------------------
+# Algorithmic FLOPs of the point-value kernel per cell and step (FMA = 2, other arithmetic
+# = 1, sqrt/div/acos/asin = 1), counted from the exact-moment formulation:
+#   EG2 at a corner    : 4 cells x (moment recurrence 43 + 3 shifts 156 + 3 contractions 234
+#                        + 3) + 4 arc pieces x 92 + set-up, foot point and outputs 87 = 2199
+#   EG2 at an edge     : 1 arc piece 92 + moments 43 + 6 shifts 312 + differences 30
+#                        + full-circle terms 32 + contractions 234 + the rest 77    =  820
+#   per DOF            : derivatives, correction, assembly ~110; Simpson-in-time fluxes 102
+#   per cell           : inverse Simpson, centre value, Simpson average, monomials  ~400
+# ------------------------------------------------------------------------------------------
+EG2_K, EG2_EDGE = 2199, 820
+PER_DOF, PER_CELL = 110 + 102, 400
+UPDATE_PER_CELL = 84
+
+
+def flops_per_cell(mode: int) -> float:
+    """Algorithmic FLOPs of the point kernel per cell-step (3 DOFs per cell)."""
+    rounds = 3 if mode == 0 else 2  # Algorithm 1 evaluates EG2 three times per DOF
+    return rounds * (EG2_K + 2 * EG2_EDGE) + 3 * PER_DOF + PER_CELL
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2508_06273_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    r = rec.get(f"{kernel}|{workload}")
+    if not r or r.get("source_sha") != source_hash():
+        return None
+    return r
+
+
+def run_gpu(st, prec, steps, warmup, stream):
+    from paper_2508_06273_amd import af
+    import torch
+    s = af.Solver.for_state(st, precision=prec)
+    s.set_stream(stream)
+    s.run(1e9, 0.3, warmup)
+    s.set_option(af.AF_OPT_TIMING, 1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    w0 = time.perf_counter()
+    t, n = s.run(1e9, 0.3, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    kp, ku, nt = s.timing()
+    out = s.get_state()
+    dofs = s.dof_count()
+    s.close()
+    assert n == steps and nt == steps, (n, nt)
+    return dict(ms_total=ms, wall_s=wall, ms_points=kp / nt, ms_update=ku / nt, t=out["t"],
+                dofs=dofs, state=out)
+
+
+def cpu_baseline(seconds: float, n_cpu: int):
+    import oracle
+    from paper_2508_06273_amd import inputs as I
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1, 16))
+    st = I.shu_vortex(n_cpu, n_gl=3)
+    oracle.run(st, 1e9, 0.3, max_steps=1, nthreads=threads)  # warm-up step
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        e, n, _ = oracle.run(st, 1e9, 0.3, max_steps=1, nthreads=threads)
+        assert e == 0
+        steps += 1
+    el = time.perf_counter() - t0
+    dofs = 4 * n_cpu * n_cpu
+    return {"value": dofs * steps / el, "unit": "DOF-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"isentropic vortex {n_cpu}x{n_cpu} (same per-DOF work as the GPU "
+                      f"workload), Algorithm 1, CFL 0.3, {steps} steps after 1 warm-up step, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--n", type=int, default=4096, help="cells per side")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-n", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs the Active Flux step on one GPU only; "
+              f"--gpus {args.gpus} (WORLD_SIZE={world}) is not supported.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2508_06273_amd import af, inputs as I
+    af.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    n = args.n
+    print(f"[bench] generating the {n}x{n} vortex", file=sys.stderr, flush=True)
+    st = I.shu_vortex(n, n_gl=3)
+    res = {}
+    for prec, name in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64")):
+        print(f"[bench] {name}: {args.warmup} warm-up + {args.steps} timed steps",
+              file=sys.stderr, flush=True)
+        res[name] = run_gpu(st, prec, args.steps, args.warmup, stream)
+    cells = n * n
+    fpc = flops_per_cell(0)
+    out = {}
+    for name, r in res.items():
+        r["value"] = r["dofs"] * args.steps / (r["ms_total"] * 1e-3)
+        r["ms_per_step"] = r["ms_total"] / args.steps
+
+    # accuracy: L1 per conserved variable against the exact (translated) vortex averages,
+    # and between the two precisions after the same steps
+    print("[bench] accuracy", file=sys.stderr, flush=True)
+    grid = st.grid
+    exact = I.cell_average(I.shu_vortex_field(res["fp64"]["t"]), grid, n_gl=3)
+    acc = {}
+    for name in ("fp32", "fp64"):
+        l1, linf = I.norms(res[name]["state"]["avg"], exact, grid)
+        acc[f"L1_vs_exact_{name}"] = [float(x) for x in l1]
+    l1d, linfd = I.norms(res["fp32"]["state"]["avg"], res["fp64"]["state"]["avg"], grid)
+    acc["L1_fp32_vs_fp64"] = [float(x) for x in l1d]
+    acc["Linf_fp32_vs_fp64"] = [float(x) for x in linfd]
+    acc["t"] = res["fp64"]["t"]
+    acc["variables"] = "rho, rho u, rho v, E"
+
+    def roofline(name, peak):
+        r = res[name]
+        achieved = fpc * cells / (r["ms_points"] * 1e-3) / 1e12
+        rec = traffic_record("k_points", f"vortex{n}_{name}")
+        traffic = None if rec is None else rec["bytes_per_launch"]
+        return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": "k_points", "kernel_ms": round(r["ms_points"], 4),
+                "flops_per_cell": fpc}
+
+    line = {
+        "metric": METRIC,
+        "value": res["fp32"]["value"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["fp32"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"isentropic vortex {n}x{n} periodic on [0,10]^2, "
+                               "Algorithm 1 with correction, CFL 0.3",
+                   "cells": cells, "dof_sites": res["fp32"]["dofs"],
+                   "precision": "fp32-bulk (FP64 averages, fluxes, tests, dt)"},
+        "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_per_step"],
+                 "speedup_fp32_vs_fp64": res["fp32"]["value"] / res["fp64"]["value"]},
+        "accuracy": acc,
+        "roofline": roofline("fp32", PEAK_FP32),
+        "roofline_fp64": roofline("fp64", PEAK_FP64),
+        "kernel_ms": {name: {"k_points": r["ms_points"], "k_update": r["ms_update"]}
+                      for name, r in res.items()},
+        "source_sha": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.cpu_n)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * af.h -- C ABI of the MI355X (gfx950) Active Flux library libaf.so.
+ *
+ * The library advances the fully discrete third-order Active Flux method for the 2D Euler
+ * equations on a Cartesian grid (Chudzik, Helzel, Porfetye, arXiv 2508.06273):
+ *   - point values at cell corners and edge midpoints are evolved to the intermediate and the
+ *     new time level with the EG2 bicharacteristic evolution operator of the locally
+ *     linearised system plus the correction term of Corollary 1 (Sec. 2, Algorithm 1; the
+ *     averaged linearisation of Sec. 3.1; the simplified method, eq. 1stStep);
+ *   - cell averages are updated conservatively with Simpson space-time fluxes
+ *     (Sec. 2, eqs. 2dfvm and F);
+ *   - optionally, point values with negative density or pressure are replaced by EG1 on
+ *     piecewise constant data and, failing that, by a Lax-Friedrichs update (Algorithm 3);
+ *   - boundaries are periodic or outflow (piecewise constant extrapolation, Sec. 4).
+ *
+ * Degrees of freedom and host array layout (all host arrays are FP64, variable-major,
+ * unpadded, C order):
+ *   avg : 4 x ny x nx            conserved cell averages (rho, rho u, rho v, E)
+ *   K   : 4 x nky x nkx          primitive (rho, u, v, p) at corners (x0 + i dx, y0 + j dy)
+ *   X   : 4 x ny  x nkx          primitive at vertical-edge midpoints (x0 + i dx, y0 + (j+1/2) dy)
+ *   Y   : 4 x nky x nx           primitive at horizontal-edge midpoints (x0 + (i+1/2) dx, y0 + j dy)
+ * with nkx = nx + (x periodic ? 0 : 1), nky = ny + (y periodic ? 0 : 1).  The ideal gas law
+ * E = p/(gamma-1) + rho (u^2 + v^2)/2 links the two sets of variables.
+ *
+ * Ownership: the caller owns every host array; the library copies in and out synchronously on
+ * the handle's stream and keeps no pointer.  Device memory belongs to the handle.
+ * Errors: every call returns AF_OK (0) or a negative code; af_last_error() gives the text.
+ * A step that fails leaves the state at the beginning of that step.  A handle is not
+ * thread-safe; different handles are independent.  The library needs a gfx950 GPU: without
+ * one, af_create returns AF_ERR_DEVICE.
+ */
+#ifndef AF_H
+#define AF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct af_handle af_handle;
+
+/* Grid: nx x ny cells covering [x0,x1] x [y0,y1]; dx = (x1-x0)/nx, dy = (y1-y0)/ny. */
+typedef struct {
+  int32_t nx, ny;
+  double x0, x1, y0, y1;
+} af_grid;
+
+/* Boundary condition per side.  Periodic must be set on both sides of an axis. */
+enum { AF_BC_PERIODIC = 0, AF_BC_OUTFLOW = 1 };
+typedef struct {
+  int32_t left, right, bottom, top;
+} af_bc;
+
+enum {
+  AF_OK = 0,
+  AF_ERR_INVALID_ARG = -1, /* bad handle, size, option or argument */
+  AF_ERR_NONPHYSICAL = -2, /* non-positive density or pressure where the method needs it */
+  AF_ERR_CFL = -3,         /* an evolution circle would leave the cells around its point */
+  AF_ERR_DEVICE = -4,      /* HIP runtime error or no usable GPU */
+  AF_ERR_OOM = -5          /* device allocation failed */
+};
+
+/* Options (af_set_option).  Changing AF_OPT_PRECISION discards the state: call
+ * af_set_state afterwards. */
+enum {
+  AF_OPT_PRECISION = 1,     /* AF_PREC_FP64 (default) or AF_PREC_FP32 (see below)        */
+  AF_OPT_LINEARISATION = 2, /* AF_LIN_AF3 (default), AF_LIN_AVG or AF_LIN_SIMPLE          */
+  AF_OPT_CORRECTION = 3,    /* 1 (default): add C of Corollary 1; 0: drop it              */
+  AF_OPT_LIMITER = 4,       /* 0 (default): none; 1: bound-preserving point values (Alg.3)*/
+  AF_OPT_GRAPH_STEPS = 5,   /* steps per captured HIP graph in af_run (even, 0 = no graph) */
+  AF_OPT_TIMING = 6         /* 1: launch eagerly and time every kernel with HIP events on the
+                               handle's stream (af_get_timing); 0 (default): off           */
+};
+/* AF_PREC_FP64: every operation in FP64.  AF_PREC_FP32: point values are stored and evolved
+ * in FP32 (the evolution operators, correction term and reconstruction); cell averages, the
+ * flux accumulation and average update, the positivity tests and the time step stay FP64. */
+enum { AF_PREC_FP64 = 0, AF_PREC_FP32 = 1 };
+/* AF_LIN_AF3: Algorithm 1 (intermediate values linearised at EG2(U^n, dt/4));
+ * AF_LIN_AVG: intermediate values linearised at the mean of the adjacent primitive cell
+ *             averages (Sec. 3.1, eq. Un+1/2);
+ * AF_LIN_SIMPLE: intermediate values linearised at U^n (eq. 1stStep).
+ * In every mode the new time level is linearised at the intermediate value. */
+enum { AF_LIN_AF3 = 0, AF_LIN_AVG = 1, AF_LIN_SIMPLE = 2 };
+
+/* Counters returned by af_get_counters (cumulative since af_set_state). */
+enum {
+  AF_CNT_EG1 = 0,        /* point values replaced by EG1 on piecewise constant data   */
+  AF_CNT_LF = 1,         /* point values replaced by the Lax-Friedrichs update        */
+  AF_CNT_CENTRE = 2,     /* cells whose inverse-Simpson centre value was not admissible
+                            and fell back to the primitive value of the average        */
+  AF_CNT_INNER = 3,      /* Algorithm 1 inner states not admissible (the intermediate
+                            value was then linearised at U^n)                          */
+  AF_CNT_STEPS = 4,      /* steps taken                                               */
+  AF_NCOUNTERS = 8
+};
+
+/* Create a solver for `grid` with ratio of specific heats `gamma` (> 1) and boundary
+ * conditions `bc`.  Allocates the device state (uninitialised until af_set_state). */
+int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_handle** out);
+
+/* Set an option (keys and values above). */
+int af_set_option(af_handle* h, int key, int64_t value);
+
+/* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) for all
+ * device work of this handle.  NULL selects the handle's own (non-blocking) stream. */
+int af_set_stream(af_handle* h, void* hip_stream);
+
+/* Copy a state in (host FP64 arrays, layout above) at time t.  Resets the counters. */
+int af_set_state(af_handle* h, const double* avg, const double* K, const double* X,
+                 const double* Y, double t);
+
+/* Copy the current state out (any output pointer may be NULL). */
+int af_get_state(const af_handle* h, double* avg, double* K, double* X, double* Y,
+                 double* t);
+
+/* One time step of size dt > 0 (Algorithm 1 steps 1-3 with the chosen options). */
+int af_step(af_handle* h, double dt);
+
+/* Advance to t_end with dt = cfl * min(dx,dy) / max over all DOFs of (max(|u|,|v|) + c),
+ * computed on the device from the current state before every step; the last step is cut
+ * to land on t_end.  max_steps > 0 bounds the number of steps.  t_reached and steps_taken
+ * (nullable) report where the run stopped. */
+int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double* t_reached,
+           int64_t* steps_taken);
+
+/* Counters (AF_NCOUNTERS values). */
+int af_get_counters(const af_handle* h, int64_t* out);
+
+/* Free the handle and its device memory (NULL is ignored). */
+void af_destroy(af_handle* h);
+
+/* Text of the last error on this handle (or of the last failed af_create if h is NULL). */
+const char* af_last_error(const af_handle* h);
+
+/* Number of DOF sites (averages + K + X + Y) of the handle's grid: the unit of the
+ * DOF-updates/s throughput figure. */
+int64_t af_dof_count(const af_handle* h);
+
+/* Kernel times gathered while AF_OPT_TIMING is on, summed since the option was last set:
+ * out[0] = milliseconds in the point-value kernel, out[1] = milliseconds in the flux/update
+ * kernel, out[2] = number of steps timed.  Both kernels run on the handle's stream. */
+int af_get_timing(const af_handle* h, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,186 @@
+"""Thin ctypes binding of libaf.so (C ABI in include/af.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts numpy arrays to
+pointers and error codes to exceptions.  It raises if the library has not been built
+(see paper_2508_06273_amd/build.py) -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaf.so")
+
+AF_OK, AF_ERR_INVALID_ARG, AF_ERR_NONPHYSICAL, AF_ERR_CFL, AF_ERR_DEVICE, AF_ERR_OOM = \
+    0, -1, -2, -3, -4, -5
+AF_BC_PERIODIC, AF_BC_OUTFLOW = 0, 1
+AF_OPT_PRECISION, AF_OPT_LINEARISATION, AF_OPT_CORRECTION, AF_OPT_LIMITER, \
+    AF_OPT_GRAPH_STEPS, AF_OPT_TIMING = 1, 2, 3, 4, 5, 6
+AF_PREC_FP64, AF_PREC_FP32 = 0, 1
+AF_LIN_AF3, AF_LIN_AVG, AF_LIN_SIMPLE = 0, 1, 2
+AF_CNT_EG1, AF_CNT_LF, AF_CNT_CENTRE, AF_CNT_INNER, AF_CNT_STEPS = 0, 1, 2, 3, 4
+AF_NCOUNTERS = 8
+
+# every symbol include/af.h declares
+EXPORTS = ["af_create", "af_set_option", "af_set_stream", "af_set_state", "af_get_state",
+           "af_step", "af_run", "af_get_counters", "af_destroy", "af_last_error",
+           "af_dof_count", "af_get_timing"]
+
+
+class AfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"af error {code}: {msg}")
+        self.code = code
+
+
+class Grid(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("x0", ct.c_double),
+                ("x1", ct.c_double), ("y0", ct.c_double), ("y1", ct.c_double)]
+
+
+class Bc(ct.Structure):
+    _fields_ = [("left", ct.c_int32), ("right", ct.c_int32), ("bottom", ct.c_int32),
+                ("top", ct.c_int32)]
+
+
+_lib = None
+_D = ct.POINTER(ct.c_double)
+_H = ct.c_void_p
+
+
+def load(path: str = LIB_PATH):
+    """Load libaf.so (raises FileNotFoundError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not built: run paper_2508_06273_amd/build.py")
+    L = ct.CDLL(path)
+    L.af_create.argtypes = [ct.POINTER(Grid), ct.c_double, ct.POINTER(Bc), ct.POINTER(_H)]
+    L.af_set_option.argtypes = [_H, ct.c_int, ct.c_int64]
+    L.af_set_stream.argtypes = [_H, ct.c_void_p]
+    L.af_set_state.argtypes = [_H, _D, _D, _D, _D, ct.c_double]
+    L.af_get_state.argtypes = [_H, _D, _D, _D, _D, _D]
+    L.af_step.argtypes = [_H, ct.c_double]
+    L.af_run.argtypes = [_H, ct.c_double, ct.c_double, ct.c_int64, _D,
+                         ct.POINTER(ct.c_int64)]
+    L.af_get_counters.argtypes = [_H, ct.POINTER(ct.c_int64)]
+    L.af_destroy.argtypes = [_H]
+    L.af_destroy.restype = None
+    L.af_last_error.argtypes = [_H]
+    L.af_last_error.restype = ct.c_char_p
+    L.af_dof_count.argtypes = [_H]
+    L.af_dof_count.restype = ct.c_int64
+    L.af_get_timing.argtypes = [_H, ct.POINTER(ct.c_double)]
+    L.af_get_timing.restype = ct.c_int
+    for name in ("af_create", "af_set_option", "af_set_stream", "af_set_state",
+                 "af_get_state", "af_step", "af_run", "af_get_counters"):
+        getattr(L, name).restype = ct.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+class Solver:
+    """One grid on the GPU.  Mirrors af_create / af_set_state / af_step / af_run / ..."""
+
+    def __init__(self, nx, ny, x0, x1, y0, y1, gamma=1.4, bc_x=AF_BC_PERIODIC,
+                 bc_y=AF_BC_PERIODIC, precision=AF_PREC_FP64, linearisation=AF_LIN_AF3,
+                 correction=True, limiter=False, graph_steps=None):
+        self.L = load()
+        self.nx, self.ny = int(nx), int(ny)
+        self.nkx = self.nx + (0 if bc_x == AF_BC_PERIODIC else 1)
+        self.nky = self.ny + (0 if bc_y == AF_BC_PERIODIC else 1)
+        self.h = _H()
+        g = Grid(self.nx, self.ny, x0, x1, y0, y1)
+        bc = Bc(bc_x, bc_x, bc_y, bc_y)
+        self._check(self.L.af_create(ct.byref(g), gamma, ct.byref(bc), ct.byref(self.h)),
+                    create=True)
+        self.set_option(AF_OPT_PRECISION, precision)
+        self.set_option(AF_OPT_LINEARISATION, linearisation)
+        self.set_option(AF_OPT_CORRECTION, int(bool(correction)))
+        self.set_option(AF_OPT_LIMITER, int(bool(limiter)))
+        if graph_steps is not None:
+            self.set_option(AF_OPT_GRAPH_STEPS, graph_steps)
+
+    @classmethod
+    def for_state(cls, st, **kw):
+        g = st.grid
+        s = cls(g.nx, g.ny, g.x0, g.x1, g.y0, g.y1, st.gamma, g.bc_x, g.bc_y, **kw)
+        s.set_state(st.avg, st.K, st.X, st.Y, st.t)
+        return s
+
+    def _check(self, rc, create=False):
+        if rc != AF_OK:
+            msg = self.L.af_last_error(None if create else self.h)
+            raise AfError(rc, (msg or b"").decode())
+
+    def close(self):
+        if self.h:
+            self.L.af_destroy(self.h)
+            self.h = _H()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key, value):
+        self._check(self.L.af_set_option(self.h, key, int(value)))
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream (its .cuda_stream handle is used) or a raw handle."""
+        handle = getattr(stream, "cuda_stream", stream)
+        self._check(self.L.af_set_stream(self.h, ct.c_void_p(handle)))
+
+    def shapes(self):
+        return dict(avg=(4, self.ny, self.nx), K=(4, self.nky, self.nkx),
+                    X=(4, self.ny, self.nkx), Y=(4, self.nky, self.nx))
+
+    def set_state(self, avg, K, X, Y, t=0.0):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (avg, K, X, Y)]
+        for a, (name, shp) in zip(arrs, self.shapes().items()):
+            if a.shape != shp:
+                raise ValueError(f"{name} has shape {a.shape}, expected {shp}")
+        self._check(self.L.af_set_state(self.h, *[_ptr(a) for a in arrs], float(t)))
+
+    def get_state(self):
+        sh = self.shapes()
+        out = {k: np.empty(v, dtype=np.float64) for k, v in sh.items()}
+        t = ct.c_double(0.0)
+        self._check(self.L.af_get_state(self.h, _ptr(out["avg"]), _ptr(out["K"]),
+                                        _ptr(out["X"]), _ptr(out["Y"]), ct.byref(t)))
+        out["t"] = t.value
+        return out
+
+    def step(self, dt):
+        self._check(self.L.af_step(self.h, float(dt)))
+
+    def run(self, t_end=float("inf"), cfl=0.3, max_steps=0):
+        t = ct.c_double(0.0)
+        n = ct.c_int64(0)
+        self._check(self.L.af_run(self.h, float(t_end), float(cfl), int(max_steps),
+                                  ct.byref(t), ct.byref(n)))
+        return t.value, n.value
+
+    def counters(self):
+        c = (ct.c_int64 * AF_NCOUNTERS)()
+        self._check(self.L.af_get_counters(self.h, c))
+        return np.array(list(c), dtype=np.int64)
+
+    def timing(self):
+        """(ms in the point kernel, ms in the update kernel, steps) while timing is on."""
+        o = (ct.c_double * 3)()
+        self._check(self.L.af_get_timing(self.h, o))
+        return o[0], o[1], int(o[2])
+
+    def dof_count(self):
+        return int(self.L.af_dof_count(self.h))

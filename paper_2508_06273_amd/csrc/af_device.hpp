@@ -1,0 +1,339 @@
+// af_device.hpp -- device math of the Active Flux step (gfx950).
+//
+// Method: Chudzik, Helzel, Porfetye, "A fully discrete truly multidimensional Active Flux
+// method for the two-dimensional Euler equations", arXiv 2508.06273.
+//
+// Everything here is templated on the bulk type R (float or double).  Quantities that the
+// method needs in FP64 whatever R is (cell averages, conserved point values, fluxes, the
+// positivity tests) are written with double explicitly.
+//
+// Evolution operators.  EG2 (Sec. 2, eq. EG2) and EG1 (Sec. 3, the first-order operator used
+// on piecewise constant data) need integrals over the circle
+//   Q(theta) = P' + c' tau (cos theta, sin theta),  P' = (x - u' tau, y - v' tau),
+// of the reconstruction times 1, cos, sin, cos^2, sin cos, sin^2.  The circle lies in the
+// cells around the degree of freedom; the grid lines through the DOF cut it where
+// cos theta = u'/c' (vertical line) and sin theta = v'/c' (horizontal line).  In cell-local
+// coordinates the circle is xi = xi0 + a C, eta = eta0 + b S (C = cos, S = sin), so each
+// cell's biquadratic becomes a polynomial sum d_kl C^k S^l (k, l <= 2) and the integrals are
+// exact combinations of the trigonometric moments  M_ab = int C^a S^b dtheta  over the arcs
+// that lie in that cell.  The moments follow from the arc end points and the arc length by
+// the standard reduction formulas, so the only transcendental functions are one acos and one
+// asin per evaluation.  The arc set of a cell is the intersection of the circular interval
+// where Q is on that side of the vertical line with the one for the horizontal line.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace af {
+
+constexpr double kPi = 3.14159265358979323846;
+
+template <class R> struct Math;
+template <> struct Math<double> {
+  static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+  static __device__ __forceinline__ double acos_(double x) { return ::acos(x); }
+  static __device__ __forceinline__ double asin_(double x) { return ::asin(x); }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+};
+template <> struct Math<float> {
+  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+  static __device__ __forceinline__ float acos_(float x) { return ::acosf(x); }
+  static __device__ __forceinline__ float asin_(float x) { return ::asinf(x); }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+
+template <class T> __device__ __forceinline__ T mx(T a, T b) { return a > b ? a : b; }
+template <class T> __device__ __forceinline__ T mn(T a, T b) { return a < b ? a : b; }
+template <class T> __device__ __forceinline__ T clamp1(T a) { return mn(mx(a, T(-1)), T(1)); }
+
+// ------------------------------------------------------------------------------------------
+// Ideal gas (paper Sec. 2).  P2C is written without FMA contraction so that a host that
+// evaluates E = p/(gamma-1) + 0.5*rho*(u*u + v*v) in this order obtains the same bits.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void p2c(const double U[4], double g1inv, double Q[4]) {
+#pragma clang fp contract(off)
+  Q[0] = U[0];
+  Q[1] = U[0] * U[1];
+  Q[2] = U[0] * U[2];
+  Q[3] = U[3] * g1inv + 0.5 * U[0] * (U[1] * U[1] + U[2] * U[2]);
+}
+
+// Admissible: rho > 0 and p > 0 (zero and NaN fail).
+template <class T> __device__ __forceinline__ bool admissible(T rho, T p) {
+  return rho > T(0) && p > T(0);
+}
+
+// Primitive value of conserved Q by deviation from a reference primitive state W (exact
+// identity; the rounding error scales with Q - P2C(W), and Q = P2C(W) returns W bitwise).
+__device__ __forceinline__ void c2p_dev(const double W[4], const double dQ[4], double gm1,
+                                        double U[4]) {
+  double rho = W[0] + dQ[0];
+  double irho = 1.0 / rho;
+  double du = (dQ[1] - W[1] * dQ[0]) * irho;
+  double dv = (dQ[2] - W[2] * dQ[0]) * irho;
+  double u = W[1] + du, v = W[2] + dv;
+  double dkin = dQ[0] * (u * u + v * v) + W[0] * (du * (u + W[1]) + dv * (v + W[2]));
+  U[0] = rho;
+  U[1] = u;
+  U[2] = v;
+  U[3] = W[3] + gm1 * (dQ[3] - 0.5 * dkin);
+}
+
+__device__ __forceinline__ void c2p_plain(const double Q[4], double gm1, double U[4]) {
+  double irho = 1.0 / Q[0];
+  U[0] = Q[0];
+  U[1] = Q[1] * irho;
+  U[2] = Q[2] * irho;
+  U[3] = gm1 * (Q[3] - 0.5 * (Q[1] * Q[1] + Q[2] * Q[2]) * irho);
+}
+
+// f(q), g(q) evaluated from primitive values, FP64.
+__device__ __forceinline__ void flux_fg(const double U[4], double g1inv, double F[4],
+                                        double G[4]) {
+  double r = U[0], u = U[1], v = U[2], p = U[3];
+  double H = p * g1inv + 0.5 * r * (u * u + v * v) + p;  // E + p
+  double ru = r * u, rv = r * v;
+  F[0] = ru;
+  F[1] = ru * u + p;
+  F[2] = ru * v;
+  F[3] = u * H;
+  G[0] = rv;
+  G[1] = rv * u;
+  G[2] = rv * v + p;
+  G[3] = v * H;
+}
+
+__device__ __forceinline__ double wave_speed(const double U[4], double gamma) {
+  double c = __builtin_sqrt(gamma * U[3] / U[0]);
+  return mx(__builtin_fabs(U[1]), __builtin_fabs(U[2])) + c;
+}
+
+// ------------------------------------------------------------------------------------------
+// Correction term of Corollary 1: C(tau) = tau^2/2 * V(U, U_x, U_y).  Returns V/2.
+// ------------------------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void corr_half(const R U[4], const R Ux[4], const R Uy[4], R gamma,
+                                          R out[4]) {
+  R rho = U[0], u = U[1], v = U[2], p = U[3];
+  R rx = Ux[0], ux = Ux[1], vx = Ux[2], px = Ux[3];
+  R ry = Uy[0], uy = Uy[1], vy = Uy[2], py = Uy[3];
+  R irho = R(1) / rho;
+  R div = ux + vy;
+  R f1 = ux * ux + uy * vx;
+  R f2 = uy * vx + vy * vy;
+  R g1 = px * (gamma * div + ux) + py * vx;
+  R g2 = py * (gamma * div + vy) + px * uy;
+  R h1 = (rx * px + ry * py) * irho;
+  R h2 = (rx * u + ry * v) * irho * irho;
+  out[0] = R(0.5) * (rho * (f1 + f2) + u * (rx * (ux + ux + vy) + ry * vx) +
+                     v * (rx * uy + ry * (ux + vy + vy)) - h1);
+  out[1] = R(0.5) * (u * f1 + v * uy * div + g1 * irho - px * h2);
+  out[2] = R(0.5) * (v * f2 + u * vx * div + g2 * irho - py * h2);
+  out[3] = R(0.5) * (u * g1 + v * g2 + gamma * p * (f1 + f2 - h1 * irho));
+}
+
+// ------------------------------------------------------------------------------------------
+// Trigonometric moments over one arc.  M[a][b] = int_arc cos^a sin^b, for a, b <= 4 except
+// (4,3), (3,4), (4,4), from the end points (Ca,Sa) -> (Cb,Sb) and the arc length L >= 0.
+// Reduction formulas (m + n) int c^m s^n = c^(m-1) s^(n+1) + (m-1) int c^(m-2) s^n
+//                                        = -c^(m+1) s^(n-1) + (n-1) int c^m s^(n-2).
+// ------------------------------------------------------------------------------------------
+template <class R> struct Mom {
+  R m[5][5];
+};
+
+// Brackets [F] = F(end) - F(start) of the products F = c^i s^j that the reduction formulas
+// need, summed over the pieces of an arc set, and the total length L.  The moments are
+// linear in these sums, so an arc set of several pieces costs one recurrence.
+template <class R> struct Br {
+  R L, s1, c1, cs, c2s, c3s, c4s, c5s, c2, c3, c4, c5, cs2, c2s2, c3s2, c4s2, cs3, c2s3, c3s3;
+};
+
+template <class R> __device__ __forceinline__ void br_zero(Br<R>& B) {
+  B.L = B.s1 = B.c1 = B.cs = B.c2s = B.c3s = B.c4s = B.c5s = B.c2 = B.c3 = B.c4 = B.c5 = R(0);
+  B.cs2 = B.c2s2 = B.c3s2 = B.c4s2 = B.cs3 = B.c2s3 = B.c3s3 = R(0);
+}
+
+// add sign * F(c, s) for every product F
+template <class R> __device__ __forceinline__ void br_end(Br<R>& B, R c, R s, R sign) {
+  const R c2 = c * c, c3 = c2 * c, c4 = c2 * c2, c5 = c4 * c;
+  const R s2 = s * s, s3 = s2 * s;
+  const R sc = sign * c, ss = sign * s, ss2 = sign * s2, ss3 = sign * s3;
+  B.s1 += ss;
+  B.c1 += sc;
+  B.cs += sc * s;
+  B.c2s += c2 * ss;
+  B.c3s += c3 * ss;
+  B.c4s += c4 * ss;
+  B.c5s += c5 * ss;
+  B.c2 += sc * c;
+  B.c3 += sign * c3;
+  B.c4 += sign * c4;
+  B.c5 += sign * c5;
+  B.cs2 += c * ss2;
+  B.c2s2 += c2 * ss2;
+  B.c3s2 += c3 * ss2;
+  B.c4s2 += c4 * ss2;
+  B.cs3 += c * ss3;
+  B.c2s3 += c2 * ss3;
+  B.c3s3 += c3 * ss3;
+}
+
+// one piece (Ca,Sa) -> (Cb,Sb) of length L; empty pieces (L <= 0) add nothing
+template <class R>
+__device__ __forceinline__ void br_piece(Br<R>& B, R Ca, R Sa, R Cb, R Sb, R L) {
+  if (L > R(0)) {
+    B.L += L;
+    br_end(B, Cb, Sb, R(1));
+    br_end(B, Ca, Sa, R(-1));
+  }
+}
+
+template <class R> __device__ __forceinline__ void moments(const Br<R>& B, Mom<R>& M) {
+  const R i2 = R(0.5), i3 = R(1) / R(3), i4 = R(0.25), i5 = R(0.2), i6 = R(1) / R(6);
+  M.m[0][0] = B.L;
+  M.m[1][0] = B.s1;
+  M.m[0][1] = -B.c1;
+  M.m[2][0] = (B.cs + M.m[0][0]) * i2;
+  M.m[3][0] = (B.c2s + R(2) * M.m[1][0]) * i3;
+  M.m[4][0] = (B.c3s + R(3) * M.m[2][0]) * i4;
+  M.m[1][1] = -B.c2 * i2;
+  M.m[2][1] = -B.c3 * i3;
+  M.m[3][1] = -B.c4 * i4;
+  M.m[4][1] = -B.c5 * i5;
+  M.m[0][2] = (M.m[0][0] - B.cs) * i2;
+  M.m[1][2] = (M.m[1][0] - B.c2s) * i3;
+  M.m[2][2] = (M.m[2][0] - B.c3s) * i4;
+  M.m[3][2] = (M.m[3][0] - B.c4s) * i5;
+  M.m[4][2] = (M.m[4][0] - B.c5s) * i6;
+  M.m[0][3] = (R(2) * M.m[0][1] - B.cs2) * i3;
+  M.m[1][3] = (R(2) * M.m[1][1] - B.c2s2) * i4;
+  M.m[2][3] = (R(2) * M.m[2][1] - B.c3s2) * i5;
+  M.m[3][3] = (R(2) * M.m[3][1] - B.c4s2) * i6;
+  M.m[0][4] = (R(3) * M.m[0][2] - B.cs3) * i4;
+  M.m[1][4] = (R(3) * M.m[1][2] - B.c2s3) * i5;
+  M.m[2][4] = (R(3) * M.m[2][2] - B.c3s3) * i6;
+  M.m[4][3] = M.m[3][4] = M.m[4][4] = R(0);
+}
+
+// ------------------------------------------------------------------------------------------
+// Cell polynomials.  LDS holds, for every halo cell and every primitive variable, the
+// monomial coefficients c_mn of xi^m eta^n (m, n <= 2) in the cell-centred frame
+// (xi, eta in [-1/2, 1/2]); c_00 is the centre value U_c.
+// ------------------------------------------------------------------------------------------
+// Lagrange nodes W[a][b] (a: left/centre/right, b: bottom/centre/top) -> monomials.
+template <class T> __device__ __forceinline__ void nodes_to_monomials(const T W[3][3], T c[9]) {
+  T t[3][3];  // t[m][b]: coefficient of xi^m on node row b
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    t[0][b] = W[1][b];
+    t[1][b] = W[2][b] - W[0][b];
+    t[2][b] = T(2) * (W[0][b] + W[2][b]) - T(4) * W[1][b];
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    c[m * 3 + 0] = t[m][1];
+    c[m * 3 + 1] = t[m][2] - t[m][0];
+    c[m * 3 + 2] = T(2) * (t[m][0] + t[m][2]) - T(4) * t[m][1];
+  }
+}
+
+// Substitute xi = xi0 + a C, eta = eta0 + b S into sum c_mn xi^m eta^n -> sum d_kl C^k S^l.
+// `cm` points at c_00 of one variable of one cell in LDS, coefficients `stride` apart.
+template <class R>
+__device__ __forceinline__ void circle_shift(const R* __restrict__ cm, int stride, R xi0,
+                                             R eta0, R a, R b, R d[9]) {
+  R e[9];
+  const R a2 = a * a, b2 = b * b, x2 = xi0 + xi0, y2 = eta0 + eta0;
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    R c0 = cm[(0 * 3 + n) * stride], c1 = cm[(1 * 3 + n) * stride], c2 = cm[(2 * 3 + n) * stride];
+    e[0 * 3 + n] = c0 + xi0 * (c1 + xi0 * c2);
+    e[1 * 3 + n] = a * (c1 + x2 * c2);
+    e[2 * 3 + n] = a2 * c2;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    R e0 = e[k * 3 + 0], e1 = e[k * 3 + 1], e2 = e[k * 3 + 2];
+    d[k * 3 + 0] = e0 + eta0 * (e1 + eta0 * e2);
+    d[k * 3 + 1] = b * (e1 + y2 * e2);
+    d[k * 3 + 2] = b2 * e2;
+  }
+}
+
+// Polynomial value at (xi, eta).
+template <class R>
+__device__ __forceinline__ R poly_eval(const R* __restrict__ cm, int stride, R xi, R eta) {
+  R r0 = cm[0 * stride] + eta * (cm[1 * stride] + eta * cm[2 * stride]);
+  R r1 = cm[3 * stride] + eta * (cm[4 * stride] + eta * cm[5 * stride]);
+  R r2 = cm[6 * stride] + eta * (cm[7 * stride] + eta * cm[8 * stride]);
+  return r0 + xi * (r1 + xi * r2);
+}
+
+// Accumulators of the circle integrals of the deviations dp, du, dv from the linearisation
+// state:  Ip = int dp, IpC = int dp C, IpS = int dp S, Jr = int (du C + dv S),
+// Ju = int (du (2C^2 - 1/2) + 2 dv S C), Jv = int (2 du S C + dv (2 S^2 - 1/2)).
+template <class R> struct Acc {
+  R Ip, IpC, IpS, Jr, Ju, Jv;
+};
+
+// Per-variable contractions with the moments of one arc set.
+template <class R>
+__device__ __forceinline__ void contract_p(const R d[9], const Mom<R>& M, Acc<R>& A) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const R x = d[k * 3 + l];
+      A.Ip += x * M.m[k][l];
+      A.IpC += x * M.m[k + 1][l];
+      A.IpS += x * M.m[k][l + 1];
+    }
+}
+template <class R>
+__device__ __forceinline__ void contract_u(const R d[9], const Mom<R>& M, Acc<R>& A) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const R x = d[k * 3 + l];
+      A.Jr += x * M.m[k + 1][l];
+      A.Ju += x * (R(2) * M.m[k + 2][l] - R(0.5) * M.m[k][l]);
+      A.Jv += x * (R(2) * M.m[k + 1][l + 1]);
+    }
+}
+template <class R>
+__device__ __forceinline__ void contract_v(const R d[9], const Mom<R>& M, Acc<R>& A) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const R x = d[k * 3 + l];
+      A.Jr += x * M.m[k][l + 1];
+      A.Ju += x * (R(2) * M.m[k + 1][l + 1]);
+      A.Jv += x * (R(2) * M.m[k][l + 2] - R(0.5) * M.m[k][l]);
+    }
+}
+
+// The same over the full circle (closed-form moments: int C^a S^b = 0 unless a, b are even;
+// 2pi, pi, pi, 3pi/4, pi/4, 3pi/4, pi/8, pi/8 for (0,0),(2,0),(0,2),(4,0),(2,2),(0,4),(4,2),(2,4)).
+template <class R> __device__ __forceinline__ void full_p(const R d[9], Acc<R>& A) {
+  const R pi = R(kPi);
+  A.Ip += R(2) * pi * d[0] + pi * (d[6] + d[2]) + R(0.25) * pi * d[8];
+  A.IpC += pi * d[3] + R(0.25) * pi * d[5];
+  A.IpS += pi * d[1] + R(0.25) * pi * d[7];
+}
+template <class R> __device__ __forceinline__ void full_u(const R d[9], Acc<R>& A) {
+  const R pi = R(kPi);
+  A.Jr += pi * d[3] + R(0.25) * pi * d[5];
+  A.Ju += pi * (d[0] + d[6]) + R(0.125) * pi * d[8];
+  A.Jv += R(0.5) * pi * d[4];
+}
+template <class R> __device__ __forceinline__ void full_v(const R d[9], Acc<R>& A) {
+  const R pi = R(kPi);
+  A.Jr += pi * d[1] + R(0.25) * pi * d[7];
+  A.Ju += R(0.5) * pi * d[4];
+  A.Jv += pi * (d[0] + d[2]) + R(0.125) * pi * d[8];
+}
+
+}  // namespace af

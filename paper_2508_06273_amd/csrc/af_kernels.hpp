@@ -1,0 +1,382 @@
+// af_kernels.hpp -- kernels of one Active Flux step (gfx950).
+//
+// One step = two launches:
+//   k_points : per 8x8 tile of DOF sites, stage the t_n point values of a one-cell halo in
+//              LDS, build the cell reconstructions of the 9x9 halo cells (inverse Simpson for
+//              the centre value, primitive Simpson average, monomial coefficients), then evolve
+//              the tile's own K, X and Y point values to the intermediate and new time levels
+//              (one wavefront per DOF kind), apply the positivity limiter, write U^{n+1} and
+//              the per-site Simpson-in-time flux sums f(U^n) + 4 f(U^{n+1/2}) + f(U^{n+1}).
+//   k_update : per cell, Simpson space-time face fluxes from the site sums and the
+//              conservative FP64 update of the cell average (paper eqs. F and 2dfvm); the
+//              last block commits t and the step counter.
+// Both accumulate the largest wave speed of the new state for the next step's time step.
+#pragma once
+#include "af_device.hpp"
+
+namespace af {
+
+enum { ERR_NONPHYS = -2, ERR_CFL = -3 };
+enum { KIND_K = 0, KIND_X = 1, KIND_Y = 2 };
+enum { LIN_AF3 = 0, LIN_AVG = 1, LIN_SIMPLE = 2 };
+
+constexpr int TILE = 8;        // sites per tile edge
+constexpr int HS = TILE + 2;   // halo sites per edge (local -1 .. TILE)
+constexpr int HC = TILE + 1;   // halo cells per edge (local -1 .. TILE-1)
+constexpr int NS = HS * HS;    // 100
+constexpr int NC = HC * HC;    // 81
+constexpr int PT_THREADS = 192;
+
+// Device-resident step control.
+struct DevState {
+  double t, dt, t_end, cfl;
+  unsigned long long smax[2];  // bit patterns of positive doubles (ordered like integers)
+  int err;
+  int active;
+  int last;   // the running step was cut to land on t_end
+  int pad0;
+  long long steps;
+  unsigned long long cnt[8];
+  unsigned int done_blocks;
+  unsigned int pad1;
+};
+
+struct Params {
+  int nx, ny, nkx, nky, per_x, per_y;
+  int tiles_x, tiles_y;
+  double dx, dy, idx, idy, gamma, hmin;
+  int mode, correction, limiter, pad;
+  long long pA, sA;  // pitch and variable stride of the cell-average arrays (doubles)
+  long long pP, sP;  // pitch and variable stride of the point-value arrays
+  long long pF, sF;  // pitch and variable stride of the flux-sum arrays (doubles)
+};
+
+template <class R> struct Bufs {
+  const double* A_in;
+  double* A_out;
+  const R* K_in;
+  const R* X_in;
+  const R* Y_in;
+  R* K_out;
+  R* X_out;
+  R* Y_out;
+  double* FK;  // 8 variables: f sums then g sums
+  double* FX;  // 4: f sums
+  double* FY;  // 4: g sums
+};
+
+__device__ __forceinline__ int wrap_cell(int i, int n, int per) {
+  if (per) { int r = i % n; return r < 0 ? r + n : r; }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+__device__ __forceinline__ int wrap_line(int i, int n, int per) {
+  if (per) { int r = i % n; return r < 0 ? r + n : r; }
+  return i < 0 ? 0 : (i > n ? n : i);
+}
+
+__device__ __forceinline__ void set_err(DevState* d, int code) { atomicCAS(&d->err, 0, code); }
+
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
+
+// Block-wide max of a non-negative double, one atomic per block.
+__device__ __forceinline__ void block_max_atomic(double v, unsigned long long* target,
+                                                 double* red) {
+  for (int off = 32; off > 0; off >>= 1) v = mx(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x / 64 + (threadIdx.y * blockDim.x) / 64;
+  const int lane = (threadIdx.x + threadIdx.y * blockDim.x) & 63;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  const int nw = (blockDim.x * blockDim.y + 63) / 64;
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    double m = red[0];
+    for (int k = 1; k < nw; ++k) m = mx(m, red[k]);
+    if (m > 0.0) atomicMax(target, dbits(m));
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Shared memory of a point tile.
+// ------------------------------------------------------------------------------------------
+template <class R> struct Smem {
+  R cp[4 * 9 * NC];  // [var][coef][cell]
+  R ub[4 * NC];      // primitive Simpson averages [var][cell]
+  R sk[4 * NS];      // t_n point values [var][site], local site (a,b) -> (a+1) + (b+1)*HS
+  R sx[4 * NS];
+  R sy[4 * NS];
+  double red[4];
+};
+
+__device__ __forceinline__ int sidx(int a, int b) { return (a + 1) + (b + 1) * HS; }
+__device__ __forceinline__ int cidx(int a, int b) { return (a + 1) + (b + 1) * HC; }
+
+template <class R> struct Geo {
+  R idx, idy, gamma, half_h;
+};
+
+// ------------------------------------------------------------------------------------------
+// EG2 at one DOF.  cb: LDS index of the lower-left cell around the DOF (K: cell (a-1,b-1);
+// X: cell (a-1,b); Y: cell (a,b-1)).  Returns the deviation dU = EG2[U] - lin.
+// ------------------------------------------------------------------------------------------
+template <class R, int KIND>
+__device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin[4], R tau,
+                                   const Geo<R>& G, R dU[4]) {
+  using MA = Math<R>;
+  const R rp = lin[0], up = lin[1], vp = lin[2], pp = lin[3];
+  if (!admissible(rp, pp)) return ERR_NONPHYS;
+  const R c = MA::sqrt_(G.gamma * pp / rp);
+  if ((mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * tau >= G.half_h) return ERR_CFL;
+  const R ic = R(1) / c;
+  const R px = -up * tau * G.idx, py = -vp * tau * G.idy;
+  const R ax = c * tau * G.idx, by = c * tau * G.idy;
+  const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
+  const R twopi = R(2 * kPi), pi = R(kPi);
+  constexpr int VS = 9 * NC;  // variable stride in cp
+  Acc<R> A = {R(0), R(0), R(0), R(0), R(0), R(0)};
+
+  if constexpr (KIND == KIND_K) {
+    // crossing points: at -+alpha (cMx, -+sx), at beta (sy, cMy), at pi - beta (-sy, cMy)
+    const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
+    const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
+    const R al = MA::acos_(cMx), be = MA::asin_(cMy);
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      const int sx = q & 1, sy = q >> 1;
+      // x interval of side sx: right (-al, al), left (al, 2pi - al)
+      const R a1 = sx ? -al : al, b1 = sx ? al : twopi - al;
+      const R sa1 = sx ? -sxx : sxx;  // sin at a1 (cos is cMx at both ends)
+      // y interval of side sy: top (be, pi - be), bottom (pi - be, 2pi + be)
+      const R a2 = sy ? be : pi - be, b2 = sy ? pi - be : twopi + be;
+      const R ca2 = sy ? syy : -syy;  // cos at a2 (sin is cMy at both ends)
+      Br<R> B;
+      br_zero(B);
+      // the intersection is made of the pieces I_x cap (I_y + 2 pi k), k = 0 and one k = +-1
+      const R kB = (sx == 0 && sy == 1) ? twopi : -twopi;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const R sh = t ? kB : R(0);
+        const R lo2 = a2 + sh, hi2 = b2 + sh;
+        const bool l1 = a1 >= lo2, h1 = b1 <= hi2;
+        const R lo = l1 ? a1 : lo2, hi = h1 ? b1 : hi2;
+        const R Ca = l1 ? cMx : ca2, Sa = l1 ? sa1 : cMy;
+        const R Cb = h1 ? cMx : -ca2, Sb = h1 ? -sa1 : cMy;
+        br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
+      }
+      Mom<R> M;
+      moments(B, M);
+      const int cell = cb + sx + sy * HC;
+      const R xi0 = px + R(0.5) - R(sx), eta0 = py + R(0.5) - R(sy);
+      R d[9];
+      circle_shift(cp + 3 * VS + cell, NC, xi0, eta0, ax, by, d);
+      d[0] -= pp;
+      contract_p(d, M, A);
+      circle_shift(cp + 1 * VS + cell, NC, xi0, eta0, ax, by, d);
+      d[0] -= up;
+      contract_u(d, M, A);
+      circle_shift(cp + 2 * VS + cell, NC, xi0, eta0, ax, by, d);
+      d[0] -= vp;
+      contract_v(d, M, A);
+    }
+  } else {
+    // one grid line: the full circle of the low-side cell plus the arc on the high side of
+    // the difference of the two cell polynomials (which vanishes on the line)
+    Mom<R> M;
+    {
+      Br<R> B;
+      br_zero(B);
+      if constexpr (KIND == KIND_X) {
+        const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
+        const R al = MA::acos_(cMx);
+        br_piece(B, cMx, -sxx, cMx, sxx, al + al);
+      } else {
+        const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
+        const R be = MA::asin_(cMy);
+        br_piece(B, syy, cMy, -syy, cMy, pi - be - be);
+      }
+      moments(B, M);
+    }
+    const int cl = cb, ch = cb + (KIND == KIND_X ? 1 : HC);
+    const R xl = (KIND == KIND_X) ? px + R(0.5) : px;
+    const R yl = (KIND == KIND_X) ? py : py + R(0.5);
+    const R xh = (KIND == KIND_X) ? px - R(0.5) : px;
+    const R yh = (KIND == KIND_X) ? py : py - R(0.5);
+#pragma unroll
+    for (int var = 1; var < 4; ++var) {
+      R lo[9], hi[9];
+      circle_shift(cp + var * VS + cl, NC, xl, yl, ax, by, lo);
+      circle_shift(cp + var * VS + ch, NC, xh, yh, ax, by, hi);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) hi[i] -= lo[i];
+      lo[0] -= lin[var];
+      if (var == 3) { full_p(lo, A); contract_p(hi, M, A); }
+      if (var == 1) { full_u(lo, A); contract_u(hi, M, A); }
+      if (var == 2) { full_v(lo, A); contract_v(hi, M, A); }
+    }
+  }
+
+  // values at the foot point P'
+  const int sxP = (KIND == KIND_Y) ? 0 : (up <= R(0) ? 1 : 0);
+  const int syP = (KIND == KIND_X) ? 0 : (vp <= R(0) ? 1 : 0);
+  const int cellP = cb + sxP + syP * HC;
+  const R xiP = (KIND == KIND_Y) ? px : px + R(0.5) - R(sxP);
+  const R etaP = (KIND == KIND_X) ? py : py + R(0.5) - R(syP);
+  const R drP = poly_eval(cp + 0 * VS + cellP, NC, xiP, etaP) - rp;
+  const R dpP = poly_eval(cp + 3 * VS + cellP, NC, xiP, etaP) - pp;
+
+  const R ipi = R(1.0 / kPi);
+  const R ic2 = ic * ic;
+  const R irc = ic / rp;
+  const R rc = rp * c;
+  dU[0] = drP - R(2) * dpP * ic2 + ipi * (A.Ip * ic2 - rp * ic * A.Jr);
+  dU[1] = ipi * (A.Ju - A.IpC * irc);
+  dU[2] = ipi * (A.Jv - A.IpS * irc);
+  dU[3] = -dpP + ipi * (A.Ip - rc * A.Jr);
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// EG1 on piecewise constant data (the primitive cell averages), used by the positivity
+// limiter.  Low moments only.  A foot point on a grid line takes the mean of the cells whose
+// closure contains it.
+// ------------------------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void low_moments(R Ca, R Sa, R Cb, R Sb, R L, R m[6]) {
+  // m: M00, M10, M01, M20, M11, M02
+  m[0] = L;
+  m[1] = Sb - Sa;
+  m[2] = Ca - Cb;
+  const R cs = Cb * Sb - Ca * Sa;
+  m[3] = R(0.5) * (cs + L);
+  m[4] = R(-0.5) * (Cb * Cb - Ca * Ca);
+  m[5] = R(0.5) * (L - cs);
+}
+
+template <class R>
+__device__ __forceinline__ void low_piece(R a1, R c1a, R s1a, R b1, R c1b, R s1b, R a2, R c2a,
+                                          R s2a, R b2, R c2b, R s2b, R m[6]) {
+  const bool lo1 = a1 >= a2, hi1 = b1 <= b2;
+  const R lo = lo1 ? a1 : a2, hi = hi1 ? b1 : b2;
+  const R L = hi - lo;
+  const R keep = L > R(0) ? R(1) : R(0);
+  low_moments(lo1 ? c1a : c2a, lo1 ? s1a : s2a, hi1 ? c1b : c2b, hi1 ? s1b : s2b,
+              L * keep, m);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) m[k] *= keep;
+}
+
+template <class R, int KIND>
+__device__ __forceinline__ int eg1_pc(const R* __restrict__ ub, int cb, const R lin[4], R tau,
+                                      const Geo<R>& G, R dU[4]) {
+  using MA = Math<R>;
+  const R rp = lin[0], up = lin[1], vp = lin[2], pp = lin[3];
+  if (!admissible(rp, pp)) return ERR_NONPHYS;
+  const R c = MA::sqrt_(G.gamma * pp / rp);
+  if ((mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * tau >= G.half_h) return ERR_CFL;
+  const R ic = R(1) / c;
+  const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
+  const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
+  const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
+  const R al = MA::acos_(cMx), be = MA::asin_(cMy);
+  const R twopi = R(2 * kPi), pi = R(kPi);
+  R Ip = 0, IpC = 0, IpS = 0, Jr = 0, Ku = 0, Kv = 0;
+  const int nq = (KIND == KIND_K) ? 4 : 2;
+  for (int q = 0; q < nq; ++q) {
+    int sx, sy;
+    if (KIND == KIND_K) { sx = q & 1; sy = q >> 1; }
+    else if (KIND == KIND_X) { sx = q; sy = 0; }
+    else { sx = 0; sy = q; }
+    R m[6] = {0, 0, 0, 0, 0, 0};
+    // x-interval of side sx (whole circle for Y), y-interval of side sy (whole for X)
+    R a1, b1, c1a, s1a, c1b, s1b, a2, b2, c2a, s2a, c2b, s2b;
+    if (KIND == KIND_Y) { a1 = -pi; b1 = pi; c1a = -1; s1a = 0; c1b = -1; s1b = 0; }
+    else if (sx) { a1 = -al; b1 = al; c1a = cMx; s1a = -sxx; c1b = cMx; s1b = sxx; }
+    else { a1 = al; b1 = twopi - al; c1a = cMx; s1a = sxx; c1b = cMx; s1b = -sxx; }
+    if (KIND == KIND_X) { a2 = -pi; b2 = pi; c2a = -1; s2a = 0; c2b = -1; s2b = 0; }
+    else if (sy) { a2 = be; b2 = pi - be; c2a = syy; s2a = cMy; c2b = -syy; s2b = cMy; }
+    else { a2 = pi - be; b2 = twopi + be; c2a = -syy; s2a = cMy; c2b = syy; s2b = cMy; }
+    for (int k = -1; k <= 1; ++k) {
+      R n[6];
+      low_piece(a1, c1a, s1a, b1, c1b, s1b, a2 + R(k) * twopi, c2a, s2a, b2 + R(k) * twopi,
+                c2b, s2b, n);
+      for (int t = 0; t < 6; ++t) m[t] += n[t];
+    }
+    const int cell = cb + (KIND == KIND_Y ? 0 : sx) + (KIND == KIND_X ? 0 : sy * HC);
+    const R dpq = ub[3 * NC + cell] - pp, duq = ub[1 * NC + cell] - up,
+            dvq = ub[2 * NC + cell] - vp;
+    Ip += dpq * m[0];
+    IpC += dpq * m[1];
+    IpS += dpq * m[2];
+    Jr += duq * m[1] + dvq * m[2];
+    Ku += duq * (R(3) * m[3] - m[0]) + R(3) * dvq * m[4];
+    Kv += R(3) * duq * m[4] + dvq * (R(3) * m[5] - m[0]);
+  }
+  // foot point values (mean over the cells whose closure contains P')
+  R P[4] = {0, 0, 0, 0};
+  {
+    const bool onx = (KIND != KIND_Y) && (up == R(0));
+    const bool ony = (KIND != KIND_X) && (vp == R(0));
+    const int sx0 = (KIND == KIND_Y) ? 0 : (up < R(0) ? 1 : 0);
+    const int sy0 = (KIND == KIND_X) ? 0 : (vp < R(0) ? 1 : 0);
+    int n = 0;
+    for (int ox = 0; ox < 2; ++ox)
+      for (int oy = 0; oy < 2; ++oy) {
+        const int sx = onx ? ox : sx0, sy = ony ? oy : sy0;
+        if ((!onx && ox) || (!ony && oy)) continue;
+        const int cell = cb + (KIND == KIND_Y ? 0 : sx) + (KIND == KIND_X ? 0 : sy * HC);
+        for (int v = 0; v < 4; ++v) P[v] += ub[v * NC + cell];
+        ++n;
+      }
+    const R inv = R(1) / R(n);
+    for (int v = 0; v < 4; ++v) P[v] = P[v] * inv - lin[v];
+  }
+  const R i2pi = R(0.5 / kPi);
+  const R ic2 = ic * ic, irc = ic / rp;
+  dU[0] = P[0] - P[3] * ic2 + i2pi * (Ip * ic2 - R(2) * rp * ic * Jr);
+  dU[1] = R(0.5) * P[1] + i2pi * (Ku - R(2) * IpC * irc);
+  dU[2] = R(0.5) * P[2] + i2pi * (Kv - R(2) * IpS * irc);
+  dU[3] = i2pi * (Ip - R(2) * rp * c * Jr);
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Lax-Friedrichs point update on the lattice of same-kind DOFs (FP64), the last resort of
+// the positivity limiter: a dual cell dx x dy centred at the DOF, Rusanov fluxes with the
+// four same-kind neighbours, time increment tau.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void lf_flux(const double UL[4], const double UR[4], int dir,
+                                        double gamma, double g1inv, double o[4]) {
+  double FL[4], GL[4], FR[4], GR[4], QL[4], QR[4];
+  flux_fg(UL, g1inv, FL, GL);
+  flux_fg(UR, g1inv, FR, GR);
+  p2c(UL, g1inv, QL);
+  p2c(UR, g1inv, QR);
+  const double sL = __builtin_fabs(UL[1 + dir]) + __builtin_sqrt(gamma * UL[3] / UL[0]);
+  const double sR = __builtin_fabs(UR[1 + dir]) + __builtin_sqrt(gamma * UR[3] / UR[0]);
+  const double al = mx(sL, sR);
+  for (int v = 0; v < 4; ++v) {
+    const double fl = dir ? GL[v] : FL[v], fr = dir ? GR[v] : FR[v];
+    o[v] = 0.5 * (fl + fr) - 0.5 * al * (QR[v] - QL[v]);
+  }
+}
+
+template <class R>
+__device__ void lf_update(const R* __restrict__ site, int a, int b, double tau, const Params& P,
+                          double out[4]) {
+  double U[5][4];
+  const int nb[5][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+  for (int k = 0; k < 5; ++k)
+    for (int v = 0; v < 4; ++v) U[k][v] = (double)site[v * NS + sidx(a + nb[k][0], b + nb[k][1])];
+  const double g1inv = 1.0 / (P.gamma - 1.0);
+  double Fe[4], Fw[4], Gn[4], Gs[4], Q0[4], Q[4];
+  lf_flux(U[0], U[1], 0, P.gamma, g1inv, Fe);
+  lf_flux(U[2], U[0], 0, P.gamma, g1inv, Fw);
+  lf_flux(U[0], U[3], 1, P.gamma, g1inv, Gn);
+  lf_flux(U[4], U[0], 1, P.gamma, g1inv, Gs);
+  p2c(U[0], g1inv, Q0);
+  for (int v = 0; v < 4; ++v)
+    Q[v] = Q0[v] - tau * P.idx * (Fe[v] - Fw[v]) - tau * P.idy * (Gn[v] - Gs[v]);
+  c2p_plain(Q, P.gamma - 1.0, out);
+}
+
+}  // namespace af

@@ -1,0 +1,963 @@
+// af_lib.hip -- kernels and host runtime of libaf.so (C ABI in include/af.h).
+//
+// Fully discrete third-order Active Flux method for the 2D Euler equations, arXiv 2508.06273.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "af.h"
+#include "af_kernels.hpp"
+
+namespace af {
+
+// ------------------------------------------------------------------------------------------
+// Kernel 1: point values of one tile of 8x8 sites.
+// ------------------------------------------------------------------------------------------
+template <class R, int KIND>
+__device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bufs<R>& B,
+                                           DevState* dev, int a, int b, int gi, int gj,
+                                           double dt, double& speed) {
+  const Geo<R> G = {R(P.idx), R(P.idy), R(P.gamma), R(0.5 * P.hmin)};
+  const R* site = (KIND == KIND_K) ? S.sk : (KIND == KIND_X ? S.sx : S.sy);
+  const int s0 = sidx(a, b);
+  R U0[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) U0[v] = site[v * NS + s0];
+
+  // cells around the DOF and the neighbours of the derivative stencils
+  int cb;
+  R Ux[4], Uy[4], Ut[4];
+  constexpr int VS = 9 * NC;
+  if constexpr (KIND == KIND_K) {
+    cb = a + b * HC;  // cell (a-1, b-1)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ux[v] = (S.sy[v * NS + sidx(a, b)] - S.sy[v * NS + sidx(a - 1, b)]) * G.idx;
+      Uy[v] = (S.sx[v * NS + sidx(a, b)] - S.sx[v * NS + sidx(a, b - 1)]) * G.idy;
+      Ut[v] = R(0.25) * ((S.ub[v * NC + cb] + S.ub[v * NC + cb + 1]) +
+                         (S.ub[v * NC + cb + HC] + S.ub[v * NC + cb + HC + 1]));
+    }
+  } else if constexpr (KIND == KIND_X) {
+    cb = a + (b + 1) * HC;  // cell (a-1, b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Uy[v] = (S.sk[v * NS + sidx(a, b + 1)] - S.sk[v * NS + sidx(a, b)]) * G.idy;
+      Ux[v] = (S.cp[v * VS + cb + 1] - S.cp[v * VS + cb]) * G.idx;
+      Ut[v] = R(0.5) * (S.ub[v * NC + cb] + S.ub[v * NC + cb + 1]);
+    }
+  } else {
+    cb = (a + 1) + b * HC;  // cell (a, b-1)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ux[v] = (S.sk[v * NS + sidx(a + 1, b)] - S.sk[v * NS + sidx(a, b)]) * G.idx;
+      Uy[v] = (S.cp[v * VS + cb + HC] - S.cp[v * VS + cb]) * G.idy;
+      Ut[v] = R(0.5) * (S.ub[v * NC + cb] + S.ub[v * NC + cb + HC]);
+    }
+  }
+  R Cv[4] = {R(0), R(0), R(0), R(0)};
+  if (P.correction) corr_half(U0, Ux, Uy, G.gamma, Cv);
+  const double h2 = 0.25 * dt * dt, f2 = dt * dt;
+
+  int e = 0;
+  R lin[4];
+  if (P.mode == LIN_AF3) {
+    R dq[4];
+    e = eg2<R, KIND>(S.cp, cb, U0, R(0.25 * dt), G, dq);
+    if (e) { set_err(dev, e); return; }
+    R q[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = U0[v] + dq[v];
+    if (admissible(q[0], q[3])) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lin[v] = q[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lin[v] = U0[v];
+      atomicAdd(&dev->cnt[AF_CNT_INNER], 1ull);
+    }
+  } else if (P.mode == LIN_AVG) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) lin[v] = Ut[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) lin[v] = U0[v];
+  }
+
+  double Uh[4], U1[4];
+  {
+    R d[4];
+    e = eg2<R, KIND>(S.cp, cb, lin, R(0.5 * dt), G, d);
+    if (e) { set_err(dev, e); return; }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Uh[v] = (double)lin[v] + (double)d[v] + h2 * (double)Cv[v];
+  }
+  // positivity of the intermediate value (Algorithm 3)
+  if (!admissible(Uh[0], Uh[3])) {
+    if (!P.limiter) { set_err(dev, ERR_NONPHYS); return; }
+    bool done = false;
+    if (admissible(Ut[0], Ut[3])) {
+      R d[4];
+      e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(0.5 * dt), G, d);
+      if (e == ERR_CFL) { set_err(dev, e); return; }
+      atomicAdd(&dev->cnt[AF_CNT_EG1], 1ull);
+      double lo[4];
+      for (int v = 0; v < 4; ++v) lo[v] = (double)Ut[v] + (double)d[v];
+      if (e == 0 && admissible(lo[0], lo[3])) {
+        for (int v = 0; v < 4; ++v) Uh[v] = lo[v];
+        done = true;
+      }
+    }
+    if (!done) {
+      lf_update<R>(site, a, b, 0.5 * dt, P, Uh);
+      atomicAdd(&dev->cnt[AF_CNT_LF], 1ull);
+      if (!admissible(Uh[0], Uh[3])) { set_err(dev, ERR_NONPHYS); return; }
+    }
+  }
+  R Uhr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Uhr[v] = (R)Uh[v];
+  {
+    R d[4];
+    e = eg2<R, KIND>(S.cp, cb, Uhr, R(dt), G, d);
+    if (e) { set_err(dev, e); return; }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) U1[v] = (double)Uhr[v] + (double)d[v] + f2 * (double)Cv[v];
+  }
+  if (P.limiter && !admissible(U1[0], U1[3])) {
+    bool done = false;
+    if (admissible(Ut[0], Ut[3])) {
+      R d[4];
+      e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(dt), G, d);
+      if (e == ERR_CFL) { set_err(dev, e); return; }
+      atomicAdd(&dev->cnt[AF_CNT_EG1], 1ull);
+      double lo[4];
+      for (int v = 0; v < 4; ++v) lo[v] = (double)Ut[v] + (double)d[v];
+      if (e == 0 && admissible(lo[0], lo[3])) {
+        for (int v = 0; v < 4; ++v) U1[v] = lo[v];
+        done = true;
+      }
+    }
+    if (!done) {
+      lf_update<R>(site, a, b, dt, P, U1);
+      atomicAdd(&dev->cnt[AF_CNT_LF], 1ull);
+      if (!admissible(U1[0], U1[3])) { set_err(dev, ERR_NONPHYS); return; }
+    }
+  }
+
+  // outputs: new point value, Simpson-in-time flux sums, wave speed
+  R* out = (KIND == KIND_K) ? B.K_out : (KIND == KIND_X ? B.X_out : B.Y_out);
+  const long long o = (long long)gj * P.pP + gi;
+  R U1r[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    U1r[v] = (R)U1[v];
+    out[v * P.sP + o] = U1r[v];
+  }
+  const double g1inv = 1.0 / (P.gamma - 1.0);
+  double U1d[4];
+  double Fs[4] = {0, 0, 0, 0}, Gs[4] = {0, 0, 0, 0};
+  {
+    double Ul[4], F[4], Gq[4];
+#pragma unroll 1
+    for (int lvl = 0; lvl < 3; ++lvl) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Ul[v] = lvl == 0 ? (double)U0[v] : (lvl == 1 ? Uh[v] : (double)U1r[v]);
+      flux_fg(Ul, g1inv, F, Gq);
+      const double w = lvl == 1 ? 4.0 : 1.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Fs[v] += w * F[v];
+        Gs[v] += w * Gq[v];
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) U1d[v] = (double)U1r[v];
+  const long long of = (long long)gj * P.pF + gi;
+  if constexpr (KIND == KIND_K) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      B.FK[v * P.sF + of] = Fs[v];
+      B.FK[(4 + v) * P.sF + of] = Gs[v];
+    }
+  } else if constexpr (KIND == KIND_X) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) B.FX[v * P.sF + of] = Fs[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) B.FY[v * P.sF + of] = Gs[v];
+  }
+  if (admissible(U1d[0], U1d[3])) speed = mx(speed, wave_speed(U1d, P.gamma));
+}
+
+// Step control shared by both kernels.  Returns false if the step does not run.
+__device__ __forceinline__ bool step_dt(const Params& P, DevState* dev, double dt_host, int slot,
+                                        double* dt_out) {
+  if (dev->err) return false;
+  double dt;
+  int last = 0;
+  if (dt_host > 0.0) {
+    dt = dt_host;
+  } else {
+    const double t = dev->t, te = dev->t_end;
+    if (!(t < te)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) dev->active = 0;
+      return false;
+    }
+    const double smax = __longlong_as_double((long long)dev->smax[slot]);
+    if (!(smax > 0.0) || !(smax < 1e300)) {
+      if (threadIdx.x == 0) set_err(dev, ERR_NONPHYS);
+      return false;
+    }
+    dt = dev->cfl * P.hmin / smax;
+    if (t + dt >= te) { dt = te - t; last = 1; }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    dev->dt = dt;
+    dev->active = 1;
+    dev->last = last;
+  }
+  *dt_out = dt;
+  return true;
+}
+
+template <class R>
+__global__ __launch_bounds__(PT_THREADS) void k_points(Params P, Bufs<R> B, DevState* dev,
+                                                      double dt_host, int slot) {
+  __shared__ Smem<R> S;
+  double dt;
+  if (!step_dt(P, dev, dt_host, slot, &dt)) return;
+
+  const int tile = blockIdx.x;
+  const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
+  const int tid = threadIdx.x;
+
+  // 1. stage the t_n point values of the halo (local sites -1 .. TILE) in LDS
+  for (int e = tid; e < 3 * NS; e += PT_THREADS) {
+    const int kind = e / NS, s = e % NS;
+    const int a = s % HS - 1, b = s / HS - 1;
+    const int gi = i0 + a, gj = j0 + b;
+    int si, sj;
+    const R* src;
+    R* dst;
+    if (kind == 0) {
+      si = wrap_line(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.K_in; dst = S.sk;
+    } else if (kind == 1) {
+      si = wrap_line(gi, P.nx, P.per_x); sj = wrap_cell(gj, P.ny, P.per_y); src = B.X_in; dst = S.sx;
+    } else {
+      si = wrap_cell(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.Y_in; dst = S.sy;
+    }
+    const long long o = (long long)sj * P.pP + si;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[v * NS + s] = src[v * P.sP + o];
+  }
+  __syncthreads();
+
+  // 2. cell reconstructions of the halo cells (local cells -1 .. TILE-1)
+  for (int c = tid; c < NC; c += PT_THREADS) {
+    const int a = c % HC - 1, b = c / HC - 1;
+    const int gi = wrap_cell(i0 + a, P.nx, P.per_x), gj = wrap_cell(j0 + b, P.ny, P.per_y);
+    const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
+    // node k of the cell: 0..3 corners K(a,b) K(a+1,b) K(a,b+1) K(a+1,b+1),
+    // 4,5 X(a,b) X(a+1,b), 6,7 Y(a,b) Y(a,b+1)
+    const R* nptr[8] = {S.sk + sidx(a, b), S.sk + sidx(a + 1, b), S.sk + sidx(a, b + 1),
+                        S.sk + sidx(a + 1, b + 1), S.sx + sidx(a, b), S.sx + sidx(a + 1, b),
+                        S.sy + sidx(a, b), S.sy + sidx(a, b + 1)};
+    auto node = [&](int k, double W[4]) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[v] = (double)nptr[k][v * NS];
+    };
+    double Qb[4];
+    const long long oa = (long long)gj * P.pA + gi;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Qb[v] = B.A_in[v * P.sA + oa];
+    // reference state: mean of the eight nodes (exact for equal nodes)
+    double Wr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wr[v] = ((((double)nptr[0][v * NS] + (double)nptr[1][v * NS]) +
+                ((double)nptr[2][v * NS] + (double)nptr[3][v * NS])) +
+               (((double)nptr[4][v * NS] + (double)nptr[5][v * NS]) +
+                ((double)nptr[6][v * NS] + (double)nptr[7][v * NS]))) * 0.125;
+    }
+    // inverse Simpson for the centre value: Q_c = Q-bar + [sum_K (Q-bar - Q_k)
+    //                                          + 4 sum_E (Q-bar - Q_e)] / 16
+    double dQ[4], Uc[4];
+    {
+      double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, W[4], Q[4];
+      for (int k = 0; k < 8; ++k) {
+        node(k, W);
+        p2c(W, g1inv, Q);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (k < 4) sK[v] += Qb[v] - Q[v];
+          else sE[v] += Qb[v] - Q[v];
+        }
+      }
+      p2c(Wr, g1inv, Q);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Q[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
+    }
+    c2p_dev(Wr, dQ, gm1, Uc);
+    if (!admissible(Uc[0], Uc[3])) {
+      c2p_plain(Qb, gm1, Uc);
+      const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
+      if (owned) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
+    }
+    // primitive Simpson average and monomial coefficients, one variable at a time
+#pragma unroll 1
+    for (int v = 0; v < 4; ++v) {
+      double w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = (double)nptr[k][v * NS];
+      const double u = Uc[v];
+      const double sK4 = ((w[0] - u) + (w[1] - u)) + ((w[2] - u) + (w[3] - u));
+      const double sE4 = ((w[4] - u) + (w[5] - u)) + ((w[6] - u) + (w[7] - u));
+      S.ub[v * NC + c] = (R)(u + (sK4 + 4.0 * sE4) * (1.0 / 36.0));
+      const double N[3][3] = {{w[0], w[4], w[2]}, {w[6], u, w[7]}, {w[1], w[5], w[3]}};
+      double cm[9];
+      nodes_to_monomials(N, cm);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) S.cp[(v * 9 + k) * NC + c] = (R)cm[k];
+    }
+  }
+  __syncthreads();
+
+  // 3. evolve the tile's own DOFs: wavefront 0 -> K, 1 -> X, 2 -> Y
+  const int kind = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int a = lane % TILE, b = lane / TILE;
+  const int gi = i0 + a, gj = j0 + b;
+  double speed = 0.0;
+  if (kind == KIND_K) {
+    if (gi < P.nkx && gj < P.nky) evolve_dof<R, KIND_K>(S, P, B, dev, a, b, gi, gj, dt, speed);
+  } else if (kind == KIND_X) {
+    if (gi < P.nkx && gj < P.ny) evolve_dof<R, KIND_X>(S, P, B, dev, a, b, gi, gj, dt, speed);
+  } else {
+    if (gi < P.nx && gj < P.nky) evolve_dof<R, KIND_Y>(S, P, B, dev, a, b, gi, gj, dt, speed);
+  }
+  block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
+}
+
+// ------------------------------------------------------------------------------------------
+// Kernel 2: Simpson space-time fluxes and the conservative update of the averages.
+// ------------------------------------------------------------------------------------------
+constexpr int UP_BX = 64, UP_BY = 4;
+
+__global__ __launch_bounds__(UP_BX* UP_BY) void k_update(Params P, const double* __restrict__ A_in,
+                                                        double* __restrict__ A_out,
+                                                        const double* __restrict__ FK,
+                                                        const double* __restrict__ FX,
+                                                        const double* __restrict__ FY,
+                                                        DevState* dev, int slot) {
+  __shared__ double red[4];
+  __shared__ int last_block;
+  const bool run = !dev->err && dev->active;
+  const int i = blockIdx.x * UP_BX + threadIdx.x, j = blockIdx.y * UP_BY + threadIdx.y;
+  double speed = 0.0;
+  const double dt = dev->dt;
+  if (run && i < P.nx && j < P.ny) {
+    const int ip = wrap_line(i + 1, P.nx, P.per_x), jp = wrap_line(j + 1, P.ny, P.per_y);
+    const long long kw0 = (long long)j * P.pF + i, kw1 = (long long)jp * P.pF + i;
+    const long long ke0 = (long long)j * P.pF + ip, ke1 = (long long)jp * P.pF + ip;
+    const long long oa = (long long)j * P.pA + i;
+    const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
+    double Q[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double* fk = FK + v * P.sF;
+      const double* gk = FK + (4 + v) * P.sF;
+      const double Fw = fk[kw0] + 4.0 * FX[v * P.sF + kw0] + fk[kw1];
+      const double Fe = fk[ke0] + 4.0 * FX[v * P.sF + ke0] + fk[ke1];
+      const double Gs = gk[kw0] + 4.0 * FY[v * P.sF + kw0] + gk[ke0];
+      const double Gn = gk[kw1] + 4.0 * FY[v * P.sF + kw1] + gk[ke1];
+      Q[v] = A_in[v * P.sA + oa] - lx * (Fe - Fw) - ly * (Gn - Gs);
+      A_out[v * P.sA + oa] = Q[v];
+    }
+    double U[4];
+    c2p_plain(Q, P.gamma - 1.0, U);
+    if (!admissible(U[0], U[3])) set_err(dev, ERR_NONPHYS);
+    else speed = wave_speed(U, P.gamma);
+  }
+  // block max into the next step's slot (tid linearised over x, y)
+  {
+    double v = speed;
+    for (int off = 32; off > 0; off >>= 1) v = mx(v, __shfl_xor(v, off, 64));
+    const int t = threadIdx.x + threadIdx.y * UP_BX;
+    if ((t & 63) == 0) red[t >> 6] = v;
+  }
+  __syncthreads();
+  const int t = threadIdx.x + threadIdx.y * UP_BX;
+  if (t == 0) {
+    double m = mx(mx(red[0], red[1]), mx(red[2], red[3]));
+    if (run && m > 0.0) atomicMax(&dev->smax[slot ^ 1], dbits(m));
+    __threadfence();
+    const unsigned int nb = gridDim.x * gridDim.y;
+    const unsigned int ticket = atomicAdd(&dev->done_blocks, 1u);
+    last_block = (ticket == nb - 1);
+  }
+  __syncthreads();
+  if (last_block && t == 0) {
+    __threadfence();
+    dev->done_blocks = 0;
+    if (run && !atomicAdd(&dev->err, 0)) {
+      dev->t = dev->last ? dev->t_end : dev->t + dt;
+      dev->steps += 1;
+      dev->smax[slot] = 0ull;
+    }
+  }
+}
+
+// Largest wave speed of the current state (averages and point values) into smax[slot].
+template <class R>
+__global__ void k_cfl(Params P, const double* __restrict__ A, const R* __restrict__ K,
+                      const R* __restrict__ X, const R* __restrict__ Y, DevState* dev,
+                      int slot) {
+  __shared__ double red[4];
+  const long long n0 = (long long)P.nx * P.ny, n1 = (long long)P.nkx * P.nky,
+                  n2 = (long long)P.nkx * P.ny, n3 = (long long)P.nx * P.nky;
+  const long long ntot = n0 + n1 + n2 + n3;
+  double speed = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ntot;
+       e += (long long)gridDim.x * blockDim.x) {
+    double U[4];
+    if (e < n0) {
+      const int i = (int)(e % P.nx), j = (int)(e / P.nx);
+      double Q[4];
+      for (int v = 0; v < 4; ++v) Q[v] = A[v * P.sA + (long long)j * P.pA + i];
+      c2p_plain(Q, P.gamma - 1.0, U);
+    } else {
+      long long r = e - n0;
+      const R* src;
+      int w;
+      if (r < n1) { src = K; w = P.nkx; }
+      else if (r < n1 + n2) { src = X; w = P.nkx; r -= n1; }
+      else { src = Y; w = P.nx; r -= n1 + n2; }
+      const int i = (int)(r % w), j = (int)(r / w);
+      for (int v = 0; v < 4; ++v) U[v] = (double)src[v * P.sP + (long long)j * P.pP + i];
+    }
+    // non-admissible values do not enter the time step (as NaN speeds would not)
+    if (admissible(U[0], U[3])) speed = mx(speed, wave_speed(U, P.gamma));
+  }
+  block_max_atomic(speed, &dev->smax[slot], red);
+}
+
+}  // namespace af
+
+// ==========================================================================================
+// Host runtime
+// ==========================================================================================
+using namespace af;
+
+struct af_handle {
+  int nx = 0, ny = 0, per_x = 1, per_y = 1, nkx = 0, nky = 0;
+  double x0 = 0, x1 = 1, y0 = 0, y1 = 1, dx = 1, dy = 1, gamma = 1.4;
+  int prec = AF_PREC_FP64, mode = AF_LIN_AF3, correction = 1, limiter = 0;
+  int graph_steps = 16;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  long long pA = 0, pP = 0, pF = 0;
+  double* A[2] = {nullptr, nullptr};
+  void* K[2] = {nullptr, nullptr};
+  void* X[2] = {nullptr, nullptr};
+  void* Y[2] = {nullptr, nullptr};
+  double* FK = nullptr;
+  double* FX = nullptr;
+  double* FY = nullptr;
+  DevState* dev = nullptr;
+  int cur = 0;
+  bool has_state = false;
+  long long steps_base = 0;
+  hipGraphExec_t gexec = nullptr;
+  int gexec_steps = 0;
+  // AF_OPT_TIMING: events around each kernel of every eager step
+  int timing = 0;
+  std::vector<hipEvent_t> ev;  // 3 per step: before points, between, after update
+  double ms_points = 0.0, ms_update = 0.0;
+  long long timed_steps = 0;
+  std::string err;
+};
+
+static std::string g_create_error;
+
+static int fail(const af_handle* h, int code, const std::string& msg) {
+  if (h) const_cast<af_handle*>(h)->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define HIP_OK(call, h)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(h, e_ == hipErrorOutOfMemory ? AF_ERR_OOM : AF_ERR_DEVICE,         \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                \
+  } while (0)
+
+static size_t rsize(const af_handle* h) { return h->prec == AF_PREC_FP32 ? 4 : 8; }
+
+static Params make_params(const af_handle* h) {
+  Params P;
+  P.nx = h->nx; P.ny = h->ny; P.nkx = h->nkx; P.nky = h->nky;
+  P.per_x = h->per_x; P.per_y = h->per_y;
+  P.tiles_x = (h->nkx + TILE - 1) / TILE;
+  P.tiles_y = (h->nky + TILE - 1) / TILE;
+  P.dx = h->dx; P.dy = h->dy; P.idx = 1.0 / h->dx; P.idy = 1.0 / h->dy;
+  P.gamma = h->gamma; P.hmin = std::min(h->dx, h->dy);
+  P.mode = h->mode; P.correction = h->correction; P.limiter = h->limiter; P.pad = 0;
+  P.pA = h->pA; P.sA = h->pA * h->ny;
+  P.pP = h->pP; P.sP = h->pP * h->nky;
+  P.pF = h->pF; P.sF = h->pF * h->nky;
+  return P;
+}
+
+static void free_buffers(af_handle* h) {
+  for (int k = 0; k < 2; ++k) {
+    if (h->A[k]) (void)hipFree(h->A[k]);
+    if (h->K[k]) (void)hipFree(h->K[k]);
+    if (h->X[k]) (void)hipFree(h->X[k]);
+    if (h->Y[k]) (void)hipFree(h->Y[k]);
+    h->A[k] = nullptr; h->K[k] = h->X[k] = h->Y[k] = nullptr;
+  }
+  if (h->FK) (void)hipFree(h->FK);
+  if (h->FX) (void)hipFree(h->FX);
+  if (h->FY) (void)hipFree(h->FY);
+  h->FK = h->FX = h->FY = nullptr;
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+  h->gexec_steps = 0;
+}
+
+static int alloc_buffers(af_handle* h) {
+  free_buffers(h);
+  h->pA = (h->nx + 31) / 32 * 32;
+  h->pP = (h->nkx + 63) / 64 * 64;
+  h->pF = h->pP;
+  const size_t na = (size_t)4 * h->pA * h->ny, np = (size_t)4 * h->pP * h->nky;
+  const size_t nf = (size_t)h->pF * h->nky;
+  for (int k = 0; k < 2; ++k) {
+    HIP_OK(hipMalloc(&h->A[k], na * 8), h);
+    HIP_OK(hipMalloc(&h->K[k], np * rsize(h)), h);
+    HIP_OK(hipMalloc(&h->X[k], np * rsize(h)), h);
+    HIP_OK(hipMalloc(&h->Y[k], np * rsize(h)), h);
+  }
+  HIP_OK(hipMalloc(&h->FK, nf * 8 * 8), h);
+  HIP_OK(hipMalloc(&h->FX, nf * 4 * 8), h);
+  HIP_OK(hipMalloc(&h->FY, nf * 4 * 8), h);
+  h->has_state = false;
+  return AF_OK;
+}
+
+extern "C" int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_handle** out) {
+  if (!out) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: out is NULL");
+  *out = nullptr;
+  if (!grid || !bc) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: NULL grid or bc");
+  if (grid->nx < 2 || grid->ny < 2 || grid->nx > (1 << 16) || grid->ny > (1 << 16))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: nx, ny must be in [2, 65536]");
+  if (!(grid->x1 > grid->x0) || !(grid->y1 > grid->y0))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: empty domain");
+  if (!(gamma > 1.0)) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: gamma must be > 1");
+  auto okbc = [](int k) { return k == AF_BC_PERIODIC || k == AF_BC_OUTFLOW; };
+  if (!okbc(bc->left) || !okbc(bc->right) || !okbc(bc->bottom) || !okbc(bc->top))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: unknown boundary kind");
+  if ((bc->left == AF_BC_PERIODIC) != (bc->right == AF_BC_PERIODIC) ||
+      (bc->bottom == AF_BC_PERIODIC) != (bc->top == AF_BC_PERIODIC))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: periodic must pair on an axis");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, AF_ERR_DEVICE, "af_create: no HIP device");
+  af_handle* h = new af_handle();
+  h->nx = grid->nx; h->ny = grid->ny;
+  h->x0 = grid->x0; h->x1 = grid->x1; h->y0 = grid->y0; h->y1 = grid->y1;
+  h->dx = (h->x1 - h->x0) / h->nx; h->dy = (h->y1 - h->y0) / h->ny;
+  h->per_x = bc->left == AF_BC_PERIODIC; h->per_y = bc->bottom == AF_BC_PERIODIC;
+  h->nkx = h->nx + (h->per_x ? 0 : 1); h->nky = h->ny + (h->per_y ? 0 : 1);
+  h->gamma = gamma;
+  int e = AF_OK;
+  if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
+    e = fail(h, AF_ERR_DEVICE, "af_create: hipStreamCreate");
+  h->stream = h->own_stream;
+  if (e == AF_OK) e = alloc_buffers(h);
+  if (e == AF_OK) {
+    hipError_t he = hipMalloc(&h->dev, sizeof(DevState));
+    if (he != hipSuccess) e = fail(h, AF_ERR_OOM, "af_create: hipMalloc(dev)");
+    else if (hipMemset(h->dev, 0, sizeof(DevState)) != hipSuccess)
+      e = fail(h, AF_ERR_DEVICE, "af_create: hipMemset");
+  }
+  if (e != AF_OK) {
+    g_create_error = h->err;
+    free_buffers(h);
+    if (h->dev) (void)hipFree(h->dev);
+    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+    delete h;
+    return e;
+  }
+  *out = h;
+  return AF_OK;
+}
+
+extern "C" void af_destroy(af_handle* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  free_buffers(h);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->dev) (void)hipFree(h->dev);
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+  delete h;
+}
+
+extern "C" const char* af_last_error(const af_handle* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" int64_t af_dof_count(const af_handle* h) {
+  if (!h) return 0;
+  return (int64_t)h->nx * h->ny + (int64_t)h->nkx * h->nky + (int64_t)h->nkx * h->ny +
+         (int64_t)h->nx * h->nky;
+}
+
+extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_option: NULL handle");
+  switch (key) {
+    case AF_OPT_PRECISION:
+      if (value != AF_PREC_FP64 && value != AF_PREC_FP32)
+        return fail(h, AF_ERR_INVALID_ARG, "af_set_option: precision must be FP64 or FP32");
+      if (value != h->prec) {
+        h->prec = (int)value;
+        return alloc_buffers(h);
+      }
+      return AF_OK;
+    case AF_OPT_LINEARISATION:
+      if (value < 0 || value > 2) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: bad mode");
+      h->mode = (int)value;
+      break;
+    case AF_OPT_CORRECTION:
+      if (value != 0 && value != 1) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: 0 or 1");
+      h->correction = (int)value;
+      break;
+    case AF_OPT_LIMITER:
+      if (value != 0 && value != 1) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: 0 or 1");
+      h->limiter = (int)value;
+      break;
+    case AF_OPT_TIMING:
+      if (value != 0 && value != 1) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: 0 or 1");
+      h->timing = (int)value;
+      h->ms_points = h->ms_update = 0.0;
+      h->timed_steps = 0;
+      break;
+    case AF_OPT_GRAPH_STEPS:
+      if (value < 0 || value > 4096 || (value & 1))
+        return fail(h, AF_ERR_INVALID_ARG, "af_set_option: graph steps must be even, 0..4096");
+      h->graph_steps = (int)value;
+      break;
+    default:
+      return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown key");
+  }
+  if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
+  return AF_OK;
+}
+
+extern "C" int af_set_stream(af_handle* h, void* s) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_stream: NULL handle");
+  (void)hipStreamSynchronize(h->stream);
+  h->stream = s ? (hipStream_t)s : h->own_stream;
+  if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
+  return AF_OK;
+}
+
+// host FP64 rows -> device pitched (double or float)
+static int upload(af_handle* h, void* dst, long long pitch, int rows, int cols, int real_bytes,
+                  const double* src) {
+  const size_t n = (size_t)4 * rows * cols;
+  if (real_bytes == 8) {
+    HIP_OK(hipMemcpy2DAsync(dst, pitch * 8, src, (size_t)cols * 8, (size_t)cols * 8,
+                            (size_t)4 * rows, hipMemcpyHostToDevice, h->stream), h);
+  } else {
+    std::vector<float> tmp(n);
+    for (size_t k = 0; k < n; ++k) tmp[k] = (float)src[k];
+    HIP_OK(hipMemcpy2DAsync(dst, pitch * 4, tmp.data(), (size_t)cols * 4, (size_t)cols * 4,
+                            (size_t)4 * rows, hipMemcpyHostToDevice, h->stream), h);
+    HIP_OK(hipStreamSynchronize(h->stream), h);
+  }
+  return AF_OK;
+}
+
+static int download(const af_handle* h, const void* src, long long pitch, int rows, int cols,
+                    int real_bytes, double* dst) {
+  const size_t n = (size_t)4 * rows * cols;
+  if (real_bytes == 8) {
+    HIP_OK(hipMemcpy2DAsync(dst, (size_t)cols * 8, src, pitch * 8, (size_t)cols * 8,
+                            (size_t)4 * rows, hipMemcpyDeviceToHost, h->stream), h);
+    HIP_OK(hipStreamSynchronize(h->stream), h);
+  } else {
+    std::vector<float> tmp(n);
+    HIP_OK(hipMemcpy2DAsync(tmp.data(), (size_t)cols * 4, src, pitch * 4, (size_t)cols * 4,
+                            (size_t)4 * rows, hipMemcpyDeviceToHost, h->stream), h);
+    HIP_OK(hipStreamSynchronize(h->stream), h);
+    for (size_t k = 0; k < n; ++k) dst[k] = (double)tmp[k];
+  }
+  return AF_OK;
+}
+
+// The padded arrays store variable v at offset v * rows * pitch: copy one variable at a time.
+static int upload4(af_handle* h, void* dst, long long pitch, int rows_alloc, int rows, int cols,
+                   const double* src) {
+  const int rb = (int)rsize(h);
+  for (int v = 0; v < 4; ++v) {
+    char* d = (char*)dst + (size_t)v * rows_alloc * pitch * rb;
+    int e = upload(h, d, pitch, rows, cols, rb, src + (size_t)v * rows * cols);
+    if (e) return e;
+  }
+  return AF_OK;
+}
+static int download4(const af_handle* h, const void* src, long long pitch, int rows_alloc,
+                     int rows, int cols, double* dst) {
+  const int rb = (int)rsize(h);
+  for (int v = 0; v < 4; ++v) {
+    const char* s = (const char*)src + (size_t)v * rows_alloc * pitch * rb;
+    int e = download(h, s, pitch, rows, cols, rb, dst + (size_t)v * rows * cols);
+    if (e) return e;
+  }
+  return AF_OK;
+}
+
+extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, const double* X,
+                            const double* Y, double t) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_state: NULL handle");
+  if (!avg || !K || !X || !Y) return fail(h, AF_ERR_INVALID_ARG, "af_set_state: NULL array");
+  if (!std::isfinite(t)) return fail(h, AF_ERR_INVALID_ARG, "af_set_state: t not finite");
+  const size_t nc = (size_t)h->nx * h->ny;
+  for (size_t k = 0; k < nc; ++k) {
+    const double r = avg[k], E = avg[3 * nc + k];
+    const double kin = 0.5 * (avg[nc + k] * avg[nc + k] + avg[2 * nc + k] * avg[2 * nc + k]) / r;
+    if (!(r > 0.0) || !((h->gamma - 1.0) * (E - kin) > 0.0))
+      return fail(h, AF_ERR_NONPHYSICAL, "af_set_state: non-admissible cell average");
+  }
+  h->cur = 0;
+  // averages: 4 x ny x nx
+  for (int v = 0; v < 4; ++v)
+    HIP_OK(hipMemcpy2DAsync(h->A[0] + (size_t)v * h->pA * h->ny, h->pA * 8, avg + v * nc,
+                            (size_t)h->nx * 8, (size_t)h->nx * 8, h->ny, hipMemcpyHostToDevice,
+                            h->stream), h);
+  int e;
+  if ((e = upload4(h, h->K[0], h->pP, h->nky, h->nky, h->nkx, K))) return e;
+  if ((e = upload4(h, h->X[0], h->pP, h->nky, h->ny, h->nkx, X))) return e;
+  if ((e = upload4(h, h->Y[0], h->pP, h->nky, h->nky, h->nx, Y))) return e;
+  DevState ds;
+  std::memset(&ds, 0, sizeof(ds));
+  ds.t = t;
+  ds.t_end = t;
+  HIP_OK(hipMemcpyAsync(h->dev, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  h->has_state = true;
+  h->steps_base = 0;
+  return AF_OK;
+}
+
+extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* X, double* Y,
+                            double* t) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_get_state: NULL handle");
+  if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_get_state: no state set");
+  const int c = h->cur;
+  const size_t nc = (size_t)h->nx * h->ny;
+  if (avg) {
+    for (int v = 0; v < 4; ++v)
+      HIP_OK(hipMemcpy2DAsync(avg + v * nc, (size_t)h->nx * 8,
+                              h->A[c] + (size_t)v * h->pA * h->ny, h->pA * 8,
+                              (size_t)h->nx * 8, h->ny, hipMemcpyDeviceToHost, h->stream), h);
+    HIP_OK(hipStreamSynchronize(h->stream), h);
+  }
+  int e;
+  if (K && (e = download4(h, h->K[c], h->pP, h->nky, h->nky, h->nkx, K))) return e;
+  if (X && (e = download4(h, h->X[c], h->pP, h->nky, h->ny, h->nkx, X))) return e;
+  if (Y && (e = download4(h, h->Y[c], h->pP, h->nky, h->nky, h->nx, Y))) return e;
+  if (t) {
+    DevState ds;
+    HIP_OK(hipMemcpyAsync(&ds, h->dev, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
+    HIP_OK(hipStreamSynchronize(h->stream), h);
+    *t = ds.t;
+  }
+  return AF_OK;
+}
+
+extern "C" int af_get_counters(const af_handle* h, int64_t* out) {
+  if (!h || !out) return fail(h, AF_ERR_INVALID_ARG, "af_get_counters: NULL argument");
+  DevState ds;
+  HIP_OK(hipMemcpyAsync(&ds, h->dev, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  for (int k = 0; k < AF_NCOUNTERS; ++k) out[k] = (int64_t)ds.cnt[k];
+  out[AF_CNT_STEPS] = ds.steps;
+  return AF_OK;
+}
+
+// enqueue one step reading buffer `in` (0/1); dt_host > 0 for a caller-given step
+template <class R>
+static void enqueue_step_t(af_handle* h, int in, double dt_host) {
+  const Params P = make_params(h);
+  const int out = in ^ 1;
+  Bufs<R> B;
+  B.A_in = h->A[in]; B.A_out = h->A[out];
+  B.K_in = (const R*)h->K[in]; B.X_in = (const R*)h->X[in]; B.Y_in = (const R*)h->Y[in];
+  B.K_out = (R*)h->K[out]; B.X_out = (R*)h->X[out]; B.Y_out = (R*)h->Y[out];
+  B.FK = h->FK; B.FX = h->FX; B.FY = h->FY;
+  const int ntiles = P.tiles_x * P.tiles_y;
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+  if (h->timing) {
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventCreate(&e2);
+    (void)hipEventRecord(e0, h->stream);
+  }
+  hipLaunchKernelGGL(k_points<R>, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
+                     dt_host, in);
+  if (h->timing) (void)hipEventRecord(e1, h->stream);
+  dim3 gu((h->nx + UP_BX - 1) / UP_BX, (h->ny + UP_BY - 1) / UP_BY);
+  hipLaunchKernelGGL(k_update, gu, dim3(UP_BX, UP_BY), 0, h->stream, P, (const double*)h->A[in],
+                     h->A[out], (const double*)h->FK, (const double*)h->FX,
+                     (const double*)h->FY, h->dev, in);
+  if (h->timing) {
+    (void)hipEventRecord(e2, h->stream);
+    h->ev.push_back(e0);
+    h->ev.push_back(e1);
+    h->ev.push_back(e2);
+  }
+}
+
+// fold recorded events into the kernel times (only steps that committed are counted)
+static void collect_timing(af_handle* h, long long committed) {
+  for (size_t k = 0; k + 2 < h->ev.size(); k += 3) {
+    float a = 0.f, b = 0.f;
+    if ((long long)(k / 3) < committed &&
+        hipEventElapsedTime(&a, h->ev[k], h->ev[k + 1]) == hipSuccess &&
+        hipEventElapsedTime(&b, h->ev[k + 1], h->ev[k + 2]) == hipSuccess) {
+      h->ms_points += a;
+      h->ms_update += b;
+      h->timed_steps += 1;
+    }
+  }
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
+}
+
+static void enqueue_step(af_handle* h, int in, double dt_host) {
+  if (h->prec == AF_PREC_FP32) enqueue_step_t<float>(h, in, dt_host);
+  else enqueue_step_t<double>(h, in, dt_host);
+}
+
+static int read_dev(const af_handle* h, DevState* ds) {
+  HIP_OK(hipMemcpyAsync(ds, h->dev, sizeof(*ds), hipMemcpyDeviceToHost, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  return AF_OK;
+}
+
+static const char* err_text(int code) {
+  switch (code) {
+    case ERR_NONPHYS: return "non-positive density or pressure";
+    case ERR_CFL: return "time step too large: an evolution circle leaves its cells";
+    default: return "device error";
+  }
+}
+
+extern "C" int af_step(af_handle* h, double dt) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step: NULL handle");
+  if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_step: no state set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, AF_ERR_INVALID_ARG, "af_step: dt must be > 0");
+  DevState ds;
+  int e = read_dev(h, &ds);
+  if (e) return e;
+  if (ds.err) {
+    ds.err = 0;
+    HIP_OK(hipMemcpyAsync(&h->dev->err, &ds.err, sizeof(int), hipMemcpyHostToDevice, h->stream), h);
+  }
+  const long long before = ds.steps;
+  enqueue_step(h, h->cur, dt);
+  HIP_OK(hipGetLastError(), h);
+  if ((e = read_dev(h, &ds))) return e;
+  if (h->timing) collect_timing(h, ds.err ? 0 : 1);
+  if (ds.err) return fail(h, ds.err, std::string("af_step: ") + err_text(ds.err));
+  if (ds.steps != before + 1) return fail(h, AF_ERR_DEVICE, "af_step: step did not commit");
+  h->cur ^= 1;
+  return AF_OK;
+}
+
+extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
+                      double* t_reached, int64_t* steps_taken) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_run: NULL handle");
+  if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_run: no state set");
+  if (!(cfl > 0.0) || !(cfl < 0.5)) return fail(h, AF_ERR_INVALID_ARG, "af_run: cfl must be in (0, 0.5)");
+  if (std::isnan(t_end)) return fail(h, AF_ERR_INVALID_ARG, "af_run: t_end is NaN");
+  DevState ds;
+  int e = read_dev(h, &ds);
+  if (e) return e;
+  const long long steps0 = ds.steps;
+  ds.err = 0;
+  ds.t_end = t_end;
+  ds.cfl = cfl;
+  ds.smax[0] = ds.smax[1] = 0ull;
+  ds.done_blocks = 0;
+  HIP_OK(hipMemcpyAsync(h->dev, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
+  {
+    const Params P = make_params(h);
+    const int c = h->cur;
+    if (h->prec == AF_PREC_FP32)
+      hipLaunchKernelGGL(k_cfl<float>, dim3(1024), dim3(256), 0, h->stream, P,
+                         (const double*)h->A[c], (const float*)h->K[c], (const float*)h->X[c],
+                         (const float*)h->Y[c], h->dev, c);
+    else
+      hipLaunchKernelGGL(k_cfl<double>, dim3(1024), dim3(256), 0, h->stream, P,
+                         (const double*)h->A[c], (const double*)h->K[c],
+                         (const double*)h->X[c], (const double*)h->Y[c], h->dev, c);
+    HIP_OK(hipGetLastError(), h);
+  }
+  long long done = 0;
+  while (true) {
+    if ((e = read_dev(h, &ds))) return e;
+    const long long executed = ds.steps - steps0;
+    if (h->timing) collect_timing(h, executed - done);
+    h->cur = (int)((h->cur + (executed - done)) & 1);
+    done = executed;
+    if (ds.err) {
+      if (t_reached) *t_reached = ds.t;
+      if (steps_taken) *steps_taken = done;
+      return fail(h, ds.err, std::string("af_run: ") + err_text(ds.err));
+    }
+    if (!(ds.t < t_end) || (max_steps > 0 && done >= max_steps)) break;
+    long long k = h->graph_steps > 0 ? h->graph_steps : 8;
+    if (max_steps > 0) k = std::min<long long>(k, max_steps - done);
+    if (h->cur == 1 && h->graph_steps > 0 && !h->timing) k = 1;  // graphs start at buffer 0
+    if (!h->timing && k == h->graph_steps && h->graph_steps > 0 && h->cur == 0) {
+      if (!h->gexec || h->gexec_steps != k) {
+        if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+        hipGraph_t g;
+        HIP_OK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), h);
+        for (long long s = 0; s < k; ++s) enqueue_step(h, (int)(s & 1), 0.0);
+        HIP_OK(hipStreamEndCapture(h->stream, &g), h);
+        HIP_OK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0), h);
+        (void)hipGraphDestroy(g);
+        h->gexec_steps = (int)k;
+      }
+      HIP_OK(hipGraphLaunch(h->gexec, h->stream), h);
+    } else {
+      for (long long s = 0; s < k; ++s) enqueue_step(h, (int)((h->cur + s) & 1), 0.0);
+    }
+    HIP_OK(hipGetLastError(), h);
+  }
+  if (t_reached) *t_reached = ds.t;
+  if (steps_taken) *steps_taken = done;
+  return AF_OK;
+}
+
+extern "C" int af_get_timing(const af_handle* h, double* out) {
+  if (!h || !out) return fail(h, AF_ERR_INVALID_ARG, "af_get_timing: NULL argument");
+  out[0] = h->ms_points;
+  out[1] = h->ms_update;
+  out[2] = (double)h->timed_steps;
+  return AF_OK;
+}

@@ -1,0 +1,300 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, plus invariants.
+
+Tolerances: the FP64 path and the oracle evaluate the same formulas in different orders and
+with different exact circle integrations (trigonometric moments vs. Gauss-Legendre), so they
+agree to rounding: |diff| <= 1e-12 * scale after the step counts used here.  The FP32 path
+stores point values in FP32 (unit roundoff 6e-8); its tolerance is 2e-5 * scale after one
+step and 1e-4 * scale after 20.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06273_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+af = pytest.importorskip("paper_2508_06273_amd.af")
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_state(st, prec=0, mode=0, correction=True, limiter=False):
+    s = af.Solver.for_state(st, precision=prec, linearisation=mode, correction=correction,
+                            limiter=limiter)
+    return s
+
+
+def maxdiff(a, b):
+    return {k: float(np.abs(a[k] - getattr(b, k)).max()) for k in ("avg", "K", "X", "Y")}
+
+
+def assert_close(out, ref, tol, label=""):
+    d = maxdiff(out, ref)
+    scale = max(float(np.abs(ref.avg).max()), float(np.abs(ref.K).max()))
+    bad = {k: v for k, v in d.items() if v > tol * scale}
+    assert not bad, f"{label}: {d} (tol {tol * scale:.3e})"
+
+
+# ------------------------------------------------------------------------------------------
+# one step, small ragged grids, all modes
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("correction", [True, False])
+def test_single_step_fp64_periodic(mode, correction):
+    _flush(f"[gpu] single step periodic mode={mode} corr={correction}")
+    g = I.Grid(21, 13, 0.0, 1.3, 0.0, 0.8)
+    st = I.state_from_field(I.fourier_field(42), g, I.GAMMA, 4)
+    dt = 0.3 * min(g.dx, g.dy) / oracle.max_speed(st)
+    s = gpu_state(st, 0, mode, correction)
+    s.step(dt)
+    out = s.get_state()
+    e, _ = oracle.step(st, dt, mode=mode, correction=correction)
+    assert e == 0
+    assert_close(out, st, 1e-12, f"mode {mode}")
+
+
+@pytest.mark.parametrize("bc", [(1, 1), (0, 1), (1, 0)])
+def test_single_step_fp64_outflow(bc):
+    _flush(f"[gpu] single step outflow bc={bc}")
+    g = I.Grid(19, 17, -1.0, 1.0, -0.7, 0.9, bc[0], bc[1])
+    st = I.state_from_field(I.fourier_field(7), g, I.GAMMA, 4)
+    dt = 0.3 * min(g.dx, g.dy) / oracle.max_speed(st)
+    s = gpu_state(st, 0, 1, True, True)
+    s.step(dt)
+    out = s.get_state()
+    e, _ = oracle.step(st, dt, mode=1, limiter=True)
+    assert e == 0
+    assert_close(out, st, 1e-12, "outflow")
+
+
+def test_config1_vortex_20_steps_fp64():
+    """Isentropic vortex 32^2, CFL 0.3, 20 steps, FP64: parity, conservation, time."""
+    _flush("[gpu] config-1 vortex 32^2 x 20 steps")
+    st = I.shu_vortex(32)
+    m0 = st.avg.reshape(4, -1).sum(axis=1)
+    s = gpu_state(st)
+    t, n = s.run(1e9, 0.3, 20)
+    out = s.get_state()
+    e, n2, _ = oracle.run(st, 1e9, 0.3, max_steps=20)
+    assert e == 0 and n == n2 == 20
+    assert abs(t - st.t) < 1e-13
+    assert_close(out, st, 1e-12, "C1")
+    m1 = out["avg"].reshape(4, -1).sum(axis=1)
+    assert np.abs(m1 - m0).max() < 1e-12 * np.abs(m0).max()
+
+
+def test_config1_vortex_fp32_bulk():
+    _flush("[gpu] config-1 vortex 32^2 x 20 steps FP32")
+    st = I.shu_vortex(32)
+    s = gpu_state(st, prec=1)
+    t, n = s.run(1e9, 0.3, 20)
+    out = s.get_state()
+    e, n2, _ = oracle.run(st, 1e9, 0.3, max_steps=20)
+    assert e == 0 and n == 20
+    assert_close(out, st, 1e-4, "C1 fp32")
+
+
+def test_single_step_fp32_bulk():
+    _flush("[gpu] single step FP32")
+    g = I.Grid(21, 13, 0.0, 1.3, 0.0, 0.8)
+    st = I.state_from_field(I.fourier_field(42), g, I.GAMMA, 4)
+    dt = 0.3 * min(g.dx, g.dy) / oracle.max_speed(st)
+    s = gpu_state(st, 1)
+    s.step(dt)
+    out = s.get_state()
+    e, _ = oracle.step(st, dt)
+    assert_close(out, st, 2e-5, "fp32 step")
+
+
+# ------------------------------------------------------------------------------------------
+# invariants
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1)])
+def test_uniform_state_bitwise(prec, mode, bc):
+    _flush(f"[gpu] uniform prec={prec} mode={mode} bc={bc}")
+    g = I.Grid(18, 11, 0.0, 1.2, 0.0, 1.0, bc[0], bc[1])
+    # values exact in FP32 so that both precisions start from the same bits
+    st = I.uniform_state(g, [1.25, 0.5, -0.375, 0.75])
+    s = gpu_state(st, prec, mode, True, True)
+    for _ in range(3):
+        s.step(0.01)
+    t, n = s.run(1e9, 0.3, 4)
+    out = s.get_state()
+    for k in ("avg", "K", "X", "Y"):
+        assert np.array_equal(out[k], getattr(st, k)), k
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_conservation_periodic(prec):
+    _flush(f"[gpu] conservation prec={prec}")
+    g = I.Grid(40, 36, 0.0, 1.0, 0.0, 1.0)
+    st = I.state_from_field(I.fourier_field(99), g, I.GAMMA, 4)
+    m0 = st.avg.reshape(4, -1).sum(axis=1)
+    s = gpu_state(st, prec)
+    s.run(1e9, 0.3, 30)
+    m1 = s.get_state()["avg"].reshape(4, -1).sum(axis=1)
+    assert np.abs(m1 - m0).max() < 1e-12 * np.abs(m0).max()
+
+
+def test_deterministic_and_checkpoint_resume():
+    _flush("[gpu] determinism / checkpoint")
+    st = I.shu_vortex(24)
+    a = gpu_state(st)
+    a.run(1e9, 0.3, 10)
+    sa = a.get_state()
+    b = gpu_state(st)
+    b.run(1e9, 0.3, 5)
+    mid = b.get_state()
+    c = gpu_state(st)
+    c.set_state(mid["avg"], mid["K"], mid["X"], mid["Y"], mid["t"])
+    c.run(1e9, 0.3, 5)
+    sc = c.get_state()
+    for k in ("avg", "K", "X", "Y"):
+        assert np.array_equal(sa[k], sc[k]), k
+    assert sa["t"] == sc["t"]
+
+
+def test_run_lands_on_t_end():
+    _flush("[gpu] t_end")
+    st = I.shu_vortex(16)
+    s = gpu_state(st)
+    t, n = s.run(0.5, 0.3)
+    e, n2, _ = oracle.run(st, 0.5, 0.3)
+    assert t == 0.5 and n == n2
+    assert_close(s.get_state(), st, 1e-12, "t_end")
+
+
+# ------------------------------------------------------------------------------------------
+# positivity limiter and error paths
+# ------------------------------------------------------------------------------------------
+def test_limiter_repairs_like_oracle():
+    _flush("[gpu] limiter EG1")
+    g = I.Grid(6, 6, 0.0, 1.0, 0.0, 1.0)
+    st = I.uniform_state(g, [1.0, 0.2, 0.1, 1.0])
+    st.K[3, 3, 3] = -3.0
+    s = gpu_state(st, 0, 1, True, True)
+    s.step(0.04)
+    out = s.get_state()
+    cnt = s.counters()
+    e, ocnt = oracle.step(st, 0.04, mode=1, limiter=True)
+    assert e == 0
+    assert cnt[af.AF_CNT_EG1] == ocnt[0] and cnt[af.AF_CNT_LF] == ocnt[1]
+    assert_close(out, st, 1e-12, "limiter")
+
+
+def test_lax_friedrichs_branch_like_oracle():
+    _flush("[gpu] limiter LF")
+    g = I.Grid(6, 6, 0.0, 1.0, 0.0, 1.0, 1, 1)
+    st = I.uniform_state(g, [1.0, 0.0, 0.0, 1.0])
+    st.K[:, 3, 3] = [1e-3, 0.0, 0.0, 1e-4]
+    st.X[1, 2:4, 4] = 3.0
+    st.X[1, 2:4, 2] = -3.0
+    s = gpu_state(st, 0, 1, True, True)
+    s.step(0.02)
+    out = s.get_state()
+    cnt = s.counters()
+    e, ocnt = oracle.step(st, 0.02, mode=1, limiter=True)
+    assert e == 0
+    assert list(cnt[:4]) == list(ocnt[:4])
+    assert_close(out, st, 1e-12, "LF")
+
+
+def test_radial_outflow_limiter_parity():
+    _flush("[gpu] radial outflow 48^2 x 10 steps")
+    st = I.radial_state(48, n_gl=3)
+    s = gpu_state(st, 0, 1, True, True)
+    t, n = s.run(1e9, 0.3, 10)
+    out = s.get_state()
+    e, n2, ocnt = oracle.run(st, 1e9, 0.3, max_steps=10, mode=1, limiter=True)
+    assert e == 0 and n == 10
+    assert_close(out, st, 1e-11, "radial")
+    assert list(s.counters()[:4]) == list(ocnt[:4])
+
+
+def test_nonphysical_step_keeps_state():
+    _flush("[gpu] error path")
+    g = I.Grid(6, 6, 0.0, 1.0, 0.0, 1.0)
+    st = I.uniform_state(g, [1.0, 0.2, 0.1, 1.0])
+    st.K[3, 3, 3] = -10.0
+    s = gpu_state(st, 0, 1, True, False)
+    with pytest.raises(af.AfError) as ei:
+        s.step(0.04)
+    assert ei.value.code == af.AF_ERR_NONPHYSICAL
+    out = s.get_state()
+    for k in ("avg", "K", "X", "Y"):
+        assert np.array_equal(out[k], getattr(st, k))
+
+
+def test_cfl_error_and_bad_arguments():
+    _flush("[gpu] cfl / args")
+    g = I.Grid(8, 8, 0.0, 1.0, 0.0, 1.0)
+    st = I.uniform_state(g, [1.0, 0.0, 0.0, 1.0])
+    s = gpu_state(st)
+    with pytest.raises(af.AfError) as ei:
+        s.step(0.6 / math.sqrt(1.4) * g.dx)
+    assert ei.value.code == af.AF_ERR_CFL
+    with pytest.raises(af.AfError) as ei:
+        s.step(-1.0)
+    assert ei.value.code == af.AF_ERR_INVALID_ARG
+    with pytest.raises(af.AfError):
+        s.set_option(99, 1)
+    bad = st.copy()
+    bad.avg[0, 2, 2] = -1.0
+    with pytest.raises(af.AfError) as ei:
+        s.set_state(bad.avg, bad.K, bad.X, bad.Y)
+    assert ei.value.code == af.AF_ERR_NONPHYSICAL
+
+
+# ------------------------------------------------------------------------------------------
+# full size (4096^2 vortex, the benchmark workload): sampled parity of one step
+# ------------------------------------------------------------------------------------------
+def _patch(full, ci, cj, half=4):
+    """Outflow patch of 2*half cells around cell (ci, cj) of a periodic state; DOFs and cells
+    at distance >= 2 from the patch edge see exactly the data of the full grid."""
+    g = full.grid
+    n = 2 * half
+    ii = (np.arange(ci - half, ci + half) % g.nx)
+    jj = (np.arange(cj - half, cj + half) % g.ny)
+    ik = (np.arange(ci - half, ci + half + 1) % g.nx)
+    jk = (np.arange(cj - half, cj + half + 1) % g.ny)
+    pg = I.Grid(n, n, g.x0 + (ci - half) * g.dx, g.x0 + (ci + half) * g.dx,
+                g.y0 + (cj - half) * g.dy, g.y0 + (cj + half) * g.dy, 1, 1)
+    st = I.State(pg, full.gamma, full.avg[:, jj][:, :, ii].copy(),
+                 full.K[:, jk][:, :, ik].copy(), full.X[:, jj][:, :, ik].copy(),
+                 full.Y[:, jk][:, :, ii].copy())
+    return st
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+def test_full_size_vortex_sampled(prec, tol):
+    n = 4096
+    _flush(f"[gpu] full-size {n}^2 sampled parity prec={prec}")
+    st = I.shu_vortex(n, n_gl=3)
+    s = gpu_state(st, prec)
+    t, steps = s.run(1e9, 0.3, 1)
+    dt = t
+    out = s.get_state()
+    rng = np.random.default_rng(5)
+    cells = [(2048, 2048), (0, 0), (n - 1, n - 1), (1000, 3000)] + \
+        [tuple(rng.integers(0, n, 2)) for _ in range(6)]
+    scale = 3.0
+    for (ci, cj) in cells:
+        p = _patch(st, ci, cj)
+        e, _ = oracle.step(p, dt)
+        assert e == 0
+        for (a, b) in [(0, 0), (1, 0), (0, 1), (-1, -1)]:
+            gi, gj = (ci + a) % n, (cj + b) % n
+            pi_, pj = 4 + a, 4 + b
+            assert abs(out["avg"][:, gj, gi] - p.avg[:, pj, pi_]).max() < tol * scale
+            assert abs(out["K"][:, gj, gi] - p.K[:, pj, pi_]).max() < tol * scale
+            assert abs(out["X"][:, gj, gi] - p.X[:, pj, pi_]).max() < tol * scale
+            assert abs(out["Y"][:, gj, gi] - p.Y[:, pj, pi_]).max() < tol * scale
