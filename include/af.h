@@ -25,7 +25,8 @@
  * Ownership: the caller owns every host array; the library copies in and out synchronously on
  * the handle's stream and keeps no pointer.  Device memory belongs to the handle.
  * Errors: every call returns AF_OK (0) or a negative code; af_last_error() gives the text.
- * A step that fails leaves the state at the beginning of that step.  A handle is not
+ * A step that fails leaves the state at the beginning of that step; if several degrees of
+ * freedom fail in one step, AF_ERR_CFL is reported before AF_ERR_NONPHYSICAL.  A handle is not
  * thread-safe; different handles are independent.  The library needs a gfx950 GPU: without
  * one, af_create returns AF_ERR_DEVICE.
  */

@@ -623,7 +623,7 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
   }
   long long cnt[OR_NCOUNTERS] = {0};
   cnt[2] = C.cnt[2];
-  for (int kind = 0; kind < 3 && err == OR_OK; ++kind) {
+  for (int kind = 0; kind < 3; ++kind) {
     long long c0 = 0, c1 = 0, c3 = 0;
     int kerr = 0;
 #pragma omp parallel for reduction(+ : c0, c1, c3) schedule(dynamic, 16)
@@ -633,8 +633,9 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
       long long lc[OR_NCOUNTERS] = {0};
       int e = dof_update(&C, kind, i, j, dt, h, f, lc);
       if (e != OR_OK) {
+        /* several failing DOFs: the most negative code wins (CFL before non-physical) */
 #pragma omp critical
-        { if (kerr == 0) kerr = e; }
+        { if (e < kerr) kerr = e; }
       }
       c0 += lc[0]; c1 += lc[1]; c3 += lc[3];
       for (int v = 0; v < 4; ++v) {
@@ -643,7 +644,7 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
       }
     }
     cnt[0] += c0; cnt[1] += c1; cnt[3] += c3;
-    if (kerr) err = kerr;
+    if (kerr < err) err = kerr;
   }
   if (err == OR_OK) {
     /* Simpson space-time fluxes (eq. F) and the finite volume update (eq. 2dfvm) */

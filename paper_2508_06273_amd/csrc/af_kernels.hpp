@@ -74,7 +74,9 @@ __device__ __forceinline__ int wrap_line(int i, int n, int per) {
   return i < 0 ? 0 : (i > n ? n : i);
 }
 
-__device__ __forceinline__ void set_err(DevState* d, int code) { atomicCAS(&d->err, 0, code); }
+// Errors are negative; when several DOFs fail in one step the most negative code wins
+// (AF_ERR_CFL = -3 before AF_ERR_NONPHYSICAL = -2), independent of the order of the waves.
+__device__ __forceinline__ void set_err(DevState* d, int code) { atomicMin(&d->err, code); }
 
 __device__ __forceinline__ unsigned long long dbits(double x) {
   return (unsigned long long)__double_as_longlong(x);
@@ -266,7 +268,7 @@ __device__ __forceinline__ void low_piece(R a1, R c1a, R s1a, R b1, R c1b, R s1b
 }
 
 template <class R, int KIND>
-__device__ __forceinline__ int eg1_pc(const R* __restrict__ ub, int cb, const R lin[4], R tau,
+__device__ __noinline__ int eg1_pc(const R* __restrict__ ub, int cb, const R lin[4], R tau,
                                       const Geo<R>& G, R dU[4]) {
   using MA = Math<R>;
   const R rp = lin[0], up = lin[1], vp = lin[2], pp = lin[3];
@@ -361,7 +363,7 @@ __device__ __forceinline__ void lf_flux(const double UL[4], const double UR[4], 
 }
 
 template <class R>
-__device__ void lf_update(const R* __restrict__ site, int a, int b, double tau, const Params& P,
+__device__ __noinline__ void lf_update(const R* __restrict__ site, int a, int b, double tau, const Params& P,
                           double out[4]) {
   double U[5][4];
   const int nb[5][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}};

@@ -672,18 +672,21 @@ extern "C" int af_set_stream(af_handle* h, void* s) {
   return AF_OK;
 }
 
-// host FP64 rows -> device pitched (double or float)
+// One variable: host FP64 rows x cols (unpadded) <-> device rows x cols with row pitch
+// `pitch` elements of `real_bytes` each.
 static int upload(af_handle* h, void* dst, long long pitch, int rows, int cols, int real_bytes,
                   const double* src) {
-  const size_t n = (size_t)4 * rows * cols;
+  if (cols > pitch) return fail(h, AF_ERR_INVALID_ARG, "upload: cols exceed pitch");
+  const size_t n = (size_t)rows * cols;
   if (real_bytes == 8) {
     HIP_OK(hipMemcpy2DAsync(dst, pitch * 8, src, (size_t)cols * 8, (size_t)cols * 8,
-                            (size_t)4 * rows, hipMemcpyHostToDevice, h->stream), h);
+                            (size_t)rows, hipMemcpyHostToDevice, h->stream), h);
+    HIP_OK(hipStreamSynchronize(h->stream), h);
   } else {
     std::vector<float> tmp(n);
     for (size_t k = 0; k < n; ++k) tmp[k] = (float)src[k];
     HIP_OK(hipMemcpy2DAsync(dst, pitch * 4, tmp.data(), (size_t)cols * 4, (size_t)cols * 4,
-                            (size_t)4 * rows, hipMemcpyHostToDevice, h->stream), h);
+                            (size_t)rows, hipMemcpyHostToDevice, h->stream), h);
     HIP_OK(hipStreamSynchronize(h->stream), h);
   }
   return AF_OK;
@@ -691,15 +694,16 @@ static int upload(af_handle* h, void* dst, long long pitch, int rows, int cols, 
 
 static int download(const af_handle* h, const void* src, long long pitch, int rows, int cols,
                     int real_bytes, double* dst) {
-  const size_t n = (size_t)4 * rows * cols;
+  if (cols > pitch) return fail(h, AF_ERR_INVALID_ARG, "download: cols exceed pitch");
+  const size_t n = (size_t)rows * cols;
   if (real_bytes == 8) {
     HIP_OK(hipMemcpy2DAsync(dst, (size_t)cols * 8, src, pitch * 8, (size_t)cols * 8,
-                            (size_t)4 * rows, hipMemcpyDeviceToHost, h->stream), h);
+                            (size_t)rows, hipMemcpyDeviceToHost, h->stream), h);
     HIP_OK(hipStreamSynchronize(h->stream), h);
   } else {
     std::vector<float> tmp(n);
     HIP_OK(hipMemcpy2DAsync(tmp.data(), (size_t)cols * 4, src, pitch * 4, (size_t)cols * 4,
-                            (size_t)4 * rows, hipMemcpyDeviceToHost, h->stream), h);
+                            (size_t)rows, hipMemcpyDeviceToHost, h->stream), h);
     HIP_OK(hipStreamSynchronize(h->stream), h);
     for (size_t k = 0; k < n; ++k) dst[k] = (double)tmp[k];
   }
@@ -709,6 +713,7 @@ static int download(const af_handle* h, const void* src, long long pitch, int ro
 // The padded arrays store variable v at offset v * rows * pitch: copy one variable at a time.
 static int upload4(af_handle* h, void* dst, long long pitch, int rows_alloc, int rows, int cols,
                    const double* src) {
+  if (rows > rows_alloc) return fail(h, AF_ERR_INVALID_ARG, "upload4: rows exceed allocation");
   const int rb = (int)rsize(h);
   for (int v = 0; v < 4; ++v) {
     char* d = (char*)dst + (size_t)v * rows_alloc * pitch * rb;
@@ -719,6 +724,7 @@ static int upload4(af_handle* h, void* dst, long long pitch, int rows_alloc, int
 }
 static int download4(const af_handle* h, const void* src, long long pitch, int rows_alloc,
                      int rows, int cols, double* dst) {
+  if (rows > rows_alloc) return fail(h, AF_ERR_INVALID_ARG, "download4: rows exceed allocation");
   const int rb = (int)rsize(h);
   for (int v = 0; v < 4; ++v) {
     const char* s = (const char*)src + (size_t)v * rows_alloc * pitch * rb;
