@@ -134,6 +134,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--prec", choices=("both", "fp32", "fp64"), default="both",
+                    help="profiling aid: run one precision only (no JSON line)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="profiling aid: also run a plain device copy of MIB MiB (the "
+                         "reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -148,14 +153,32 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
 
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 copies of {nb} bytes", file=sys.stderr, flush=True)
+        del src, dst
+
     n = args.n
     print(f"[bench] generating the {n}x{n} vortex", file=sys.stderr, flush=True)
     st = I.shu_vortex(n, n_gl=3)
     res = {}
-    for prec, name in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64")):
+    precs = [(af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64")]
+    if args.prec != "both":
+        precs = [p for p in precs if p[1] == args.prec]
+    for prec, name in precs:
         print(f"[bench] {name}: {args.warmup} warm-up + {args.steps} timed steps",
               file=sys.stderr, flush=True)
         res[name] = run_gpu(st, prec, args.steps, args.warmup, stream)
+    if args.prec != "both":
+        for name, r in res.items():
+            print(f"[bench] {name}: {r['ms_total'] / args.steps:.3f} ms/step, k_points "
+                  f"{r['ms_points']:.3f} ms, k_update {r['ms_update']:.3f} ms", file=sys.stderr)
+        return
     cells = n * n
     fpc = flops_per_cell(0)
     out = {}
