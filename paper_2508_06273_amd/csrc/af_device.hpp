@@ -117,7 +117,7 @@ __device__ __forceinline__ void corr_half(const R U[4], const R Ux[4], const R U
   R rho = U[0], u = U[1], v = U[2], p = U[3];
   R rx = Ux[0], ux = Ux[1], vx = Ux[2], px = Ux[3];
   R ry = Uy[0], uy = Uy[1], vy = Uy[2], py = Uy[3];
-  R irho = R(1) / rho;
+  R irho = (sizeof(R) == 4) ? R(__builtin_amdgcn_rcpf(float(rho))) : R(1) / rho;
   R div = ux + vy;
   R f1 = ux * ux + uy * vx;
   R f2 = uy * vx + vy * vy;

@@ -65,12 +65,22 @@ template <class R> struct Bufs {
   double* FY;  // 4: g sums
 };
 
+// Index of a (possibly ghost) cell or grid line, i >= -n: periodic wrap, or the outflow
+// copy of the nearest boundary cell (line).  The common case needs no integer division.
+__device__ __forceinline__ int wrap_per(int i, int n) {
+  if (i < 0) return i + n;
+  if (i >= n) {
+    i -= n;
+    if (i >= n) i %= n;  // grids narrower than a tile
+  }
+  return i;
+}
 __device__ __forceinline__ int wrap_cell(int i, int n, int per) {
-  if (per) { int r = i % n; return r < 0 ? r + n : r; }
+  if (per) return wrap_per(i, n);
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 __device__ __forceinline__ int wrap_line(int i, int n, int per) {
-  if (per) { int r = i % n; return r < 0 ? r + n : r; }
+  if (per) return wrap_per(i, n);
   return i < 0 ? 0 : (i > n ? n : i);
 }
 
@@ -82,7 +92,17 @@ __device__ __forceinline__ unsigned long long dbits(double x) {
   return (unsigned long long)__double_as_longlong(x);
 }
 
-// Block-wide max of a non-negative double, one atomic per block.
+// Max of a positive double into *target (bit patterns of positive doubles order like
+// unsigned integers).  The current value is read first: once the maximum is reached almost no
+// block issues the atomic, so thousands of blocks do not serialise on one address.
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* target, double m) {
+  if (!(m > 0.0)) return;
+  const unsigned long long b = dbits(m);
+  if (b > __hip_atomic_load(target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(target, b);
+}
+
+// Block-wide max of a non-negative double, at most one atomic per block.
 __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* target,
                                                  double* red) {
   for (int off = 32; off > 0; off >>= 1) v = mx(v, __shfl_xor(v, off, 64));
@@ -94,7 +114,7 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* t
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     double m = red[0];
     for (int k = 1; k < nw; ++k) m = mx(m, red[k]);
-    if (m > 0.0) atomicMax(target, dbits(m));
+    atomic_max_pos(target, m);
   }
 }
 
@@ -117,6 +137,12 @@ template <class R> struct Geo {
   R idx, idy, gamma, half_h;
 };
 
+// a / b in the bulk precision: IEEE division in FP64, hardware reciprocal (1 ulp) in FP32
+template <class R> __device__ __forceinline__ R qdiv(R a, R b) { return a / b; }
+template <> __device__ __forceinline__ float qdiv<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+
 // ------------------------------------------------------------------------------------------
 // EG2 at one DOF.  cb: LDS index of the lower-left cell around the DOF (K: cell (a-1,b-1);
 // X: cell (a-1,b); Y: cell (a,b-1)).  Returns the deviation dU = EG2[U] - lin.
@@ -127,9 +153,9 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
   using MA = Math<R>;
   const R rp = lin[0], up = lin[1], vp = lin[2], pp = lin[3];
   if (!admissible(rp, pp)) return ERR_NONPHYS;
-  const R c = MA::sqrt_(G.gamma * pp / rp);
+  const R c = MA::sqrt_(qdiv(G.gamma * pp, rp));
   if ((mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * tau >= G.half_h) return ERR_CFL;
-  const R ic = R(1) / c;
+  const R ic = qdiv(R(1), c);
   const R px = -up * tau * G.idx, py = -vp * tau * G.idy;
   const R ax = c * tau * G.idx, by = c * tau * G.idy;
   const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
@@ -228,7 +254,7 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
 
   const R ipi = R(1.0 / kPi);
   const R ic2 = ic * ic;
-  const R irc = ic / rp;
+  const R irc = qdiv(ic, rp);
   const R rc = rp * c;
   dU[0] = drP - R(2) * dpP * ic2 + ipi * (A.Ip * ic2 - rp * ic * A.Jr);
   dU[1] = ipi * (A.Ju - A.IpC * irc);

@@ -348,62 +348,68 @@ __global__ __launch_bounds__(PT_THREADS) void k_points(Params P, Bufs<R> B, DevS
 // ------------------------------------------------------------------------------------------
 // Kernel 2: Simpson space-time fluxes and the conservative update of the averages.
 // ------------------------------------------------------------------------------------------
-constexpr int UP_BX = 64, UP_BY = 4;
+constexpr int UP_THREADS = 256;
+constexpr int UP_MAX_BLOCKS = 1024;
 
-__global__ __launch_bounds__(UP_BX* UP_BY) void k_update(Params P, const double* __restrict__ A_in,
-                                                        double* __restrict__ A_out,
-                                                        const double* __restrict__ FK,
-                                                        const double* __restrict__ FX,
-                                                        const double* __restrict__ FY,
-                                                        DevState* dev, int slot) {
+__global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* __restrict__ A_in,
+                                                      double* __restrict__ A_out,
+                                                      const double* __restrict__ FK,
+                                                      const double* __restrict__ FX,
+                                                      const double* __restrict__ FY,
+                                                      DevState* dev, int slot) {
   __shared__ double red[4];
   __shared__ int last_block;
   const bool run = !dev->err && dev->active;
-  const int i = blockIdx.x * UP_BX + threadIdx.x, j = blockIdx.y * UP_BY + threadIdx.y;
-  double speed = 0.0;
   const double dt = dev->dt;
-  if (run && i < P.nx && j < P.ny) {
-    const int ip = wrap_line(i + 1, P.nx, P.per_x), jp = wrap_line(j + 1, P.ny, P.per_y);
-    const long long kw0 = (long long)j * P.pF + i, kw1 = (long long)jp * P.pF + i;
-    const long long ke0 = (long long)j * P.pF + ip, ke1 = (long long)jp * P.pF + ip;
-    const long long oa = (long long)j * P.pA + i;
-    const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
-    double Q[4];
+  const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
+  double speed = 0.0;
+  bool bad = false;
+  if (run) {
+    // rows of cells, 256 consecutive cells of a row per pass (coalesced)
+    const int chunks_x = (P.nx + UP_THREADS - 1) / UP_THREADS;
+    const long long nwork = (long long)chunks_x * P.ny;
+    for (long long w = blockIdx.x; w < nwork; w += gridDim.x) {
+      const int j = (int)(w / chunks_x);
+      const int i = (int)(w % chunks_x) * UP_THREADS + threadIdx.x;
+      if (i >= P.nx) continue;
+      const int ip = wrap_line(i + 1, P.nx, P.per_x), jp = wrap_line(j + 1, P.ny, P.per_y);
+      const long long kw0 = (long long)j * P.pF + i, kw1 = (long long)jp * P.pF + i;
+      const long long ke0 = (long long)j * P.pF + ip, ke1 = (long long)jp * P.pF + ip;
+      const long long oa = (long long)j * P.pA + i;
+      double Q[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double* fk = FK + v * P.sF;
-      const double* gk = FK + (4 + v) * P.sF;
-      const double Fw = fk[kw0] + 4.0 * FX[v * P.sF + kw0] + fk[kw1];
-      const double Fe = fk[ke0] + 4.0 * FX[v * P.sF + ke0] + fk[ke1];
-      const double Gs = gk[kw0] + 4.0 * FY[v * P.sF + kw0] + gk[ke0];
-      const double Gn = gk[kw1] + 4.0 * FY[v * P.sF + kw1] + gk[ke1];
-      Q[v] = A_in[v * P.sA + oa] - lx * (Fe - Fw) - ly * (Gn - Gs);
-      A_out[v * P.sA + oa] = Q[v];
+      for (int v = 0; v < 4; ++v) {
+        const double* fk = FK + v * P.sF;
+        const double* gk = FK + (4 + v) * P.sF;
+        const double Fw = fk[kw0] + 4.0 * FX[v * P.sF + kw0] + fk[kw1];
+        const double Fe = fk[ke0] + 4.0 * FX[v * P.sF + ke0] + fk[ke1];
+        const double Gs = gk[kw0] + 4.0 * FY[v * P.sF + kw0] + gk[ke0];
+        const double Gn = gk[kw1] + 4.0 * FY[v * P.sF + kw1] + gk[ke1];
+        Q[v] = A_in[v * P.sA + oa] - lx * (Fe - Fw) - ly * (Gn - Gs);
+        A_out[v * P.sA + oa] = Q[v];
+      }
+      double U[4];
+      c2p_plain(Q, P.gamma - 1.0, U);
+      if (!admissible(U[0], U[3])) bad = true;
+      else speed = mx(speed, wave_speed(U, P.gamma));
     }
-    double U[4];
-    c2p_plain(Q, P.gamma - 1.0, U);
-    if (!admissible(U[0], U[3])) set_err(dev, ERR_NONPHYS);
-    else speed = wave_speed(U, P.gamma);
   }
-  // block max into the next step's slot (tid linearised over x, y)
+  if (bad) set_err(dev, ERR_NONPHYS);
   {
     double v = speed;
     for (int off = 32; off > 0; off >>= 1) v = mx(v, __shfl_xor(v, off, 64));
-    const int t = threadIdx.x + threadIdx.y * UP_BX;
-    if ((t & 63) == 0) red[t >> 6] = v;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   }
   __syncthreads();
-  const int t = threadIdx.x + threadIdx.y * UP_BX;
-  if (t == 0) {
+  if (threadIdx.x == 0) {
     double m = mx(mx(red[0], red[1]), mx(red[2], red[3]));
-    if (run && m > 0.0) atomicMax(&dev->smax[slot ^ 1], dbits(m));
+    if (run) atomic_max_pos(&dev->smax[slot ^ 1], m);
     __threadfence();
-    const unsigned int nb = gridDim.x * gridDim.y;
     const unsigned int ticket = atomicAdd(&dev->done_blocks, 1u);
-    last_block = (ticket == nb - 1);
+    last_block = (ticket == gridDim.x - 1);
   }
   __syncthreads();
-  if (last_block && t == 0) {
+  if (last_block && threadIdx.x == 0) {
     __threadfence();
     dev->done_blocks = 0;
     if (run && !atomicAdd(&dev->err, 0)) {
@@ -824,8 +830,9 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
   hipLaunchKernelGGL(k_points<R>, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
                      dt_host, in);
   if (h->timing) (void)hipEventRecord(e1, h->stream);
-  dim3 gu((h->nx + UP_BX - 1) / UP_BX, (h->ny + UP_BY - 1) / UP_BY);
-  hipLaunchKernelGGL(k_update, gu, dim3(UP_BX, UP_BY), 0, h->stream, P, (const double*)h->A[in],
+  const long long nwork = (long long)((h->nx + UP_THREADS - 1) / UP_THREADS) * h->ny;
+  const int gu = (int)std::min<long long>(nwork, UP_MAX_BLOCKS);
+  hipLaunchKernelGGL(k_update, dim3(gu), dim3(UP_THREADS), 0, h->stream, P, (const double*)h->A[in],
                      h->A[out], (const double*)h->FK, (const double*)h->FX,
                      (const double*)h->FY, h->dev, in);
   if (h->timing) {
