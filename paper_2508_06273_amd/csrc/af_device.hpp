@@ -277,41 +277,87 @@ template <class R> struct Acc {
   R Ip, IpC, IpS, Jr, Ju, Jv;
 };
 
-// Per-variable contractions with the moments of one arc set.
+// Arc (-alpha, alpha) from (m, -s) to (m, s), symmetric in S: the moments with odd b vanish.
+// Arc (beta, pi - beta) from (q, w) to (-q, w), symmetric in C: the moments with odd a vanish.
+// (The reduction formulas above, with the brackets of these end points written out.)
 template <class R>
+__device__ __forceinline__ void moments_sym_x(R m, R s, R alpha, Mom<R>& M) {
+  const R i3 = R(1) / R(3), i5 = R(0.2), i6 = R(1) / R(6);
+  const R ms = m * s, m2s = m * ms, m3s = m * m2s, m4s = m * m3s, m5s = m * m4s;
+  const R s2 = s * s;
+  M.m[0][0] = alpha + alpha;
+  M.m[1][0] = s + s;
+  M.m[2][0] = ms + alpha;
+  M.m[3][0] = (R(2) * m2s + R(2) * M.m[1][0]) * i3;
+  M.m[4][0] = (R(2) * m3s + R(3) * M.m[2][0]) * R(0.25);
+  M.m[0][2] = alpha - ms;
+  M.m[1][2] = (M.m[1][0] - R(2) * m2s) * i3;
+  M.m[2][2] = (M.m[2][0] - R(2) * m3s) * R(0.25);
+  M.m[3][2] = (M.m[3][0] - R(2) * m4s) * i5;
+  M.m[4][2] = (M.m[4][0] - R(2) * m5s) * i6;
+  M.m[0][4] = (R(3) * M.m[0][2] - R(2) * ms * s2) * R(0.25);
+  M.m[1][4] = (R(3) * M.m[1][2] - R(2) * m2s * s2) * i5;
+  M.m[2][4] = (R(3) * M.m[2][2] - R(2) * m3s * s2) * i6;
+}
+template <class R>
+__device__ __forceinline__ void moments_sym_y(R q, R w, R L, Mom<R>& M) {
+  const R i3 = R(1) / R(3), i5 = R(0.2), i6 = R(1) / R(6);
+  const R q2 = q * q, q3 = q2 * q, q5 = q3 * q2, w2 = w * w;
+  const R qw = q * w, q3w = q3 * w;
+  M.m[0][0] = L;
+  M.m[0][1] = q + q;
+  M.m[2][0] = (L - R(2) * qw) * R(0.5);
+  M.m[4][0] = (R(3) * M.m[2][0] - R(2) * q3w) * R(0.25);
+  M.m[2][1] = R(2) * q3 * i3;
+  M.m[4][1] = R(2) * q5 * i5;
+  M.m[0][2] = (L + R(2) * qw) * R(0.5);
+  M.m[2][2] = (M.m[2][0] + R(2) * q3w) * R(0.25);
+  M.m[4][2] = (M.m[4][0] + R(2) * q5 * w) * i6;
+  M.m[0][3] = (R(4) * q + R(2) * qw * w) * i3;
+  M.m[2][3] = (R(2) * M.m[2][1] + R(2) * q3w * w) * i5;
+  M.m[0][4] = (R(3) * M.m[0][2] + R(2) * qw * w2) * R(0.25);
+  M.m[2][4] = (R(3) * M.m[2][2] + R(2) * q3w * w2) * i6;
+}
+
+// Per-variable contractions with the moments of one arc set.  SYM = 1 (odd-b moments zero)
+// or 2 (odd-a moments zero) drops the terms that vanish identically; SYM = 0 keeps all.
+template <int SYM> __device__ __forceinline__ constexpr bool nz(int a, int b) {
+  return SYM == 1 ? (b % 2 == 0) : (SYM == 2 ? (a % 2 == 0) : true);
+}
+template <int SYM, class R>
 __device__ __forceinline__ void contract_p(const R d[9], const Mom<R>& M, Acc<R>& A) {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       const R x = d[k * 3 + l];
-      A.Ip += x * M.m[k][l];
-      A.IpC += x * M.m[k + 1][l];
-      A.IpS += x * M.m[k][l + 1];
+      if (nz<SYM>(k, l)) A.Ip += x * M.m[k][l];
+      if (nz<SYM>(k + 1, l)) A.IpC += x * M.m[k + 1][l];
+      if (nz<SYM>(k, l + 1)) A.IpS += x * M.m[k][l + 1];
     }
 }
-template <class R>
+template <int SYM, class R>
 __device__ __forceinline__ void contract_u(const R d[9], const Mom<R>& M, Acc<R>& A) {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       const R x = d[k * 3 + l];
-      A.Jr += x * M.m[k + 1][l];
-      A.Ju += x * (R(2) * M.m[k + 2][l] - R(0.5) * M.m[k][l]);
-      A.Jv += x * (R(2) * M.m[k + 1][l + 1]);
+      if (nz<SYM>(k + 1, l)) A.Jr += x * M.m[k + 1][l];
+      if (nz<SYM>(k, l)) A.Ju += x * (R(2) * M.m[k + 2][l] - R(0.5) * M.m[k][l]);
+      if (nz<SYM>(k + 1, l + 1)) A.Jv += x * (R(2) * M.m[k + 1][l + 1]);
     }
 }
-template <class R>
+template <int SYM, class R>
 __device__ __forceinline__ void contract_v(const R d[9], const Mom<R>& M, Acc<R>& A) {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       const R x = d[k * 3 + l];
-      A.Jr += x * M.m[k][l + 1];
-      A.Ju += x * (R(2) * M.m[k + 1][l + 1]);
-      A.Jv += x * (R(2) * M.m[k][l + 2] - R(0.5) * M.m[k][l]);
+      if (nz<SYM>(k, l + 1)) A.Jr += x * M.m[k][l + 1];
+      if (nz<SYM>(k + 1, l + 1)) A.Ju += x * (R(2) * M.m[k + 1][l + 1]);
+      if (nz<SYM>(k, l)) A.Jv += x * (R(2) * M.m[k][l + 2] - R(0.5) * M.m[k][l]);
     }
 }
 

@@ -159,15 +159,17 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
   const R px = -up * tau * G.idx, py = -vp * tau * G.idy;
   const R ax = c * tau * G.idx, by = c * tau * G.idy;
   const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
-  const R twopi = R(2 * kPi), pi = R(kPi);
+  const R pi = R(kPi);
   constexpr int VS = 9 * NC;  // variable stride in cp
   Acc<R> A = {R(0), R(0), R(0), R(0), R(0), R(0)};
 
   if constexpr (KIND == KIND_K) {
-    // crossing points: at -+alpha (cMx, -+sx), at beta (sy, cMy), at pi - beta (-sy, cMy)
+    // corner: for each of the four cells, the arc set where the circle lies in that cell
+    // (the intersection of the x-interval of its side with the y-interval of its side)
     const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
     const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
     const R al = MA::acos_(cMx), be = MA::asin_(cMy);
+    const R twopi = R(2 * kPi);
 #pragma unroll 1
     for (int q = 0; q < 4; ++q) {
       const int sx = q & 1, sy = q >> 1;
@@ -198,37 +200,32 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
       R d[9];
       circle_shift(cp + 3 * VS + cell, NC, xi0, eta0, ax, by, d);
       d[0] -= pp;
-      contract_p(d, M, A);
+      contract_p<0>(d, M, A);
       circle_shift(cp + 1 * VS + cell, NC, xi0, eta0, ax, by, d);
       d[0] -= up;
-      contract_u(d, M, A);
+      contract_u<0>(d, M, A);
       circle_shift(cp + 2 * VS + cell, NC, xi0, eta0, ax, by, d);
       d[0] -= vp;
-      contract_v(d, M, A);
+      contract_v<0>(d, M, A);
     }
   } else {
-    // one grid line: the full circle of the low-side cell plus the arc on the high side of
-    // the difference of the two cell polynomials (which vanishes on the line)
+    // edge: the low-side cell on the full circle plus, on the high-side arc, the difference of
+    // the two cell polynomials (it vanishes on the grid line by continuity).  The high-side
+    // arc is symmetric, so half of its moments vanish.
     Mom<R> M;
-    {
-      Br<R> B;
-      br_zero(B);
-      if constexpr (KIND == KIND_X) {
-        const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
-        const R al = MA::acos_(cMx);
-        br_piece(B, cMx, -sxx, cMx, sxx, al + al);
-      } else {
-        const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
-        const R be = MA::asin_(cMy);
-        br_piece(B, syy, cMy, -syy, cMy, pi - be - be);
-      }
-      moments(B, M);
+    if constexpr (KIND == KIND_X) {
+      const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
+      moments_sym_x(cMx, sxx, MA::acos_(cMx), M);
+    } else {
+      const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
+      moments_sym_y(syy, cMy, pi - R(2) * MA::asin_(cMy), M);
     }
     const int cl = cb, ch = cb + (KIND == KIND_X ? 1 : HC);
     const R xl = (KIND == KIND_X) ? px + R(0.5) : px;
     const R yl = (KIND == KIND_X) ? py : py + R(0.5);
     const R xh = (KIND == KIND_X) ? px - R(0.5) : px;
     const R yh = (KIND == KIND_X) ? py : py - R(0.5);
+    constexpr int SYM = (KIND == KIND_X) ? 1 : 2;
 #pragma unroll
     for (int var = 1; var < 4; ++var) {
       R lo[9], hi[9];
@@ -236,10 +233,10 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
       circle_shift(cp + var * VS + ch, NC, xh, yh, ax, by, hi);
 #pragma unroll
       for (int i = 0; i < 9; ++i) hi[i] -= lo[i];
-      lo[0] -= lin[var];
-      if (var == 3) { full_p(lo, A); contract_p(hi, M, A); }
-      if (var == 1) { full_u(lo, A); contract_u(hi, M, A); }
-      if (var == 2) { full_v(lo, A); contract_v(hi, M, A); }
+      lo[0] -= (var == 1 ? up : (var == 2 ? vp : pp));
+      if (var == 3) { full_p(lo, A); contract_p<SYM>(hi, M, A); }
+      if (var == 1) { full_u(lo, A); contract_u<SYM>(hi, M, A); }
+      if (var == 2) { full_v(lo, A); contract_v<SYM>(hi, M, A); }
     }
   }
 

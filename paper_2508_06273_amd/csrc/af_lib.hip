@@ -228,9 +228,8 @@ __device__ __forceinline__ bool step_dt(const Params& P, DevState* dev, double d
 }
 
 template <class R>
-__global__ __launch_bounds__(PT_THREADS) void k_points(Params P, Bufs<R> B, DevState* dev,
-                                                      double dt_host, int slot) {
-  __shared__ Smem<R> S;
+__device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const Bufs<R>& B,
+                                            DevState* dev, double dt_host, int slot) {
   double dt;
   if (!step_dt(P, dev, dt_host, slot, &dt)) return;
 
@@ -343,6 +342,35 @@ __global__ __launch_bounds__(PT_THREADS) void k_points(Params P, Bufs<R> B, DevS
     if (gi < P.nx && gj < P.nky) evolve_dof<R, KIND_Y>(S, P, B, dev, a, b, gi, gj, dt, speed);
   }
   block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
+}
+
+// One launch per step and precision.  AF_WAVES_F32 / AF_WAVES_F64 set the wavefronts per SIMD
+// that the register allocation aims at (0: the compiler's choice).
+#ifndef AF_WAVES_F32
+#define AF_WAVES_F32 0
+#endif
+#ifndef AF_WAVES_F64
+#define AF_WAVES_F64 3
+#endif
+#if AF_WAVES_F32 > 0
+#define AF_ATTR_F32 __attribute__((amdgpu_waves_per_eu(AF_WAVES_F32)))
+#else
+#define AF_ATTR_F32
+#endif
+#if AF_WAVES_F64 > 0
+#define AF_ATTR_F64 __attribute__((amdgpu_waves_per_eu(AF_WAVES_F64)))
+#else
+#define AF_ATTR_F64
+#endif
+__global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
+void k_points_f32(Params P, Bufs<float> B, DevState* dev, double dt_host, int slot) {
+  __shared__ Smem<float> S;
+  points_body<float>(S, P, B, dev, dt_host, slot);
+}
+__global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
+void k_points_f64(Params P, Bufs<double> B, DevState* dev, double dt_host, int slot) {
+  __shared__ Smem<double> S;
+  points_body<double>(S, P, B, dev, dt_host, slot);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -827,8 +855,12 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
     (void)hipEventCreate(&e2);
     (void)hipEventRecord(e0, h->stream);
   }
-  hipLaunchKernelGGL(k_points<R>, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
-                     dt_host, in);
+  if constexpr (sizeof(R) == 4)
+    hipLaunchKernelGGL(k_points_f32, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
+                       dt_host, in);
+  else
+    hipLaunchKernelGGL(k_points_f64, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
+                       dt_host, in);
   if (h->timing) (void)hipEventRecord(e1, h->stream);
   const long long nwork = (long long)((h->nx + UP_THREADS - 1) / UP_THREADS) * h->ny;
   const int gu = (int)std::min<long long>(nwork, UP_MAX_BLOCKS);
