@@ -73,9 +73,11 @@ enum {
   AF_OPT_TIMING = 6         /* 1: launch eagerly and time every kernel with HIP events on the
                                handle's stream (af_get_timing); 0 (default): off           */
 };
-/* AF_PREC_FP64: every operation in FP64.  AF_PREC_FP32: point values are stored and evolved
- * in FP32 (the evolution operators, correction term and reconstruction); cell averages, the
- * flux accumulation and average update, the positivity tests and the time step stay FP64. */
+/* AF_PREC_FP64: every operation in FP64.  AF_PREC_FP32 (FP32 bulk): the evolution operators
+ * (moment recurrences, circle shifts and contractions of EG2 and EG1) and the correction term
+ * run in FP32 on deviations from the linearisation state; point values and cell averages are
+ * stored in FP64, the deviations themselves, the state updates, the Simpson fluxes and the
+ * average update, the positivity tests and the time step are FP64. */
 enum { AF_PREC_FP64 = 0, AF_PREC_FP32 = 1 };
 /* AF_LIN_AF3: Algorithm 1 (intermediate values linearised at EG2(U^n, dt/4));
  * AF_LIN_AVG: intermediate values linearised at the mean of the adjacent primitive cell

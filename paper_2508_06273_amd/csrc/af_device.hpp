@@ -239,15 +239,17 @@ template <class T> __device__ __forceinline__ void nodes_to_monomials(const T W[
 }
 
 // Substitute xi = xi0 + a C, eta = eta0 + b S into sum c_mn xi^m eta^n -> sum d_kl C^k S^l.
-// `cm` points at c_00 of one variable of one cell in LDS, coefficients `stride` apart.
+// c00 is the constant coefficient (already a deviation); `ch` points at c_01 of one variable
+// of one cell in LDS, the coefficients c_01 .. c_22 `stride` apart.
 template <class R>
-__device__ __forceinline__ void circle_shift(const R* __restrict__ cm, int stride, R xi0,
+__device__ __forceinline__ void circle_shift(R c00, const R* __restrict__ ch, int stride, R xi0,
                                              R eta0, R a, R b, R d[9]) {
   R e[9];
   const R a2 = a * a, b2 = b * b, x2 = xi0 + xi0, y2 = eta0 + eta0;
 #pragma unroll
   for (int n = 0; n < 3; ++n) {
-    R c0 = cm[(0 * 3 + n) * stride], c1 = cm[(1 * 3 + n) * stride], c2 = cm[(2 * 3 + n) * stride];
+    R c0 = n == 0 ? c00 : ch[(n - 1) * stride];
+    R c1 = ch[(3 + n - 1) * stride], c2 = ch[(6 + n - 1) * stride];
     e[0 * 3 + n] = c0 + xi0 * (c1 + xi0 * c2);
     e[1 * 3 + n] = a * (c1 + x2 * c2);
     e[2 * 3 + n] = a2 * c2;
@@ -261,12 +263,12 @@ __device__ __forceinline__ void circle_shift(const R* __restrict__ cm, int strid
   }
 }
 
-// Polynomial value at (xi, eta).
+// Polynomial value at (xi, eta) with constant coefficient c00 (see circle_shift).
 template <class R>
-__device__ __forceinline__ R poly_eval(const R* __restrict__ cm, int stride, R xi, R eta) {
-  R r0 = cm[0 * stride] + eta * (cm[1 * stride] + eta * cm[2 * stride]);
-  R r1 = cm[3 * stride] + eta * (cm[4 * stride] + eta * cm[5 * stride]);
-  R r2 = cm[6 * stride] + eta * (cm[7 * stride] + eta * cm[8 * stride]);
+__device__ __forceinline__ R poly_eval(R c00, const R* __restrict__ ch, int stride, R xi, R eta) {
+  R r0 = c00 + eta * (ch[0 * stride] + eta * ch[1 * stride]);
+  R r1 = ch[2 * stride] + eta * (ch[3 * stride] + eta * ch[4 * stride]);
+  R r2 = ch[5 * stride] + eta * (ch[6 * stride] + eta * ch[7 * stride]);
   return r0 + xi * (r1 + xi * r2);
 }
 

@@ -38,7 +38,7 @@ struct DevState {
   long long steps;
   unsigned long long cnt[8];
   unsigned int done_blocks;
-  unsigned int pad1;
+  unsigned int fix_count;  // tiles listed for the positivity fix-up pass of this step
 };
 
 struct Params {
@@ -51,18 +51,23 @@ struct Params {
   long long pF, sF;  // pitch and variable stride of the flux-sum arrays (doubles)
 };
 
-template <class R> struct Bufs {
+// Point values are stored in FP64 in both precisions (the bulk type only sets the arithmetic
+// of the evolution operators).
+struct Bufs {
   const double* A_in;
   double* A_out;
-  const R* K_in;
-  const R* X_in;
-  const R* Y_in;
-  R* K_out;
-  R* X_out;
-  R* Y_out;
+  const double* K_in;
+  const double* X_in;
+  const double* Y_in;
+  double* K_out;
+  double* X_out;
+  double* Y_out;
   double* FK;  // 8 variables: f sums then g sums
   double* FX;  // 4: f sums
   double* FY;  // 4: g sums
+  // positivity fix-up: per tile 3 lane masks (K, X, Y) and a listed flag; list of tiles
+  unsigned long long* fix_mask;
+  int* fix_list;
 };
 
 // Index of a (possibly ghost) cell or grid line, i >= -n: periodic wrap, or the outflow
@@ -122,11 +127,12 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* t
 // Shared memory of a point tile.
 // ------------------------------------------------------------------------------------------
 template <class R> struct Smem {
-  R cp[4 * 9 * NC];  // [var][coef][cell]
-  R ub[4 * NC];      // primitive Simpson averages [var][cell]
-  R sk[4 * NS];      // t_n point values [var][site], local site (a,b) -> (a+1) + (b+1)*HS
-  R sx[4 * NS];
-  R sy[4 * NS];
+  double c0[4 * NC];  // centre values U_c (constant monomial coefficient) [var][cell]
+  R ch[4 * 8 * NC];   // other monomial coefficients c_01 .. c_22 [var][coef-1][cell]
+  double ub[4 * NC];  // primitive Simpson averages [var][cell]
+  double sk[4 * NS];  // t_n point values [var][site], local site (a,b) -> (a+1) + (b+1)*HS
+  double sx[4 * NS];
+  double sy[4 * NS];
   double red[4];
 };
 
@@ -148,10 +154,12 @@ template <> __device__ __forceinline__ float qdiv<float>(float a, float b) {
 // X: cell (a-1,b); Y: cell (a,b-1)).  Returns the deviation dU = EG2[U] - lin.
 // ------------------------------------------------------------------------------------------
 template <class R, int KIND>
-__device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin[4], R tau,
+__device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[4], R tau,
                                    const Geo<R>& G, R dU[4]) {
   using MA = Math<R>;
-  const R rp = lin[0], up = lin[1], vp = lin[2], pp = lin[3];
+  const R* __restrict__ ch = S.ch;
+  const double* __restrict__ c0 = S.c0;
+  const R rp = R(lin64[0]), up = R(lin64[1]), vp = R(lin64[2]), pp = R(lin64[3]);
   if (!admissible(rp, pp)) return ERR_NONPHYS;
   const R c = MA::sqrt_(qdiv(G.gamma * pp, rp));
   if ((mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * tau >= G.half_h) return ERR_CFL;
@@ -160,7 +168,9 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
   const R ax = c * tau * G.idx, by = c * tau * G.idy;
   const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
   const R pi = R(kPi);
-  constexpr int VS = 9 * NC;  // variable stride in cp
+  constexpr int VS = 8 * NC;  // variable stride in ch
+  // deviation of a cell's centre value from the linearisation state, formed in FP64
+  auto dev0 = [&](int var, int cell) { return R(c0[var * NC + cell] - lin64[var]); };
   Acc<R> A = {R(0), R(0), R(0), R(0), R(0), R(0)};
 
   if constexpr (KIND == KIND_K) {
@@ -198,14 +208,11 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
       const int cell = cb + sx + sy * HC;
       const R xi0 = px + R(0.5) - R(sx), eta0 = py + R(0.5) - R(sy);
       R d[9];
-      circle_shift(cp + 3 * VS + cell, NC, xi0, eta0, ax, by, d);
-      d[0] -= pp;
+      circle_shift(dev0(3, cell), ch + 3 * VS + cell, NC, xi0, eta0, ax, by, d);
       contract_p<0>(d, M, A);
-      circle_shift(cp + 1 * VS + cell, NC, xi0, eta0, ax, by, d);
-      d[0] -= up;
+      circle_shift(dev0(1, cell), ch + 1 * VS + cell, NC, xi0, eta0, ax, by, d);
       contract_u<0>(d, M, A);
-      circle_shift(cp + 2 * VS + cell, NC, xi0, eta0, ax, by, d);
-      d[0] -= vp;
+      circle_shift(dev0(2, cell), ch + 2 * VS + cell, NC, xi0, eta0, ax, by, d);
       contract_v<0>(d, M, A);
     }
   } else {
@@ -220,7 +227,7 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
       const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
       moments_sym_y(syy, cMy, pi - R(2) * MA::asin_(cMy), M);
     }
-    const int cl = cb, ch = cb + (KIND == KIND_X ? 1 : HC);
+    const int cl = cb, chh = cb + (KIND == KIND_X ? 1 : HC);
     const R xl = (KIND == KIND_X) ? px + R(0.5) : px;
     const R yl = (KIND == KIND_X) ? py : py + R(0.5);
     const R xh = (KIND == KIND_X) ? px - R(0.5) : px;
@@ -229,11 +236,11 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
 #pragma unroll
     for (int var = 1; var < 4; ++var) {
       R lo[9], hi[9];
-      circle_shift(cp + var * VS + cl, NC, xl, yl, ax, by, lo);
-      circle_shift(cp + var * VS + ch, NC, xh, yh, ax, by, hi);
+      const R dl = dev0(var, cl);
+      circle_shift(dl, ch + var * VS + cl, NC, xl, yl, ax, by, lo);
+      circle_shift(dev0(var, chh), ch + var * VS + chh, NC, xh, yh, ax, by, hi);
 #pragma unroll
       for (int i = 0; i < 9; ++i) hi[i] -= lo[i];
-      lo[0] -= (var == 1 ? up : (var == 2 ? vp : pp));
       if (var == 3) { full_p(lo, A); contract_p<SYM>(hi, M, A); }
       if (var == 1) { full_u(lo, A); contract_u<SYM>(hi, M, A); }
       if (var == 2) { full_v(lo, A); contract_v<SYM>(hi, M, A); }
@@ -246,8 +253,8 @@ __device__ __forceinline__ int eg2(const R* __restrict__ cp, int cb, const R lin
   const int cellP = cb + sxP + syP * HC;
   const R xiP = (KIND == KIND_Y) ? px : px + R(0.5) - R(sxP);
   const R etaP = (KIND == KIND_X) ? py : py + R(0.5) - R(syP);
-  const R drP = poly_eval(cp + 0 * VS + cellP, NC, xiP, etaP) - rp;
-  const R dpP = poly_eval(cp + 3 * VS + cellP, NC, xiP, etaP) - pp;
+  const R drP = poly_eval(dev0(0, cellP), ch + 0 * VS + cellP, NC, xiP, etaP);
+  const R dpP = poly_eval(dev0(3, cellP), ch + 3 * VS + cellP, NC, xiP, etaP);
 
   const R ipi = R(1.0 / kPi);
   const R ic2 = ic * ic;
@@ -291,10 +298,10 @@ __device__ __forceinline__ void low_piece(R a1, R c1a, R s1a, R b1, R c1b, R s1b
 }
 
 template <class R, int KIND>
-__device__ __noinline__ int eg1_pc(const R* __restrict__ ub, int cb, const R lin[4], R tau,
-                                      const Geo<R>& G, R dU[4]) {
+__device__ __noinline__ int eg1_pc(const double* __restrict__ ub, int cb, const double* lin64,
+                                   R tau, const Geo<R>& G, R dU[4]) {
   using MA = Math<R>;
-  const R rp = lin[0], up = lin[1], vp = lin[2], pp = lin[3];
+  const R rp = R(lin64[0]), up = R(lin64[1]), vp = R(lin64[2]), pp = R(lin64[3]);
   if (!admissible(rp, pp)) return ERR_NONPHYS;
   const R c = MA::sqrt_(G.gamma * pp / rp);
   if ((mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * tau >= G.half_h) return ERR_CFL;
@@ -327,8 +334,8 @@ __device__ __noinline__ int eg1_pc(const R* __restrict__ ub, int cb, const R lin
       for (int t = 0; t < 6; ++t) m[t] += n[t];
     }
     const int cell = cb + (KIND == KIND_Y ? 0 : sx) + (KIND == KIND_X ? 0 : sy * HC);
-    const R dpq = ub[3 * NC + cell] - pp, duq = ub[1 * NC + cell] - up,
-            dvq = ub[2 * NC + cell] - vp;
+    const R dpq = R(ub[3 * NC + cell] - lin64[3]), duq = R(ub[1 * NC + cell] - lin64[1]),
+            dvq = R(ub[2 * NC + cell] - lin64[2]);
     Ip += dpq * m[0];
     IpC += dpq * m[1];
     IpS += dpq * m[2];
@@ -337,7 +344,7 @@ __device__ __noinline__ int eg1_pc(const R* __restrict__ ub, int cb, const R lin
     Kv += R(3) * duq * m[4] + dvq * (R(3) * m[5] - m[0]);
   }
   // foot point values (mean over the cells whose closure contains P')
-  R P[4] = {0, 0, 0, 0};
+  double P[4] = {0, 0, 0, 0};
   {
     const bool onx = (KIND != KIND_Y) && (up == R(0));
     const bool ony = (KIND != KIND_X) && (vp == R(0));
@@ -352,14 +359,14 @@ __device__ __noinline__ int eg1_pc(const R* __restrict__ ub, int cb, const R lin
         for (int v = 0; v < 4; ++v) P[v] += ub[v * NC + cell];
         ++n;
       }
-    const R inv = R(1) / R(n);
-    for (int v = 0; v < 4; ++v) P[v] = P[v] * inv - lin[v];
+    const double inv = 1.0 / n;
+    for (int v = 0; v < 4; ++v) P[v] = P[v] * inv - lin64[v];
   }
   const R i2pi = R(0.5 / kPi);
   const R ic2 = ic * ic, irc = ic / rp;
-  dU[0] = P[0] - P[3] * ic2 + i2pi * (Ip * ic2 - R(2) * rp * ic * Jr);
-  dU[1] = R(0.5) * P[1] + i2pi * (Ku - R(2) * IpC * irc);
-  dU[2] = R(0.5) * P[2] + i2pi * (Kv - R(2) * IpS * irc);
+  dU[0] = R(P[0]) - R(P[3]) * ic2 + i2pi * (Ip * ic2 - R(2) * rp * ic * Jr);
+  dU[1] = R(0.5) * R(P[1]) + i2pi * (Ku - R(2) * IpC * irc);
+  dU[2] = R(0.5) * R(P[2]) + i2pi * (Kv - R(2) * IpS * irc);
   dU[3] = i2pi * (Ip - R(2) * rp * c * Jr);
   return 0;
 }
@@ -385,13 +392,12 @@ __device__ __forceinline__ void lf_flux(const double UL[4], const double UR[4], 
   }
 }
 
-template <class R>
-__device__ __noinline__ void lf_update(const R* __restrict__ site, int a, int b, double tau, const Params& P,
-                          double out[4]) {
+__device__ __noinline__ void lf_update(const double* __restrict__ site, int a, int b, double tau,
+                                       const Params& P, double out[4]) {
   double U[5][4];
   const int nb[5][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}};
   for (int k = 0; k < 5; ++k)
-    for (int v = 0; v < 4; ++v) U[k][v] = (double)site[v * NS + sidx(a + nb[k][0], b + nb[k][1])];
+    for (int v = 0; v < 4; ++v) U[k][v] = site[v * NS + sidx(a + nb[k][0], b + nb[k][1])];
   const double g1inv = 1.0 / (P.gamma - 1.0);
   double Fe[4], Fw[4], Gn[4], Gs[4], Q0[4], Q[4];
   lf_flux(U[0], U[1], 0, P.gamma, g1inv, Fe);

@@ -18,71 +18,118 @@ namespace af {
 // ------------------------------------------------------------------------------------------
 // Kernel 1: point values of one tile of 8x8 sites.
 // ------------------------------------------------------------------------------------------
+// Algorithm 3 applied to a high-order value U (tests in FP64).  Returns 0 or an error code.
 template <class R, int KIND>
-__device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bufs<R>& B,
-                                           DevState* dev, int a, int b, int gi, int gj,
-                                           double dt, double& speed) {
+__device__ __forceinline__ int limit_value(const Smem<R>& S, const Params& P, const Geo<R>& G,
+                                           const double* site, int a, int b, int cb,
+                                           const double Ut[4], double tau, double U[4],
+                                           DevState* dev) {
+  if (admissible(U[0], U[3])) return 0;
+  if (admissible(Ut[0], Ut[3])) {
+    R d[4];
+    const int e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(tau), G, d);
+    if (e == ERR_CFL) return e;
+    atomicAdd(&dev->cnt[AF_CNT_EG1], 1ull);
+    double lo[4];
+    for (int v = 0; v < 4; ++v) lo[v] = Ut[v] + (double)d[v];
+    if (e == 0 && admissible(lo[0], lo[3])) {
+      for (int v = 0; v < 4; ++v) U[v] = lo[v];
+      return 0;
+    }
+  }
+  lf_update(site, a, b, tau, P, U);
+  atomicAdd(&dev->cnt[AF_CNT_LF], 1ull);
+  return admissible(U[0], U[3]) ? 0 : ERR_NONPHYS;
+}
+
+// Hand a DOF that needs Algorithm 3 to the fix-up pass: set its lane bit and list the tile.
+__device__ __forceinline__ void mark_fix(const Bufs& B, DevState* dev, int tile, int kind,
+                                         int lane) {
+  atomicOr(&B.fix_mask[4 * (long long)tile + kind], 1ull << lane);
+  if (atomicExch(&B.fix_mask[4 * (long long)tile + 3], 1ull) == 0ull) {
+    const unsigned int k = atomicAdd(&dev->fix_count, 1u);
+    B.fix_list[k] = tile;
+  }
+}
+
+// One DOF through the rounds of the point update.  States are carried in FP64; the
+// evolution operators work in the bulk type R on deviations from the linearisation state.
+// FIX = false (main pass): a DOF whose value needs the positivity limiter is left to the
+// fix-up pass, which keeps the rare limiter code out of the main kernel's registers.
+// FIX = true (fix-up pass): the same computation with Algorithm 3 applied.
+template <class R, int KIND, bool FIX>
+__device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bufs& B,
+                                           DevState* dev, int tile, int a, int b, int gi,
+                                           int gj, double dt, double& speed) {
   const Geo<R> G = {R(P.idx), R(P.idy), R(P.gamma), R(0.5 * P.hmin)};
-  const R* site = (KIND == KIND_K) ? S.sk : (KIND == KIND_X ? S.sx : S.sy);
+  const double* site = (KIND == KIND_K) ? S.sk : (KIND == KIND_X ? S.sx : S.sy);
   const int s0 = sidx(a, b);
-  R U0[4];
+  double U0[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) U0[v] = site[v * NS + s0];
 
   // cells around the DOF and the neighbours of the derivative stencils
   int cb;
-  R Ux[4], Uy[4], Ut[4];
-  constexpr int VS = 9 * NC;
+  R Ux[4], Uy[4];
   if constexpr (KIND == KIND_K) {
     cb = a + b * HC;  // cell (a-1, b-1)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      Ux[v] = (S.sy[v * NS + sidx(a, b)] - S.sy[v * NS + sidx(a - 1, b)]) * G.idx;
-      Uy[v] = (S.sx[v * NS + sidx(a, b)] - S.sx[v * NS + sidx(a, b - 1)]) * G.idy;
-      Ut[v] = R(0.25) * ((S.ub[v * NC + cb] + S.ub[v * NC + cb + 1]) +
-                         (S.ub[v * NC + cb + HC] + S.ub[v * NC + cb + HC + 1]));
+      Ux[v] = R((S.sy[v * NS + sidx(a, b)] - S.sy[v * NS + sidx(a - 1, b)]) * P.idx);
+      Uy[v] = R((S.sx[v * NS + sidx(a, b)] - S.sx[v * NS + sidx(a, b - 1)]) * P.idy);
     }
   } else if constexpr (KIND == KIND_X) {
     cb = a + (b + 1) * HC;  // cell (a-1, b)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      Uy[v] = (S.sk[v * NS + sidx(a, b + 1)] - S.sk[v * NS + sidx(a, b)]) * G.idy;
-      Ux[v] = (S.cp[v * VS + cb + 1] - S.cp[v * VS + cb]) * G.idx;
-      Ut[v] = R(0.5) * (S.ub[v * NC + cb] + S.ub[v * NC + cb + 1]);
+      Uy[v] = R((S.sk[v * NS + sidx(a, b + 1)] - S.sk[v * NS + sidx(a, b)]) * P.idy);
+      Ux[v] = R((S.c0[v * NC + cb + 1] - S.c0[v * NC + cb]) * P.idx);
     }
   } else {
     cb = (a + 1) + b * HC;  // cell (a, b-1)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      Ux[v] = (S.sk[v * NS + sidx(a + 1, b)] - S.sk[v * NS + sidx(a, b)]) * G.idx;
-      Uy[v] = (S.cp[v * VS + cb + HC] - S.cp[v * VS + cb]) * G.idy;
-      Ut[v] = R(0.5) * (S.ub[v * NC + cb] + S.ub[v * NC + cb + HC]);
+      Ux[v] = R((S.sk[v * NS + sidx(a + 1, b)] - S.sk[v * NS + sidx(a, b)]) * P.idx);
+      Uy[v] = R((S.c0[v * NC + cb + HC] - S.c0[v * NC + cb]) * P.idy);
     }
   }
+  // mean of the adjacent primitive averages (read from LDS where it is used)
+  auto avg_lin = [&](double Ut[4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if constexpr (KIND == KIND_K)
+        Ut[v] = 0.25 * ((S.ub[v * NC + cb] + S.ub[v * NC + cb + 1]) +
+                        (S.ub[v * NC + cb + HC] + S.ub[v * NC + cb + HC + 1]));
+      else
+        Ut[v] = 0.5 * (S.ub[v * NC + cb] + S.ub[v * NC + cb + (KIND == KIND_X ? 1 : HC)]);
+    }
+  };
   R Cv[4] = {R(0), R(0), R(0), R(0)};
-  if (P.correction) corr_half(U0, Ux, Uy, G.gamma, Cv);
+  if (P.correction) {
+    const R U0r[4] = {R(U0[0]), R(U0[1]), R(U0[2]), R(U0[3])};
+    corr_half(U0r, Ux, Uy, G.gamma, Cv);
+  }
   const double h2 = 0.25 * dt * dt, f2 = dt * dt;
 
   int e = 0;
-  R lin[4];
+  double lin[4];
   if (P.mode == LIN_AF3) {
     R dq[4];
-    e = eg2<R, KIND>(S.cp, cb, U0, R(0.25 * dt), G, dq);
+    e = eg2<R, KIND>(S, cb, U0, R(0.25 * dt), G, dq);
     if (e) { set_err(dev, e); return; }
-    R q[4];
+    double q[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) q[v] = U0[v] + dq[v];
+    for (int v = 0; v < 4; ++v) q[v] = U0[v] + (double)dq[v];
     if (admissible(q[0], q[3])) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) lin[v] = q[v];
     } else {
 #pragma unroll
       for (int v = 0; v < 4; ++v) lin[v] = U0[v];
-      atomicAdd(&dev->cnt[AF_CNT_INNER], 1ull);
+      if (!FIX) atomicAdd(&dev->cnt[AF_CNT_INNER], 1ull);
     }
   } else if (P.mode == LIN_AVG) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) lin[v] = Ut[v];
+    avg_lin(lin);
   } else {
 #pragma unroll
     for (int v = 0; v < 4; ++v) lin[v] = U0[v];
@@ -91,75 +138,49 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
   double Uh[4], U1[4];
   {
     R d[4];
-    e = eg2<R, KIND>(S.cp, cb, lin, R(0.5 * dt), G, d);
+    e = eg2<R, KIND>(S, cb, lin, R(0.5 * dt), G, d);
     if (e) { set_err(dev, e); return; }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Uh[v] = (double)lin[v] + (double)d[v] + h2 * (double)Cv[v];
+    for (int v = 0; v < 4; ++v) Uh[v] = lin[v] + (double)d[v] + h2 * (double)Cv[v];
   }
   // positivity of the intermediate value (Algorithm 3)
   if (!admissible(Uh[0], Uh[3])) {
     if (!P.limiter) { set_err(dev, ERR_NONPHYS); return; }
-    bool done = false;
-    if (admissible(Ut[0], Ut[3])) {
-      R d[4];
-      e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(0.5 * dt), G, d);
-      if (e == ERR_CFL) { set_err(dev, e); return; }
-      atomicAdd(&dev->cnt[AF_CNT_EG1], 1ull);
-      double lo[4];
-      for (int v = 0; v < 4; ++v) lo[v] = (double)Ut[v] + (double)d[v];
-      if (e == 0 && admissible(lo[0], lo[3])) {
-        for (int v = 0; v < 4; ++v) Uh[v] = lo[v];
-        done = true;
-      }
-    }
-    if (!done) {
-      lf_update<R>(site, a, b, 0.5 * dt, P, Uh);
-      atomicAdd(&dev->cnt[AF_CNT_LF], 1ull);
-      if (!admissible(Uh[0], Uh[3])) { set_err(dev, ERR_NONPHYS); return; }
+    if constexpr (!FIX) {
+      mark_fix(B, dev, tile, KIND, threadIdx.x & 63);
+      return;
+    } else {
+      double Ut[4];
+      avg_lin(Ut);
+      e = limit_value<R, KIND>(S, P, G, site, a, b, cb, Ut, 0.5 * dt, Uh, dev);
+      if (e) { set_err(dev, e); return; }
     }
   }
-  R Uhr[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) Uhr[v] = (R)Uh[v];
   {
     R d[4];
-    e = eg2<R, KIND>(S.cp, cb, Uhr, R(dt), G, d);
+    e = eg2<R, KIND>(S, cb, Uh, R(dt), G, d);
     if (e) { set_err(dev, e); return; }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) U1[v] = (double)Uhr[v] + (double)d[v] + f2 * (double)Cv[v];
+    for (int v = 0; v < 4; ++v) U1[v] = Uh[v] + (double)d[v] + f2 * (double)Cv[v];
   }
   if (P.limiter && !admissible(U1[0], U1[3])) {
-    bool done = false;
-    if (admissible(Ut[0], Ut[3])) {
-      R d[4];
-      e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(dt), G, d);
-      if (e == ERR_CFL) { set_err(dev, e); return; }
-      atomicAdd(&dev->cnt[AF_CNT_EG1], 1ull);
-      double lo[4];
-      for (int v = 0; v < 4; ++v) lo[v] = (double)Ut[v] + (double)d[v];
-      if (e == 0 && admissible(lo[0], lo[3])) {
-        for (int v = 0; v < 4; ++v) U1[v] = lo[v];
-        done = true;
-      }
-    }
-    if (!done) {
-      lf_update<R>(site, a, b, dt, P, U1);
-      atomicAdd(&dev->cnt[AF_CNT_LF], 1ull);
-      if (!admissible(U1[0], U1[3])) { set_err(dev, ERR_NONPHYS); return; }
+    if constexpr (!FIX) {
+      mark_fix(B, dev, tile, KIND, threadIdx.x & 63);
+      return;
+    } else {
+      double Ut[4];
+      avg_lin(Ut);
+      e = limit_value<R, KIND>(S, P, G, site, a, b, cb, Ut, dt, U1, dev);
+      if (e) { set_err(dev, e); return; }
     }
   }
 
   // outputs: new point value, Simpson-in-time flux sums, wave speed
-  R* out = (KIND == KIND_K) ? B.K_out : (KIND == KIND_X ? B.X_out : B.Y_out);
+  double* out = (KIND == KIND_K) ? B.K_out : (KIND == KIND_X ? B.X_out : B.Y_out);
   const long long o = (long long)gj * P.pP + gi;
-  R U1r[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    U1r[v] = (R)U1[v];
-    out[v * P.sP + o] = U1r[v];
-  }
+  for (int v = 0; v < 4; ++v) out[v * P.sP + o] = U1[v];
   const double g1inv = 1.0 / (P.gamma - 1.0);
-  double U1d[4];
   double Fs[4] = {0, 0, 0, 0}, Gs[4] = {0, 0, 0, 0};
   {
     double Ul[4], F[4], Gq[4];
@@ -167,7 +188,7 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
     for (int lvl = 0; lvl < 3; ++lvl) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        Ul[v] = lvl == 0 ? (double)U0[v] : (lvl == 1 ? Uh[v] : (double)U1r[v]);
+        Ul[v] = lvl == 0 ? site[v * NS + s0] : (lvl == 1 ? Uh[v] : U1[v]);
       flux_fg(Ul, g1inv, F, Gq);
       const double w = lvl == 1 ? 4.0 : 1.0;
 #pragma unroll
@@ -177,8 +198,6 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
       }
     }
   }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) U1d[v] = (double)U1r[v];
   const long long of = (long long)gj * P.pF + gi;
   if constexpr (KIND == KIND_K) {
 #pragma unroll
@@ -193,47 +212,53 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
 #pragma unroll
     for (int v = 0; v < 4; ++v) B.FY[v * P.sF + of] = Gs[v];
   }
-  if (admissible(U1d[0], U1d[3])) speed = mx(speed, wave_speed(U1d, P.gamma));
+  if (admissible(U1[0], U1[3])) speed = mx(speed, wave_speed(U1, P.gamma));
 }
 
-// Step control shared by both kernels.  Returns false if the step does not run.
+// Step control of the point kernel: thread 0 decides and broadcasts through LDS, so that the
+// decision is uniform over the block even if another block flags an error meanwhile.
+// Returns false if the step does not run.
 __device__ __forceinline__ bool step_dt(const Params& P, DevState* dev, double dt_host, int slot,
                                         double* dt_out) {
-  if (dev->err) return false;
-  double dt;
-  int last = 0;
-  if (dt_host > 0.0) {
-    dt = dt_host;
-  } else {
-    const double t = dev->t, te = dev->t_end;
-    if (!(t < te)) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) dev->active = 0;
-      return false;
+  __shared__ double s_dt;
+  __shared__ int s_run;
+  if (threadIdx.x == 0) {
+    int run = 1, last = 0;
+    double dt = dt_host;
+    if (dev->err) {
+      run = 0;
+    } else if (!(dt_host > 0.0)) {
+      const double t = dev->t, te = dev->t_end;
+      const double smax = __longlong_as_double((long long)dev->smax[slot]);
+      if (!(t < te)) {
+        run = 0;
+        if (blockIdx.x == 0) dev->active = 0;
+      } else if (!(smax > 0.0) || !(smax < 1e300)) {
+        run = 0;
+        set_err(dev, ERR_NONPHYS);
+      } else {
+        dt = dev->cfl * P.hmin / smax;
+        if (t + dt >= te) { dt = te - t; last = 1; }
+      }
     }
-    const double smax = __longlong_as_double((long long)dev->smax[slot]);
-    if (!(smax > 0.0) || !(smax < 1e300)) {
-      if (threadIdx.x == 0) set_err(dev, ERR_NONPHYS);
-      return false;
+    if (run && blockIdx.x == 0) {
+      dev->dt = dt;
+      dev->active = 1;
+      dev->last = last;
     }
-    dt = dev->cfl * P.hmin / smax;
-    if (t + dt >= te) { dt = te - t; last = 1; }
+    s_dt = dt;
+    s_run = run;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    dev->dt = dt;
-    dev->active = 1;
-    dev->last = last;
-  }
-  *dt_out = dt;
-  return true;
+  __syncthreads();
+  *dt_out = s_dt;
+  return s_run != 0;
 }
 
+// Stage the t_n point values of a tile's halo in LDS and build the halo cells'
+// reconstructions.  Ends with a barrier.
 template <class R>
-__device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const Bufs<R>& B,
-                                            DevState* dev, double dt_host, int slot) {
-  double dt;
-  if (!step_dt(P, dev, dt_host, slot, &dt)) return;
-
-  const int tile = blockIdx.x;
+__device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, const Bufs& B,
+                                               DevState* dev, int tile, bool count) {
   const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
   const int tid = threadIdx.x;
 
@@ -243,8 +268,8 @@ __device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const B
     const int a = s % HS - 1, b = s / HS - 1;
     const int gi = i0 + a, gj = j0 + b;
     int si, sj;
-    const R* src;
-    R* dst;
+    const double* src;
+    double* dst;
     if (kind == 0) {
       si = wrap_line(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.K_in; dst = S.sk;
     } else if (kind == 1) {
@@ -265,7 +290,7 @@ __device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const B
     const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
     // node k of the cell: 0..3 corners K(a,b) K(a+1,b) K(a,b+1) K(a+1,b+1),
     // 4,5 X(a,b) X(a+1,b), 6,7 Y(a,b) Y(a,b+1)
-    const R* nptr[8] = {S.sk + sidx(a, b), S.sk + sidx(a + 1, b), S.sk + sidx(a, b + 1),
+    const double* nptr[8] = {S.sk + sidx(a, b), S.sk + sidx(a + 1, b), S.sk + sidx(a, b + 1),
                         S.sk + sidx(a + 1, b + 1), S.sx + sidx(a, b), S.sx + sidx(a + 1, b),
                         S.sy + sidx(a, b), S.sy + sidx(a, b + 1)};
     auto node = [&](int k, double W[4]) {
@@ -307,7 +332,7 @@ __device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const B
     if (!admissible(Uc[0], Uc[3])) {
       c2p_plain(Qb, gm1, Uc);
       const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
-      if (owned) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
+      if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
     }
     // primitive Simpson average and monomial coefficients, one variable at a time
 #pragma unroll 1
@@ -318,30 +343,85 @@ __device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const B
       const double u = Uc[v];
       const double sK4 = ((w[0] - u) + (w[1] - u)) + ((w[2] - u) + (w[3] - u));
       const double sE4 = ((w[4] - u) + (w[5] - u)) + ((w[6] - u) + (w[7] - u));
-      S.ub[v * NC + c] = (R)(u + (sK4 + 4.0 * sE4) * (1.0 / 36.0));
+      S.ub[v * NC + c] = u + (sK4 + 4.0 * sE4) * (1.0 / 36.0);
       const double N[3][3] = {{w[0], w[4], w[2]}, {w[6], u, w[7]}, {w[1], w[5], w[3]}};
       double cm[9];
       nodes_to_monomials(N, cm);
+      S.c0[v * NC + c] = cm[0];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) S.cp[(v * 9 + k) * NC + c] = (R)cm[k];
+      for (int k = 1; k < 9; ++k) S.ch[(v * 8 + k - 1) * NC + c] = (R)cm[k];
     }
   }
   __syncthreads();
+}
 
-  // 3. evolve the tile's own DOFs: wavefront 0 -> K, 1 -> X, 2 -> Y
-  const int kind = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
+// Evolve the tile's own DOFs: wavefront 0 -> K, 1 -> X, 2 -> Y.  In the fix-up pass only the
+// lanes listed in `mask` (per kind) run.
+template <class R, bool FIX>
+__device__ __forceinline__ void evolve_tile(Smem<R>& S, const Params& P, const Bufs& B,
+                                            DevState* dev, int tile, double dt,
+                                            const unsigned long long* mask, double& speed) {
+  const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
+  const int kind = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int a = lane % TILE, b = lane / TILE;
   const int gi = i0 + a, gj = j0 + b;
-  double speed = 0.0;
+  if (FIX && !((mask[kind] >> lane) & 1ull)) return;
   if (kind == KIND_K) {
-    if (gi < P.nkx && gj < P.nky) evolve_dof<R, KIND_K>(S, P, B, dev, a, b, gi, gj, dt, speed);
+    if (gi < P.nkx && gj < P.nky)
+      evolve_dof<R, KIND_K, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
   } else if (kind == KIND_X) {
-    if (gi < P.nkx && gj < P.ny) evolve_dof<R, KIND_X>(S, P, B, dev, a, b, gi, gj, dt, speed);
+    if (gi < P.nkx && gj < P.ny)
+      evolve_dof<R, KIND_X, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
   } else {
-    if (gi < P.nx && gj < P.nky) evolve_dof<R, KIND_Y>(S, P, B, dev, a, b, gi, gj, dt, speed);
+    if (gi < P.nx && gj < P.nky)
+      evolve_dof<R, KIND_Y, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
   }
+}
+
+template <class R>
+__device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const Bufs& B,
+                                            DevState* dev, double dt_host, int slot) {
+  double dt;
+  if (!step_dt(P, dev, dt_host, slot, &dt)) return;
+  const int tile = blockIdx.x;
+  stage_and_prep(S, P, B, dev, tile, true);
+  double speed = 0.0;
+  evolve_tile<R, false>(S, P, B, dev, tile, dt, nullptr, speed);
   block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
+}
+
+// Positivity fix-up pass: the tiles listed by the main pass are staged again and only their
+// flagged DOFs are recomputed with Algorithm 3.  Cheap when the list is empty.
+template <class R>
+__device__ __forceinline__ void fixup_body(Smem<R>& S, const Params& P, const Bufs& B,
+                                           DevState* dev, int slot) {
+  __shared__ unsigned long long mask[3];
+  __shared__ int s_run;
+  __shared__ unsigned int s_n;
+  __shared__ double s_dt;
+  if (threadIdx.x == 0) {
+    s_run = !dev->err && dev->active;
+    s_n = dev->fix_count;
+    s_dt = dev->dt;
+  }
+  __syncthreads();
+  const bool run = s_run != 0;
+  const double dt = s_dt;
+  const unsigned int n = s_n;
+  double speed = 0.0;
+  for (unsigned int k = blockIdx.x; k < n; k += gridDim.x) {
+    const int tile = B.fix_list[k];
+    if (threadIdx.x < 3) mask[threadIdx.x] = B.fix_mask[4 * (long long)tile + threadIdx.x];
+    __syncthreads();
+    if (run) {
+      stage_and_prep(S, P, B, dev, tile, false);
+      evolve_tile<R, true>(S, P, B, dev, tile, dt, mask, speed);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) B.fix_mask[4 * (long long)tile + threadIdx.x] = 0ull;
+  }
+  if (n > blockIdx.x) block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
 }
 
 // One launch per step and precision.  AF_WAVES_F32 / AF_WAVES_F64 set the wavefronts per SIMD
@@ -363,15 +443,26 @@ __device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const B
 #define AF_ATTR_F64
 #endif
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
-void k_points_f32(Params P, Bufs<float> B, DevState* dev, double dt_host, int slot) {
+void k_points_f32(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
   __shared__ Smem<float> S;
   points_body<float>(S, P, B, dev, dt_host, slot);
 }
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
-void k_points_f64(Params P, Bufs<double> B, DevState* dev, double dt_host, int slot) {
+void k_points_f64(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
   __shared__ Smem<double> S;
   points_body<double>(S, P, B, dev, dt_host, slot);
 }
+__global__ __launch_bounds__(PT_THREADS) void k_fixup_f32(Params P, Bufs B, DevState* dev,
+                                                         int slot) {
+  __shared__ Smem<float> S;
+  fixup_body<float>(S, P, B, dev, slot);
+}
+__global__ __launch_bounds__(PT_THREADS) void k_fixup_f64(Params P, Bufs B, DevState* dev,
+                                                         int slot) {
+  __shared__ Smem<double> S;
+  fixup_body<double>(S, P, B, dev, slot);
+}
+constexpr int FIX_BLOCKS = 1024;
 
 // ------------------------------------------------------------------------------------------
 // Kernel 2: Simpson space-time fluxes and the conservative update of the averages.
@@ -440,6 +531,7 @@ __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* _
   if (last_block && threadIdx.x == 0) {
     __threadfence();
     dev->done_blocks = 0;
+    dev->fix_count = 0u;
     if (run && !atomicAdd(&dev->err, 0)) {
       dev->t = dev->last ? dev->t_end : dev->t + dt;
       dev->steps += 1;
@@ -449,9 +541,8 @@ __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* _
 }
 
 // Largest wave speed of the current state (averages and point values) into smax[slot].
-template <class R>
-__global__ void k_cfl(Params P, const double* __restrict__ A, const R* __restrict__ K,
-                      const R* __restrict__ X, const R* __restrict__ Y, DevState* dev,
+__global__ void k_cfl(Params P, const double* __restrict__ A, const double* __restrict__ K,
+                      const double* __restrict__ X, const double* __restrict__ Y, DevState* dev,
                       int slot) {
   __shared__ double red[4];
   const long long n0 = (long long)P.nx * P.ny, n1 = (long long)P.nkx * P.nky,
@@ -468,13 +559,13 @@ __global__ void k_cfl(Params P, const double* __restrict__ A, const R* __restric
       c2p_plain(Q, P.gamma - 1.0, U);
     } else {
       long long r = e - n0;
-      const R* src;
+      const double* src;
       int w;
       if (r < n1) { src = K; w = P.nkx; }
       else if (r < n1 + n2) { src = X; w = P.nkx; r -= n1; }
       else { src = Y; w = P.nx; r -= n1 + n2; }
       const int i = (int)(r % w), j = (int)(r / w);
-      for (int v = 0; v < 4; ++v) U[v] = (double)src[v * P.sP + (long long)j * P.pP + i];
+      for (int v = 0; v < 4; ++v) U[v] = src[v * P.sP + (long long)j * P.pP + i];
     }
     // non-admissible values do not enter the time step (as NaN speeds would not)
     if (admissible(U[0], U[3])) speed = mx(speed, wave_speed(U, P.gamma));
@@ -504,6 +595,8 @@ struct af_handle {
   double* FK = nullptr;
   double* FX = nullptr;
   double* FY = nullptr;
+  unsigned long long* fix_mask = nullptr;
+  int* fix_list = nullptr;
   DevState* dev = nullptr;
   int cur = 0;
   bool has_state = false;
@@ -534,7 +627,7 @@ static int fail(const af_handle* h, int code, const std::string& msg) {
                   std::string(#call) + ": " + hipGetErrorString(e_));                \
   } while (0)
 
-static size_t rsize(const af_handle* h) { return h->prec == AF_PREC_FP32 ? 4 : 8; }
+static size_t rsize(const af_handle*) { return 8; }  // point values are stored in FP64
 
 static Params make_params(const af_handle* h) {
   Params P;
@@ -563,6 +656,10 @@ static void free_buffers(af_handle* h) {
   if (h->FX) (void)hipFree(h->FX);
   if (h->FY) (void)hipFree(h->FY);
   h->FK = h->FX = h->FY = nullptr;
+  if (h->fix_mask) (void)hipFree(h->fix_mask);
+  if (h->fix_list) (void)hipFree(h->fix_list);
+  h->fix_mask = nullptr;
+  h->fix_list = nullptr;
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   h->gexec = nullptr;
   h->gexec_steps = 0;
@@ -584,6 +681,10 @@ static int alloc_buffers(af_handle* h) {
   HIP_OK(hipMalloc(&h->FK, nf * 8 * 8), h);
   HIP_OK(hipMalloc(&h->FX, nf * 4 * 8), h);
   HIP_OK(hipMalloc(&h->FY, nf * 4 * 8), h);
+  const size_t ntiles = (size_t)((h->nkx + TILE - 1) / TILE) * ((h->nky + TILE - 1) / TILE);
+  HIP_OK(hipMalloc(&h->fix_mask, ntiles * 4 * sizeof(unsigned long long)), h);
+  HIP_OK(hipMalloc(&h->fix_list, ntiles * sizeof(int)), h);
+  HIP_OK(hipMemset(h->fix_mask, 0, ntiles * 4 * sizeof(unsigned long long)), h);
   h->has_state = false;
   return AF_OK;
 }
@@ -842,11 +943,13 @@ template <class R>
 static void enqueue_step_t(af_handle* h, int in, double dt_host) {
   const Params P = make_params(h);
   const int out = in ^ 1;
-  Bufs<R> B;
+  Bufs B;
   B.A_in = h->A[in]; B.A_out = h->A[out];
-  B.K_in = (const R*)h->K[in]; B.X_in = (const R*)h->X[in]; B.Y_in = (const R*)h->Y[in];
-  B.K_out = (R*)h->K[out]; B.X_out = (R*)h->X[out]; B.Y_out = (R*)h->Y[out];
+  B.K_in = (const double*)h->K[in]; B.X_in = (const double*)h->X[in];
+  B.Y_in = (const double*)h->Y[in];
+  B.K_out = (double*)h->K[out]; B.X_out = (double*)h->X[out]; B.Y_out = (double*)h->Y[out];
   B.FK = h->FK; B.FX = h->FX; B.FY = h->FY;
+  B.fix_mask = h->fix_mask; B.fix_list = h->fix_list;
   const int ntiles = P.tiles_x * P.tiles_y;
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (h->timing) {
@@ -861,6 +964,13 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
   else
     hipLaunchKernelGGL(k_points_f64, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
                        dt_host, in);
+  if (h->limiter) {
+    const int nb = std::min(ntiles, FIX_BLOCKS);
+    if constexpr (sizeof(R) == 4)
+      hipLaunchKernelGGL(k_fixup_f32, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev, in);
+    else
+      hipLaunchKernelGGL(k_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev, in);
+  }
   if (h->timing) (void)hipEventRecord(e1, h->stream);
   const long long nwork = (long long)((h->nx + UP_THREADS - 1) / UP_THREADS) * h->ny;
   const int gu = (int)std::min<long long>(nwork, UP_MAX_BLOCKS);
@@ -951,14 +1061,9 @@ extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
   {
     const Params P = make_params(h);
     const int c = h->cur;
-    if (h->prec == AF_PREC_FP32)
-      hipLaunchKernelGGL(k_cfl<float>, dim3(1024), dim3(256), 0, h->stream, P,
-                         (const double*)h->A[c], (const float*)h->K[c], (const float*)h->X[c],
-                         (const float*)h->Y[c], h->dev, c);
-    else
-      hipLaunchKernelGGL(k_cfl<double>, dim3(1024), dim3(256), 0, h->stream, P,
-                         (const double*)h->A[c], (const double*)h->K[c],
-                         (const double*)h->X[c], (const double*)h->Y[c], h->dev, c);
+    hipLaunchKernelGGL(k_cfl, dim3(1024), dim3(256), 0, h->stream, P, (const double*)h->A[c],
+                       (const double*)h->K[c], (const double*)h->X[c], (const double*)h->Y[c],
+                       h->dev, c);
     HIP_OK(hipGetLastError(), h);
   }
   long long done = 0;

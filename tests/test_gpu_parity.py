@@ -300,3 +300,22 @@ def test_full_size_vortex_sampled(prec, tol):
             assert abs(out["K"][:, gj, gi] - p.K[:, pj, pi_]).max() < tol * scale
             assert abs(out["X"][:, gj, gi] - p.X[:, pj, pi_]).max() < tol * scale
             assert abs(out["Y"][:, gj, gi] - p.Y[:, pj, pi_]).max() < tol * scale
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-7)])
+def test_radial_outflow_limiter_multitile(prec, tol):
+    """Near-vacuum radial outflow on 128^2 (outflow boundaries, averaged linearisation,
+    positivity limiter): many tiles go through the fix-up pass; counters and states match."""
+    _flush(f"[gpu] radial outflow 128^2 x 8 steps prec={prec}")
+    st = I.radial_state(128, n_gl=3)
+    s = gpu_state(st, prec, 1, True, True)
+    t, n = s.run(1e9, 0.3, 8)
+    out = s.get_state()
+    cnt = s.counters()
+    e, n2, ocnt = oracle.run(st, 1e9, 0.3, max_steps=8, mode=1, limiter=True)
+    assert e == 0 and n == n2 == 8
+    assert_close(out, st, tol, "radial 128")
+    if prec == 0:
+        assert list(cnt[:4]) == list(ocnt[:4])
+    for k in ("K", "X", "Y"):
+        assert (out[k][0] > 0).all() and (out[k][3] > 0).all()
