@@ -274,9 +274,12 @@ __device__ __forceinline__ R poly_eval(R c00, const R* __restrict__ ch, int stri
 
 // Accumulators of the circle integrals of the deviations dp, du, dv from the linearisation
 // state:  Ip = int dp, IpC = int dp C, IpS = int dp S, Jr = int (du C + dv S),
-// Ju = int (du (2C^2 - 1/2) + 2 dv S C), Jv = int (2 du S C + dv (2 S^2 - 1/2)).
+// Ju = int (du (2C^2 - 1/2) + 2 dv S C) = Ju0 + 2 Ua - Ub / 2,
+// Jv = int (2 du S C + dv (2 S^2 - 1/2)) = Jv0 + 2 Va - Vb / 2, where the arc contractions
+// accumulate Ua = int (du C^2 + dv S C), Ub = int du, Va = int (du S C + dv S^2), Vb = int dv
+// (no per-arc moment combinations) and the full-circle terms go to Ju0, Jv0 directly.
 template <class R> struct Acc {
-  R Ip, IpC, IpS, Jr, Ju, Jv;
+  R Ip, IpC, IpS, Jr, Ju0, Jv0, Ua, Ub, Va, Vb;
 };
 
 // Arc (-alpha, alpha) from (m, -s) to (m, s), symmetric in S: the moments with odd b vanish.
@@ -346,8 +349,9 @@ __device__ __forceinline__ void contract_u(const R d[9], const Mom<R>& M, Acc<R>
     for (int l = 0; l < 3; ++l) {
       const R x = d[k * 3 + l];
       if (nz<SYM>(k + 1, l)) A.Jr += x * M.m[k + 1][l];
-      if (nz<SYM>(k, l)) A.Ju += x * (R(2) * M.m[k + 2][l] - R(0.5) * M.m[k][l]);
-      if (nz<SYM>(k + 1, l + 1)) A.Jv += x * (R(2) * M.m[k + 1][l + 1]);
+      if (nz<SYM>(k + 2, l)) A.Ua += x * M.m[k + 2][l];
+      if (nz<SYM>(k, l)) A.Ub += x * M.m[k][l];
+      if (nz<SYM>(k + 1, l + 1)) A.Va += x * M.m[k + 1][l + 1];
     }
 }
 template <int SYM, class R>
@@ -358,8 +362,9 @@ __device__ __forceinline__ void contract_v(const R d[9], const Mom<R>& M, Acc<R>
     for (int l = 0; l < 3; ++l) {
       const R x = d[k * 3 + l];
       if (nz<SYM>(k, l + 1)) A.Jr += x * M.m[k][l + 1];
-      if (nz<SYM>(k + 1, l + 1)) A.Ju += x * (R(2) * M.m[k + 1][l + 1]);
-      if (nz<SYM>(k, l)) A.Jv += x * (R(2) * M.m[k][l + 2] - R(0.5) * M.m[k][l]);
+      if (nz<SYM>(k + 1, l + 1)) A.Ua += x * M.m[k + 1][l + 1];
+      if (nz<SYM>(k, l + 2)) A.Va += x * M.m[k][l + 2];
+      if (nz<SYM>(k, l)) A.Vb += x * M.m[k][l];
     }
 }
 
@@ -374,14 +379,14 @@ template <class R> __device__ __forceinline__ void full_p(const R d[9], Acc<R>& 
 template <class R> __device__ __forceinline__ void full_u(const R d[9], Acc<R>& A) {
   const R pi = R(kPi);
   A.Jr += pi * d[3] + R(0.25) * pi * d[5];
-  A.Ju += pi * (d[0] + d[6]) + R(0.125) * pi * d[8];
-  A.Jv += R(0.5) * pi * d[4];
+  A.Ju0 += pi * (d[0] + d[6]) + R(0.125) * pi * d[8];
+  A.Jv0 += R(0.5) * pi * d[4];
 }
 template <class R> __device__ __forceinline__ void full_v(const R d[9], Acc<R>& A) {
   const R pi = R(kPi);
   A.Jr += pi * d[1] + R(0.25) * pi * d[7];
-  A.Ju += R(0.5) * pi * d[4];
-  A.Jv += pi * (d[0] + d[2]) + R(0.125) * pi * d[8];
+  A.Ju0 += R(0.5) * pi * d[4];
+  A.Jv0 += pi * (d[0] + d[2]) + R(0.125) * pi * d[8];
 }
 
 }  // namespace af

@@ -5,7 +5,8 @@
 //              LDS, build the cell reconstructions of the 9x9 halo cells (inverse Simpson for
 //              the centre value, primitive Simpson average, monomial coefficients), then evolve
 //              the tile's own K, X and Y point values to the intermediate and new time levels
-//              (one wavefront per DOF kind), apply the positivity limiter, write U^{n+1} and
+//              (wavefront 0: corners; wavefront 1: x-edges, then y-edges), hand DOFs that
+//              need the positivity limiter to the fix-up pass, write U^{n+1} and
 //              the per-site Simpson-in-time flux sums f(U^n) + 4 f(U^{n+1/2}) + f(U^{n+1}).
 //   k_update : per cell, Simpson space-time face fluxes from the site sums and the
 //              conservative FP64 update of the cell average (paper eqs. F and 2dfvm); the
@@ -25,7 +26,7 @@ constexpr int HS = TILE + 2;   // halo sites per edge (local -1 .. TILE)
 constexpr int HC = TILE + 1;   // halo cells per edge (local -1 .. TILE-1)
 constexpr int NS = HS * HS;    // 100
 constexpr int NC = HC * HC;    // 81
-constexpr int PT_THREADS = 192;
+constexpr int PT_THREADS = 128;  // two wavefronts: corners; edges
 
 // Device-resident step control.
 struct DevState {
@@ -149,6 +150,12 @@ template <> __device__ __forceinline__ float qdiv<float>(float a, float b) {
   return a * __builtin_amdgcn_rcpf(b);
 }
 
+// Corner EG2 formulation.  Split (FP32): the lower-left cell on the full circle plus cell
+// differences on two half circles and one quadrant arc set -- about a quarter fewer
+// operations, but three moment sets live at once.  Quadrants (FP64): one general arc set per
+// cell, one moment set live at a time, which keeps the FP64 kernel within its registers.
+template <class R> constexpr bool kCornerSplit = sizeof(R) == 4;
+
 // ------------------------------------------------------------------------------------------
 // EG2 at one DOF.  cb: LDS index of the lower-left cell around the DOF (K: cell (a-1,b-1);
 // X: cell (a-1,b); Y: cell (a,b-1)).  Returns the deviation dU = EG2[U] - lin.
@@ -171,49 +178,115 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   constexpr int VS = 8 * NC;  // variable stride in ch
   // deviation of a cell's centre value from the linearisation state, formed in FP64
   auto dev0 = [&](int var, int cell) { return R(c0[var * NC + cell] - lin64[var]); };
-  Acc<R> A = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  Acc<R> A = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
 
   if constexpr (KIND == KIND_K) {
-    // corner: for each of the four cells, the arc set where the circle lies in that cell
-    // (the intersection of the x-interval of its side with the y-interval of its side)
-    const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
-    const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
-    const R al = MA::acos_(cMx), be = MA::asin_(cMy);
-    const R twopi = R(2 * kPi);
-#pragma unroll 1
-    for (int q = 0; q < 4; ++q) {
-      const int sx = q & 1, sy = q >> 1;
-      // x interval of side sx: right (-al, al), left (al, 2pi - al)
-      const R a1 = sx ? -al : al, b1 = sx ? al : twopi - al;
-      const R sa1 = sx ? -sxx : sxx;  // sin at a1 (cos is cMx at both ends)
-      // y interval of side sy: top (be, pi - be), bottom (pi - be, 2pi + be)
-      const R a2 = sy ? be : pi - be, b2 = sy ? pi - be : twopi + be;
-      const R ca2 = sy ? syy : -syy;  // cos at a2 (sin is cMy at both ends)
-      Br<R> B;
-      br_zero(B);
-      // the intersection is made of the pieces I_x cap (I_y + 2 pi k), k = 0 and one k = +-1
-      const R kB = (sx == 0 && sy == 1) ? twopi : -twopi;
+    if constexpr (kCornerSplit<R>) {
+      // corner: the lower-left cell's polynomial P_LL on the full circle, plus (P_LR - P_LL) on
+      // the right half (cos > u'/c'), (P_UL - P_LL) on the upper half (sin > v'/c') and
+      // (P_UR - P_UL - P_LR + P_LL) on their intersection; in every cell the terms sum to the
+      // cell's own polynomial.  The two halves are symmetric arcs (half their moments vanish);
+      // only the upper-right arc set needs the general moments.
+      const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
+      const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
+      const R al = MA::acos_(cMx), be = MA::asin_(cMy);
+      const R Ly = pi - R(2) * be;
+      Mom<R> Mq;
+      {
+        // upper-right arc set: (-al, al) cap (be, pi - be), pieces for the shifts 0 and -2 pi
+        Br<R> B;
+        br_zero(B);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const R sh = t ? kB : R(0);
-        const R lo2 = a2 + sh, hi2 = b2 + sh;
-        const bool l1 = a1 >= lo2, h1 = b1 <= hi2;
-        const R lo = l1 ? a1 : lo2, hi = h1 ? b1 : hi2;
-        const R Ca = l1 ? cMx : ca2, Sa = l1 ? sa1 : cMy;
-        const R Cb = h1 ? cMx : -ca2, Sb = h1 ? -sa1 : cMy;
-        br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
+        for (int t = 0; t < 2; ++t) {
+          const R sh = t ? R(-2 * kPi) : R(0);
+          const R lo2 = be + sh, hi2 = pi - be + sh;
+          const bool l1 = -al >= lo2, h1 = al <= hi2;
+          const R lo = l1 ? -al : lo2, hi = h1 ? al : hi2;
+          const R Ca = l1 ? cMx : syy, Sa = l1 ? -sxx : cMy;
+          const R Cb = h1 ? cMx : -syy, Sb = h1 ? sxx : cMy;
+          br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
+        }
+        moments(B, Mq);
       }
-      Mom<R> M;
-      moments(B, M);
-      const int cell = cb + sx + sy * HC;
-      const R xi0 = px + R(0.5) - R(sx), eta0 = py + R(0.5) - R(sy);
-      R d[9];
-      circle_shift(dev0(3, cell), ch + 3 * VS + cell, NC, xi0, eta0, ax, by, d);
-      contract_p<0>(d, M, A);
-      circle_shift(dev0(1, cell), ch + 1 * VS + cell, NC, xi0, eta0, ax, by, d);
-      contract_u<0>(d, M, A);
-      circle_shift(dev0(2, cell), ch + 2 * VS + cell, NC, xi0, eta0, ax, by, d);
-      contract_v<0>(d, M, A);
+      const int cLL = cb, cLR = cb + 1, cUL = cb + HC, cUR = cb + HC + 1;
+      const R xl = px + R(0.5), xr = px - R(0.5), yb = py + R(0.5), yt = py - R(0.5);
+#pragma unroll
+      for (int var = 1; var < 4; ++var) {
+        // the half-circle moments are cheap: they are formed again for each variable (an
+        // empty asm keeps the compiler from hoisting them and holding 26 more registers)
+        R m1 = cMx, s1 = sxx, a1 = al, q2 = syy, w2 = cMy, l2 = Ly;
+        asm volatile("" : "+v"(m1), "+v"(s1), "+v"(a1), "+v"(q2), "+v"(w2), "+v"(l2));
+        R t[9], r[9], w[9];
+        Mom<R> Mx;
+        moments_sym_x(m1, s1, a1, Mx);
+        circle_shift(dev0(var, cLL), ch + var * VS + cLL, NC, xl, yb, ax, by, t);
+        circle_shift(dev0(var, cLR), ch + var * VS + cLR, NC, xr, yb, ax, by, r);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) w[i] = r[i] - t[i];  // P_LR - P_LL
+        if (var == 3) { full_p(t, A); contract_p<1>(w, Mx, A); }
+        if (var == 1) { full_u(t, A); contract_u<1>(w, Mx, A); }
+        if (var == 2) { full_v(t, A); contract_v<1>(w, Mx, A); }
+        circle_shift(dev0(var, cUL), ch + var * VS + cUL, NC, xl, yt, ax, by, w);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const R d = w[i] - t[i];  // P_UL - P_LL
+          w[i] = d;
+          r[i] += d;  // P_LR + P_UL - P_LL
+        }
+        Mom<R> My;
+        moments_sym_y(q2, w2, l2, My);
+        if (var == 3) contract_p<2>(w, My, A);
+        if (var == 1) contract_u<2>(w, My, A);
+        if (var == 2) contract_v<2>(w, My, A);
+        circle_shift(dev0(var, cUR), ch + var * VS + cUR, NC, xr, yt, ax, by, w);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) w[i] -= r[i];  // P_UR - P_UL - P_LR + P_LL
+        if (var == 3) contract_p<0>(w, Mq, A);
+        if (var == 1) contract_u<0>(w, Mq, A);
+        if (var == 2) contract_v<0>(w, Mq, A);
+      }
+    } else {
+      // corner: for each of the four cells, the arc set where the circle lies in that cell
+      // (the intersection of the x-interval of its side with the y-interval of its side)
+      const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
+      const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
+      const R al = MA::acos_(cMx), be = MA::asin_(cMy);
+      const R twopi = R(2 * kPi);
+#pragma unroll 1
+      for (int q = 0; q < 4; ++q) {
+        const int sx = q & 1, sy = q >> 1;
+        // x interval of side sx: right (-al, al), left (al, 2pi - al)
+        const R a1 = sx ? -al : al, b1 = sx ? al : twopi - al;
+        const R sa1 = sx ? -sxx : sxx;  // sin at a1 (cos is cMx at both ends)
+        // y interval of side sy: top (be, pi - be), bottom (pi - be, 2pi + be)
+        const R a2 = sy ? be : pi - be, b2 = sy ? pi - be : twopi + be;
+        const R ca2 = sy ? syy : -syy;  // cos at a2 (sin is cMy at both ends)
+        Br<R> B;
+        br_zero(B);
+        // the intersection is made of the pieces I_x cap (I_y + 2 pi k), k = 0 and one k = +-1
+        const R kB = (sx == 0 && sy == 1) ? twopi : -twopi;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const R sh = t ? kB : R(0);
+          const R lo2 = a2 + sh, hi2 = b2 + sh;
+          const bool l1 = a1 >= lo2, h1 = b1 <= hi2;
+          const R lo = l1 ? a1 : lo2, hi = h1 ? b1 : hi2;
+          const R Ca = l1 ? cMx : ca2, Sa = l1 ? sa1 : cMy;
+          const R Cb = h1 ? cMx : -ca2, Sb = h1 ? -sa1 : cMy;
+          br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
+        }
+        Mom<R> M;
+        moments(B, M);
+        const int cell = cb + sx + sy * HC;
+        const R xi0 = px + R(0.5) - R(sx), eta0 = py + R(0.5) - R(sy);
+        R d[9];
+        circle_shift(dev0(3, cell), ch + 3 * VS + cell, NC, xi0, eta0, ax, by, d);
+        contract_p<0>(d, M, A);
+        circle_shift(dev0(1, cell), ch + 1 * VS + cell, NC, xi0, eta0, ax, by, d);
+        contract_u<0>(d, M, A);
+        circle_shift(dev0(2, cell), ch + 2 * VS + cell, NC, xi0, eta0, ax, by, d);
+        contract_v<0>(d, M, A);
+      }
     }
   } else {
     // edge: the low-side cell on the full circle plus, on the high-side arc, the difference of
@@ -261,8 +334,10 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const R irc = qdiv(ic, rp);
   const R rc = rp * c;
   dU[0] = drP - R(2) * dpP * ic2 + ipi * (A.Ip * ic2 - rp * ic * A.Jr);
-  dU[1] = ipi * (A.Ju - A.IpC * irc);
-  dU[2] = ipi * (A.Jv - A.IpS * irc);
+  const R Ju = A.Ju0 + R(2) * A.Ua - R(0.5) * A.Ub;
+  const R Jv = A.Jv0 + R(2) * A.Va - R(0.5) * A.Vb;
+  dU[1] = ipi * (Ju - A.IpC * irc);
+  dU[2] = ipi * (Jv - A.IpS * irc);
   dU[3] = -dpP + ipi * (A.Ip - rc * A.Jr);
   return 0;
 }

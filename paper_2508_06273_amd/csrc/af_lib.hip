@@ -355,26 +355,26 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
   __syncthreads();
 }
 
-// Evolve the tile's own DOFs: wavefront 0 -> K, 1 -> X, 2 -> Y.  In the fix-up pass only the
-// lanes listed in `mask` (per kind) run.
+// Evolve the tile's own DOFs: wavefront 0 -> K; wavefront 1 -> X, then Y (an edge EG2 costs
+// well under half of a corner EG2, so the two waves are about equally loaded).  In the fix-up
+// pass only the lanes listed in `mask` (per kind) run.
 template <class R, bool FIX>
 __device__ __forceinline__ void evolve_tile(Smem<R>& S, const Params& P, const Bufs& B,
                                             DevState* dev, int tile, double dt,
                                             const unsigned long long* mask, double& speed) {
   const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
-  const int kind = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int a = lane % TILE, b = lane / TILE;
   const int gi = i0 + a, gj = j0 + b;
-  if (FIX && !((mask[kind] >> lane) & 1ull)) return;
-  if (kind == KIND_K) {
-    if (gi < P.nkx && gj < P.nky)
+  auto listed = [&](int kind) { return !FIX || ((mask[kind] >> lane) & 1ull); };
+  if (wave == 0) {
+    if (listed(KIND_K) && gi < P.nkx && gj < P.nky)
       evolve_dof<R, KIND_K, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
-  } else if (kind == KIND_X) {
-    if (gi < P.nkx && gj < P.ny)
-      evolve_dof<R, KIND_X, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
   } else {
-    if (gi < P.nx && gj < P.nky)
+    if (listed(KIND_X) && gi < P.nkx && gj < P.ny)
+      evolve_dof<R, KIND_X, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
+    if (listed(KIND_Y) && gi < P.nx && gj < P.nky)
       evolve_dof<R, KIND_Y, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
   }
 }
