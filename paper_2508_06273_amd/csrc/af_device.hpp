@@ -238,28 +238,31 @@ template <class T> __device__ __forceinline__ void nodes_to_monomials(const T W[
   }
 }
 
-// Substitute xi = xi0 + a C, eta = eta0 + b S into sum c_mn xi^m eta^n -> sum d_kl C^k S^l.
+// Substitute xi = xi0 + a C, eta = eta0 + a S into sum c_mn xi^m eta^n.  The result is
+// sum e_kl (aC)^k (aS)^l; the powers of the radius a are carried by the moments (see
+// scale_moments), so the substitution itself needs no multiplications by a.  Both local
+// coordinates are in units of dx (the y-coefficients are stored premultiplied by (dx/dy)^n).
 // c00 is the constant coefficient (already a deviation); `ch` points at c_01 of one variable
 // of one cell in LDS, the coefficients c_01 .. c_22 `stride` apart.
 template <class R>
 __device__ __forceinline__ void circle_shift(R c00, const R* __restrict__ ch, int stride, R xi0,
-                                             R eta0, R a, R b, R d[9]) {
+                                             R eta0, R d[9]) {
   R e[9];
-  const R a2 = a * a, b2 = b * b, x2 = xi0 + xi0, y2 = eta0 + eta0;
+  const R x2 = xi0 + xi0, y2 = eta0 + eta0;
 #pragma unroll
   for (int n = 0; n < 3; ++n) {
     R c0 = n == 0 ? c00 : ch[(n - 1) * stride];
     R c1 = ch[(3 + n - 1) * stride], c2 = ch[(6 + n - 1) * stride];
     e[0 * 3 + n] = c0 + xi0 * (c1 + xi0 * c2);
-    e[1 * 3 + n] = a * (c1 + x2 * c2);
-    e[2 * 3 + n] = a2 * c2;
+    e[1 * 3 + n] = c1 + x2 * c2;
+    e[2 * 3 + n] = c2;
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     R e0 = e[k * 3 + 0], e1 = e[k * 3 + 1], e2 = e[k * 3 + 2];
     d[k * 3 + 0] = e0 + eta0 * (e1 + eta0 * e2);
-    d[k * 3 + 1] = b * (e1 + y2 * e2);
-    d[k * 3 + 2] = b2 * e2;
+    d[k * 3 + 1] = e1 + y2 * e2;
+    d[k * 3 + 2] = e2;
   }
 }
 
@@ -274,12 +277,12 @@ __device__ __forceinline__ R poly_eval(R c00, const R* __restrict__ ch, int stri
 
 // Accumulators of the circle integrals of the deviations dp, du, dv from the linearisation
 // state:  Ip = int dp, IpC = int dp C, IpS = int dp S, Jr = int (du C + dv S),
-// Ju = int (du (2C^2 - 1/2) + 2 dv S C) = Ju0 + 2 Ua - Ub / 2,
-// Jv = int (2 du S C + dv (2 S^2 - 1/2)) = Jv0 + 2 Va - Vb / 2, where the arc contractions
-// accumulate Ua = int (du C^2 + dv S C), Ub = int du, Va = int (du S C + dv S^2), Vb = int dv
-// (no per-arc moment combinations) and the full-circle terms go to Ju0, Jv0 directly.
+// Ju = int (du (2C^2 - 1/2) + 2 dv S C) = 2 Ua - Ub / 2,
+// Jv = int (2 du S C + dv (2 S^2 - 1/2)) = 2 Va - Vb / 2, with Ua = int (du C^2 + dv S C),
+// Ub = int du, Va = int (du S C + dv S^2), Vb = int dv (no per-arc moment combinations).
+// With scaled moments IpC, IpS, Jr hold a times and Ua, Va a^2 times their values.
 template <class R> struct Acc {
-  R Ip, IpC, IpS, Jr, Ju0, Jv0, Ua, Ub, Va, Vb;
+  R Ip, IpC, IpS, Jr, Ua, Ub, Va, Vb;
 };
 
 // Arc (-alpha, alpha) from (m, -s) to (m, s), symmetric in S: the moments with odd b vanish.
@@ -324,10 +327,12 @@ __device__ __forceinline__ void moments_sym_y(R q, R w, R L, Mom<R>& M) {
   M.m[2][4] = (R(3) * M.m[2][2] + R(2) * q3w * w2) * i6;
 }
 
-// Per-variable contractions with the moments of one arc set.  SYM = 1 (odd-b moments zero)
-// or 2 (odd-a moments zero) drops the terms that vanish identically; SYM = 0 keeps all.
+// Per-variable contractions with the moments of one arc set.  SYM = 1 (odd-b moments zero),
+// 2 (odd-a moments zero) or 3 (full circle: both) drops the terms that vanish identically;
+// SYM = 0 keeps all.
 template <int SYM> __device__ __forceinline__ constexpr bool nz(int a, int b) {
-  return SYM == 1 ? (b % 2 == 0) : (SYM == 2 ? (a % 2 == 0) : true);
+  return SYM == 1 ? (b % 2 == 0)
+                  : (SYM == 2 ? (a % 2 == 0) : (SYM == 3 ? (a % 2 == 0 && b % 2 == 0) : true));
 }
 template <int SYM, class R>
 __device__ __forceinline__ void contract_p(const R d[9], const Mom<R>& M, Acc<R>& A) {
@@ -368,25 +373,36 @@ __device__ __forceinline__ void contract_v(const R d[9], const Mom<R>& M, Acc<R>
     }
 }
 
-// The same over the full circle (closed-form moments: int C^a S^b = 0 unless a, b are even;
-// 2pi, pi, pi, 3pi/4, pi/4, 3pi/4, pi/8, pi/8 for (0,0),(2,0),(0,2),(4,0),(2,2),(0,4),(4,2),(2,4)).
-template <class R> __device__ __forceinline__ void full_p(const R d[9], Acc<R>& A) {
-  const R pi = R(kPi);
-  A.Ip += R(2) * pi * d[0] + pi * (d[6] + d[2]) + R(0.25) * pi * d[8];
-  A.IpC += pi * d[3] + R(0.25) * pi * d[5];
-  A.IpS += pi * d[1] + R(0.25) * pi * d[7];
+// Moments of the scaled circle: M[i][j] <- a^(i+j) M[i][j] (the entries the contractions
+// read for the arc symmetry SYM).  Contracting these with the coefficients e of circle_shift
+// gives a times the true C-weighted and S-weighted integrals and a^2 times the quadratic
+// ones; the caller divides once at the end.
+template <int SYM, class R> __device__ __forceinline__ void scale_moments(Mom<R>& M, R a) {
+  R pw[7];
+  pw[0] = R(1);
+  pw[1] = a;
+  pw[2] = a * a;
+  pw[3] = pw[2] * a;
+  pw[4] = pw[2] * pw[2];
+  pw[5] = pw[4] * a;
+  pw[6] = pw[4] * pw[2];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+      if (i + j > 0 && i + j <= 6 && nz<SYM>(i, j)) M.m[i][j] *= pw[i + j];
 }
-template <class R> __device__ __forceinline__ void full_u(const R d[9], Acc<R>& A) {
-  const R pi = R(kPi);
-  A.Jr += pi * d[3] + R(0.25) * pi * d[5];
-  A.Ju0 += pi * (d[0] + d[6]) + R(0.125) * pi * d[8];
-  A.Jv0 += R(0.5) * pi * d[4];
-}
-template <class R> __device__ __forceinline__ void full_v(const R d[9], Acc<R>& A) {
-  const R pi = R(kPi);
-  A.Jr += pi * d[1] + R(0.25) * pi * d[7];
-  A.Ju0 += R(0.5) * pi * d[4];
-  A.Jv0 += pi * (d[0] + d[2]) + R(0.125) * pi * d[8];
+
+// Scaled moments of the full circle (SYM = 3: only even powers of C and S survive):
+// int C^a S^b over [0, 2pi] = 2pi, pi, pi, 3pi/4, pi/4, 3pi/4, pi/8, pi/8 for
+// (0,0),(2,0),(0,2),(4,0),(2,2),(0,4),(4,2),(2,4).
+template <class R> __device__ __forceinline__ void full_moments(Mom<R>& M, R a) {
+  const R pi = R(kPi), a2 = a * a, a4 = a2 * a2, a6 = a4 * a2;
+  M.m[0][0] = R(2) * pi;
+  M.m[2][0] = M.m[0][2] = pi * a2;
+  M.m[4][0] = M.m[0][4] = R(0.75) * pi * a4;
+  M.m[2][2] = R(0.25) * pi * a4;
+  M.m[4][2] = M.m[2][4] = R(0.125) * pi * a6;
 }
 
 }  // namespace af

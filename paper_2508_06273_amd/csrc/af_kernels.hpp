@@ -140,8 +140,10 @@ template <class R> struct Smem {
 __device__ __forceinline__ int sidx(int a, int b) { return (a + 1) + (b + 1) * HS; }
 __device__ __forceinline__ int cidx(int a, int b) { return (a + 1) + (b + 1) * HC; }
 
+// idx = 1/dx; hy = dy / (2 dx): half a cell in y in units of dx (the local frame of the circle
+// integrals uses dx in both directions).
 template <class R> struct Geo {
-  R idx, idy, gamma, half_h;
+  R idx, hy, gamma, half_h;
 };
 
 // a / b in the bulk precision: IEEE division in FP64, hardware reciprocal (1 ulp) in FP32
@@ -171,14 +173,18 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const R c = MA::sqrt_(qdiv(G.gamma * pp, rp));
   if ((mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * tau >= G.half_h) return ERR_CFL;
   const R ic = qdiv(R(1), c);
-  const R px = -up * tau * G.idx, py = -vp * tau * G.idy;
-  const R ax = c * tau * G.idx, by = c * tau * G.idy;
+  // foot point offset and circle radius in units of dx
+  const R px = -up * tau * G.idx, py = -vp * tau * G.idx;
+  const R ar = c * tau * G.idx;
+  const R hy = G.hy;
   const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
   const R pi = R(kPi);
   constexpr int VS = 8 * NC;  // variable stride in ch
   // deviation of a cell's centre value from the linearisation state, formed in FP64
   auto dev0 = [&](int var, int cell) { return R(c0[var * NC + cell] - lin64[var]); };
-  Acc<R> A = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+  Acc<R> A = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+  Mom<R> Mf;
+  full_moments(Mf, ar);
 
   if constexpr (KIND == KIND_K) {
     if constexpr (kCornerSplit<R>) {
@@ -207,26 +213,28 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
           br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
         }
         moments(B, Mq);
+        scale_moments<0>(Mq, ar);
       }
       const int cLL = cb, cLR = cb + 1, cUL = cb + HC, cUR = cb + HC + 1;
-      const R xl = px + R(0.5), xr = px - R(0.5), yb = py + R(0.5), yt = py - R(0.5);
+      const R xl = px + R(0.5), xr = px - R(0.5), yb = py + hy, yt = py - hy;
 #pragma unroll
       for (int var = 1; var < 4; ++var) {
         // the half-circle moments are cheap: they are formed again for each variable (an
         // empty asm keeps the compiler from hoisting them and holding 26 more registers)
-        R m1 = cMx, s1 = sxx, a1 = al, q2 = syy, w2 = cMy, l2 = Ly;
-        asm volatile("" : "+v"(m1), "+v"(s1), "+v"(a1), "+v"(q2), "+v"(w2), "+v"(l2));
+        R m1 = cMx, s1 = sxx, a1 = al, q2 = syy, w2 = cMy, l2 = Ly, r1 = ar;
+        asm volatile("" : "+v"(m1), "+v"(s1), "+v"(a1), "+v"(q2), "+v"(w2), "+v"(l2), "+v"(r1));
         R t[9], r[9], w[9];
         Mom<R> Mx;
         moments_sym_x(m1, s1, a1, Mx);
-        circle_shift(dev0(var, cLL), ch + var * VS + cLL, NC, xl, yb, ax, by, t);
-        circle_shift(dev0(var, cLR), ch + var * VS + cLR, NC, xr, yb, ax, by, r);
+        scale_moments<1>(Mx, r1);
+        circle_shift(dev0(var, cLL), ch + var * VS + cLL, NC, xl, yb, t);
+        circle_shift(dev0(var, cLR), ch + var * VS + cLR, NC, xr, yb, r);
 #pragma unroll
         for (int i = 0; i < 9; ++i) w[i] = r[i] - t[i];  // P_LR - P_LL
-        if (var == 3) { full_p(t, A); contract_p<1>(w, Mx, A); }
-        if (var == 1) { full_u(t, A); contract_u<1>(w, Mx, A); }
-        if (var == 2) { full_v(t, A); contract_v<1>(w, Mx, A); }
-        circle_shift(dev0(var, cUL), ch + var * VS + cUL, NC, xl, yt, ax, by, w);
+        if (var == 3) { contract_p<3>(t, Mf, A); contract_p<1>(w, Mx, A); }
+        if (var == 1) { contract_u<3>(t, Mf, A); contract_u<1>(w, Mx, A); }
+        if (var == 2) { contract_v<3>(t, Mf, A); contract_v<1>(w, Mx, A); }
+        circle_shift(dev0(var, cUL), ch + var * VS + cUL, NC, xl, yt, w);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
           const R d = w[i] - t[i];  // P_UL - P_LL
@@ -235,10 +243,11 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
         }
         Mom<R> My;
         moments_sym_y(q2, w2, l2, My);
+        scale_moments<2>(My, r1);
         if (var == 3) contract_p<2>(w, My, A);
         if (var == 1) contract_u<2>(w, My, A);
         if (var == 2) contract_v<2>(w, My, A);
-        circle_shift(dev0(var, cUR), ch + var * VS + cUR, NC, xr, yt, ax, by, w);
+        circle_shift(dev0(var, cUR), ch + var * VS + cUR, NC, xr, yt, w);
 #pragma unroll
         for (int i = 0; i < 9; ++i) w[i] -= r[i];  // P_UR - P_UL - P_LR + P_LL
         if (var == 3) contract_p<0>(w, Mq, A);
@@ -277,14 +286,15 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
         }
         Mom<R> M;
         moments(B, M);
+        scale_moments<0>(M, ar);
         const int cell = cb + sx + sy * HC;
-        const R xi0 = px + R(0.5) - R(sx), eta0 = py + R(0.5) - R(sy);
+        const R xi0 = px + R(0.5) - R(sx), eta0 = py + (sy ? -hy : hy);
         R d[9];
-        circle_shift(dev0(3, cell), ch + 3 * VS + cell, NC, xi0, eta0, ax, by, d);
+        circle_shift(dev0(3, cell), ch + 3 * VS + cell, NC, xi0, eta0, d);
         contract_p<0>(d, M, A);
-        circle_shift(dev0(1, cell), ch + 1 * VS + cell, NC, xi0, eta0, ax, by, d);
+        circle_shift(dev0(1, cell), ch + 1 * VS + cell, NC, xi0, eta0, d);
         contract_u<0>(d, M, A);
-        circle_shift(dev0(2, cell), ch + 2 * VS + cell, NC, xi0, eta0, ax, by, d);
+        circle_shift(dev0(2, cell), ch + 2 * VS + cell, NC, xi0, eta0, d);
         contract_v<0>(d, M, A);
       }
     }
@@ -296,27 +306,29 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
     if constexpr (KIND == KIND_X) {
       const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
       moments_sym_x(cMx, sxx, MA::acos_(cMx), M);
+      scale_moments<1>(M, ar);
     } else {
       const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
       moments_sym_y(syy, cMy, pi - R(2) * MA::asin_(cMy), M);
+      scale_moments<2>(M, ar);
     }
     const int cl = cb, chh = cb + (KIND == KIND_X ? 1 : HC);
     const R xl = (KIND == KIND_X) ? px + R(0.5) : px;
-    const R yl = (KIND == KIND_X) ? py : py + R(0.5);
+    const R yl = (KIND == KIND_X) ? py : py + hy;
     const R xh = (KIND == KIND_X) ? px - R(0.5) : px;
-    const R yh = (KIND == KIND_X) ? py : py - R(0.5);
+    const R yh = (KIND == KIND_X) ? py : py - hy;
     constexpr int SYM = (KIND == KIND_X) ? 1 : 2;
 #pragma unroll
     for (int var = 1; var < 4; ++var) {
       R lo[9], hi[9];
       const R dl = dev0(var, cl);
-      circle_shift(dl, ch + var * VS + cl, NC, xl, yl, ax, by, lo);
-      circle_shift(dev0(var, chh), ch + var * VS + chh, NC, xh, yh, ax, by, hi);
+      circle_shift(dl, ch + var * VS + cl, NC, xl, yl, lo);
+      circle_shift(dev0(var, chh), ch + var * VS + chh, NC, xh, yh, hi);
 #pragma unroll
       for (int i = 0; i < 9; ++i) hi[i] -= lo[i];
-      if (var == 3) { full_p(lo, A); contract_p<SYM>(hi, M, A); }
-      if (var == 1) { full_u(lo, A); contract_u<SYM>(hi, M, A); }
-      if (var == 2) { full_v(lo, A); contract_v<SYM>(hi, M, A); }
+      if (var == 3) { contract_p<3>(lo, Mf, A); contract_p<SYM>(hi, M, A); }
+      if (var == 1) { contract_u<3>(lo, Mf, A); contract_u<SYM>(hi, M, A); }
+      if (var == 2) { contract_v<3>(lo, Mf, A); contract_v<SYM>(hi, M, A); }
     }
   }
 
@@ -325,20 +337,23 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const int syP = (KIND == KIND_X) ? 0 : (vp <= R(0) ? 1 : 0);
   const int cellP = cb + sxP + syP * HC;
   const R xiP = (KIND == KIND_Y) ? px : px + R(0.5) - R(sxP);
-  const R etaP = (KIND == KIND_X) ? py : py + R(0.5) - R(syP);
+  const R etaP = (KIND == KIND_X) ? py : py + (syP ? -hy : hy);
   const R drP = poly_eval(dev0(0, cellP), ch + 0 * VS + cellP, NC, xiP, etaP);
   const R dpP = poly_eval(dev0(3, cellP), ch + 3 * VS + cellP, NC, xiP, etaP);
 
+  // undo the moment scaling: first-order integrals carry a factor ar, second-order ar^2
+  const R ia = qdiv(R(1), ar), ia2 = ia * ia;
+  const R IpC = A.IpC * ia, IpS = A.IpS * ia, Jr = A.Jr * ia;
+  const R Ju = R(2) * A.Ua * ia2 - R(0.5) * A.Ub;
+  const R Jv = R(2) * A.Va * ia2 - R(0.5) * A.Vb;
   const R ipi = R(1.0 / kPi);
   const R ic2 = ic * ic;
   const R irc = qdiv(ic, rp);
   const R rc = rp * c;
-  dU[0] = drP - R(2) * dpP * ic2 + ipi * (A.Ip * ic2 - rp * ic * A.Jr);
-  const R Ju = A.Ju0 + R(2) * A.Ua - R(0.5) * A.Ub;
-  const R Jv = A.Jv0 + R(2) * A.Va - R(0.5) * A.Vb;
-  dU[1] = ipi * (Ju - A.IpC * irc);
-  dU[2] = ipi * (Jv - A.IpS * irc);
-  dU[3] = -dpP + ipi * (A.Ip - rc * A.Jr);
+  dU[0] = drP - R(2) * dpP * ic2 + ipi * (A.Ip * ic2 - rp * ic * Jr);
+  dU[1] = ipi * (Ju - IpC * irc);
+  dU[2] = ipi * (Jv - IpS * irc);
+  dU[3] = -dpP + ipi * (A.Ip - rc * Jr);
   return 0;
 }
 

@@ -61,7 +61,7 @@ template <class R, int KIND, bool FIX>
 __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bufs& B,
                                            DevState* dev, int tile, int a, int b, int gi,
                                            int gj, double dt, double& speed) {
-  const Geo<R> G = {R(P.idx), R(P.idy), R(P.gamma), R(0.5 * P.hmin)};
+  const Geo<R> G = {R(P.idx), R(0.5 * P.dy * P.idx), R(P.gamma), R(0.5 * P.hmin)};
   const double* site = (KIND == KIND_K) ? S.sk : (KIND == KIND_X ? S.sx : S.sy);
   const int s0 = sidx(a, b);
   double U0[4];
@@ -334,6 +334,7 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
       const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
       if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
     }
+    const double rho = P.dx / P.dy, rho2 = rho * rho;
     // primitive Simpson average and monomial coefficients, one variable at a time
 #pragma unroll 1
     for (int v = 0; v < 4; ++v) {
@@ -348,8 +349,12 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
       double cm[9];
       nodes_to_monomials(N, cm);
       S.c0[v * NC + c] = cm[0];
+      // c_mn of xi^m eta^n -> coefficient of xi^m (eta dy/dx)^n: the circle integrals use
+      // dx as the unit length in both directions
 #pragma unroll
-      for (int k = 1; k < 9; ++k) S.ch[(v * 8 + k - 1) * NC + c] = (R)cm[k];
+      for (int k = 1; k < 9; ++k)
+        S.ch[(v * 8 + k - 1) * NC + c] = (R)(k % 3 == 0 ? cm[k] : (k % 3 == 1 ? cm[k] * rho
+                                                                              : cm[k] * rho2));
     }
   }
   __syncthreads();
