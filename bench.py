@@ -34,24 +34,33 @@ PEAK_FP32 = 157.3  # TFLOP/s, MI355X vector FP32 (published)
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
 
 # ------------------------------------------------------------------------------------------
-# Algorithmic FLOPs of the point-value kernel per cell and step (FMA = 2, other arithmetic
-# = 1, sqrt/div/acos/asin = 1), counted from the exact-moment formulation:
-#   EG2 at a corner    : 4 cells x (moment recurrence 43 + 3 shifts 156 + 3 contractions 234
-#                        + 3) + 4 arc pieces x 92 + set-up, foot point and outputs 87 = 2199
-#   EG2 at an edge     : 1 arc piece 92 + moments 43 + 6 shifts 312 + differences 30
-#                        + full-circle terms 32 + contractions 234 + the rest 77    =  820
-#   per DOF            : derivatives, correction, assembly ~110; Simpson-in-time fluxes 102
-#   per cell           : inverse Simpson, centre value, Simpson average, monomials  ~400
+# Algorithmic FLOPs of the point kernel per cell and step (add, sub, mul, div, sqrt, acos,
+# asin = 1; FMA = 2), counted operation by operation from the exact-moment formulation that
+# each path evaluates, for the generic subsonic DOF (one arc piece per arc set):
+#   EG2 set-up, foot point and outputs                                   82
+#   corner, FP32 (full circle + two half circles + one quadrant arc set) 1689
+#   corner, FP64 (one general arc set per cell, four cells)              2006
+#   x-edge (full circle + one half circle)                                579
+#   y-edge                                                                584
+#   per DOF: derivatives 16, correction 74, assembly 31, Simpson-in-time
+#            fluxes 54 + sums (K 32, X/Y 16), wave speed 4               213 / 197 / 197
+#   per cell: inverse Simpson 197, centre value 25, Simpson average 72,
+#             monomials 120 + aspect 24, constants 2                       440
+# (the EG2 figures include the set-up).  Algorithm 1 evaluates EG2 three times per DOF, the
+# averaged linearisation twice (plus 32 for the mean of the adjacent averages).
 # ------------------------------------------------------------------------------------------
-EG2_K, EG2_EDGE = 2199, 820
-PER_DOF, PER_CELL = 110 + 102, 400
-UPDATE_PER_CELL = 84
+EG2_K = {"fp32": 1689, "fp64": 2006}
+EG2_X, EG2_Y = 579, 584
+PER_DOF = 213 + 197 + 197
+PER_CELL = 440
+PEAK_NONPACKED = 78.6  # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
 
-def flops_per_cell(mode: int) -> float:
+def flops_per_cell(mode: int, prec: str) -> float:
     """Algorithmic FLOPs of the point kernel per cell-step (3 DOFs per cell)."""
-    rounds = 3 if mode == 0 else 2  # Algorithm 1 evaluates EG2 three times per DOF
-    return rounds * (EG2_K + 2 * EG2_EDGE) + 3 * PER_DOF + PER_CELL
+    rounds = 3 if mode == 0 else 2
+    extra = 0 if mode == 0 else 32
+    return rounds * (EG2_K[prec] + EG2_X + EG2_Y) + PER_DOF + PER_CELL + extra
 
 
 def source_hash() -> str:
@@ -75,6 +84,52 @@ def traffic_record(kernel: str, workload: str):
     if not r or r.get("source_sha") != source_hash():
         return None
     return r
+
+
+def _counter_means(db: str, counter: str):
+    """Mean value of one rocprofv3 counter per kernel name (rocpd SQLite output)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    cols = [d[0] for d in cur.execute("select * from counters_collection limit 1").description]
+    acc = {}
+    for row in cur.execute("select * from counters_collection"):
+        d = dict(zip(cols, row))
+        if d["counter_name"] == counter:
+            acc.setdefault(d["kernel_name"], []).append(float(d["value"]))
+    con.close()
+    return acc
+
+
+def record_traffic(fetch_db: str, write_db: str, copy_mib: int, n: int):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, in
+    KiB per dispatch) of `bench.py --calibrate-copy MIB`: each counter is scaled by what it
+    reads for the elementwise copy kernel, which reads and writes exactly MIB MiB."""
+    fetch = _counter_means(fetch_db, "FETCH_SIZE")
+    write = _counter_means(write_db, "WRITE_SIZE")
+    nb_kib = copy_mib * 1024.0
+    cf = max(v for k, vals in fetch.items() if "elementwise" in k for v in vals)
+    cw = max(v for k, vals in write.items() if "elementwise" in k for v in vals)
+    sf, sw = nb_kib / cf, nb_kib / cw
+    out = {"_calibration": {"copy_kib": nb_kib, "fetch_kib_read": cf, "write_kib_read": cw,
+                            "fetch_scale": sf, "write_scale": sw}}
+    for prec in ("f32", "f64"):
+        for kname in ("k_points", "k_update"):
+            kf = [v for k, vals in fetch.items() if f"{kname}_{prec}" in k or
+                  (kname == "k_update" and "k_update" in k) for v in vals]
+            kw = [v for k, vals in write.items() if f"{kname}_{prec}" in k or
+                  (kname == "k_update" and "k_update" in k) for v in vals]
+            if not kf or not kw:
+                continue
+            f_kib, w_kib = sum(kf) / len(kf), sum(kw) / len(kw)
+            b = (f_kib * sf + w_kib * sw) * 1024.0
+            out[f"{kname}|vortex{n}_fp{prec[1:]}"] = {
+                "bytes_per_launch": round(b), "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
+                "source_sha": source_hash()}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1, sort_keys=True))
 
 
 def run_gpu(st, prec, steps, warmup, stream):
@@ -139,7 +194,14 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="profiling aid: also run a plain device copy of MIB MiB (the "
                          "reference kernel for the HBM byte counters)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="profiling aid: write profiles/traffic.json from two rocprofv3 --pmc "
+                         "result databases of a --calibrate-copy run, then exit")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args.record_traffic[0], args.record_traffic[1],
+                       args.calibrate_copy or 1024, args.n)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs the Active Flux step on one GPU only; "
@@ -181,7 +243,6 @@ def main():
                   f"{r['ms_points']:.3f} ms, k_update {r['ms_update']:.3f} ms", file=sys.stderr)
         return
     cells = n * n
-    fpc = flops_per_cell(0)
     out = {}
     for name, r in res.items():
         r["value"] = r["dofs"] * args.steps / (r["ms_total"] * 1e-3)
@@ -204,13 +265,15 @@ def main():
 
     def roofline(name, peak):
         r = res[name]
+        fpc = flops_per_cell(0, name)
         achieved = fpc * cells / (r["ms_points"] * 1e-3) / 1e12
         rec = traffic_record("k_points", f"vortex{n}_{name}")
         traffic = None if rec is None else rec["bytes_per_launch"]
         return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "k_points", "kernel_ms": round(r["ms_points"], 4),
-                "flops_per_cell": fpc}
+                "flops_per_cell": fpc,
+                "frac_of_nonpacked_issue_peak": round(achieved / PEAK_NONPACKED, 4)}
 
     line = {
         "metric": METRIC,

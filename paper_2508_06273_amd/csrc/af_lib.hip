@@ -384,12 +384,22 @@ __device__ __forceinline__ void evolve_tile(Smem<R>& S, const Params& P, const B
   }
 }
 
+// Workgroups are dealt to the eight XCDs in turn (block b to XCD b mod 8), and each XCD has its
+// own L2.  Giving XCD x the contiguous tile range [x * ntiles/8, (x+1) * ntiles/8), in row
+// order, keeps the halos that neighbouring tiles share in one L2.  A bijection on the tile
+// indices (the last ntiles mod 8 tiles map to themselves).
+__device__ __forceinline__ int tile_of_block(int b, int ntiles) {
+  const int per = ntiles >> 3;
+  if (b >= (per << 3)) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
 template <class R>
 __device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const Bufs& B,
                                             DevState* dev, double dt_host, int slot) {
   double dt;
   if (!step_dt(P, dev, dt_host, slot, &dt)) return;
-  const int tile = blockIdx.x;
+  const int tile = tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y);
   stage_and_prep(S, P, B, dev, tile, true);
   double speed = 0.0;
   evolve_tile<R, false>(S, P, B, dev, tile, dt, nullptr, speed);
@@ -613,6 +623,7 @@ struct af_handle {
   std::vector<hipEvent_t> ev;  // 3 per step: before points, between, after update
   double ms_points = 0.0, ms_update = 0.0;
   long long timed_steps = 0;
+  double* stage = nullptr;  // pinned host staging buffer of host <-> device copies
   std::string err;
 };
 
@@ -632,7 +643,6 @@ static int fail(const af_handle* h, int code, const std::string& msg) {
                   std::string(#call) + ": " + hipGetErrorString(e_));                \
   } while (0)
 
-static size_t rsize(const af_handle*) { return 8; }  // point values are stored in FP64
 
 static Params make_params(const af_handle* h) {
   Params P;
@@ -679,9 +689,9 @@ static int alloc_buffers(af_handle* h) {
   const size_t nf = (size_t)h->pF * h->nky;
   for (int k = 0; k < 2; ++k) {
     HIP_OK(hipMalloc(&h->A[k], na * 8), h);
-    HIP_OK(hipMalloc(&h->K[k], np * rsize(h)), h);
-    HIP_OK(hipMalloc(&h->X[k], np * rsize(h)), h);
-    HIP_OK(hipMalloc(&h->Y[k], np * rsize(h)), h);
+    HIP_OK(hipMalloc(&h->K[k], np * sizeof(double)), h);
+    HIP_OK(hipMalloc(&h->X[k], np * sizeof(double)), h);
+    HIP_OK(hipMalloc(&h->Y[k], np * sizeof(double)), h);
   }
   HIP_OK(hipMalloc(&h->FK, nf * 8 * 8), h);
   HIP_OK(hipMalloc(&h->FX, nf * 4 * 8), h);
@@ -749,6 +759,7 @@ extern "C" void af_destroy(af_handle* h) {
   free_buffers(h);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->dev) (void)hipFree(h->dev);
+  if (h->stage) (void)hipHostFree(h->stage);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   delete h;
 }
@@ -812,64 +823,53 @@ extern "C" int af_set_stream(af_handle* h, void* s) {
   return AF_OK;
 }
 
-// One variable: host FP64 rows x cols (unpadded) <-> device rows x cols with row pitch
-// `pitch` elements of `real_bytes` each.
-static int upload(af_handle* h, void* dst, long long pitch, int rows, int cols, int real_bytes,
-                  const double* src) {
-  if (cols > pitch) return fail(h, AF_ERR_INVALID_ARG, "upload: cols exceed pitch");
-  const size_t n = (size_t)rows * cols;
-  if (real_bytes == 8) {
-    HIP_OK(hipMemcpy2DAsync(dst, pitch * 8, src, (size_t)cols * 8, (size_t)cols * 8,
-                            (size_t)rows, hipMemcpyHostToDevice, h->stream), h);
-    HIP_OK(hipStreamSynchronize(h->stream), h);
-  } else {
-    std::vector<float> tmp(n);
-    for (size_t k = 0; k < n; ++k) tmp[k] = (float)src[k];
-    HIP_OK(hipMemcpy2DAsync(dst, pitch * 4, tmp.data(), (size_t)cols * 4, (size_t)cols * 4,
-                            (size_t)rows, hipMemcpyHostToDevice, h->stream), h);
-    HIP_OK(hipStreamSynchronize(h->stream), h);
+// Host <-> device copies go through a pinned staging buffer, in blocks of whole rows: one
+// 2D copy per block between the padded device rows and the staging buffer, one memcpy between
+// the staging buffer and the caller's array.  Synchronous on the handle's stream.
+constexpr size_t STAGE_BYTES = 8u << 20;
+
+static int ensure_stage(const af_handle* hc) {
+  af_handle* h = const_cast<af_handle*>(hc);
+  if (!h->stage) HIP_OK(hipHostMalloc((void**)&h->stage, STAGE_BYTES, hipHostMallocDefault), h);
+  return AF_OK;
+}
+
+// One variable: host FP64 rows x cols (unpadded, row-major) <-> device FP64 rows x cols with
+// a row pitch of `pitch` elements.
+static int copy2d(const af_handle* h, bool to_device, double* dev, long long pitch, int rows,
+                  int cols, double* host) {
+  if (cols > pitch) return fail(h, AF_ERR_INVALID_ARG, "copy2d: cols exceed pitch");
+  if (int e = ensure_stage(h)) return e;
+  const size_t row_bytes = (size_t)cols * 8;
+  const int block = (int)std::max<size_t>(1, STAGE_BYTES / row_bytes);
+  for (int r0 = 0; r0 < rows; r0 += block) {
+    const int nr = std::min(block, rows - r0);
+    double* d = dev + (size_t)r0 * pitch;
+    double* hst = host + (size_t)r0 * cols;
+    if (to_device) {
+      std::memcpy(h->stage, hst, (size_t)nr * row_bytes);
+      HIP_OK(hipMemcpy2DAsync(d, pitch * 8, h->stage, row_bytes, row_bytes, (size_t)nr,
+                              hipMemcpyHostToDevice, h->stream), h);
+      HIP_OK(hipStreamSynchronize(h->stream), h);
+    } else {
+      HIP_OK(hipMemcpy2DAsync(h->stage, row_bytes, d, pitch * 8, row_bytes, (size_t)nr,
+                              hipMemcpyDeviceToHost, h->stream), h);
+      HIP_OK(hipStreamSynchronize(h->stream), h);
+      std::memcpy(hst, h->stage, (size_t)nr * row_bytes);
+    }
   }
   return AF_OK;
 }
 
-static int download(const af_handle* h, const void* src, long long pitch, int rows, int cols,
-                    int real_bytes, double* dst) {
-  if (cols > pitch) return fail(h, AF_ERR_INVALID_ARG, "download: cols exceed pitch");
-  const size_t n = (size_t)rows * cols;
-  if (real_bytes == 8) {
-    HIP_OK(hipMemcpy2DAsync(dst, (size_t)cols * 8, src, pitch * 8, (size_t)cols * 8,
-                            (size_t)rows, hipMemcpyDeviceToHost, h->stream), h);
-    HIP_OK(hipStreamSynchronize(h->stream), h);
-  } else {
-    std::vector<float> tmp(n);
-    HIP_OK(hipMemcpy2DAsync(tmp.data(), (size_t)cols * 4, src, pitch * 4, (size_t)cols * 4,
-                            (size_t)rows, hipMemcpyDeviceToHost, h->stream), h);
-    HIP_OK(hipStreamSynchronize(h->stream), h);
-    for (size_t k = 0; k < n; ++k) dst[k] = (double)tmp[k];
-  }
-  return AF_OK;
-}
-
-// The padded arrays store variable v at offset v * rows * pitch: copy one variable at a time.
-static int upload4(af_handle* h, void* dst, long long pitch, int rows_alloc, int rows, int cols,
-                   const double* src) {
-  if (rows > rows_alloc) return fail(h, AF_ERR_INVALID_ARG, "upload4: rows exceed allocation");
-  const int rb = (int)rsize(h);
+// The padded arrays store variable v at offset v * rows_alloc * pitch: copy one variable at a
+// time.
+static int copy4(const af_handle* h, bool to_device, void* dev, long long pitch, int rows_alloc,
+                 int rows, int cols, double* host) {
+  if (rows > rows_alloc) return fail(h, AF_ERR_INVALID_ARG, "copy4: rows exceed allocation");
   for (int v = 0; v < 4; ++v) {
-    char* d = (char*)dst + (size_t)v * rows_alloc * pitch * rb;
-    int e = upload(h, d, pitch, rows, cols, rb, src + (size_t)v * rows * cols);
-    if (e) return e;
-  }
-  return AF_OK;
-}
-static int download4(const af_handle* h, const void* src, long long pitch, int rows_alloc,
-                     int rows, int cols, double* dst) {
-  if (rows > rows_alloc) return fail(h, AF_ERR_INVALID_ARG, "download4: rows exceed allocation");
-  const int rb = (int)rsize(h);
-  for (int v = 0; v < 4; ++v) {
-    const char* s = (const char*)src + (size_t)v * rows_alloc * pitch * rb;
-    int e = download(h, s, pitch, rows, cols, rb, dst + (size_t)v * rows * cols);
-    if (e) return e;
+    double* d = (double*)dev + (size_t)v * rows_alloc * pitch;
+    if (int e = copy2d(h, to_device, d, pitch, rows, cols, host + (size_t)v * rows * cols))
+      return e;
   }
   return AF_OK;
 }
@@ -887,15 +887,15 @@ extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, co
       return fail(h, AF_ERR_NONPHYSICAL, "af_set_state: non-admissible cell average");
   }
   h->cur = 0;
-  // averages: 4 x ny x nx
-  for (int v = 0; v < 4; ++v)
-    HIP_OK(hipMemcpy2DAsync(h->A[0] + (size_t)v * h->pA * h->ny, h->pA * 8, avg + v * nc,
-                            (size_t)h->nx * 8, (size_t)h->nx * 8, h->ny, hipMemcpyHostToDevice,
-                            h->stream), h);
   int e;
-  if ((e = upload4(h, h->K[0], h->pP, h->nky, h->nky, h->nkx, K))) return e;
-  if ((e = upload4(h, h->X[0], h->pP, h->nky, h->ny, h->nkx, X))) return e;
-  if ((e = upload4(h, h->Y[0], h->pP, h->nky, h->nky, h->nx, Y))) return e;
+  if ((e = copy4(h, true, h->A[0], h->pA, h->ny, h->ny, h->nx, const_cast<double*>(avg))))
+    return e;
+  if ((e = copy4(h, true, h->K[0], h->pP, h->nky, h->nky, h->nkx, const_cast<double*>(K))))
+    return e;
+  if ((e = copy4(h, true, h->X[0], h->pP, h->nky, h->ny, h->nkx, const_cast<double*>(X))))
+    return e;
+  if ((e = copy4(h, true, h->Y[0], h->pP, h->nky, h->nky, h->nx, const_cast<double*>(Y))))
+    return e;
   DevState ds;
   std::memset(&ds, 0, sizeof(ds));
   ds.t = t;
@@ -912,18 +912,11 @@ extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* 
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_get_state: NULL handle");
   if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_get_state: no state set");
   const int c = h->cur;
-  const size_t nc = (size_t)h->nx * h->ny;
-  if (avg) {
-    for (int v = 0; v < 4; ++v)
-      HIP_OK(hipMemcpy2DAsync(avg + v * nc, (size_t)h->nx * 8,
-                              h->A[c] + (size_t)v * h->pA * h->ny, h->pA * 8,
-                              (size_t)h->nx * 8, h->ny, hipMemcpyDeviceToHost, h->stream), h);
-    HIP_OK(hipStreamSynchronize(h->stream), h);
-  }
   int e;
-  if (K && (e = download4(h, h->K[c], h->pP, h->nky, h->nky, h->nkx, K))) return e;
-  if (X && (e = download4(h, h->X[c], h->pP, h->nky, h->ny, h->nkx, X))) return e;
-  if (Y && (e = download4(h, h->Y[c], h->pP, h->nky, h->nky, h->nx, Y))) return e;
+  if (avg && (e = copy4(h, false, h->A[c], h->pA, h->ny, h->ny, h->nx, avg))) return e;
+  if (K && (e = copy4(h, false, h->K[c], h->pP, h->nky, h->nky, h->nkx, K))) return e;
+  if (X && (e = copy4(h, false, h->X[c], h->pP, h->nky, h->ny, h->nkx, X))) return e;
+  if (Y && (e = copy4(h, false, h->Y[c], h->pP, h->nky, h->nky, h->nx, Y))) return e;
   if (t) {
     DevState ds;
     HIP_OK(hipMemcpyAsync(&ds, h->dev, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
