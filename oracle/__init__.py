@@ -78,6 +78,9 @@ def lib():
             L.or_dof_update.argtypes = [P, _D, _D, _D, _D, ct.c_int, ct.c_int, ct.c_int,
                                         ct.c_double, _D, _D, _LL]
             L.or_dof_update.restype = ct.c_int
+            L.or_lf_point.argtypes = [P, _D, _D, _D, _D, ct.c_int, ct.c_int, ct.c_int,
+                                      ct.c_double, _D]
+            L.or_lf_point.restype = ct.c_int
             L.or_eg_cb.argtypes = [ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.c_int, _D,
                                    ct.c_double, ct.c_double, FIELD_CB, ct.c_int, _D]
             L.or_eg_cb.restype = ct.c_int
@@ -201,6 +204,16 @@ def dof_update(state, kind, ci, cj, dt, **kw):
     e = lib().or_dof_update(ct.byref(c), _p(A), _p(K), _p(X), _p(Y), kind, ci, cj, float(dt),
                             _p(h), _p(f), cnt.ctypes.data_as(_LL))
     return e, h, f, cnt
+
+
+def lf_point(state, kind, ci, cj, tau, **kw):
+    """Lax-Friedrichs point update of one DOF (the last branch of Algorithm 3)."""
+    c = cfg_for(state, **kw)
+    A, K, X, Y = _arrays(state)
+    o = np.zeros(4)
+    e = lib().or_lf_point(ct.byref(c), _p(A), _p(K), _p(X), _p(Y), kind, ci, cj, float(tau),
+                          _p(o))
+    return e, o
 
 
 def eg_field(order, xb, yb, vline, hline, lin, tau, field, gamma=1.4, gl_n=10):

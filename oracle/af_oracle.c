@@ -801,6 +801,15 @@ int or_dof_update(const or_cfg* c, const double* A, const double* K, const doubl
   return e;
 }
 
+int or_lf_point(const or_cfg* c, const double* A, const double* K, const double* X,
+                const double* Y, int kind, int ci, int cj, double tau, double out[4]) {
+  ctx C;
+  int e = ctx_init(&C, c, A, K, X, Y);
+  if (e == OR_OK) dof_lf(&C, kind, ci, cj, tau, out);
+  ctx_free(&C);
+  return e;
+}
+
 int or_eg_cb(int order, double xb, double yb, int vline, int hline, const double lin[4],
              double tau, double gamma, or_field_cb cb, int gl_n, double out[4]) {
   double glx[64], glw[64];

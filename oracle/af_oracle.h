@@ -59,6 +59,8 @@ int or_dof_eg(const or_cfg* c, const double* A, const double* K, const double* X
 int or_dof_update(const or_cfg* c, const double* A, const double* K, const double* X,
                   const double* Y, int kind, int ci, int cj, double dt, double half[4],
                   double full[4], long long* counters);
+int or_lf_point(const or_cfg* c, const double* A, const double* K, const double* X,
+                const double* Y, int kind, int ci, int cj, double tau, double out[4]);
 typedef void (*or_field_cb)(double x, double y, double* out4);
 int or_eg_cb(int order, double xb, double yb, int vline, int hline, const double lin[4],
              double tau, double gamma, or_field_cb cb, int gl_n, double out[4]);

@@ -464,6 +464,62 @@ def test_lax_friedrichs_fallback_keeps_positivity():
         assert (arr[0] > 0).all() and (arr[3] > 0).all()
 
 
+def _smooth_field(x, y):
+    tp = 2.0 * math.pi
+    return np.stack([1.0 + 0.2 * np.sin(tp * x) * np.cos(tp * y), 0.3 * np.cos(tp * x),
+                     0.2 * np.sin(tp * y), 1.0 + 0.1 * np.cos(tp * (x + y))])
+
+
+def _flux_divergence(x, y, d=1e-5):
+    """-(df/dx + dg/dy) of the smooth field at (x, y), by central differences of the exact
+    fluxes (error ~d^2)."""
+    def fg(xx, yy):
+        r, u, v, p = _smooth_field(np.array(xx), np.array(yy))
+        E = p / (G - 1) + 0.5 * r * (u * u + v * v)
+        return (np.array([r * u, r * u * u + p, r * u * v, u * (E + p)]),
+                np.array([r * v, r * u * v, r * v * v + p, v * (E + p)]))
+    fe, _ = fg(x + d, y)
+    fw, _ = fg(x - d, y)
+    _, gn = fg(x, y + d)
+    _, gs = fg(x, y - d)
+    return -((fe - fw) + (gn - gs)) / (2.0 * d)
+
+
+def test_lax_friedrichs_update_is_consistent_first_order():
+    """The LF point update (R10 reading: Rusanov fluxes on the same-kind lattice) approximates
+    the conservation law: (Q_new - Q)/tau -> -(f_x + g_y) at first order in h."""
+    errs = []
+    for n in (32, 64, 128):
+        g = I.Grid(n, n, 0.0, 1.0, 0.0, 1.0)
+        st = I.state_from_field(_smooth_field, g, G, n_gl=2)
+        i = j = n // 4  # corner at (1/4, 1/4)
+        tau = 0.1 / n
+        e, U1 = oracle.lf_point(st, oracle.KIND_K, i, j, tau)
+        assert e == 0
+        Q0 = I.prim_to_cons(st.K[:, j, i])
+        Q1 = I.prim_to_cons(U1)
+        errs.append(np.abs((Q1 - Q0) / tau - _flux_divergence(0.25, 0.25)).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.7 < r1 < 2.3 and 1.7 < r2 < 2.3, errs
+    assert errs[2] < 0.3  # the O(h) dissipation alpha h Q_xx / 2 is ~0.1 here
+
+
+def test_lax_friedrichs_update_is_dissipative():
+    """At rest with uniform pressure, the LF update of a density step is pure diffusion: the new
+    value lies between its neighbours and moves towards the larger one (fixes the sign of the
+    Rusanov dissipation); velocity and pressure stay unchanged."""
+    g = I.Grid(8, 8, 0.0, 1.0, 0.0, 1.0)
+    st = I.uniform_state(g, [1.0, 0.0, 0.0, 1.0])
+    st.K[0, :, 5:] = 2.0  # density step between K columns 4 and 5
+    tau = 0.2 * g.dx / math.sqrt(G * 1.0 / 1.0)
+    e, U = oracle.lf_point(st, oracle.KIND_K, 4, 3, tau)
+    assert e == 0
+    assert 1.0 < U[0] < 2.0
+    e, U = oracle.lf_point(st, oracle.KIND_K, 5, 3, tau)
+    assert e == 0 and 1.0 < U[0] < 2.0
+    assert abs(U[1]) < 1e-15 and abs(U[2]) < 1e-15 and abs(U[3] - 1.0) < 1e-14
+
+
 def test_radial_outflow_positivity_small():
     st = I.radial_state(32, n_gl=3)
     e, n, cnt = oracle.run(st, 1e9, 0.3, max_steps=20, mode=1, limiter=True)
