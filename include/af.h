@@ -62,8 +62,7 @@ enum {
   AF_ERR_OOM = -5          /* device allocation failed */
 };
 
-/* Options (af_set_option).  Changing AF_OPT_PRECISION discards the state: call
- * af_set_state afterwards. */
+/* Options (af_set_option).  They apply from the next step on; the state is kept. */
 enum {
   AF_OPT_PRECISION = 1,     /* AF_PREC_FP64 (default) or AF_PREC_FP32 (see below)        */
   AF_OPT_LINEARISATION = 2, /* AF_LIN_AF3 (default), AF_LIN_AVG or AF_LIN_SIMPLE          */
@@ -144,6 +143,39 @@ int64_t af_dof_count(const af_handle* h);
  * out[0] = milliseconds in the point-value kernel, out[1] = milliseconds in the flux/update
  * kernel, out[2] = number of steps timed.  Both kernels run on the handle's stream. */
 int af_get_timing(const af_handle* h, double* out);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched grids: many independent grids (own sizes, domains, boundaries, time steps) in one
+ * handle, advanced together with one launch of each kernel per step for all grids.  This is
+ * the method of Sec. 2 applied to each grid independently; nothing couples the grids.
+ * Options, af_set_stream, af_step, af_run, af_get_counters, af_get_timing, af_dof_count,
+ * af_last_error and af_destroy work on batched handles as on single ones:
+ *   af_step(dt)  steps every grid with the same dt; a grid whose step fails keeps its state,
+ *                the others advance; the most negative error code is returned, its text
+ *                names the grid;
+ *   af_run       gives every grid its own dt from its own wave speeds; each grid stops at
+ *                t_end or after max_steps of its own steps; t_reached is the smallest time
+ *                over the grids, steps_taken the largest number of steps;
+ *   af_get_counters sums the counters over the grids (AF_CNT_STEPS: the largest).
+ * af_set_state / af_get_state work only when n == 1; use the _grid variants.
+ * --------------------------------------------------------------------------------------- */
+
+/* Create a handle for n >= 1 grids: grids[g], bcs[g] as for af_create, one gamma. */
+int af_create_batch(int32_t n, const af_grid* grids, double gamma, const af_bc* bcs,
+                    af_handle** out);
+
+/* Number of grids of the handle (1 for af_create handles; 0 for NULL). */
+int32_t af_batch_size(const af_handle* h);
+
+/* af_set_state / af_get_state for grid g (0 <= g < n; g = 0 on single handles).  Arrays as
+ * for one grid of grids[g]'s sizes.  Every grid needs a state before af_step or af_run. */
+int af_set_state_grid(af_handle* h, int32_t g, const double* avg, const double* K,
+                      const double* X, const double* Y, double t);
+int af_get_state_grid(const af_handle* h, int32_t g, double* avg, double* K, double* X,
+                      double* Y, double* t);
+
+/* Time and steps taken (since af_set_state_grid) of grid g (nullable outputs). */
+int af_get_grid_info(const af_handle* h, int32_t g, double* t, int64_t* steps);
 
 #ifdef __cplusplus
 }

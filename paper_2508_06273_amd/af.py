@@ -27,7 +27,8 @@ AF_NCOUNTERS = 8
 # every symbol include/af.h declares
 EXPORTS = ["af_create", "af_set_option", "af_set_stream", "af_set_state", "af_get_state",
            "af_step", "af_run", "af_get_counters", "af_destroy", "af_last_error",
-           "af_dof_count", "af_get_timing"]
+           "af_dof_count", "af_get_timing", "af_create_batch", "af_batch_size",
+           "af_set_state_grid", "af_get_state_grid", "af_get_grid_info"]
 
 
 class AfError(RuntimeError):
@@ -76,8 +77,16 @@ def load(path: str = LIB_PATH):
     L.af_dof_count.restype = ct.c_int64
     L.af_get_timing.argtypes = [_H, ct.POINTER(ct.c_double)]
     L.af_get_timing.restype = ct.c_int
+    L.af_create_batch.argtypes = [ct.c_int32, ct.POINTER(Grid), ct.c_double, ct.POINTER(Bc),
+                                  ct.POINTER(_H)]
+    L.af_batch_size.argtypes = [_H]
+    L.af_batch_size.restype = ct.c_int32
+    L.af_set_state_grid.argtypes = [_H, ct.c_int32, _D, _D, _D, _D, ct.c_double]
+    L.af_get_state_grid.argtypes = [_H, ct.c_int32, _D, _D, _D, _D, _D]
+    L.af_get_grid_info.argtypes = [_H, ct.c_int32, _D, ct.POINTER(ct.c_int64)]
     for name in ("af_create", "af_set_option", "af_set_stream", "af_set_state",
-                 "af_get_state", "af_step", "af_run", "af_get_counters"):
+                 "af_get_state", "af_step", "af_run", "af_get_counters", "af_create_batch",
+                 "af_set_state_grid", "af_get_state_grid", "af_get_grid_info"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -88,34 +97,22 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(_D)
 
 
-class Solver:
-    """One grid on the GPU.  Mirrors af_create / af_set_state / af_step / af_run / ..."""
+def _shapes(nx, ny, nkx, nky):
+    return dict(avg=(4, ny, nx), K=(4, nky, nkx), X=(4, ny, nkx), Y=(4, nky, nx))
 
-    def __init__(self, nx, ny, x0, x1, y0, y1, gamma=1.4, bc_x=AF_BC_PERIODIC,
-                 bc_y=AF_BC_PERIODIC, precision=AF_PREC_FP64, linearisation=AF_LIN_AF3,
-                 correction=True, limiter=False, graph_steps=None):
-        self.L = load()
-        self.nx, self.ny = int(nx), int(ny)
-        self.nkx = self.nx + (0 if bc_x == AF_BC_PERIODIC else 1)
-        self.nky = self.ny + (0 if bc_y == AF_BC_PERIODIC else 1)
-        self.h = _H()
-        g = Grid(self.nx, self.ny, x0, x1, y0, y1)
-        bc = Bc(bc_x, bc_x, bc_y, bc_y)
-        self._check(self.L.af_create(ct.byref(g), gamma, ct.byref(bc), ct.byref(self.h)),
-                    create=True)
+
+class _Handle:
+    """Calls shared by single-grid and batched handles."""
+
+    h = None
+
+    def _options(self, precision, linearisation, correction, limiter, graph_steps):
         self.set_option(AF_OPT_PRECISION, precision)
         self.set_option(AF_OPT_LINEARISATION, linearisation)
         self.set_option(AF_OPT_CORRECTION, int(bool(correction)))
         self.set_option(AF_OPT_LIMITER, int(bool(limiter)))
         if graph_steps is not None:
             self.set_option(AF_OPT_GRAPH_STEPS, graph_steps)
-
-    @classmethod
-    def for_state(cls, st, **kw):
-        g = st.grid
-        s = cls(g.nx, g.ny, g.x0, g.x1, g.y0, g.y1, st.gamma, g.bc_x, g.bc_y, **kw)
-        s.set_state(st.avg, st.K, st.X, st.Y, st.t)
-        return s
 
     def _check(self, rc, create=False):
         if rc != AF_OK:
@@ -141,26 +138,6 @@ class Solver:
         handle = getattr(stream, "cuda_stream", stream)
         self._check(self.L.af_set_stream(self.h, ct.c_void_p(handle)))
 
-    def shapes(self):
-        return dict(avg=(4, self.ny, self.nx), K=(4, self.nky, self.nkx),
-                    X=(4, self.ny, self.nkx), Y=(4, self.nky, self.nx))
-
-    def set_state(self, avg, K, X, Y, t=0.0):
-        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (avg, K, X, Y)]
-        for a, (name, shp) in zip(arrs, self.shapes().items()):
-            if a.shape != shp:
-                raise ValueError(f"{name} has shape {a.shape}, expected {shp}")
-        self._check(self.L.af_set_state(self.h, *[_ptr(a) for a in arrs], float(t)))
-
-    def get_state(self):
-        sh = self.shapes()
-        out = {k: np.empty(v, dtype=np.float64) for k, v in sh.items()}
-        t = ct.c_double(0.0)
-        self._check(self.L.af_get_state(self.h, _ptr(out["avg"]), _ptr(out["K"]),
-                                        _ptr(out["X"]), _ptr(out["Y"]), ct.byref(t)))
-        out["t"] = t.value
-        return out
-
     def step(self, dt):
         self._check(self.L.af_step(self.h, float(dt)))
 
@@ -184,3 +161,112 @@ class Solver:
 
     def dof_count(self):
         return int(self.L.af_dof_count(self.h))
+
+    def _set(self, g, shapes, avg, K, X, Y, t):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (avg, K, X, Y)]
+        for a, (name, shp) in zip(arrs, shapes.items()):
+            if a.shape != shp:
+                raise ValueError(f"{name} has shape {a.shape}, expected {shp}")
+        self._check(self.L.af_set_state_grid(self.h, g, *[_ptr(a) for a in arrs], float(t)))
+
+    def _get(self, g, shapes):
+        out = {k: np.empty(v, dtype=np.float64) for k, v in shapes.items()}
+        t = ct.c_double(0.0)
+        self._check(self.L.af_get_state_grid(self.h, g, _ptr(out["avg"]), _ptr(out["K"]),
+                                             _ptr(out["X"]), _ptr(out["Y"]), ct.byref(t)))
+        out["t"] = t.value
+        return out
+
+    def grid_info(self, g=0):
+        """(t, steps taken) of grid g."""
+        t = ct.c_double(0.0)
+        n = ct.c_int64(0)
+        self._check(self.L.af_get_grid_info(self.h, g, ct.byref(t), ct.byref(n)))
+        return t.value, n.value
+
+
+class Solver(_Handle):
+    """One grid on the GPU.  Mirrors af_create / af_set_state / af_step / af_run / ..."""
+
+    def __init__(self, nx, ny, x0, x1, y0, y1, gamma=1.4, bc_x=AF_BC_PERIODIC,
+                 bc_y=AF_BC_PERIODIC, precision=AF_PREC_FP64, linearisation=AF_LIN_AF3,
+                 correction=True, limiter=False, graph_steps=None):
+        self.L = load()
+        self.nx, self.ny = int(nx), int(ny)
+        self.nkx = self.nx + (0 if bc_x == AF_BC_PERIODIC else 1)
+        self.nky = self.ny + (0 if bc_y == AF_BC_PERIODIC else 1)
+        self.h = _H()
+        g = Grid(self.nx, self.ny, x0, x1, y0, y1)
+        bc = Bc(bc_x, bc_x, bc_y, bc_y)
+        self._check(self.L.af_create(ct.byref(g), gamma, ct.byref(bc), ct.byref(self.h)),
+                    create=True)
+        self._options(precision, linearisation, correction, limiter, graph_steps)
+
+    @classmethod
+    def for_state(cls, st, **kw):
+        g = st.grid
+        s = cls(g.nx, g.ny, g.x0, g.x1, g.y0, g.y1, st.gamma, g.bc_x, g.bc_y, **kw)
+        s.set_state(st.avg, st.K, st.X, st.Y, st.t)
+        return s
+
+    def shapes(self):
+        return _shapes(self.nx, self.ny, self.nkx, self.nky)
+
+    def set_state(self, avg, K, X, Y, t=0.0):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (avg, K, X, Y)]
+        for a, (name, shp) in zip(arrs, self.shapes().items()):
+            if a.shape != shp:
+                raise ValueError(f"{name} has shape {a.shape}, expected {shp}")
+        self._check(self.L.af_set_state(self.h, *[_ptr(a) for a in arrs], float(t)))
+
+    def get_state(self):
+        sh = self.shapes()
+        out = {k: np.empty(v, dtype=np.float64) for k, v in sh.items()}
+        t = ct.c_double(0.0)
+        self._check(self.L.af_get_state(self.h, _ptr(out["avg"]), _ptr(out["K"]),
+                                        _ptr(out["X"]), _ptr(out["Y"]), ct.byref(t)))
+        out["t"] = t.value
+        return out
+
+
+class BatchSolver(_Handle):
+    """Several independent grids in one handle (af_create_batch): one launch of each kernel
+    per step for all grids, each grid with its own time step."""
+
+    def __init__(self, grids, gamma=1.4, precision=AF_PREC_FP64, linearisation=AF_LIN_AF3,
+                 correction=True, limiter=False, graph_steps=None):
+        """grids: sequence of (nx, ny, x0, x1, y0, y1, bc_x, bc_y)."""
+        self.L = load()
+        n = len(grids)
+        G = (Grid * n)()
+        B = (Bc * n)()
+        self.dims = []
+        for k, (nx, ny, x0, x1, y0, y1, bx, by) in enumerate(grids):
+            G[k] = Grid(int(nx), int(ny), x0, x1, y0, y1)
+            B[k] = Bc(bx, bx, by, by)
+            self.dims.append((int(nx), int(ny), int(nx) + (0 if bx == AF_BC_PERIODIC else 1),
+                              int(ny) + (0 if by == AF_BC_PERIODIC else 1)))
+        self.h = _H()
+        self._check(self.L.af_create_batch(n, G, gamma, B, ct.byref(self.h)), create=True)
+        self._options(precision, linearisation, correction, limiter, graph_steps)
+
+    @classmethod
+    def for_states(cls, states, **kw):
+        grids = [(st.grid.nx, st.grid.ny, st.grid.x0, st.grid.x1, st.grid.y0, st.grid.y1,
+                  st.grid.bc_x, st.grid.bc_y) for st in states]
+        s = cls(grids, states[0].gamma, **kw)
+        for g, st in enumerate(states):
+            s.set_state(g, st.avg, st.K, st.X, st.Y, st.t)
+        return s
+
+    def __len__(self):
+        return int(self.L.af_batch_size(self.h))
+
+    def shapes(self, g):
+        return _shapes(*self.dims[g])
+
+    def set_state(self, g, avg, K, X, Y, t=0.0):
+        self._set(g, self.shapes(g), avg, K, X, Y, t)
+
+    def get_state(self, g):
+        return self._get(g, self.shapes(g))

@@ -9,8 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaf.so")
-SOURCES = [os.path.join(CSRC, "af_lib.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("af_device.hpp", "af_kernels.hpp")] + \
+SOURCES = [os.path.join(CSRC, f) for f in ("af_lib.hip", "af_batch.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("af_device.hpp", "af_kernels.hpp", "af_step.hpp",
+                                           "af_host.hpp")] + \
     [os.path.join(ROOT, "include", "af.h")]
 ARCH = "gfx950"
 # packed FP32 instructions are disabled for all device code

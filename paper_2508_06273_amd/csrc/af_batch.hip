@@ -1,0 +1,615 @@
+// af_batch.hip -- many independent grids advanced together (af_create_batch in af.h).
+//
+// The grids' arrays are packed into one allocation per array kind.  Every step is one launch
+// of each kernel for all grids: the point kernel runs one workgroup per 8x8-site tile of any
+// grid (a per-tile table gives the grid), the update kernel one workgroup per row of cells of
+// any grid, then a commit kernel advances each grid's time.  Each grid keeps its own time step
+// (CFL from its own wave speeds), time, step limit and buffer index on the device, so the
+// sequence of launches is the same for every step and is captured once in a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "af.h"
+#include "af_host.hpp"
+#include "af_step.hpp"
+
+namespace af {
+
+// Per-grid device descriptor: geometry and options, and the buffers for each of the two
+// buffer indices (t_n state in buffer `cur`, t_n+1 in `cur ^ 1`).
+struct GridDesc {
+  Params P;
+  Bufs B[2];
+  int tile_base;  // first global tile of the grid
+  int row_base;   // first global row of cells of the grid
+};
+
+constexpr int BU_THREADS = 128;  // batched update: cells of one row per pass
+
+// Point kernel over the tiles of all grids.  Tile order: XCD-aware over the global tile index.
+template <class R>
+__device__ __forceinline__ void batch_points(Smem<R>& S, const GridDesc* __restrict__ desc,
+                                             const int* __restrict__ tile_grid, int total_tiles,
+                                             DevState* devs, double dt_host) {
+  __shared__ int s_g, s_cur;
+  const int t = tile_of_block(blockIdx.x, total_tiles);
+  if (threadIdx.x == 0) {
+    const int g = tile_grid[t];
+    s_g = g;
+    s_cur = devs[g].cur;
+  }
+  __syncthreads();
+  const int g = __builtin_amdgcn_readfirstlane(s_g);
+  const int cur = __builtin_amdgcn_readfirstlane(s_cur);
+  const Params P = desc[g].P;
+  const Bufs B = desc[g].B[cur];
+  const int local = t - desc[g].tile_base;
+  points_body<R>(S, P, B, devs + g, dt_host, cur, local, local == 0);
+}
+
+__global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
+void kb_points_f32(const GridDesc* desc, const int* tile_grid, int total_tiles, DevState* devs,
+                   double dt_host) {
+  __shared__ Smem<float> S;
+  batch_points<float>(S, desc, tile_grid, total_tiles, devs, dt_host);
+}
+__global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
+void kb_points_f64(const GridDesc* desc, const int* tile_grid, int total_tiles, DevState* devs,
+                   double dt_host) {
+  __shared__ Smem<double> S;
+  batch_points<double>(S, desc, tile_grid, total_tiles, devs, dt_host);
+}
+
+// Positivity fix-up over the global list of flagged tiles (entries are global tile indices).
+template <class R>
+__device__ __forceinline__ void batch_fixup(Smem<R>& S, const GridDesc* __restrict__ desc,
+                                            const int* __restrict__ tile_grid, DevState* devs,
+                                            const int* fix_list, const unsigned int* fix_count) {
+  __shared__ unsigned long long mask[3];
+  __shared__ unsigned int s_n;
+  __shared__ int s_g, s_cur, s_run, s_tile;
+  __shared__ double s_dt;
+  if (threadIdx.x == 0) s_n = *fix_count;
+  __syncthreads();
+  const unsigned int n = s_n;
+  for (unsigned int k = blockIdx.x; k < n; k += gridDim.x) {
+    if (threadIdx.x == 0) {
+      const int t = fix_list[k];
+      const int g = tile_grid[t];
+      s_g = g;
+      s_tile = t - desc[g].tile_base;
+      s_cur = devs[g].cur;
+      s_run = !devs[g].err && devs[g].active;
+      s_dt = devs[g].dt;
+    }
+    __syncthreads();
+    const int g = __builtin_amdgcn_readfirstlane(s_g);
+    const int cur = __builtin_amdgcn_readfirstlane(s_cur);
+    const Params P = desc[g].P;
+    const Bufs B = desc[g].B[cur];
+    double speed = 0.0;
+    fixup_tile<R>(S, P, B, devs + g, s_tile, s_dt, s_run != 0, mask, speed);
+    block_max_atomic(speed, &devs[g].smax[cur ^ 1], S.red);
+    __syncthreads();  // the next entry overwrites the shared values
+  }
+}
+__global__ __launch_bounds__(PT_THREADS) void kb_fixup_f32(const GridDesc* desc,
+                                                          const int* tile_grid, DevState* devs,
+                                                          const int* fix_list,
+                                                          const unsigned int* fix_count) {
+  __shared__ Smem<float> S;
+  batch_fixup<float>(S, desc, tile_grid, devs, fix_list, fix_count);
+}
+__global__ __launch_bounds__(PT_THREADS) void kb_fixup_f64(const GridDesc* desc,
+                                                          const int* tile_grid, DevState* devs,
+                                                          const int* fix_list,
+                                                          const unsigned int* fix_count) {
+  __shared__ Smem<double> S;
+  batch_fixup<double>(S, desc, tile_grid, devs, fix_list, fix_count);
+}
+
+// Update kernel: one workgroup per row of cells of any grid (XCD-aware row order), the
+// grid's largest new wave speed by one atomic per row.
+__global__ __launch_bounds__(BU_THREADS) void kb_update(const GridDesc* __restrict__ desc,
+                                                       const int* __restrict__ row_grid,
+                                                       int total_rows, DevState* devs) {
+  __shared__ double red[BU_THREADS / 64];
+  const int r = tile_of_block(blockIdx.x, total_rows);
+  const int g = __builtin_amdgcn_readfirstlane(row_grid[r]);
+  const Params& P = desc[g].P;
+  DevState* dev = devs + g;
+  const int cur = dev->cur;
+  const Bufs& B = desc[g].B[cur];
+  const bool run = !dev->err && dev->active;
+  const double dt = dev->dt;
+  const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
+  const int j = r - desc[g].row_base;
+  double speed = 0.0;
+  bool bad = false;
+  if (run)
+    for (int i = threadIdx.x; i < P.nx; i += BU_THREADS)
+      if (!update_cell(P, B.A_in, B.A_out, B.FK, B.FX, B.FY, lx, ly, i, j, speed)) bad = true;
+  if (bad) set_err(dev, ERR_NONPHYS);
+  for (int off = 32; off > 0; off >>= 1) speed = mx(speed, __shfl_xor(speed, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = speed;
+  __syncthreads();
+  if (threadIdx.x == 0 && run) {
+    double m = red[0];
+    for (int k = 1; k < BU_THREADS / 64; ++k) m = mx(m, red[k]);
+    atomic_max_pos(&dev->smax[cur ^ 1], m);
+  }
+}
+
+// Commit: every grid whose step ran without error advances t and its step counter, clears the
+// wave-speed slot of the old state and switches to the other buffer.
+__global__ void kb_commit(DevState* devs, int n, unsigned int* fix_count) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) *fix_count = 0u;
+  if (g >= n) return;
+  DevState* d = devs + g;
+  if (!d->err && d->active) {
+    d->t = d->last ? d->t_end : d->t + d->dt;
+    d->steps += 1;
+    d->smax[d->cur] = 0ull;
+    d->cur ^= 1;
+  }
+}
+
+// Wave speed of every grid's current state into its smax[cur], before a run: `per` workgroups
+// per grid.
+__global__ void kb_cfl(const GridDesc* __restrict__ desc, DevState* devs, int per) {
+  __shared__ double red[4];
+  const int g = blockIdx.x / per, part = blockIdx.x % per;
+  const Params& P = desc[g].P;
+  const int cur = devs[g].cur;
+  const Bufs& B = desc[g].B[cur];
+  const double speed = state_speed(P, B.A_in, B.K_in, B.X_in, B.Y_in,
+                                   (long long)part * blockDim.x + threadIdx.x,
+                                   (long long)per * blockDim.x);
+  block_max_atomic(speed, &devs[g].smax[cur], red);
+}
+
+}  // namespace af
+
+// ==========================================================================================
+// Host side
+// ==========================================================================================
+struct BatchGrid {
+  int nx, ny, per_x, per_y, nkx, nky;
+  double x0, y0, dx, dy;
+  long long pA, pP;        // row pitches (elements)
+  size_t oA, oP, oF;       // element offsets of the grid in the packed arrays
+  int tile_base, tiles_x, tiles_y, row_base;
+  bool has_state;
+};
+
+struct Batch {
+  int n = 0;
+  std::vector<BatchGrid> g;
+  double* A[2] = {nullptr, nullptr};
+  double* K[2] = {nullptr, nullptr};
+  double* X[2] = {nullptr, nullptr};
+  double* Y[2] = {nullptr, nullptr};
+  double* FK = nullptr;
+  double* FX = nullptr;
+  double* FY = nullptr;
+  unsigned long long* fix_mask = nullptr;
+  int* fix_list = nullptr;
+  unsigned int* fix_count = nullptr;
+  GridDesc* d_desc = nullptr;
+  int* d_tile_grid = nullptr;
+  int* d_row_grid = nullptr;
+  DevState* d_devs = nullptr;
+  int total_tiles = 0, total_rows = 0;
+  bool desc_valid = false;
+  hipGraphExec_t gexec = nullptr;
+  int gexec_steps = 0;
+};
+
+static size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+static void batch_free(Batch* b) {
+  for (int k = 0; k < 2; ++k) {
+    for (double* p : {b->A[k], b->K[k], b->X[k], b->Y[k]})
+      if (p) (void)hipFree(p);
+  }
+  for (void* p : {(void*)b->FK, (void*)b->FX, (void*)b->FY, (void*)b->fix_mask,
+                  (void*)b->fix_list, (void*)b->fix_count, (void*)b->d_desc,
+                  (void*)b->d_tile_grid, (void*)b->d_row_grid, (void*)b->d_devs})
+    if (p) (void)hipFree(p);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  delete b;
+}
+
+void batch_invalidate(af_handle* h) {
+  if (!h->batch) return;
+  h->batch->desc_valid = false;
+  if (h->batch->gexec) {
+    (void)hipGraphExecDestroy(h->batch->gexec);
+    h->batch->gexec = nullptr;
+    h->batch->gexec_steps = 0;
+  }
+}
+
+int batch_count(const af_handle* h) { return h->batch ? h->batch->n : 1; }
+
+void batch_destroy(af_handle* h) {
+  if (h->batch) batch_free(h->batch);
+  h->batch = nullptr;
+}
+
+int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af_handle* h) {
+  Batch* b = new Batch();
+  h->batch = b;
+  b->n = n;
+  b->g.resize(n);
+  size_t nA = 0, nP = 0, nF = 0;
+  long long tiles = 0, rows = 0;
+  for (int k = 0; k < n; ++k) {
+    const af_grid& G = grids[k];
+    const af_bc& bc = bcs[k];
+    BatchGrid& q = b->g[k];
+    q.nx = G.nx; q.ny = G.ny;
+    q.per_x = bc.left == AF_BC_PERIODIC; q.per_y = bc.bottom == AF_BC_PERIODIC;
+    q.nkx = q.nx + (q.per_x ? 0 : 1); q.nky = q.ny + (q.per_y ? 0 : 1);
+    q.x0 = G.x0; q.y0 = G.y0;
+    q.dx = (G.x1 - G.x0) / G.nx; q.dy = (G.y1 - G.y0) / G.ny;
+    q.pA = (q.nx + 31) / 32 * 32;
+    q.pP = (q.nkx + 63) / 64 * 64;
+    q.oA = nA; q.oP = nP; q.oF = nF;
+    nA += round_up((size_t)4 * q.pA * q.ny, 64);
+    nP += round_up((size_t)4 * q.pP * q.nky, 64);
+    nF += round_up((size_t)q.pP * q.nky, 64);
+    q.tiles_x = (q.nkx + TILE - 1) / TILE;
+    q.tiles_y = (q.nky + TILE - 1) / TILE;
+    q.tile_base = (int)tiles;
+    q.row_base = (int)rows;
+    tiles += (long long)q.tiles_x * q.tiles_y;
+    rows += q.ny;
+    q.has_state = false;
+  }
+  if (tiles > INT_MAX / 2 || rows > INT_MAX / 2)
+    return fail(h, AF_ERR_INVALID_ARG, "af_create_batch: too many tiles");
+  b->total_tiles = (int)tiles;
+  b->total_rows = (int)rows;
+  for (int k = 0; k < 2; ++k) {
+    HIP_OK(hipMalloc(&b->A[k], nA * 8), h);
+    HIP_OK(hipMalloc(&b->K[k], nP * 8), h);
+    HIP_OK(hipMalloc(&b->X[k], nP * 8), h);
+    HIP_OK(hipMalloc(&b->Y[k], nP * 8), h);
+  }
+  HIP_OK(hipMalloc(&b->FK, nF * 8 * 8), h);
+  HIP_OK(hipMalloc(&b->FX, nF * 4 * 8), h);
+  HIP_OK(hipMalloc(&b->FY, nF * 4 * 8), h);
+  HIP_OK(hipMalloc(&b->fix_mask, (size_t)tiles * 4 * sizeof(unsigned long long)), h);
+  HIP_OK(hipMemset(b->fix_mask, 0, (size_t)tiles * 4 * sizeof(unsigned long long)), h);
+  HIP_OK(hipMalloc(&b->fix_list, (size_t)tiles * sizeof(int)), h);
+  HIP_OK(hipMalloc(&b->fix_count, sizeof(unsigned int)), h);
+  HIP_OK(hipMemset(b->fix_count, 0, sizeof(unsigned int)), h);
+  HIP_OK(hipMalloc(&b->d_desc, (size_t)n * sizeof(GridDesc)), h);
+  HIP_OK(hipMalloc(&b->d_devs, (size_t)n * sizeof(DevState)), h);
+  HIP_OK(hipMemset(b->d_devs, 0, (size_t)n * sizeof(DevState)), h);
+  // the grid of every tile and of every row
+  std::vector<int> tg((size_t)tiles), rg((size_t)rows);
+  for (int k = 0; k < n; ++k) {
+    const BatchGrid& q = b->g[k];
+    std::fill(tg.begin() + q.tile_base, tg.begin() + q.tile_base + q.tiles_x * q.tiles_y, k);
+    std::fill(rg.begin() + q.row_base, rg.begin() + q.row_base + q.ny, k);
+  }
+  HIP_OK(hipMalloc(&b->d_tile_grid, tg.size() * sizeof(int)), h);
+  HIP_OK(hipMalloc(&b->d_row_grid, rg.size() * sizeof(int)), h);
+  HIP_OK(hipMemcpy(b->d_tile_grid, tg.data(), tg.size() * sizeof(int), hipMemcpyHostToDevice), h);
+  HIP_OK(hipMemcpy(b->d_row_grid, rg.data(), rg.size() * sizeof(int), hipMemcpyHostToDevice), h);
+  (void)gamma;
+  return AF_OK;
+}
+
+// Descriptors of all grids for the handle's current options (uploaded before a step or run).
+static int upload_desc(af_handle* h) {
+  Batch* b = h->batch;
+  if (b->desc_valid) return AF_OK;
+  std::vector<GridDesc> d((size_t)b->n);
+  for (int k = 0; k < b->n; ++k) {
+    const BatchGrid& q = b->g[k];
+    Params& P = d[k].P;
+    P.nx = q.nx; P.ny = q.ny; P.nkx = q.nkx; P.nky = q.nky;
+    P.per_x = q.per_x; P.per_y = q.per_y;
+    P.tiles_x = q.tiles_x; P.tiles_y = q.tiles_y;
+    P.dx = q.dx; P.dy = q.dy; P.idx = 1.0 / q.dx; P.idy = 1.0 / q.dy;
+    P.gamma = h->gamma; P.hmin = std::min(q.dx, q.dy);
+    P.mode = h->mode; P.correction = h->correction; P.limiter = h->limiter; P.pad = 0;
+    P.pA = q.pA; P.sA = q.pA * q.ny;
+    P.pP = q.pP; P.sP = q.pP * q.nky;
+    P.pF = q.pP; P.sF = q.pP * q.nky;
+    for (int in = 0; in < 2; ++in) {
+      Bufs& B = d[k].B[in];
+      const int out = in ^ 1;
+      B.A_in = b->A[in] + q.oA; B.A_out = b->A[out] + q.oA;
+      B.K_in = b->K[in] + q.oP; B.X_in = b->X[in] + q.oP; B.Y_in = b->Y[in] + q.oP;
+      B.K_out = b->K[out] + q.oP; B.X_out = b->X[out] + q.oP; B.Y_out = b->Y[out] + q.oP;
+      B.FK = b->FK + 8 * q.oF; B.FX = b->FX + 4 * q.oF; B.FY = b->FY + 4 * q.oF;
+      B.fix_mask = b->fix_mask + 4 * (size_t)q.tile_base;
+      B.fix_list = b->fix_list;
+      B.fix_count = b->fix_count;
+      B.tile_base = q.tile_base;
+    }
+    d[k].tile_base = q.tile_base;
+    d[k].row_base = q.row_base;
+  }
+  HIP_OK(hipMemcpyAsync(b->d_desc, d.data(), d.size() * sizeof(GridDesc), hipMemcpyHostToDevice,
+                        h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  b->desc_valid = true;
+  return AF_OK;
+}
+
+int64_t batch_dof_count(const af_handle* h) {
+  int64_t s = 0;
+  for (const BatchGrid& q : h->batch->g)
+    s += (int64_t)q.nx * q.ny + (int64_t)q.nkx * q.nky + (int64_t)q.nkx * q.ny +
+         (int64_t)q.nx * q.nky;
+  return s;
+}
+
+static int read_devs(const af_handle* h, std::vector<DevState>& ds) {
+  const Batch* b = h->batch;
+  ds.resize((size_t)b->n);
+  HIP_OK(hipMemcpyAsync(ds.data(), b->d_devs, ds.size() * sizeof(DevState),
+                        hipMemcpyDeviceToHost, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  return AF_OK;
+}
+static int write_devs(af_handle* h, const std::vector<DevState>& ds) {
+  HIP_OK(hipMemcpyAsync(h->batch->d_devs, ds.data(), ds.size() * sizeof(DevState),
+                        hipMemcpyHostToDevice, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  return AF_OK;
+}
+
+int batch_set_state(af_handle* h, int g, const double* avg, const double* K, const double* X,
+                    const double* Y, double t) {
+  Batch* b = h->batch;
+  if (g < 0 || g >= b->n) return fail(h, AF_ERR_INVALID_ARG, "af_set_state_grid: bad grid index");
+  if (!avg || !K || !X || !Y) return fail(h, AF_ERR_INVALID_ARG, "af_set_state_grid: NULL array");
+  if (!std::isfinite(t)) return fail(h, AF_ERR_INVALID_ARG, "af_set_state_grid: t not finite");
+  BatchGrid& q = b->g[g];
+  const size_t nc = (size_t)q.nx * q.ny;
+  for (size_t k = 0; k < nc; ++k) {
+    const double r = avg[k], E = avg[3 * nc + k];
+    const double kin = 0.5 * (avg[nc + k] * avg[nc + k] + avg[2 * nc + k] * avg[2 * nc + k]) / r;
+    if (!(r > 0.0) || !((h->gamma - 1.0) * (E - kin) > 0.0))
+      return fail(h, AF_ERR_NONPHYSICAL, "af_set_state_grid: non-admissible cell average");
+  }
+  int e;
+  if ((e = copy4(h, true, b->A[0] + q.oA, q.pA, q.ny, q.ny, q.nx, const_cast<double*>(avg))))
+    return e;
+  if ((e = copy4(h, true, b->K[0] + q.oP, q.pP, q.nky, q.nky, q.nkx, const_cast<double*>(K))))
+    return e;
+  if ((e = copy4(h, true, b->X[0] + q.oP, q.pP, q.nky, q.ny, q.nkx, const_cast<double*>(X))))
+    return e;
+  if ((e = copy4(h, true, b->Y[0] + q.oP, q.pP, q.nky, q.nky, q.nx, const_cast<double*>(Y))))
+    return e;
+  DevState ds;
+  std::memset(&ds, 0, sizeof(ds));
+  ds.t = t;
+  ds.t_end = t;
+  ds.steps_limit = LLONG_MAX;
+  ds.cur = 0;
+  HIP_OK(hipMemcpyAsync(b->d_devs + g, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  q.has_state = true;
+  return AF_OK;
+}
+
+int batch_get_state(const af_handle* h, int g, double* avg, double* K, double* X, double* Y,
+                    double* t) {
+  const Batch* b = h->batch;
+  if (g < 0 || g >= b->n) return fail(h, AF_ERR_INVALID_ARG, "af_get_state_grid: bad grid index");
+  const BatchGrid& q = b->g[g];
+  if (!q.has_state) return fail(h, AF_ERR_INVALID_ARG, "af_get_state_grid: no state set");
+  DevState ds;
+  HIP_OK(hipMemcpyAsync(&ds, b->d_devs + g, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  const int c = ds.cur;
+  int e;
+  if (avg && (e = copy4(h, false, b->A[c] + q.oA, q.pA, q.ny, q.ny, q.nx, avg))) return e;
+  if (K && (e = copy4(h, false, b->K[c] + q.oP, q.pP, q.nky, q.nky, q.nkx, K))) return e;
+  if (X && (e = copy4(h, false, b->X[c] + q.oP, q.pP, q.nky, q.ny, q.nkx, X))) return e;
+  if (Y && (e = copy4(h, false, b->Y[c] + q.oP, q.pP, q.nky, q.nky, q.nx, Y))) return e;
+  if (t) *t = ds.t;
+  return AF_OK;
+}
+
+int batch_grid_info(const af_handle* h, int g, double* t, int64_t* steps) {
+  const Batch* b = h->batch;
+  if (g < 0 || g >= b->n) return fail(h, AF_ERR_INVALID_ARG, "af_get_grid_info: bad grid index");
+  DevState ds;
+  HIP_OK(hipMemcpyAsync(&ds, b->d_devs + g, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  if (t) *t = ds.t;
+  if (steps) *steps = ds.steps;
+  return AF_OK;
+}
+
+int batch_get_counters(const af_handle* h, int64_t* out) {
+  std::vector<DevState> ds;
+  if (int e = read_devs(h, ds)) return e;
+  for (int k = 0; k < AF_NCOUNTERS; ++k) out[k] = 0;
+  for (const DevState& d : ds) {
+    for (int k = 0; k < AF_NCOUNTERS; ++k)
+      if (k != AF_CNT_STEPS) out[k] += (int64_t)d.cnt[k];
+    out[AF_CNT_STEPS] = std::max<int64_t>(out[AF_CNT_STEPS], d.steps);
+  }
+  return AF_OK;
+}
+
+// One step of every grid: point kernel, fix-up (limiter on), update, commit.
+template <class R>
+static void enqueue_batch_step(af_handle* h, double dt_host) {
+  Batch* b = h->batch;
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+  if (h->timing) {
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventCreate(&e2);
+    (void)hipEventRecord(e0, h->stream);
+  }
+  if constexpr (sizeof(R) == 4)
+    hipLaunchKernelGGL(kb_points_f32, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
+                       b->d_desc, b->d_tile_grid, b->total_tiles, b->d_devs, dt_host);
+  else
+    hipLaunchKernelGGL(kb_points_f64, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
+                       b->d_desc, b->d_tile_grid, b->total_tiles, b->d_devs, dt_host);
+  if (h->limiter) {
+    const int nb = std::min(b->total_tiles, FIX_BLOCKS);
+    if constexpr (sizeof(R) == 4)
+      hipLaunchKernelGGL(kb_fixup_f32, dim3(nb), dim3(PT_THREADS), 0, h->stream, b->d_desc,
+                         b->d_tile_grid, b->d_devs, b->fix_list, b->fix_count);
+    else
+      hipLaunchKernelGGL(kb_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, h->stream, b->d_desc,
+                         b->d_tile_grid, b->d_devs, b->fix_list, b->fix_count);
+  }
+  if (h->timing) (void)hipEventRecord(e1, h->stream);
+  hipLaunchKernelGGL(kb_update, dim3(b->total_rows), dim3(BU_THREADS), 0, h->stream, b->d_desc,
+                     b->d_row_grid, b->total_rows, b->d_devs);
+  hipLaunchKernelGGL(kb_commit, dim3((b->n + 63) / 64), dim3(64), 0, h->stream, b->d_devs, b->n,
+                     b->fix_count);
+  if (h->timing) {
+    (void)hipEventRecord(e2, h->stream);
+    h->ev.push_back(e0);
+    h->ev.push_back(e1);
+    h->ev.push_back(e2);
+  }
+}
+static void enqueue_batch(af_handle* h, double dt_host) {
+  if (h->prec == AF_PREC_FP32) enqueue_batch_step<float>(h, dt_host);
+  else enqueue_batch_step<double>(h, dt_host);
+}
+
+static void collect_batch_timing(af_handle* h) {
+  for (size_t k = 0; k + 2 < h->ev.size(); k += 3) {
+    float a = 0.f, c = 0.f;
+    if (hipEventElapsedTime(&a, h->ev[k], h->ev[k + 1]) == hipSuccess &&
+        hipEventElapsedTime(&c, h->ev[k + 1], h->ev[k + 2]) == hipSuccess) {
+      h->ms_points += a;
+      h->ms_update += c;
+      h->timed_steps += 1;
+    }
+  }
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
+}
+
+static const char* batch_err_text(int code) {
+  switch (code) {
+    case ERR_NONPHYS: return "non-positive density or pressure";
+    case ERR_CFL: return "time step too large: an evolution circle leaves its cells";
+    default: return "device error";
+  }
+}
+
+// the most negative error over the grids (CFL before NONPHYSICAL), and the first grid with it
+static int first_error(const std::vector<DevState>& ds, int* grid) {
+  int e = 0;
+  for (size_t k = 0; k < ds.size(); ++k)
+    if (ds[k].err < e) { e = ds[k].err; *grid = (int)k; }
+  return e;
+}
+
+static int check_all_state(const af_handle* h, const char* fn) {
+  for (const BatchGrid& q : h->batch->g)
+    if (!q.has_state) return fail(h, AF_ERR_INVALID_ARG, std::string(fn) + ": a grid has no state");
+  return AF_OK;
+}
+
+int batch_step(af_handle* h, double dt) {
+  if (int e = check_all_state(h, "af_step")) return e;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, AF_ERR_INVALID_ARG, "af_step: dt must be > 0");
+  if (int e = upload_desc(h)) return e;
+  std::vector<DevState> ds;
+  if (int e = read_devs(h, ds)) return e;
+  for (DevState& d : ds) {
+    d.err = 0;
+    d.steps_limit = LLONG_MAX;
+  }
+  if (int e = write_devs(h, ds)) return e;
+  enqueue_batch(h, dt);
+  HIP_OK(hipGetLastError(), h);
+  if (int e = read_devs(h, ds)) return e;
+  if (h->timing) collect_batch_timing(h);
+  int g = 0;
+  if (int e = first_error(ds, &g))
+    return fail(h, e, "af_step: grid " + std::to_string(g) + ": " + batch_err_text(e));
+  return AF_OK;
+}
+
+int batch_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double* t_reached,
+              int64_t* steps_taken) {
+  if (int e = check_all_state(h, "af_run")) return e;
+  if (!(cfl > 0.0) || !(cfl < 0.5)) return fail(h, AF_ERR_INVALID_ARG, "af_run: cfl must be in (0, 0.5)");
+  if (std::isnan(t_end)) return fail(h, AF_ERR_INVALID_ARG, "af_run: t_end is NaN");
+  Batch* b = h->batch;
+  if (int e = upload_desc(h)) return e;
+  std::vector<DevState> ds;
+  if (int e = read_devs(h, ds)) return e;
+  std::vector<long long> steps0((size_t)b->n);
+  for (int k = 0; k < b->n; ++k) {
+    DevState& d = ds[k];
+    steps0[k] = d.steps;
+    d.err = 0;
+    d.t_end = t_end;
+    d.cfl = cfl;
+    d.smax[0] = d.smax[1] = 0ull;
+    d.active = 0;
+    d.steps_limit = max_steps > 0 ? d.steps + max_steps : LLONG_MAX;
+  }
+  if (int e = write_devs(h, ds)) return e;
+  const int per = 16;
+  hipLaunchKernelGGL(kb_cfl, dim3(b->n * per), dim3(256), 0, h->stream, b->d_desc, b->d_devs, per);
+  HIP_OK(hipGetLastError(), h);
+  const long long chunk = h->graph_steps > 0 ? h->graph_steps : 8;
+  while (true) {
+    // every grid stops by itself at t_end or at its step limit; the host only checks between
+    // chunks whether any grid is still running or has failed
+    if (h->timing) {
+      for (long long s = 0; s < chunk; ++s) enqueue_batch(h, 0.0);
+    } else {
+      if (!b->gexec || b->gexec_steps != chunk) {
+        if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+        hipGraph_t gr;
+        HIP_OK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), h);
+        for (long long s = 0; s < chunk; ++s) enqueue_batch(h, 0.0);
+        HIP_OK(hipStreamEndCapture(h->stream, &gr), h);
+        HIP_OK(hipGraphInstantiate(&b->gexec, gr, nullptr, nullptr, 0), h);
+        (void)hipGraphDestroy(gr);
+        b->gexec_steps = (int)chunk;
+      }
+      HIP_OK(hipGraphLaunch(b->gexec, h->stream), h);
+    }
+    HIP_OK(hipGetLastError(), h);
+    if (int e = read_devs(h, ds)) return e;
+    if (h->timing) collect_batch_timing(h);
+    double tmin = INFINITY;
+    long long smax = 0;
+    bool running = false;
+    for (int k = 0; k < b->n; ++k) {
+      tmin = std::min(tmin, ds[k].t);
+      smax = std::max(smax, ds[k].steps - steps0[k]);
+      if (ds[k].t < t_end && ds[k].steps < ds[k].steps_limit) running = true;
+    }
+    if (t_reached) *t_reached = tmin;
+    if (steps_taken) *steps_taken = smax;
+    int g = 0;
+    if (int e = first_error(ds, &g))
+      return fail(h, e, "af_run: grid " + std::to_string(g) + ": " + batch_err_text(e));
+    if (!running) break;
+  }
+  return AF_OK;
+}

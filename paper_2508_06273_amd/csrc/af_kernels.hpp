@@ -37,9 +37,12 @@ struct DevState {
   int last;   // the running step was cut to land on t_end
   int pad0;
   long long steps;
+  long long steps_limit;  // no step runs once steps reaches this
   unsigned long long cnt[8];
   unsigned int done_blocks;
   unsigned int fix_count;  // tiles listed for the positivity fix-up pass of this step
+  int cur;                 // batched grids: buffer index of the current state
+  int pad1;
 };
 
 struct Params {
@@ -67,8 +70,11 @@ struct Bufs {
   double* FX;  // 4: f sums
   double* FY;  // 4: g sums
   // positivity fix-up: per tile 3 lane masks (K, X, Y) and a listed flag; list of tiles
+  // (numbered from tile_base), and its length
   unsigned long long* fix_mask;
   int* fix_list;
+  unsigned int* fix_count;
+  int tile_base;
 };
 
 // Index of a (possibly ghost) cell or grid line, i >= -n: periodic wrap, or the outflow

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -11,403 +12,28 @@
 #include <vector>
 
 #include "af.h"
-#include "af_kernels.hpp"
+#include "af_host.hpp"
+#include "af_step.hpp"
 
 namespace af {
 
 // ------------------------------------------------------------------------------------------
-// Kernel 1: point values of one tile of 8x8 sites.
+// Kernel 1: point values, one workgroup per 8x8-site tile (XCD-aware tile order).
 // ------------------------------------------------------------------------------------------
-// Algorithm 3 applied to a high-order value U (tests in FP64).  Returns 0 or an error code.
-template <class R, int KIND>
-__device__ __forceinline__ int limit_value(const Smem<R>& S, const Params& P, const Geo<R>& G,
-                                           const double* site, int a, int b, int cb,
-                                           const double Ut[4], double tau, double U[4],
-                                           DevState* dev) {
-  if (admissible(U[0], U[3])) return 0;
-  if (admissible(Ut[0], Ut[3])) {
-    R d[4];
-    const int e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(tau), G, d);
-    if (e == ERR_CFL) return e;
-    atomicAdd(&dev->cnt[AF_CNT_EG1], 1ull);
-    double lo[4];
-    for (int v = 0; v < 4; ++v) lo[v] = Ut[v] + (double)d[v];
-    if (e == 0 && admissible(lo[0], lo[3])) {
-      for (int v = 0; v < 4; ++v) U[v] = lo[v];
-      return 0;
-    }
-  }
-  lf_update(site, a, b, tau, P, U);
-  atomicAdd(&dev->cnt[AF_CNT_LF], 1ull);
-  return admissible(U[0], U[3]) ? 0 : ERR_NONPHYS;
+__global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
+void k_points_f32(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
+  __shared__ Smem<float> S;
+  points_body<float>(S, P, B, dev, dt_host, slot,
+                     tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y), blockIdx.x == 0);
+}
+__global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
+void k_points_f64(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
+  __shared__ Smem<double> S;
+  points_body<double>(S, P, B, dev, dt_host, slot,
+                      tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y), blockIdx.x == 0);
 }
 
-// Hand a DOF that needs Algorithm 3 to the fix-up pass: set its lane bit and list the tile.
-__device__ __forceinline__ void mark_fix(const Bufs& B, DevState* dev, int tile, int kind,
-                                         int lane) {
-  atomicOr(&B.fix_mask[4 * (long long)tile + kind], 1ull << lane);
-  if (atomicExch(&B.fix_mask[4 * (long long)tile + 3], 1ull) == 0ull) {
-    const unsigned int k = atomicAdd(&dev->fix_count, 1u);
-    B.fix_list[k] = tile;
-  }
-}
-
-// One DOF through the rounds of the point update.  States are carried in FP64; the
-// evolution operators work in the bulk type R on deviations from the linearisation state.
-// FIX = false (main pass): a DOF whose value needs the positivity limiter is left to the
-// fix-up pass, which keeps the rare limiter code out of the main kernel's registers.
-// FIX = true (fix-up pass): the same computation with Algorithm 3 applied.
-template <class R, int KIND, bool FIX>
-__device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bufs& B,
-                                           DevState* dev, int tile, int a, int b, int gi,
-                                           int gj, double dt, double& speed) {
-  const Geo<R> G = {R(P.idx), R(0.5 * P.dy * P.idx), R(P.gamma), R(0.5 * P.hmin)};
-  const double* site = (KIND == KIND_K) ? S.sk : (KIND == KIND_X ? S.sx : S.sy);
-  const int s0 = sidx(a, b);
-  double U0[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) U0[v] = site[v * NS + s0];
-
-  // cells around the DOF and the neighbours of the derivative stencils
-  int cb;
-  R Ux[4], Uy[4];
-  if constexpr (KIND == KIND_K) {
-    cb = a + b * HC;  // cell (a-1, b-1)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Ux[v] = R((S.sy[v * NS + sidx(a, b)] - S.sy[v * NS + sidx(a - 1, b)]) * P.idx);
-      Uy[v] = R((S.sx[v * NS + sidx(a, b)] - S.sx[v * NS + sidx(a, b - 1)]) * P.idy);
-    }
-  } else if constexpr (KIND == KIND_X) {
-    cb = a + (b + 1) * HC;  // cell (a-1, b)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Uy[v] = R((S.sk[v * NS + sidx(a, b + 1)] - S.sk[v * NS + sidx(a, b)]) * P.idy);
-      Ux[v] = R((S.c0[v * NC + cb + 1] - S.c0[v * NC + cb]) * P.idx);
-    }
-  } else {
-    cb = (a + 1) + b * HC;  // cell (a, b-1)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Ux[v] = R((S.sk[v * NS + sidx(a + 1, b)] - S.sk[v * NS + sidx(a, b)]) * P.idx);
-      Uy[v] = R((S.c0[v * NC + cb + HC] - S.c0[v * NC + cb]) * P.idy);
-    }
-  }
-  // mean of the adjacent primitive averages (read from LDS where it is used)
-  auto avg_lin = [&](double Ut[4]) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      if constexpr (KIND == KIND_K)
-        Ut[v] = 0.25 * ((S.ub[v * NC + cb] + S.ub[v * NC + cb + 1]) +
-                        (S.ub[v * NC + cb + HC] + S.ub[v * NC + cb + HC + 1]));
-      else
-        Ut[v] = 0.5 * (S.ub[v * NC + cb] + S.ub[v * NC + cb + (KIND == KIND_X ? 1 : HC)]);
-    }
-  };
-  R Cv[4] = {R(0), R(0), R(0), R(0)};
-  if (P.correction) {
-    const R U0r[4] = {R(U0[0]), R(U0[1]), R(U0[2]), R(U0[3])};
-    corr_half(U0r, Ux, Uy, G.gamma, Cv);
-  }
-  const double h2 = 0.25 * dt * dt, f2 = dt * dt;
-
-  int e = 0;
-  double lin[4];
-  if (P.mode == LIN_AF3) {
-    R dq[4];
-    e = eg2<R, KIND>(S, cb, U0, R(0.25 * dt), G, dq);
-    if (e) { set_err(dev, e); return; }
-    double q[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) q[v] = U0[v] + (double)dq[v];
-    if (admissible(q[0], q[3])) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) lin[v] = q[v];
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) lin[v] = U0[v];
-      if (!FIX) atomicAdd(&dev->cnt[AF_CNT_INNER], 1ull);
-    }
-  } else if (P.mode == LIN_AVG) {
-    avg_lin(lin);
-  } else {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) lin[v] = U0[v];
-  }
-
-  double Uh[4], U1[4];
-  {
-    R d[4];
-    e = eg2<R, KIND>(S, cb, lin, R(0.5 * dt), G, d);
-    if (e) { set_err(dev, e); return; }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Uh[v] = lin[v] + (double)d[v] + h2 * (double)Cv[v];
-  }
-  // positivity of the intermediate value (Algorithm 3)
-  if (!admissible(Uh[0], Uh[3])) {
-    if (!P.limiter) { set_err(dev, ERR_NONPHYS); return; }
-    if constexpr (!FIX) {
-      mark_fix(B, dev, tile, KIND, threadIdx.x & 63);
-      return;
-    } else {
-      double Ut[4];
-      avg_lin(Ut);
-      e = limit_value<R, KIND>(S, P, G, site, a, b, cb, Ut, 0.5 * dt, Uh, dev);
-      if (e) { set_err(dev, e); return; }
-    }
-  }
-  {
-    R d[4];
-    e = eg2<R, KIND>(S, cb, Uh, R(dt), G, d);
-    if (e) { set_err(dev, e); return; }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) U1[v] = Uh[v] + (double)d[v] + f2 * (double)Cv[v];
-  }
-  if (P.limiter && !admissible(U1[0], U1[3])) {
-    if constexpr (!FIX) {
-      mark_fix(B, dev, tile, KIND, threadIdx.x & 63);
-      return;
-    } else {
-      double Ut[4];
-      avg_lin(Ut);
-      e = limit_value<R, KIND>(S, P, G, site, a, b, cb, Ut, dt, U1, dev);
-      if (e) { set_err(dev, e); return; }
-    }
-  }
-
-  // outputs: new point value, Simpson-in-time flux sums, wave speed
-  double* out = (KIND == KIND_K) ? B.K_out : (KIND == KIND_X ? B.X_out : B.Y_out);
-  const long long o = (long long)gj * P.pP + gi;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) out[v * P.sP + o] = U1[v];
-  const double g1inv = 1.0 / (P.gamma - 1.0);
-  double Fs[4] = {0, 0, 0, 0}, Gs[4] = {0, 0, 0, 0};
-  {
-    double Ul[4], F[4], Gq[4];
-#pragma unroll 1
-    for (int lvl = 0; lvl < 3; ++lvl) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        Ul[v] = lvl == 0 ? site[v * NS + s0] : (lvl == 1 ? Uh[v] : U1[v]);
-      flux_fg(Ul, g1inv, F, Gq);
-      const double w = lvl == 1 ? 4.0 : 1.0;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Fs[v] += w * F[v];
-        Gs[v] += w * Gq[v];
-      }
-    }
-  }
-  const long long of = (long long)gj * P.pF + gi;
-  if constexpr (KIND == KIND_K) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      B.FK[v * P.sF + of] = Fs[v];
-      B.FK[(4 + v) * P.sF + of] = Gs[v];
-    }
-  } else if constexpr (KIND == KIND_X) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) B.FX[v * P.sF + of] = Fs[v];
-  } else {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) B.FY[v * P.sF + of] = Gs[v];
-  }
-  if (admissible(U1[0], U1[3])) speed = mx(speed, wave_speed(U1, P.gamma));
-}
-
-// Step control of the point kernel: thread 0 decides and broadcasts through LDS, so that the
-// decision is uniform over the block even if another block flags an error meanwhile.
-// Returns false if the step does not run.
-__device__ __forceinline__ bool step_dt(const Params& P, DevState* dev, double dt_host, int slot,
-                                        double* dt_out) {
-  __shared__ double s_dt;
-  __shared__ int s_run;
-  if (threadIdx.x == 0) {
-    int run = 1, last = 0;
-    double dt = dt_host;
-    if (dev->err) {
-      run = 0;
-    } else if (!(dt_host > 0.0)) {
-      const double t = dev->t, te = dev->t_end;
-      const double smax = __longlong_as_double((long long)dev->smax[slot]);
-      if (!(t < te)) {
-        run = 0;
-        if (blockIdx.x == 0) dev->active = 0;
-      } else if (!(smax > 0.0) || !(smax < 1e300)) {
-        run = 0;
-        set_err(dev, ERR_NONPHYS);
-      } else {
-        dt = dev->cfl * P.hmin / smax;
-        if (t + dt >= te) { dt = te - t; last = 1; }
-      }
-    }
-    if (run && blockIdx.x == 0) {
-      dev->dt = dt;
-      dev->active = 1;
-      dev->last = last;
-    }
-    s_dt = dt;
-    s_run = run;
-  }
-  __syncthreads();
-  *dt_out = s_dt;
-  return s_run != 0;
-}
-
-// Stage the t_n point values of a tile's halo in LDS and build the halo cells'
-// reconstructions.  Ends with a barrier.
-template <class R>
-__device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, const Bufs& B,
-                                               DevState* dev, int tile, bool count) {
-  const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
-  const int tid = threadIdx.x;
-
-  // 1. stage the t_n point values of the halo (local sites -1 .. TILE) in LDS
-  for (int e = tid; e < 3 * NS; e += PT_THREADS) {
-    const int kind = e / NS, s = e % NS;
-    const int a = s % HS - 1, b = s / HS - 1;
-    const int gi = i0 + a, gj = j0 + b;
-    int si, sj;
-    const double* src;
-    double* dst;
-    if (kind == 0) {
-      si = wrap_line(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.K_in; dst = S.sk;
-    } else if (kind == 1) {
-      si = wrap_line(gi, P.nx, P.per_x); sj = wrap_cell(gj, P.ny, P.per_y); src = B.X_in; dst = S.sx;
-    } else {
-      si = wrap_cell(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.Y_in; dst = S.sy;
-    }
-    const long long o = (long long)sj * P.pP + si;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) dst[v * NS + s] = src[v * P.sP + o];
-  }
-  __syncthreads();
-
-  // 2. cell reconstructions of the halo cells (local cells -1 .. TILE-1)
-  for (int c = tid; c < NC; c += PT_THREADS) {
-    const int a = c % HC - 1, b = c / HC - 1;
-    const int gi = wrap_cell(i0 + a, P.nx, P.per_x), gj = wrap_cell(j0 + b, P.ny, P.per_y);
-    const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
-    // node k of the cell: 0..3 corners K(a,b) K(a+1,b) K(a,b+1) K(a+1,b+1),
-    // 4,5 X(a,b) X(a+1,b), 6,7 Y(a,b) Y(a,b+1)
-    const double* nptr[8] = {S.sk + sidx(a, b), S.sk + sidx(a + 1, b), S.sk + sidx(a, b + 1),
-                        S.sk + sidx(a + 1, b + 1), S.sx + sidx(a, b), S.sx + sidx(a + 1, b),
-                        S.sy + sidx(a, b), S.sy + sidx(a, b + 1)};
-    auto node = [&](int k, double W[4]) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) W[v] = (double)nptr[k][v * NS];
-    };
-    double Qb[4];
-    const long long oa = (long long)gj * P.pA + gi;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Qb[v] = B.A_in[v * P.sA + oa];
-    // reference state: mean of the eight nodes (exact for equal nodes)
-    double Wr[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Wr[v] = ((((double)nptr[0][v * NS] + (double)nptr[1][v * NS]) +
-                ((double)nptr[2][v * NS] + (double)nptr[3][v * NS])) +
-               (((double)nptr[4][v * NS] + (double)nptr[5][v * NS]) +
-                ((double)nptr[6][v * NS] + (double)nptr[7][v * NS]))) * 0.125;
-    }
-    // inverse Simpson for the centre value: Q_c = Q-bar + [sum_K (Q-bar - Q_k)
-    //                                          + 4 sum_E (Q-bar - Q_e)] / 16
-    double dQ[4], Uc[4];
-    {
-      double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, W[4], Q[4];
-      for (int k = 0; k < 8; ++k) {
-        node(k, W);
-        p2c(W, g1inv, Q);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (k < 4) sK[v] += Qb[v] - Q[v];
-          else sE[v] += Qb[v] - Q[v];
-        }
-      }
-      p2c(Wr, g1inv, Q);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Q[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
-    }
-    c2p_dev(Wr, dQ, gm1, Uc);
-    if (!admissible(Uc[0], Uc[3])) {
-      c2p_plain(Qb, gm1, Uc);
-      const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
-      if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
-    }
-    const double rho = P.dx / P.dy, rho2 = rho * rho;
-    // primitive Simpson average and monomial coefficients, one variable at a time
-#pragma unroll 1
-    for (int v = 0; v < 4; ++v) {
-      double w[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) w[k] = (double)nptr[k][v * NS];
-      const double u = Uc[v];
-      const double sK4 = ((w[0] - u) + (w[1] - u)) + ((w[2] - u) + (w[3] - u));
-      const double sE4 = ((w[4] - u) + (w[5] - u)) + ((w[6] - u) + (w[7] - u));
-      S.ub[v * NC + c] = u + (sK4 + 4.0 * sE4) * (1.0 / 36.0);
-      const double N[3][3] = {{w[0], w[4], w[2]}, {w[6], u, w[7]}, {w[1], w[5], w[3]}};
-      double cm[9];
-      nodes_to_monomials(N, cm);
-      S.c0[v * NC + c] = cm[0];
-      // c_mn of xi^m eta^n -> coefficient of xi^m (eta dy/dx)^n: the circle integrals use
-      // dx as the unit length in both directions
-#pragma unroll
-      for (int k = 1; k < 9; ++k)
-        S.ch[(v * 8 + k - 1) * NC + c] = (R)(k % 3 == 0 ? cm[k] : (k % 3 == 1 ? cm[k] * rho
-                                                                              : cm[k] * rho2));
-    }
-  }
-  __syncthreads();
-}
-
-// Evolve the tile's own DOFs: wavefront 0 -> K; wavefront 1 -> X, then Y (an edge EG2 costs
-// well under half of a corner EG2, so the two waves are about equally loaded).  In the fix-up
-// pass only the lanes listed in `mask` (per kind) run.
-template <class R, bool FIX>
-__device__ __forceinline__ void evolve_tile(Smem<R>& S, const Params& P, const Bufs& B,
-                                            DevState* dev, int tile, double dt,
-                                            const unsigned long long* mask, double& speed) {
-  const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int a = lane % TILE, b = lane / TILE;
-  const int gi = i0 + a, gj = j0 + b;
-  auto listed = [&](int kind) { return !FIX || ((mask[kind] >> lane) & 1ull); };
-  if (wave == 0) {
-    if (listed(KIND_K) && gi < P.nkx && gj < P.nky)
-      evolve_dof<R, KIND_K, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
-  } else {
-    if (listed(KIND_X) && gi < P.nkx && gj < P.ny)
-      evolve_dof<R, KIND_X, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
-    if (listed(KIND_Y) && gi < P.nx && gj < P.nky)
-      evolve_dof<R, KIND_Y, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
-  }
-}
-
-// Workgroups are dealt to the eight XCDs in turn (block b to XCD b mod 8), and each XCD has its
-// own L2.  Giving XCD x the contiguous tile range [x * ntiles/8, (x+1) * ntiles/8), in row
-// order, keeps the halos that neighbouring tiles share in one L2.  A bijection on the tile
-// indices (the last ntiles mod 8 tiles map to themselves).
-__device__ __forceinline__ int tile_of_block(int b, int ntiles) {
-  const int per = ntiles >> 3;
-  if (b >= (per << 3)) return b;
-  return (b & 7) * per + (b >> 3);
-}
-
-template <class R>
-__device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const Bufs& B,
-                                            DevState* dev, double dt_host, int slot) {
-  double dt;
-  if (!step_dt(P, dev, dt_host, slot, &dt)) return;
-  const int tile = tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y);
-  stage_and_prep(S, P, B, dev, tile, true);
-  double speed = 0.0;
-  evolve_tile<R, false>(S, P, B, dev, tile, dt, nullptr, speed);
-  block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
-}
-
-// Positivity fix-up pass: the tiles listed by the main pass are staged again and only their
-// flagged DOFs are recomputed with Algorithm 3.  Cheap when the list is empty.
+// Positivity fix-up pass over the tiles the point kernel listed.  Cheap when the list is empty.
 template <class R>
 __device__ __forceinline__ void fixup_body(Smem<R>& S, const Params& P, const Bufs& B,
                                            DevState* dev, int slot) {
@@ -417,55 +43,15 @@ __device__ __forceinline__ void fixup_body(Smem<R>& S, const Params& P, const Bu
   __shared__ double s_dt;
   if (threadIdx.x == 0) {
     s_run = !dev->err && dev->active;
-    s_n = dev->fix_count;
+    s_n = *B.fix_count;
     s_dt = dev->dt;
   }
   __syncthreads();
-  const bool run = s_run != 0;
-  const double dt = s_dt;
   const unsigned int n = s_n;
   double speed = 0.0;
-  for (unsigned int k = blockIdx.x; k < n; k += gridDim.x) {
-    const int tile = B.fix_list[k];
-    if (threadIdx.x < 3) mask[threadIdx.x] = B.fix_mask[4 * (long long)tile + threadIdx.x];
-    __syncthreads();
-    if (run) {
-      stage_and_prep(S, P, B, dev, tile, false);
-      evolve_tile<R, true>(S, P, B, dev, tile, dt, mask, speed);
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) B.fix_mask[4 * (long long)tile + threadIdx.x] = 0ull;
-  }
+  for (unsigned int k = blockIdx.x; k < n; k += gridDim.x)
+    fixup_tile<R>(S, P, B, dev, B.fix_list[k], s_dt, s_run != 0, mask, speed);
   if (n > blockIdx.x) block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
-}
-
-// One launch per step and precision.  AF_WAVES_F32 / AF_WAVES_F64 set the wavefronts per SIMD
-// that the register allocation aims at (0: the compiler's choice).
-#ifndef AF_WAVES_F32
-#define AF_WAVES_F32 0
-#endif
-#ifndef AF_WAVES_F64
-#define AF_WAVES_F64 3
-#endif
-#if AF_WAVES_F32 > 0
-#define AF_ATTR_F32 __attribute__((amdgpu_waves_per_eu(AF_WAVES_F32)))
-#else
-#define AF_ATTR_F32
-#endif
-#if AF_WAVES_F64 > 0
-#define AF_ATTR_F64 __attribute__((amdgpu_waves_per_eu(AF_WAVES_F64)))
-#else
-#define AF_ATTR_F64
-#endif
-__global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
-void k_points_f32(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
-  __shared__ Smem<float> S;
-  points_body<float>(S, P, B, dev, dt_host, slot);
-}
-__global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
-void k_points_f64(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
-  __shared__ Smem<double> S;
-  points_body<double>(S, P, B, dev, dt_host, slot);
 }
 __global__ __launch_bounds__(PT_THREADS) void k_fixup_f32(Params P, Bufs B, DevState* dev,
                                                          int slot) {
@@ -477,21 +63,19 @@ __global__ __launch_bounds__(PT_THREADS) void k_fixup_f64(Params P, Bufs B, DevS
   __shared__ Smem<double> S;
   fixup_body<double>(S, P, B, dev, slot);
 }
-constexpr int FIX_BLOCKS = 1024;
 
 // ------------------------------------------------------------------------------------------
-// Kernel 2: Simpson space-time fluxes and the conservative update of the averages.
+// Kernel 2: Simpson space-time fluxes and the conservative update of the averages.  Rows of
+// cells, UP_THREADS consecutive cells of a row per pass (coalesced); the last block to finish
+// commits t, the step counter and the wave-speed slot.
 // ------------------------------------------------------------------------------------------
-constexpr int UP_THREADS = 256;
-constexpr int UP_MAX_BLOCKS = 1024;
-
 __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* __restrict__ A_in,
                                                       double* __restrict__ A_out,
                                                       const double* __restrict__ FK,
                                                       const double* __restrict__ FX,
                                                       const double* __restrict__ FY,
                                                       DevState* dev, int slot) {
-  __shared__ double red[4];
+  __shared__ double red[UP_THREADS / 64];
   __shared__ int last_block;
   const bool run = !dev->err && dev->active;
   const double dt = dev->dt;
@@ -499,33 +83,12 @@ __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* _
   double speed = 0.0;
   bool bad = false;
   if (run) {
-    // rows of cells, 256 consecutive cells of a row per pass (coalesced)
     const int chunks_x = (P.nx + UP_THREADS - 1) / UP_THREADS;
     const long long nwork = (long long)chunks_x * P.ny;
     for (long long w = blockIdx.x; w < nwork; w += gridDim.x) {
       const int j = (int)(w / chunks_x);
       const int i = (int)(w % chunks_x) * UP_THREADS + threadIdx.x;
-      if (i >= P.nx) continue;
-      const int ip = wrap_line(i + 1, P.nx, P.per_x), jp = wrap_line(j + 1, P.ny, P.per_y);
-      const long long kw0 = (long long)j * P.pF + i, kw1 = (long long)jp * P.pF + i;
-      const long long ke0 = (long long)j * P.pF + ip, ke1 = (long long)jp * P.pF + ip;
-      const long long oa = (long long)j * P.pA + i;
-      double Q[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double* fk = FK + v * P.sF;
-        const double* gk = FK + (4 + v) * P.sF;
-        const double Fw = fk[kw0] + 4.0 * FX[v * P.sF + kw0] + fk[kw1];
-        const double Fe = fk[ke0] + 4.0 * FX[v * P.sF + ke0] + fk[ke1];
-        const double Gs = gk[kw0] + 4.0 * FY[v * P.sF + kw0] + gk[ke0];
-        const double Gn = gk[kw1] + 4.0 * FY[v * P.sF + kw1] + gk[ke1];
-        Q[v] = A_in[v * P.sA + oa] - lx * (Fe - Fw) - ly * (Gn - Gs);
-        A_out[v * P.sA + oa] = Q[v];
-      }
-      double U[4];
-      c2p_plain(Q, P.gamma - 1.0, U);
-      if (!admissible(U[0], U[3])) bad = true;
-      else speed = mx(speed, wave_speed(U, P.gamma));
+      if (i < P.nx && !update_cell(P, A_in, A_out, FK, FX, FY, lx, ly, i, j, speed)) bad = true;
     }
   }
   if (bad) set_err(dev, ERR_NONPHYS);
@@ -536,7 +99,8 @@ __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* _
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double m = mx(mx(red[0], red[1]), mx(red[2], red[3]));
+    double m = red[0];
+    for (int k = 1; k < UP_THREADS / 64; ++k) m = mx(m, red[k]);
     if (run) atomic_max_pos(&dev->smax[slot ^ 1], m);
     __threadfence();
     const unsigned int ticket = atomicAdd(&dev->done_blocks, 1u);
@@ -560,31 +124,8 @@ __global__ void k_cfl(Params P, const double* __restrict__ A, const double* __re
                       const double* __restrict__ X, const double* __restrict__ Y, DevState* dev,
                       int slot) {
   __shared__ double red[4];
-  const long long n0 = (long long)P.nx * P.ny, n1 = (long long)P.nkx * P.nky,
-                  n2 = (long long)P.nkx * P.ny, n3 = (long long)P.nx * P.nky;
-  const long long ntot = n0 + n1 + n2 + n3;
-  double speed = 0.0;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ntot;
-       e += (long long)gridDim.x * blockDim.x) {
-    double U[4];
-    if (e < n0) {
-      const int i = (int)(e % P.nx), j = (int)(e / P.nx);
-      double Q[4];
-      for (int v = 0; v < 4; ++v) Q[v] = A[v * P.sA + (long long)j * P.pA + i];
-      c2p_plain(Q, P.gamma - 1.0, U);
-    } else {
-      long long r = e - n0;
-      const double* src;
-      int w;
-      if (r < n1) { src = K; w = P.nkx; }
-      else if (r < n1 + n2) { src = X; w = P.nkx; r -= n1; }
-      else { src = Y; w = P.nx; r -= n1 + n2; }
-      const int i = (int)(r % w), j = (int)(r / w);
-      for (int v = 0; v < 4; ++v) U[v] = src[v * P.sP + (long long)j * P.pP + i];
-    }
-    // non-admissible values do not enter the time step (as NaN speeds would not)
-    if (admissible(U[0], U[3])) speed = mx(speed, wave_speed(U, P.gamma));
-  }
+  const double speed = state_speed(P, A, K, X, Y, blockIdx.x * (long long)blockDim.x + threadIdx.x,
+                                   (long long)gridDim.x * blockDim.x);
   block_max_atomic(speed, &dev->smax[slot], red);
 }
 
@@ -595,54 +136,13 @@ __global__ void k_cfl(Params P, const double* __restrict__ A, const double* __re
 // ==========================================================================================
 using namespace af;
 
-struct af_handle {
-  int nx = 0, ny = 0, per_x = 1, per_y = 1, nkx = 0, nky = 0;
-  double x0 = 0, x1 = 1, y0 = 0, y1 = 1, dx = 1, dy = 1, gamma = 1.4;
-  int prec = AF_PREC_FP64, mode = AF_LIN_AF3, correction = 1, limiter = 0;
-  int graph_steps = 16;
-  hipStream_t stream = nullptr;
-  hipStream_t own_stream = nullptr;
-  long long pA = 0, pP = 0, pF = 0;
-  double* A[2] = {nullptr, nullptr};
-  void* K[2] = {nullptr, nullptr};
-  void* X[2] = {nullptr, nullptr};
-  void* Y[2] = {nullptr, nullptr};
-  double* FK = nullptr;
-  double* FX = nullptr;
-  double* FY = nullptr;
-  unsigned long long* fix_mask = nullptr;
-  int* fix_list = nullptr;
-  DevState* dev = nullptr;
-  int cur = 0;
-  bool has_state = false;
-  long long steps_base = 0;
-  hipGraphExec_t gexec = nullptr;
-  int gexec_steps = 0;
-  // AF_OPT_TIMING: events around each kernel of every eager step
-  int timing = 0;
-  std::vector<hipEvent_t> ev;  // 3 per step: before points, between, after update
-  double ms_points = 0.0, ms_update = 0.0;
-  long long timed_steps = 0;
-  double* stage = nullptr;  // pinned host staging buffer of host <-> device copies
-  std::string err;
-};
+std::string g_create_error;
 
-static std::string g_create_error;
-
-static int fail(const af_handle* h, int code, const std::string& msg) {
+int fail(const af_handle* h, int code, const std::string& msg) {
   if (h) const_cast<af_handle*>(h)->err = msg;
   else g_create_error = msg;
   return code;
 }
-
-#define HIP_OK(call, h)                                                              \
-  do {                                                                               \
-    hipError_t e_ = (call);                                                          \
-    if (e_ != hipSuccess)                                                            \
-      return fail(h, e_ == hipErrorOutOfMemory ? AF_ERR_OOM : AF_ERR_DEVICE,         \
-                  std::string(#call) + ": " + hipGetErrorString(e_));                \
-  } while (0)
-
 
 static Params make_params(const af_handle* h) {
   Params P;
@@ -704,21 +204,37 @@ static int alloc_buffers(af_handle* h) {
   return AF_OK;
 }
 
+static int check_grid(const af_grid* grid, const af_bc* bc, const char* fn) {
+  const std::string f(fn);
+  if (grid->nx < 2 || grid->ny < 2 || grid->nx > (1 << 16) || grid->ny > (1 << 16))
+    return fail(nullptr, AF_ERR_INVALID_ARG, f + ": nx, ny must be in [2, 65536]");
+  if (!(grid->x1 > grid->x0) || !(grid->y1 > grid->y0))
+    return fail(nullptr, AF_ERR_INVALID_ARG, f + ": empty domain");
+  auto okbc = [](int k) { return k == AF_BC_PERIODIC || k == AF_BC_OUTFLOW; };
+  if (!okbc(bc->left) || !okbc(bc->right) || !okbc(bc->bottom) || !okbc(bc->top))
+    return fail(nullptr, AF_ERR_INVALID_ARG, f + ": unknown boundary kind");
+  if ((bc->left == AF_BC_PERIODIC) != (bc->right == AF_BC_PERIODIC) ||
+      (bc->bottom == AF_BC_PERIODIC) != (bc->top == AF_BC_PERIODIC))
+    return fail(nullptr, AF_ERR_INVALID_ARG, f + ": periodic must pair on an axis");
+  return AF_OK;
+}
+
+static void destroy_handle(af_handle* h) {
+  free_buffers(h);
+  batch_destroy(h);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->dev) (void)hipFree(h->dev);
+  if (h->stage) (void)hipHostFree(h->stage);
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+  delete h;
+}
+
 extern "C" int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_handle** out) {
   if (!out) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: out is NULL");
   *out = nullptr;
   if (!grid || !bc) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: NULL grid or bc");
-  if (grid->nx < 2 || grid->ny < 2 || grid->nx > (1 << 16) || grid->ny > (1 << 16))
-    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: nx, ny must be in [2, 65536]");
-  if (!(grid->x1 > grid->x0) || !(grid->y1 > grid->y0))
-    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: empty domain");
+  if (int e = check_grid(grid, bc, "af_create")) return e;
   if (!(gamma > 1.0)) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: gamma must be > 1");
-  auto okbc = [](int k) { return k == AF_BC_PERIODIC || k == AF_BC_OUTFLOW; };
-  if (!okbc(bc->left) || !okbc(bc->right) || !okbc(bc->bottom) || !okbc(bc->top))
-    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: unknown boundary kind");
-  if ((bc->left == AF_BC_PERIODIC) != (bc->right == AF_BC_PERIODIC) ||
-      (bc->bottom == AF_BC_PERIODIC) != (bc->top == AF_BC_PERIODIC))
-    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: periodic must pair on an axis");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail(nullptr, AF_ERR_DEVICE, "af_create: no HIP device");
@@ -742,26 +258,51 @@ extern "C" int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_
   }
   if (e != AF_OK) {
     g_create_error = h->err;
-    free_buffers(h);
-    if (h->dev) (void)hipFree(h->dev);
-    if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
-    delete h;
+    destroy_handle(h);
     return e;
   }
   *out = h;
   return AF_OK;
 }
 
+extern "C" int af_create_batch(int32_t n, const af_grid* grids, double gamma, const af_bc* bcs,
+                               af_handle** out) {
+  if (!out) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create_batch: out is NULL");
+  *out = nullptr;
+  if (n < 1 || !grids || !bcs)
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create_batch: need n >= 1 grids and bcs");
+  for (int k = 0; k < n; ++k)
+    if (int e = check_grid(&grids[k], &bcs[k], "af_create_batch")) return e;
+  if (!(gamma > 1.0)) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create_batch: gamma must be > 1");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, AF_ERR_DEVICE, "af_create_batch: no HIP device");
+  af_handle* h = new af_handle();
+  h->gamma = gamma;
+  int e = AF_OK;
+  if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
+    e = fail(h, AF_ERR_DEVICE, "af_create_batch: hipStreamCreate");
+  h->stream = h->own_stream;
+  if (e == AF_OK) e = batch_create(n, grids, gamma, bcs, h);
+  if (e != AF_OK) {
+    g_create_error = h->err;
+    destroy_handle(h);
+    return e;
+  }
+  *out = h;
+  return AF_OK;
+}
+
+extern "C" int32_t af_batch_size(const af_handle* h) {
+  if (!h) return 0;
+  return h->batch ? batch_count(h) : 1;
+}
+
 extern "C" void af_destroy(af_handle* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
-  free_buffers(h);
-  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
-  if (h->dev) (void)hipFree(h->dev);
-  if (h->stage) (void)hipHostFree(h->stage);
-  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
-  delete h;
+  destroy_handle(h);
 }
 
 extern "C" const char* af_last_error(const af_handle* h) {
@@ -770,6 +311,7 @@ extern "C" const char* af_last_error(const af_handle* h) {
 
 extern "C" int64_t af_dof_count(const af_handle* h) {
   if (!h) return 0;
+  if (h->batch) return batch_dof_count(h);
   return (int64_t)h->nx * h->ny + (int64_t)h->nkx * h->nky + (int64_t)h->nkx * h->ny +
          (int64_t)h->nx * h->nky;
 }
@@ -780,11 +322,8 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
     case AF_OPT_PRECISION:
       if (value != AF_PREC_FP64 && value != AF_PREC_FP32)
         return fail(h, AF_ERR_INVALID_ARG, "af_set_option: precision must be FP64 or FP32");
-      if (value != h->prec) {
-        h->prec = (int)value;
-        return alloc_buffers(h);
-      }
-      return AF_OK;
+      h->prec = (int)value;  // storage is FP64 in both precisions: the state is kept
+      break;
     case AF_OPT_LINEARISATION:
       if (value < 0 || value > 2) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: bad mode");
       h->mode = (int)value;
@@ -812,6 +351,7 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
       return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown key");
   }
   if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
+  batch_invalidate(h);
   return AF_OK;
 }
 
@@ -820,6 +360,7 @@ extern "C" int af_set_stream(af_handle* h, void* s) {
   (void)hipStreamSynchronize(h->stream);
   h->stream = s ? (hipStream_t)s : h->own_stream;
   if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
+  batch_invalidate(h);
   return AF_OK;
 }
 
@@ -836,7 +377,7 @@ static int ensure_stage(const af_handle* hc) {
 
 // One variable: host FP64 rows x cols (unpadded, row-major) <-> device FP64 rows x cols with
 // a row pitch of `pitch` elements.
-static int copy2d(const af_handle* h, bool to_device, double* dev, long long pitch, int rows,
+int copy2d(const af_handle* h, bool to_device, double* dev, long long pitch, int rows,
                   int cols, double* host) {
   if (cols > pitch) return fail(h, AF_ERR_INVALID_ARG, "copy2d: cols exceed pitch");
   if (int e = ensure_stage(h)) return e;
@@ -863,7 +404,7 @@ static int copy2d(const af_handle* h, bool to_device, double* dev, long long pit
 
 // The padded arrays store variable v at offset v * rows_alloc * pitch: copy one variable at a
 // time.
-static int copy4(const af_handle* h, bool to_device, void* dev, long long pitch, int rows_alloc,
+int copy4(const af_handle* h, bool to_device, void* dev, long long pitch, int rows_alloc,
                  int rows, int cols, double* host) {
   if (rows > rows_alloc) return fail(h, AF_ERR_INVALID_ARG, "copy4: rows exceed allocation");
   for (int v = 0; v < 4; ++v) {
@@ -877,6 +418,11 @@ static int copy4(const af_handle* h, bool to_device, void* dev, long long pitch,
 extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, const double* X,
                             const double* Y, double t) {
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_state: NULL handle");
+  if (h->batch) {
+    if (batch_count(h) != 1)
+      return fail(h, AF_ERR_INVALID_ARG, "af_set_state: batched handle, use af_set_state_grid");
+    return batch_set_state(h, 0, avg, K, X, Y, t);
+  }
   if (!avg || !K || !X || !Y) return fail(h, AF_ERR_INVALID_ARG, "af_set_state: NULL array");
   if (!std::isfinite(t)) return fail(h, AF_ERR_INVALID_ARG, "af_set_state: t not finite");
   const size_t nc = (size_t)h->nx * h->ny;
@@ -900,6 +446,7 @@ extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, co
   std::memset(&ds, 0, sizeof(ds));
   ds.t = t;
   ds.t_end = t;
+  ds.steps_limit = LLONG_MAX;
   HIP_OK(hipMemcpyAsync(h->dev, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
   HIP_OK(hipStreamSynchronize(h->stream), h);
   h->has_state = true;
@@ -910,6 +457,11 @@ extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, co
 extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* X, double* Y,
                             double* t) {
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_get_state: NULL handle");
+  if (h->batch) {
+    if (batch_count(h) != 1)
+      return fail(h, AF_ERR_INVALID_ARG, "af_get_state: batched handle, use af_get_state_grid");
+    return batch_get_state(h, 0, avg, K, X, Y, t);
+  }
   if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_get_state: no state set");
   const int c = h->cur;
   int e;
@@ -928,6 +480,7 @@ extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* 
 
 extern "C" int af_get_counters(const af_handle* h, int64_t* out) {
   if (!h || !out) return fail(h, AF_ERR_INVALID_ARG, "af_get_counters: NULL argument");
+  if (h->batch) return batch_get_counters(h, out);
   DevState ds;
   HIP_OK(hipMemcpyAsync(&ds, h->dev, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
   HIP_OK(hipStreamSynchronize(h->stream), h);
@@ -948,6 +501,7 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
   B.K_out = (double*)h->K[out]; B.X_out = (double*)h->X[out]; B.Y_out = (double*)h->Y[out];
   B.FK = h->FK; B.FX = h->FX; B.FY = h->FY;
   B.fix_mask = h->fix_mask; B.fix_list = h->fix_list;
+  B.fix_count = &h->dev->fix_count; B.tile_base = 0;
   const int ntiles = P.tiles_x * P.tiles_y;
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (h->timing) {
@@ -1020,15 +574,15 @@ static const char* err_text(int code) {
 
 extern "C" int af_step(af_handle* h, double dt) {
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step: NULL handle");
+  if (h->batch) return batch_step(h, dt);
   if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_step: no state set");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, AF_ERR_INVALID_ARG, "af_step: dt must be > 0");
   DevState ds;
   int e = read_dev(h, &ds);
   if (e) return e;
-  if (ds.err) {
-    ds.err = 0;
-    HIP_OK(hipMemcpyAsync(&h->dev->err, &ds.err, sizeof(int), hipMemcpyHostToDevice, h->stream), h);
-  }
+  ds.err = 0;
+  ds.steps_limit = LLONG_MAX;
+  HIP_OK(hipMemcpyAsync(h->dev, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
   const long long before = ds.steps;
   enqueue_step(h, h->cur, dt);
   HIP_OK(hipGetLastError(), h);
@@ -1043,6 +597,7 @@ extern "C" int af_step(af_handle* h, double dt) {
 extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
                       double* t_reached, int64_t* steps_taken) {
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_run: NULL handle");
+  if (h->batch) return batch_run(h, t_end, cfl, max_steps, t_reached, steps_taken);
   if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_run: no state set");
   if (!(cfl > 0.0) || !(cfl < 0.5)) return fail(h, AF_ERR_INVALID_ARG, "af_run: cfl must be in (0, 0.5)");
   if (std::isnan(t_end)) return fail(h, AF_ERR_INVALID_ARG, "af_run: t_end is NaN");
@@ -1055,6 +610,7 @@ extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
   ds.cfl = cfl;
   ds.smax[0] = ds.smax[1] = 0ull;
   ds.done_blocks = 0;
+  ds.steps_limit = max_steps > 0 ? steps0 + max_steps : LLONG_MAX;
   HIP_OK(hipMemcpyAsync(h->dev, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
   {
     const Params P = make_params(h);
@@ -1107,5 +663,38 @@ extern "C" int af_get_timing(const af_handle* h, double* out) {
   out[0] = h->ms_points;
   out[1] = h->ms_update;
   out[2] = (double)h->timed_steps;
+  return AF_OK;
+}
+
+extern "C" int af_set_state_grid(af_handle* h, int32_t g, const double* avg, const double* K,
+                                 const double* X, const double* Y, double t) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_state_grid: NULL handle");
+  if (!h->batch) {
+    if (g != 0) return fail(h, AF_ERR_INVALID_ARG, "af_set_state_grid: bad grid index");
+    return af_set_state(h, avg, K, X, Y, t);
+  }
+  return batch_set_state(h, g, avg, K, X, Y, t);
+}
+
+extern "C" int af_get_state_grid(const af_handle* h, int32_t g, double* avg, double* K, double* X,
+                                 double* Y, double* t) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_get_state_grid: NULL handle");
+  if (!h->batch) {
+    if (g != 0) return fail(h, AF_ERR_INVALID_ARG, "af_get_state_grid: bad grid index");
+    return af_get_state(h, avg, K, X, Y, t);
+  }
+  return batch_get_state(h, g, avg, K, X, Y, t);
+}
+
+extern "C" int af_get_grid_info(const af_handle* h, int32_t g, double* t, int64_t* steps) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_get_grid_info: NULL handle");
+  if (h->batch) return batch_grid_info(h, g, t, steps);
+  if (g != 0) return fail(h, AF_ERR_INVALID_ARG, "af_get_grid_info: bad grid index");
+  if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_get_grid_info: no state set");
+  DevState ds;
+  HIP_OK(hipMemcpyAsync(&ds, h->dev, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  if (t) *t = ds.t;
+  if (steps) *steps = ds.steps;
   return AF_OK;
 }

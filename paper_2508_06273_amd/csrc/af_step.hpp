@@ -1,0 +1,511 @@
+// af_step.hpp -- device functions of one Active Flux step shared by the single-grid and the
+// batched kernels: step control, halo staging and cell reconstruction, the point-value update
+// of a tile (with the hand-off to the positivity fix-up), the fix-up of a tile, the
+// conservative update of a cell and the wave-speed maximum of a state.
+#pragma once
+#include "af.h"
+#include "af_kernels.hpp"
+
+namespace af {
+
+// AF_WAVES_F32 / AF_WAVES_F64 set the wavefronts per SIMD that the register allocation of the
+// point kernels aims at (0: the compiler's choice).
+#ifndef AF_WAVES_F32
+#define AF_WAVES_F32 0
+#endif
+#ifndef AF_WAVES_F64
+#define AF_WAVES_F64 0
+#endif
+#if AF_WAVES_F32 > 0
+#define AF_ATTR_F32 __attribute__((amdgpu_waves_per_eu(AF_WAVES_F32)))
+#else
+#define AF_ATTR_F32
+#endif
+#if AF_WAVES_F64 > 0
+#define AF_ATTR_F64 __attribute__((amdgpu_waves_per_eu(AF_WAVES_F64)))
+#else
+#define AF_ATTR_F64
+#endif
+
+constexpr int FIX_BLOCKS = 1024;     // fix-up workgroups (grid-stride over the listed tiles)
+constexpr int UP_THREADS = 256;      // update kernel workgroup
+constexpr int UP_MAX_BLOCKS = 1024;  // update kernel grid cap (grid-stride)
+
+// ------------------------------------------------------------------------------------------
+// Kernel 1: point values of one tile of 8x8 sites.
+// ------------------------------------------------------------------------------------------
+// Algorithm 3 applied to a high-order value U (tests in FP64).  Returns 0 or an error code.
+template <class R, int KIND>
+__device__ __forceinline__ int limit_value(const Smem<R>& S, const Params& P, const Geo<R>& G,
+                                           const double* site, int a, int b, int cb,
+                                           const double Ut[4], double tau, double U[4],
+                                           DevState* dev) {
+  if (admissible(U[0], U[3])) return 0;
+  if (admissible(Ut[0], Ut[3])) {
+    R d[4];
+    const int e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(tau), G, d);
+    if (e == ERR_CFL) return e;
+    atomicAdd(&dev->cnt[AF_CNT_EG1], 1ull);
+    double lo[4];
+    for (int v = 0; v < 4; ++v) lo[v] = Ut[v] + (double)d[v];
+    if (e == 0 && admissible(lo[0], lo[3])) {
+      for (int v = 0; v < 4; ++v) U[v] = lo[v];
+      return 0;
+    }
+  }
+  lf_update(site, a, b, tau, P, U);
+  atomicAdd(&dev->cnt[AF_CNT_LF], 1ull);
+  return admissible(U[0], U[3]) ? 0 : ERR_NONPHYS;
+}
+
+// Hand a DOF that needs Algorithm 3 to the fix-up pass: set its lane bit and list the tile.
+__device__ __forceinline__ void mark_fix(const Bufs& B, int tile, int kind, int lane) {
+  atomicOr(&B.fix_mask[4 * (long long)tile + kind], 1ull << lane);
+  if (atomicExch(&B.fix_mask[4 * (long long)tile + 3], 1ull) == 0ull) {
+    const unsigned int k = atomicAdd(B.fix_count, 1u);
+    B.fix_list[k] = B.tile_base + tile;
+  }
+}
+
+// One DOF through the rounds of the point update.  States are carried in FP64; the
+// evolution operators work in the bulk type R on deviations from the linearisation state.
+// FIX = false (main pass): a DOF whose value needs the positivity limiter is left to the
+// fix-up pass, which keeps the rare limiter code out of the main kernel's registers.
+// FIX = true (fix-up pass): the same computation with Algorithm 3 applied.
+template <class R, int KIND, bool FIX>
+__device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bufs& B,
+                                           DevState* dev, int tile, int a, int b, int gi,
+                                           int gj, double dt, double& speed) {
+  const Geo<R> G = {R(P.idx), R(0.5 * P.dy * P.idx), R(P.gamma), R(0.5 * P.hmin)};
+  const double* site = (KIND == KIND_K) ? S.sk : (KIND == KIND_X ? S.sx : S.sy);
+  const int s0 = sidx(a, b);
+  double U0[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) U0[v] = site[v * NS + s0];
+
+  // cells around the DOF and the neighbours of the derivative stencils
+  int cb;
+  R Ux[4], Uy[4];
+  if constexpr (KIND == KIND_K) {
+    cb = a + b * HC;  // cell (a-1, b-1)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ux[v] = R((S.sy[v * NS + sidx(a, b)] - S.sy[v * NS + sidx(a - 1, b)]) * P.idx);
+      Uy[v] = R((S.sx[v * NS + sidx(a, b)] - S.sx[v * NS + sidx(a, b - 1)]) * P.idy);
+    }
+  } else if constexpr (KIND == KIND_X) {
+    cb = a + (b + 1) * HC;  // cell (a-1, b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Uy[v] = R((S.sk[v * NS + sidx(a, b + 1)] - S.sk[v * NS + sidx(a, b)]) * P.idy);
+      Ux[v] = R((S.c0[v * NC + cb + 1] - S.c0[v * NC + cb]) * P.idx);
+    }
+  } else {
+    cb = (a + 1) + b * HC;  // cell (a, b-1)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Ux[v] = R((S.sk[v * NS + sidx(a + 1, b)] - S.sk[v * NS + sidx(a, b)]) * P.idx);
+      Uy[v] = R((S.c0[v * NC + cb + HC] - S.c0[v * NC + cb]) * P.idy);
+    }
+  }
+  // mean of the adjacent primitive averages (read from LDS where it is used)
+  auto avg_lin = [&](double Ut[4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if constexpr (KIND == KIND_K)
+        Ut[v] = 0.25 * ((S.ub[v * NC + cb] + S.ub[v * NC + cb + 1]) +
+                        (S.ub[v * NC + cb + HC] + S.ub[v * NC + cb + HC + 1]));
+      else
+        Ut[v] = 0.5 * (S.ub[v * NC + cb] + S.ub[v * NC + cb + (KIND == KIND_X ? 1 : HC)]);
+    }
+  };
+  R Cv[4] = {R(0), R(0), R(0), R(0)};
+  if (P.correction) {
+    const R U0r[4] = {R(U0[0]), R(U0[1]), R(U0[2]), R(U0[3])};
+    corr_half(U0r, Ux, Uy, G.gamma, Cv);
+  }
+  const double h2 = 0.25 * dt * dt, f2 = dt * dt;
+
+  int e = 0;
+  double lin[4];
+  if (P.mode == LIN_AF3) {
+    R dq[4];
+    e = eg2<R, KIND>(S, cb, U0, R(0.25 * dt), G, dq);
+    if (e) { set_err(dev, e); return; }
+    double q[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = U0[v] + (double)dq[v];
+    if (admissible(q[0], q[3])) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lin[v] = q[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lin[v] = U0[v];
+      if (!FIX) atomicAdd(&dev->cnt[AF_CNT_INNER], 1ull);
+    }
+  } else if (P.mode == LIN_AVG) {
+    avg_lin(lin);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) lin[v] = U0[v];
+  }
+
+  double Uh[4], U1[4];
+  {
+    R d[4];
+    e = eg2<R, KIND>(S, cb, lin, R(0.5 * dt), G, d);
+    if (e) { set_err(dev, e); return; }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Uh[v] = lin[v] + (double)d[v] + h2 * (double)Cv[v];
+  }
+  // positivity of the intermediate value (Algorithm 3)
+  if (!admissible(Uh[0], Uh[3])) {
+    if (!P.limiter) { set_err(dev, ERR_NONPHYS); return; }
+    if constexpr (!FIX) {
+      mark_fix(B, tile, KIND, threadIdx.x & 63);
+      return;
+    } else {
+      double Ut[4];
+      avg_lin(Ut);
+      e = limit_value<R, KIND>(S, P, G, site, a, b, cb, Ut, 0.5 * dt, Uh, dev);
+      if (e) { set_err(dev, e); return; }
+    }
+  }
+  {
+    R d[4];
+    e = eg2<R, KIND>(S, cb, Uh, R(dt), G, d);
+    if (e) { set_err(dev, e); return; }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) U1[v] = Uh[v] + (double)d[v] + f2 * (double)Cv[v];
+  }
+  if (P.limiter && !admissible(U1[0], U1[3])) {
+    if constexpr (!FIX) {
+      mark_fix(B, tile, KIND, threadIdx.x & 63);
+      return;
+    } else {
+      double Ut[4];
+      avg_lin(Ut);
+      e = limit_value<R, KIND>(S, P, G, site, a, b, cb, Ut, dt, U1, dev);
+      if (e) { set_err(dev, e); return; }
+    }
+  }
+
+  // outputs: new point value, Simpson-in-time flux sums, wave speed
+  double* out = (KIND == KIND_K) ? B.K_out : (KIND == KIND_X ? B.X_out : B.Y_out);
+  const long long o = (long long)gj * P.pP + gi;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[v * P.sP + o] = U1[v];
+  const double g1inv = 1.0 / (P.gamma - 1.0);
+  double Fs[4] = {0, 0, 0, 0}, Gs[4] = {0, 0, 0, 0};
+  {
+    double Ul[4], F[4], Gq[4];
+#pragma unroll 1
+    for (int lvl = 0; lvl < 3; ++lvl) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Ul[v] = lvl == 0 ? site[v * NS + s0] : (lvl == 1 ? Uh[v] : U1[v]);
+      flux_fg(Ul, g1inv, F, Gq);
+      const double w = lvl == 1 ? 4.0 : 1.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Fs[v] += w * F[v];
+        Gs[v] += w * Gq[v];
+      }
+    }
+  }
+  const long long of = (long long)gj * P.pF + gi;
+  if constexpr (KIND == KIND_K) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      B.FK[v * P.sF + of] = Fs[v];
+      B.FK[(4 + v) * P.sF + of] = Gs[v];
+    }
+  } else if constexpr (KIND == KIND_X) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) B.FX[v * P.sF + of] = Fs[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) B.FY[v * P.sF + of] = Gs[v];
+  }
+  if (admissible(U1[0], U1[3])) speed = mx(speed, wave_speed(U1, P.gamma));
+}
+
+// Step control of the point kernel: thread 0 decides and broadcasts through LDS, so that the
+// decision is uniform over the block even if another block flags an error meanwhile.  One
+// block per grid (`leader`) records dt and the run flags for the later kernels of the step.
+// Returns false if the step does not run.
+__device__ __forceinline__ bool step_dt(const Params& P, DevState* dev, double dt_host, int slot,
+                                        bool leader, double* dt_out) {
+  __shared__ double s_dt;
+  __shared__ int s_run;
+  if (threadIdx.x == 0) {
+    int run = 1, last = 0;
+    double dt = dt_host;
+    if (dev->err) {
+      run = 0;
+    } else if (dev->steps >= dev->steps_limit) {
+      run = 0;
+      if (leader) dev->active = 0;
+    } else if (!(dt_host > 0.0)) {
+      const double t = dev->t, te = dev->t_end;
+      const double smax = __longlong_as_double((long long)dev->smax[slot]);
+      if (!(t < te)) {
+        run = 0;
+        if (leader) dev->active = 0;
+      } else if (!(smax > 0.0) || !(smax < 1e300)) {
+        run = 0;
+        set_err(dev, ERR_NONPHYS);
+      } else {
+        dt = dev->cfl * P.hmin / smax;
+        if (t + dt >= te) { dt = te - t; last = 1; }
+      }
+    }
+    if (run && leader) {
+      dev->dt = dt;
+      dev->active = 1;
+      dev->last = last;
+    }
+    s_dt = dt;
+    s_run = run;
+  }
+  __syncthreads();
+  *dt_out = s_dt;
+  return s_run != 0;
+}
+
+// Stage the t_n point values of a tile's halo in LDS and build the halo cells'
+// reconstructions.  Ends with a barrier.
+template <class R>
+__device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, const Bufs& B,
+                                               DevState* dev, int tile, bool count) {
+  const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
+  const int tid = threadIdx.x;
+
+  // 1. stage the t_n point values of the halo (local sites -1 .. TILE) in LDS
+  for (int e = tid; e < 3 * NS; e += PT_THREADS) {
+    const int kind = e / NS, s = e % NS;
+    const int a = s % HS - 1, b = s / HS - 1;
+    const int gi = i0 + a, gj = j0 + b;
+    int si, sj;
+    const double* src;
+    double* dst;
+    if (kind == 0) {
+      si = wrap_line(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.K_in; dst = S.sk;
+    } else if (kind == 1) {
+      si = wrap_line(gi, P.nx, P.per_x); sj = wrap_cell(gj, P.ny, P.per_y); src = B.X_in; dst = S.sx;
+    } else {
+      si = wrap_cell(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.Y_in; dst = S.sy;
+    }
+    const long long o = (long long)sj * P.pP + si;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[v * NS + s] = src[v * P.sP + o];
+  }
+  __syncthreads();
+
+  // 2. cell reconstructions of the halo cells (local cells -1 .. TILE-1)
+  for (int c = tid; c < NC; c += PT_THREADS) {
+    const int a = c % HC - 1, b = c / HC - 1;
+    const int gi = wrap_cell(i0 + a, P.nx, P.per_x), gj = wrap_cell(j0 + b, P.ny, P.per_y);
+    const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
+    // node k of the cell: 0..3 corners K(a,b) K(a+1,b) K(a,b+1) K(a+1,b+1),
+    // 4,5 X(a,b) X(a+1,b), 6,7 Y(a,b) Y(a,b+1)
+    const double* nptr[8] = {S.sk + sidx(a, b), S.sk + sidx(a + 1, b), S.sk + sidx(a, b + 1),
+                        S.sk + sidx(a + 1, b + 1), S.sx + sidx(a, b), S.sx + sidx(a + 1, b),
+                        S.sy + sidx(a, b), S.sy + sidx(a, b + 1)};
+    auto node = [&](int k, double W[4]) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[v] = (double)nptr[k][v * NS];
+    };
+    double Qb[4];
+    const long long oa = (long long)gj * P.pA + gi;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Qb[v] = B.A_in[v * P.sA + oa];
+    // reference state: mean of the eight nodes (exact for equal nodes)
+    double Wr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wr[v] = ((((double)nptr[0][v * NS] + (double)nptr[1][v * NS]) +
+                ((double)nptr[2][v * NS] + (double)nptr[3][v * NS])) +
+               (((double)nptr[4][v * NS] + (double)nptr[5][v * NS]) +
+                ((double)nptr[6][v * NS] + (double)nptr[7][v * NS]))) * 0.125;
+    }
+    // inverse Simpson for the centre value: Q_c = Q-bar + [sum_K (Q-bar - Q_k)
+    //                                          + 4 sum_E (Q-bar - Q_e)] / 16
+    double dQ[4], Uc[4];
+    {
+      double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, W[4], Q[4];
+      for (int k = 0; k < 8; ++k) {
+        node(k, W);
+        p2c(W, g1inv, Q);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (k < 4) sK[v] += Qb[v] - Q[v];
+          else sE[v] += Qb[v] - Q[v];
+        }
+      }
+      p2c(Wr, g1inv, Q);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Q[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
+    }
+    c2p_dev(Wr, dQ, gm1, Uc);
+    if (!admissible(Uc[0], Uc[3])) {
+      c2p_plain(Qb, gm1, Uc);
+      const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
+      if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
+    }
+    const double rho = P.dx / P.dy, rho2 = rho * rho;
+    // primitive Simpson average and monomial coefficients, one variable at a time
+#pragma unroll 1
+    for (int v = 0; v < 4; ++v) {
+      double w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = (double)nptr[k][v * NS];
+      const double u = Uc[v];
+      const double sK4 = ((w[0] - u) + (w[1] - u)) + ((w[2] - u) + (w[3] - u));
+      const double sE4 = ((w[4] - u) + (w[5] - u)) + ((w[6] - u) + (w[7] - u));
+      S.ub[v * NC + c] = u + (sK4 + 4.0 * sE4) * (1.0 / 36.0);
+      const double N[3][3] = {{w[0], w[4], w[2]}, {w[6], u, w[7]}, {w[1], w[5], w[3]}};
+      double cm[9];
+      nodes_to_monomials(N, cm);
+      S.c0[v * NC + c] = cm[0];
+      // c_mn of xi^m eta^n -> coefficient of xi^m (eta dy/dx)^n: the circle integrals use
+      // dx as the unit length in both directions
+#pragma unroll
+      for (int k = 1; k < 9; ++k)
+        S.ch[(v * 8 + k - 1) * NC + c] = (R)(k % 3 == 0 ? cm[k] : (k % 3 == 1 ? cm[k] * rho
+                                                                              : cm[k] * rho2));
+    }
+  }
+  __syncthreads();
+}
+
+// Evolve the tile's own DOFs: wavefront 0 -> K; wavefront 1 -> X, then Y (an edge EG2 costs
+// well under half of a corner EG2, so the two waves are about equally loaded).  In the fix-up
+// pass only the lanes listed in `mask` (per kind) run.
+template <class R, bool FIX>
+__device__ __forceinline__ void evolve_tile(Smem<R>& S, const Params& P, const Bufs& B,
+                                            DevState* dev, int tile, double dt,
+                                            const unsigned long long* mask, double& speed) {
+  const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int a = lane % TILE, b = lane / TILE;
+  const int gi = i0 + a, gj = j0 + b;
+  auto listed = [&](int kind) { return !FIX || ((mask[kind] >> lane) & 1ull); };
+  if (wave == 0) {
+    if (listed(KIND_K) && gi < P.nkx && gj < P.nky)
+      evolve_dof<R, KIND_K, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
+  } else {
+    if (listed(KIND_X) && gi < P.nkx && gj < P.ny)
+      evolve_dof<R, KIND_X, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
+    if (listed(KIND_Y) && gi < P.nx && gj < P.nky)
+      evolve_dof<R, KIND_Y, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
+  }
+}
+
+// Workgroups are dealt to the eight XCDs in turn (block b to XCD b mod 8), and each XCD has its
+// own L2.  Giving XCD x the contiguous tile range [x * ntiles/8, (x+1) * ntiles/8), in row
+// order, keeps the halos that neighbouring tiles share in one L2.  A bijection on the tile
+// indices (the last ntiles mod 8 tiles map to themselves).
+__device__ __forceinline__ int tile_of_block(int b, int ntiles) {
+  const int per = ntiles >> 3;
+  if (b >= (per << 3)) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+// One tile of the point kernel.  `slot` is the buffer index of the t_n state (its wave-speed
+// maximum is smax[slot]; the new state's goes to smax[slot ^ 1]).
+template <class R>
+__device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const Bufs& B,
+                                            DevState* dev, double dt_host, int slot, int tile,
+                                            bool leader) {
+  double dt;
+  if (!step_dt(P, dev, dt_host, slot, leader, &dt)) return;
+  stage_and_prep(S, P, B, dev, tile, true);
+  double speed = 0.0;
+  evolve_tile<R, false>(S, P, B, dev, tile, dt, nullptr, speed);
+  block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
+}
+
+// Positivity fix-up of one listed tile: stage and prepare it again and recompute only the
+// lanes flagged in its masks with Algorithm 3; then clear the masks.  Block-uniform `run`.
+template <class R>
+__device__ __forceinline__ void fixup_tile(Smem<R>& S, const Params& P, const Bufs& B,
+                                           DevState* dev, int tile, double dt, bool run,
+                                           unsigned long long* mask, double& speed) {
+  if (threadIdx.x < 3) mask[threadIdx.x] = B.fix_mask[4 * (long long)tile + threadIdx.x];
+  __syncthreads();
+  if (run) {
+    stage_and_prep(S, P, B, dev, tile, false);
+    evolve_tile<R, true>(S, P, B, dev, tile, dt, mask, speed);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) B.fix_mask[4 * (long long)tile + threadIdx.x] = 0ull;
+}
+
+// Conservative update of cell (i, j) (eqs. F and 2dfvm): the four Simpson face fluxes from the
+// per-site Simpson-in-time sums, then the FP64 update.  lx = dt / (36 dx), ly = dt / (36 dy).
+// Returns false if the new average is not admissible; else raises `speed` to its wave speed.
+__device__ __forceinline__ bool update_cell(const Params& P, const double* __restrict__ A_in,
+                                            double* __restrict__ A_out,
+                                            const double* __restrict__ FK,
+                                            const double* __restrict__ FX,
+                                            const double* __restrict__ FY, double lx, double ly,
+                                            int i, int j, double& speed) {
+  const int ip = wrap_line(i + 1, P.nx, P.per_x), jp = wrap_line(j + 1, P.ny, P.per_y);
+  const long long kw0 = (long long)j * P.pF + i, kw1 = (long long)jp * P.pF + i;
+  const long long ke0 = (long long)j * P.pF + ip, ke1 = (long long)jp * P.pF + ip;
+  const long long oa = (long long)j * P.pA + i;
+  double Q[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double* fk = FK + v * P.sF;
+    const double* gk = FK + (4 + v) * P.sF;
+    const double Fw = fk[kw0] + 4.0 * FX[v * P.sF + kw0] + fk[kw1];
+    const double Fe = fk[ke0] + 4.0 * FX[v * P.sF + ke0] + fk[ke1];
+    const double Gs = gk[kw0] + 4.0 * FY[v * P.sF + kw0] + gk[ke0];
+    const double Gn = gk[kw1] + 4.0 * FY[v * P.sF + kw1] + gk[ke1];
+    Q[v] = A_in[v * P.sA + oa] - lx * (Fe - Fw) - ly * (Gn - Gs);
+    A_out[v * P.sA + oa] = Q[v];
+  }
+  double U[4];
+  c2p_plain(Q, P.gamma - 1.0, U);
+  if (!admissible(U[0], U[3])) return false;
+  speed = mx(speed, wave_speed(U, P.gamma));
+  return true;
+}
+
+// Largest wave speed over the DOFs e0, e0 + stride, ... of a state (averages, then K, X, Y in
+// storage order), for the time step before a run.  Non-admissible values do not enter.
+__device__ __forceinline__ double state_speed(const Params& P, const double* __restrict__ A,
+                                              const double* __restrict__ K,
+                                              const double* __restrict__ X,
+                                              const double* __restrict__ Y, long long e0,
+                                              long long stride) {
+  const long long n0 = (long long)P.nx * P.ny, n1 = (long long)P.nkx * P.nky,
+                  n2 = (long long)P.nkx * P.ny, n3 = (long long)P.nx * P.nky;
+  const long long ntot = n0 + n1 + n2 + n3;
+  double speed = 0.0;
+  for (long long e = e0; e < ntot; e += stride) {
+    double U[4];
+    if (e < n0) {
+      const int i = (int)(e % P.nx), j = (int)(e / P.nx);
+      double Q[4];
+      for (int v = 0; v < 4; ++v) Q[v] = A[v * P.sA + (long long)j * P.pA + i];
+      c2p_plain(Q, P.gamma - 1.0, U);
+    } else {
+      long long r = e - n0;
+      const double* src;
+      int w;
+      if (r < n1) { src = K; w = P.nkx; }
+      else if (r < n1 + n2) { src = X; w = P.nkx; r -= n1; }
+      else { src = Y; w = P.nx; r -= n1 + n2; }
+      const int i = (int)(r % w), j = (int)(r / w);
+      for (int v = 0; v < 4; ++v) U[v] = src[v * P.sP + (long long)j * P.pP + i];
+    }
+    if (admissible(U[0], U[3])) speed = mx(speed, wave_speed(U, P.gamma));
+  }
+  return speed;
+}
+
+}  // namespace af

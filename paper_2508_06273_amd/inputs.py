@@ -362,6 +362,42 @@ def fourier_field(seed: int):
     return fn
 
 
+def fourier_tensor(seed: int, xs: np.ndarray, ys: np.ndarray) -> np.ndarray:
+    """fourier_field(seed) on the tensor grid ys x xs, shape (4, len(ys), len(xs)).
+
+    Each variable is base + amp * Re(sum_q a_q e^{i phi_q} e^{2 pi i m_q x} e^{2 pi i n_q y}),
+    one (ny x 8) @ (8 x nx) complex product per variable."""
+    amp = [0.2, 0.3, 0.3, 0.2]
+    base = [1.0, 0.0, 0.0, 1.0]
+    out = np.empty((4, len(ys), len(xs)))
+    for k in range(4):
+        m, n, phi, a = fourier_modes(seed + 17 * k)
+        ex = np.exp(2j * math.pi * np.outer(xs, m))            # (nx, 8)
+        ey = np.exp(2j * math.pi * np.outer(ys, n)) * (a * np.exp(1j * phi))  # (ny, 8)
+        out[k] = base[k] + amp[k] * (ey @ ex.T).real
+    return out
+
+
+def fourier_state(seed: int, grid: Grid, gamma: float = GAMMA, n_gl: int = 4,
+                  name: str = "") -> State:
+    """state_from_field(fourier_field(seed), grid, gamma, n_gl) computed on tensor grids."""
+    g, w = np.polynomial.legendre.leggauss(n_gl)
+    g, w = 0.5 * g, 0.5 * w
+    xc = grid.x0 + (np.arange(grid.nx) + 0.5) * grid.dx
+    yc = grid.y0 + (np.arange(grid.ny) + 0.5) * grid.dy
+    avg = np.zeros((4, grid.ny, grid.nx))
+    for b in range(n_gl):
+        for a in range(n_gl):
+            W = fourier_tensor(seed, xc + g[a] * grid.dx, yc + g[b] * grid.dy)
+            avg += (w[a] * w[b]) * prim_to_cons(W, gamma)
+    xk = grid.x0 + np.arange(grid.nkx) * grid.dx
+    yk = grid.y0 + np.arange(grid.nky) * grid.dy
+    K = fourier_tensor(seed, xk, yk)
+    X = fourier_tensor(seed, xk, yc)
+    Y = fourier_tensor(seed, xc, yk)
+    return State(grid, gamma, avg, K, X, Y, 0.0, name)
+
+
 def batched_sizes(n_grids: int = 256, seed: int = SEED_BASE + 4000, lo: int = 64,
                   hi: int = 512):
     u = uniform01(seed, n_grids)
@@ -370,12 +406,13 @@ def batched_sizes(n_grids: int = 256, seed: int = SEED_BASE + 4000, lo: int = 64
 
 def batched_states(n_grids: int = 256, seed: int = SEED_BASE + 4000, lo: int = 64,
                    hi: int = 512, n_gl: int = 4, sizes=None):
+    """The batched workload: periodic N x N grids on [0,1]^2, N ~ U{lo..hi}, grid g with the
+    Fourier data of seed + 100 (g + 1)."""
     sizes = batched_sizes(n_grids, seed, lo, hi) if sizes is None else sizes
     out = []
     for g, N in enumerate(sizes):
         grid = Grid(int(N), int(N), 0.0, 1.0, 0.0, 1.0)
-        out.append(state_from_field(fourier_field(seed + 100 * (g + 1)), grid, GAMMA, n_gl,
-                                    f"batch{g}_{N}"))
+        out.append(fourier_state(seed + 100 * (g + 1), grid, GAMMA, n_gl, f"batch{g}_{N}"))
     return out
 
 

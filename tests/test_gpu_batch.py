@@ -1,0 +1,192 @@
+"""Batched grids (af_create_batch): many independent grids advanced with one launch of each
+kernel per step.
+
+The batched kernels run the same per-DOF arithmetic as the single-grid kernels (only the
+mapping of workgroups to tiles and rows differs, and the wave-speed maximum is order
+independent), so a batch must reproduce separate single-grid handles bit for bit, each grid
+with its own time step.  Against the FP64 oracle the tolerance is the single-grid one.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06273_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+af = pytest.importorskip("paper_2508_06273_amd.af")
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _mixed_states():
+    """Uneven grids: ragged tile counts, an outflow grid, a non-square domain, a tiny grid."""
+    out = [I.fourier_state(11, I.Grid(37, 29, 0.0, 1.0, 0.0, 1.0), I.GAMMA, 3),
+           I.fourier_state(12, I.Grid(16, 16, 0.0, 1.0, 0.0, 1.0), I.GAMMA, 3),
+           I.fourier_state(13, I.Grid(9, 11, 0.0, 1.0, 0.0, 1.0), I.GAMMA, 3),
+           I.shu_vortex(40, n_gl=3),
+           I.radial_state(24, n_gl=3, noise=0.0)]
+    g = out[4].grid
+    assert g.bc_x == I.BC_OUTFLOW
+    return out
+
+
+def _singles(states, steps, **kw):
+    res = []
+    for st in states:
+        s = af.Solver.for_state(st, **kw)
+        t, n = s.run(1e9, 0.3, steps)
+        res.append((s.get_state(), n, s.counters()))
+        s.close()
+    return res
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("mode,limiter", [(0, False), (1, True)])
+def test_batch_equals_single_handles(prec, mode, limiter):
+    _flush(f"[gpu] batch vs single handles prec={prec} mode={mode} limiter={limiter}")
+    states = _mixed_states()
+    kw = dict(precision=prec, linearisation=mode, limiter=limiter)
+    ref = _singles(states, 7, **kw)
+    b = af.BatchSolver.for_states(states, **kw)
+    assert len(b) == len(states)
+    t, n = b.run(1e9, 0.3, 7)
+    assert n == 7
+    for g, (out_s, n_s, _) in enumerate(ref):
+        out_b = b.get_state(g)
+        tg, ng = b.grid_info(g)
+        assert ng == n_s == 7
+        assert tg == out_s["t"]
+        for k in ("avg", "K", "X", "Y"):
+            assert np.array_equal(out_b[k], out_s[k]), (g, k)
+    cnt = b.counters()
+    tot = sum(c for (_, _, c) in ref)
+    assert list(cnt[:4]) == list(tot[:4])
+    assert b.dof_count() == sum(st.grid.dof_count() for st in states)
+    b.close()
+
+
+def test_batch_matches_oracle_fp64():
+    _flush("[gpu] batch vs oracle, 3 grids x 4 steps")
+    states = _mixed_states()[:3]
+    b = af.BatchSolver.for_states(states)
+    b.run(1e9, 0.3, 4)
+    for g, st in enumerate(states):
+        e, n, _ = oracle.run(st, 1e9, 0.3, max_steps=4)
+        assert e == 0 and n == 4
+        out = b.get_state(g)
+        scale = max(float(np.abs(st.avg).max()), float(np.abs(st.K).max()))
+        for k in ("avg", "K", "X", "Y"):
+            assert np.abs(out[k] - getattr(st, k)).max() < 1e-12 * scale, (g, k)
+    b.close()
+
+
+def test_batch_each_grid_lands_on_t_end():
+    """Own time step per grid: a coarse and a fine grid reach the same t_end with different
+    step counts, each exactly, as separate handles do."""
+    _flush("[gpu] batch per-grid t_end")
+    states = [I.fourier_state(21, I.Grid(12, 12, 0.0, 1.0, 0.0, 1.0), I.GAMMA, 3),
+              I.fourier_state(22, I.Grid(48, 48, 0.0, 1.0, 0.0, 1.0), I.GAMMA, 3)]
+    t_end = 0.05
+    b = af.BatchSolver.for_states(states)
+    t, n = b.run(t_end, 0.3)
+    info = [b.grid_info(g) for g in range(2)]
+    assert info[0][0] == t_end and info[1][0] == t_end
+    assert info[1][1] > info[0][1]
+    for g, st in enumerate(states):
+        s = af.Solver.for_state(st)
+        ts, ns = s.run(t_end, 0.3)
+        assert ts == t_end and ns == info[g][1]
+        ref = s.get_state()
+        out = b.get_state(g)
+        for k in ("avg", "K", "X", "Y"):
+            assert np.array_equal(out[k], ref[k])
+        s.close()
+    assert t == t_end and n == info[1][1]
+    b.close()
+
+
+def test_batch_step_error_stays_in_its_grid():
+    """af_step with one dt for all grids: the fine grid violates its CFL bound and keeps its
+    state; the coarse grid advances; the error names the failing grid."""
+    _flush("[gpu] batch step error isolation")
+    coarse = I.fourier_state(31, I.Grid(8, 8, 0.0, 1.0, 0.0, 1.0), I.GAMMA, 3)
+    fine = I.fourier_state(32, I.Grid(64, 64, 0.0, 1.0, 0.0, 1.0), I.GAMMA, 3)
+    b = af.BatchSolver.for_states([coarse, fine])
+    dt = 0.3 / 8 / 1.6  # within the coarse grid's bound, far beyond the fine grid's
+    with pytest.raises(af.AfError) as ei:
+        b.step(dt)
+    assert ei.value.code == af.AF_ERR_CFL and "grid 1" in str(ei.value)
+    out_f = b.get_state(1)
+    for k in ("avg", "K", "X", "Y"):
+        assert np.array_equal(out_f[k], getattr(fine, k))
+    assert b.grid_info(1) == (0.0, 0)
+    tc, nc = b.grid_info(0)
+    assert nc == 1 and tc == dt
+    s = af.Solver.for_state(coarse)
+    s.step(dt)
+    ref = s.get_state()
+    out_c = b.get_state(0)
+    for k in ("avg", "K", "X", "Y"):
+        assert np.array_equal(out_c[k], ref[k])
+    s.close()
+    b.close()
+
+
+def test_batch_bad_arguments():
+    import ctypes as ct
+    states = _mixed_states()[:2]
+    b = af.BatchSolver.for_states(states)
+    P = lambda a: np.ascontiguousarray(a).ctypes.data_as(ct.POINTER(ct.c_double))
+    st = states[0]
+    # grid index out of range: refused by the library before any copy
+    assert b.L.af_set_state_grid(b.h, 2, P(st.avg), P(st.K), P(st.X), P(st.Y), 0.0) == \
+        af.AF_ERR_INVALID_ARG
+    out = np.zeros(st.avg.shape)
+    assert b.L.af_get_state_grid(b.h, -1, P(out), None, None, None, None) == \
+        af.AF_ERR_INVALID_ARG
+    # the single-grid calls refuse a handle with several grids
+    assert b.L.af_get_state(b.h, P(out), None, None, None, None) == af.AF_ERR_INVALID_ARG
+    # shapes are checked by the binding
+    with pytest.raises(ValueError):
+        b.set_state(0, states[1].avg, states[1].K, states[1].X, states[1].Y)
+    b.close()
+    with pytest.raises(af.AfError):
+        af.BatchSolver([])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_workload_full_size_sampled(prec):
+    """The batched workload at its full size (256 periodic grids, N ~ U{64..512}), in the launch
+    configuration the benchmark times: 3 steps, then the three smallest grids are compared bit
+    for bit with single-grid handles and the smallest with the oracle."""
+    _flush(f"[gpu] batched workload 256 grids, prec={prec}")
+    sizes = I.batched_sizes()
+    states = I.batched_states(n_gl=2, sizes=sizes)
+    b = af.BatchSolver.for_states(states, precision=prec)
+    t, n = b.run(1e9, 0.3, 3)
+    assert n == 3
+    small = list(np.argsort(sizes, kind="stable")[:3])
+    for g in small:
+        s = af.Solver.for_state(states[g], precision=prec)
+        s.run(1e9, 0.3, 3)
+        ref = s.get_state()
+        out = b.get_state(int(g))
+        for k in ("avg", "K", "X", "Y"):
+            assert np.array_equal(out[k], ref[k]), (g, k)
+        s.close()
+    g0 = int(small[0])
+    st = states[g0]
+    e, n2, _ = oracle.run(st, 1e9, 0.3, max_steps=3)
+    assert e == 0 and n2 == 3
+    out = b.get_state(g0)
+    tol = 1e-12 if prec == 0 else 1e-5
+    scale = max(float(np.abs(st.avg).max()), float(np.abs(st.K).max()))
+    for k in ("avg", "K", "X", "Y"):
+        assert np.abs(out[k] - getattr(st, k)).max() < tol * scale, k
+    b.close()

@@ -3,7 +3,7 @@
 Tolerances: the FP64 path and the oracle evaluate the same formulas in different orders and
 with different exact circle integrations (trigonometric moments vs. Gauss-Legendre), so they
 agree to rounding: |diff| <= 1e-12 * scale after the step counts used here.  The FP32 path
-stores point values in FP32 (unit roundoff 6e-8); its tolerance is 2e-5 * scale after one
+evaluates the evolution operators in FP32 on FP64 deviations; its tolerance is 2e-5 * scale after one
 step and 1e-4 * scale after 20.
 """
 import math
