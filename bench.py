@@ -158,6 +158,40 @@ def run_gpu(st, prec, steps, warmup, stream):
                 dofs=dofs, state=out)
 
 
+def run_batched(prec, steps, warmup, stream, n_gl=2):
+    """The batched workload (256 periodic grids, N ~ U{64..512}, own dt per grid): DOF-updates/s
+    of one graph-captured launch sequence per step for all grids."""
+    from paper_2508_06273_amd import af, inputs as I
+    import torch
+    states = run_batched.states
+    if states is None:
+        states = run_batched.states = I.batched_states(n_gl=n_gl)
+    b = af.BatchSolver.for_states(states, precision=prec)
+    b.set_stream(stream)
+    b.run(1e9, 0.3, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t, n = b.run(1e9, 0.3, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert n == steps
+    # per-kernel times from a few eager steps with events
+    b.set_option(af.AF_OPT_TIMING, 1)
+    b.run(1e9, 0.3, 16)
+    kp, ku, nt = b.timing()
+    dofs = b.dof_count()
+    b.close()
+    return dict(value=dofs * steps / (ms * 1e-3), ms_per_step=ms / steps,
+                ms_points=kp / nt, ms_update=ku / nt, dofs=dofs,
+                cells=sum(st.grid.nx * st.grid.ny for st in states), grids=len(states))
+
+
+run_batched.states = None
+
+
 def cpu_baseline(seconds: float, n_cpu: int):
     import oracle
     from paper_2508_06273_amd import inputs as I
@@ -189,6 +223,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-grids leg (256 uneven grids)")
+    ap.add_argument("--batched-steps", type=int, default=32,
+                    help="timed steps of the batched leg (a multiple of 16: whole graphs)")
     ap.add_argument("--prec", choices=("both", "fp32", "fp64"), default="both",
                     help="profiling aid: run one precision only (no JSON line)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -301,6 +339,21 @@ def main():
                       for name, r in res.items()},
         "source_sha": source_hash(),
     }
+    if not args.no_batched:
+        print("[bench] batched workload: 256 grids", file=sys.stderr, flush=True)
+        bres = {name: run_batched(prec, args.batched_steps, 16, stream)
+                for prec, name in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64"))}
+        line["batched"] = {
+            "workload": "256 periodic grids N x N on [0,1]^2, N ~ U{64..512} (seeded), random "
+                        "Fourier data, Algorithm 1 with correction, CFL 0.3, own dt per grid",
+            "grids": bres["fp32"]["grids"], "cells": bres["fp32"]["cells"],
+            "dof_sites": bres["fp32"]["dofs"], "steps": args.batched_steps,
+            "fp32": {k: bres["fp32"][k] for k in ("value", "ms_per_step", "ms_points",
+                                                   "ms_update")},
+            "fp64": {k: bres["fp64"][k] for k in ("value", "ms_per_step", "ms_points",
+                                                   "ms_update")},
+            "speedup_fp32_vs_fp64": bres["fp32"]["value"] / bres["fp64"]["value"],
+            "unit": "DOF-updates/s"}
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, args.cpu_n)

@@ -189,30 +189,35 @@ __device__ __forceinline__ void br_piece(Br<R>& B, R Ca, R Sa, R Cb, R Sb, R L) 
   }
 }
 
-template <class R> __device__ __forceinline__ void moments(const Br<R>& B, Mom<R>& M) {
+// Moments of the circle of radius a (M'[i][j] = a^(i+j) M[i][j]) from brackets taken at the
+// scaled end points (a C, a S): the reduction formulas keep their form with a^2 on the
+// lower-order moment.
+template <class R>
+__device__ __forceinline__ void moments(const Br<R>& B, R a2, Mom<R>& M) {
   const R i2 = R(0.5), i3 = R(1) / R(3), i4 = R(0.25), i5 = R(0.2), i6 = R(1) / R(6);
+  const R b2 = a2 + a2, b3 = b2 + a2;
   M.m[0][0] = B.L;
   M.m[1][0] = B.s1;
   M.m[0][1] = -B.c1;
-  M.m[2][0] = (B.cs + M.m[0][0]) * i2;
-  M.m[3][0] = (B.c2s + R(2) * M.m[1][0]) * i3;
-  M.m[4][0] = (B.c3s + R(3) * M.m[2][0]) * i4;
+  M.m[2][0] = (B.cs + a2 * M.m[0][0]) * i2;
+  M.m[3][0] = (B.c2s + b2 * M.m[1][0]) * i3;
+  M.m[4][0] = (B.c3s + b3 * M.m[2][0]) * i4;
   M.m[1][1] = -B.c2 * i2;
   M.m[2][1] = -B.c3 * i3;
   M.m[3][1] = -B.c4 * i4;
   M.m[4][1] = -B.c5 * i5;
-  M.m[0][2] = (M.m[0][0] - B.cs) * i2;
-  M.m[1][2] = (M.m[1][0] - B.c2s) * i3;
-  M.m[2][2] = (M.m[2][0] - B.c3s) * i4;
-  M.m[3][2] = (M.m[3][0] - B.c4s) * i5;
-  M.m[4][2] = (M.m[4][0] - B.c5s) * i6;
-  M.m[0][3] = (R(2) * M.m[0][1] - B.cs2) * i3;
-  M.m[1][3] = (R(2) * M.m[1][1] - B.c2s2) * i4;
-  M.m[2][3] = (R(2) * M.m[2][1] - B.c3s2) * i5;
-  M.m[3][3] = (R(2) * M.m[3][1] - B.c4s2) * i6;
-  M.m[0][4] = (R(3) * M.m[0][2] - B.cs3) * i4;
-  M.m[1][4] = (R(3) * M.m[1][2] - B.c2s3) * i5;
-  M.m[2][4] = (R(3) * M.m[2][2] - B.c3s3) * i6;
+  M.m[0][2] = (a2 * M.m[0][0] - B.cs) * i2;
+  M.m[1][2] = (a2 * M.m[1][0] - B.c2s) * i3;
+  M.m[2][2] = (a2 * M.m[2][0] - B.c3s) * i4;
+  M.m[3][2] = (a2 * M.m[3][0] - B.c4s) * i5;
+  M.m[4][2] = (a2 * M.m[4][0] - B.c5s) * i6;
+  M.m[0][3] = (b2 * M.m[0][1] - B.cs2) * i3;
+  M.m[1][3] = (b2 * M.m[1][1] - B.c2s2) * i4;
+  M.m[2][3] = (b2 * M.m[2][1] - B.c3s2) * i5;
+  M.m[3][3] = (b2 * M.m[3][1] - B.c4s2) * i6;
+  M.m[0][4] = (b3 * M.m[0][2] - B.cs3) * i4;
+  M.m[1][4] = (b3 * M.m[1][2] - B.c2s3) * i5;
+  M.m[2][4] = (b3 * M.m[2][2] - B.c3s3) * i6;
   M.m[4][3] = M.m[3][4] = M.m[4][4] = R(0);
 }
 
@@ -239,8 +244,8 @@ template <class T> __device__ __forceinline__ void nodes_to_monomials(const T W[
 }
 
 // Substitute xi = xi0 + a C, eta = eta0 + a S into sum c_mn xi^m eta^n.  The result is
-// sum e_kl (aC)^k (aS)^l; the powers of the radius a are carried by the moments (see
-// scale_moments), so the substitution itself needs no multiplications by a.  Both local
+// sum e_kl (aC)^k (aS)^l; the powers of the radius a are carried by the moments (those of the
+// circle of radius a), so the substitution itself needs no multiplication by a.  Both local
 // coordinates are in units of dx (the y-coefficients are stored premultiplied by (dx/dy)^n).
 // c00 is the constant coefficient (already a deviation); `ch` points at c_01 of one variable
 // of one cell in LDS, the coefficients c_01 .. c_22 `stride` apart.
@@ -287,44 +292,49 @@ template <class R> struct Acc {
 
 // Arc (-alpha, alpha) from (m, -s) to (m, s), symmetric in S: the moments with odd b vanish.
 // Arc (beta, pi - beta) from (q, w) to (-q, w), symmetric in C: the moments with odd a vanish.
-// (The reduction formulas above, with the brackets of these end points written out.)
+// Scaled moments of the circle of radius a, from the scaled end points ma = a m, sa = a s
+// (qa = a q, wa = a w) and a2 = a^2: the reduction formulas above with the brackets of these
+// end points written out.
 template <class R>
-__device__ __forceinline__ void moments_sym_x(R m, R s, R alpha, Mom<R>& M) {
+__device__ __forceinline__ void moments_sym_x(R ma, R sa, R alpha, R a2, Mom<R>& M) {
   const R i3 = R(1) / R(3), i5 = R(0.2), i6 = R(1) / R(6);
-  const R ms = m * s, m2s = m * ms, m3s = m * m2s, m4s = m * m3s, m5s = m * m4s;
-  const R s2 = s * s;
+  const R s2 = sa + sa;
+  const R m1s = ma * s2, m2s = ma * m1s, m3s = ma * m2s, m4s = ma * m3s, m5s = ma * m4s;
+  const R sa2 = sa * sa;
+  const R b2 = a2 + a2, b3 = b2 + a2;
   M.m[0][0] = alpha + alpha;
-  M.m[1][0] = s + s;
-  M.m[2][0] = ms + alpha;
-  M.m[3][0] = (R(2) * m2s + R(2) * M.m[1][0]) * i3;
-  M.m[4][0] = (R(2) * m3s + R(3) * M.m[2][0]) * R(0.25);
-  M.m[0][2] = alpha - ms;
-  M.m[1][2] = (M.m[1][0] - R(2) * m2s) * i3;
-  M.m[2][2] = (M.m[2][0] - R(2) * m3s) * R(0.25);
-  M.m[3][2] = (M.m[3][0] - R(2) * m4s) * i5;
-  M.m[4][2] = (M.m[4][0] - R(2) * m5s) * i6;
-  M.m[0][4] = (R(3) * M.m[0][2] - R(2) * ms * s2) * R(0.25);
-  M.m[1][4] = (R(3) * M.m[1][2] - R(2) * m2s * s2) * i5;
-  M.m[2][4] = (R(3) * M.m[2][2] - R(2) * m3s * s2) * i6;
+  M.m[1][0] = s2;
+  M.m[2][0] = R(0.5) * m1s + a2 * alpha;
+  M.m[3][0] = (m2s + b2 * M.m[1][0]) * i3;
+  M.m[4][0] = (m3s + b3 * M.m[2][0]) * R(0.25);
+  M.m[0][2] = a2 * alpha - R(0.5) * m1s;
+  M.m[1][2] = (a2 * M.m[1][0] - m2s) * i3;
+  M.m[2][2] = (a2 * M.m[2][0] - m3s) * R(0.25);
+  M.m[3][2] = (a2 * M.m[3][0] - m4s) * i5;
+  M.m[4][2] = (a2 * M.m[4][0] - m5s) * i6;
+  M.m[0][4] = (b3 * M.m[0][2] - m1s * sa2) * R(0.25);
+  M.m[1][4] = (b3 * M.m[1][2] - m2s * sa2) * i5;
+  M.m[2][4] = (b3 * M.m[2][2] - m3s * sa2) * i6;
 }
 template <class R>
-__device__ __forceinline__ void moments_sym_y(R q, R w, R L, Mom<R>& M) {
+__device__ __forceinline__ void moments_sym_y(R qa, R wa, R L, R a2, Mom<R>& M) {
   const R i3 = R(1) / R(3), i5 = R(0.2), i6 = R(1) / R(6);
-  const R q2 = q * q, q3 = q2 * q, q5 = q3 * q2, w2 = w * w;
-  const R qw = q * w, q3w = q3 * w;
+  const R q2 = qa * qa, q3 = q2 * qa, q5 = q3 * q2, w2 = wa * wa;
+  const R qw = qa * wa, q3w = q3 * wa;
+  const R b2 = a2 + a2, b3 = b2 + a2;
   M.m[0][0] = L;
-  M.m[0][1] = q + q;
-  M.m[2][0] = (L - R(2) * qw) * R(0.5);
-  M.m[4][0] = (R(3) * M.m[2][0] - R(2) * q3w) * R(0.25);
+  M.m[0][1] = qa + qa;
+  M.m[2][0] = R(0.5) * (a2 * L) - qw;
+  M.m[4][0] = (b3 * M.m[2][0] - R(2) * q3w) * R(0.25);
   M.m[2][1] = R(2) * q3 * i3;
   M.m[4][1] = R(2) * q5 * i5;
-  M.m[0][2] = (L + R(2) * qw) * R(0.5);
-  M.m[2][2] = (M.m[2][0] + R(2) * q3w) * R(0.25);
-  M.m[4][2] = (M.m[4][0] + R(2) * q5 * w) * i6;
-  M.m[0][3] = (R(4) * q + R(2) * qw * w) * i3;
-  M.m[2][3] = (R(2) * M.m[2][1] + R(2) * q3w * w) * i5;
-  M.m[0][4] = (R(3) * M.m[0][2] + R(2) * qw * w2) * R(0.25);
-  M.m[2][4] = (R(3) * M.m[2][2] + R(2) * q3w * w2) * i6;
+  M.m[0][2] = R(0.5) * (a2 * L) + qw;
+  M.m[2][2] = (a2 * M.m[2][0] + R(2) * q3w) * R(0.25);
+  M.m[4][2] = (a2 * M.m[4][0] + R(2) * q5 * wa) * i6;
+  M.m[0][3] = (R(2) * b2 * qa + R(2) * qw * wa) * i3;
+  M.m[2][3] = (b2 * M.m[2][1] + R(2) * q3w * wa) * i5;
+  M.m[0][4] = (b3 * M.m[0][2] + R(2) * qw * w2) * R(0.25);
+  M.m[2][4] = (b3 * M.m[2][2] + R(2) * q3w * w2) * i6;
 }
 
 // Per-variable contractions with the moments of one arc set.  SYM = 1 (odd-b moments zero),
@@ -371,26 +381,6 @@ __device__ __forceinline__ void contract_v(const R d[9], const Mom<R>& M, Acc<R>
       if (nz<SYM>(k, l + 2)) A.Va += x * M.m[k][l + 2];
       if (nz<SYM>(k, l)) A.Vb += x * M.m[k][l];
     }
-}
-
-// Moments of the scaled circle: M[i][j] <- a^(i+j) M[i][j] (the entries the contractions
-// read for the arc symmetry SYM).  Contracting these with the coefficients e of circle_shift
-// gives a times the true C-weighted and S-weighted integrals and a^2 times the quadratic
-// ones; the caller divides once at the end.
-template <int SYM, class R> __device__ __forceinline__ void scale_moments(Mom<R>& M, R a) {
-  R pw[7];
-  pw[0] = R(1);
-  pw[1] = a;
-  pw[2] = a * a;
-  pw[3] = pw[2] * a;
-  pw[4] = pw[2] * pw[2];
-  pw[5] = pw[4] * a;
-  pw[6] = pw[4] * pw[2];
-#pragma unroll
-  for (int i = 0; i < 5; ++i)
-#pragma unroll
-    for (int j = 0; j < 5; ++j)
-      if (i + j > 0 && i + j <= 6 && nz<SYM>(i, j)) M.m[i][j] *= pw[i + j];
 }
 
 // Scaled moments of the full circle (SYM = 3: only even powers of C and S survive):

@@ -203,6 +203,8 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
       const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
       const R al = MA::acos_(cMx), be = MA::asin_(cMy);
       const R Ly = pi - R(2) * be;
+      // end points of the arcs on the circle of radius ar (the moments are those of that circle)
+      const R cxa = ar * cMx, sxa = ar * sxx, sya = ar * syy, cya = ar * cMy, a2 = ar * ar;
       Mom<R> Mq;
       {
         // upper-right arc set: (-al, al) cap (be, pi - be), pieces for the shifts 0 and -2 pi
@@ -214,12 +216,11 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
           const R lo2 = be + sh, hi2 = pi - be + sh;
           const bool l1 = -al >= lo2, h1 = al <= hi2;
           const R lo = l1 ? -al : lo2, hi = h1 ? al : hi2;
-          const R Ca = l1 ? cMx : syy, Sa = l1 ? -sxx : cMy;
-          const R Cb = h1 ? cMx : -syy, Sb = h1 ? sxx : cMy;
+          const R Ca = l1 ? cxa : sya, Sa = l1 ? -sxa : cya;
+          const R Cb = h1 ? cxa : -sya, Sb = h1 ? sxa : cya;
           br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
         }
-        moments(B, Mq);
-        scale_moments<0>(Mq, ar);
+        moments(B, a2, Mq);
       }
       const int cLL = cb, cLR = cb + 1, cUL = cb + HC, cUR = cb + HC + 1;
       const R xl = px + R(0.5), xr = px - R(0.5), yb = py + hy, yt = py - hy;
@@ -227,12 +228,11 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
       for (int var = 1; var < 4; ++var) {
         // the half-circle moments are cheap: they are formed again for each variable (an
         // empty asm keeps the compiler from hoisting them and holding 26 more registers)
-        R m1 = cMx, s1 = sxx, a1 = al, q2 = syy, w2 = cMy, l2 = Ly, r1 = ar;
-        asm volatile("" : "+v"(m1), "+v"(s1), "+v"(a1), "+v"(q2), "+v"(w2), "+v"(l2), "+v"(r1));
+        R m1 = cxa, s1 = sxa, a1 = al, q2 = sya, w2 = cya, l2 = Ly, r2 = a2;
+        asm volatile("" : "+v"(m1), "+v"(s1), "+v"(a1), "+v"(q2), "+v"(w2), "+v"(l2), "+v"(r2));
         R t[9], r[9], w[9];
         Mom<R> Mx;
-        moments_sym_x(m1, s1, a1, Mx);
-        scale_moments<1>(Mx, r1);
+        moments_sym_x(m1, s1, a1, r2, Mx);
         circle_shift(dev0(var, cLL), ch + var * VS + cLL, NC, xl, yb, t);
         circle_shift(dev0(var, cLR), ch + var * VS + cLR, NC, xr, yb, r);
 #pragma unroll
@@ -248,8 +248,7 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
           r[i] += d;  // P_LR + P_UL - P_LL
         }
         Mom<R> My;
-        moments_sym_y(q2, w2, l2, My);
-        scale_moments<2>(My, r1);
+        moments_sym_y(q2, w2, l2, r2, My);
         if (var == 3) contract_p<2>(w, My, A);
         if (var == 1) contract_u<2>(w, My, A);
         if (var == 2) contract_v<2>(w, My, A);
@@ -267,15 +266,17 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
       const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
       const R al = MA::acos_(cMx), be = MA::asin_(cMy);
       const R twopi = R(2 * kPi);
+      // end points of the arcs on the circle of radius ar (the moments are those of that circle)
+      const R cxa = ar * cMx, sxa = ar * sxx, sya = ar * syy, cya = ar * cMy, ar2 = ar * ar;
 #pragma unroll 1
       for (int q = 0; q < 4; ++q) {
         const int sx = q & 1, sy = q >> 1;
         // x interval of side sx: right (-al, al), left (al, 2pi - al)
         const R a1 = sx ? -al : al, b1 = sx ? al : twopi - al;
-        const R sa1 = sx ? -sxx : sxx;  // sin at a1 (cos is cMx at both ends)
+        const R sa1 = sx ? -sxa : sxa;  // a sin at a1 (a cos is cxa at both ends)
         // y interval of side sy: top (be, pi - be), bottom (pi - be, 2pi + be)
         const R a2 = sy ? be : pi - be, b2 = sy ? pi - be : twopi + be;
-        const R ca2 = sy ? syy : -syy;  // cos at a2 (sin is cMy at both ends)
+        const R ca2 = sy ? sya : -sya;  // a cos at a2 (a sin is cya at both ends)
         Br<R> B;
         br_zero(B);
         // the intersection is made of the pieces I_x cap (I_y + 2 pi k), k = 0 and one k = +-1
@@ -286,13 +287,12 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
           const R lo2 = a2 + sh, hi2 = b2 + sh;
           const bool l1 = a1 >= lo2, h1 = b1 <= hi2;
           const R lo = l1 ? a1 : lo2, hi = h1 ? b1 : hi2;
-          const R Ca = l1 ? cMx : ca2, Sa = l1 ? sa1 : cMy;
-          const R Cb = h1 ? cMx : -ca2, Sb = h1 ? -sa1 : cMy;
+          const R Ca = l1 ? cxa : ca2, Sa = l1 ? sa1 : cya;
+          const R Cb = h1 ? cxa : -ca2, Sb = h1 ? -sa1 : cya;
           br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
         }
         Mom<R> M;
-        moments(B, M);
-        scale_moments<0>(M, ar);
+        moments(B, ar2, M);
         const int cell = cb + sx + sy * HC;
         const R xi0 = px + R(0.5) - R(sx), eta0 = py + (sy ? -hy : hy);
         R d[9];
@@ -311,12 +311,10 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
     Mom<R> M;
     if constexpr (KIND == KIND_X) {
       const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
-      moments_sym_x(cMx, sxx, MA::acos_(cMx), M);
-      scale_moments<1>(M, ar);
+      moments_sym_x(ar * cMx, ar * sxx, MA::acos_(cMx), ar * ar, M);
     } else {
       const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
-      moments_sym_y(syy, cMy, pi - R(2) * MA::asin_(cMy), M);
-      scale_moments<2>(M, ar);
+      moments_sym_y(ar * syy, ar * cMy, pi - R(2) * MA::asin_(cMy), ar * ar, M);
     }
     const int cl = cb, chh = cb + (KIND == KIND_X ? 1 : HC);
     const R xl = (KIND == KIND_X) ? px + R(0.5) : px;

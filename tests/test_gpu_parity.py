@@ -260,20 +260,47 @@ def test_cfl_error_and_bad_arguments():
 # full size (4096^2 vortex, the benchmark workload): sampled parity of one step
 # ------------------------------------------------------------------------------------------
 def _patch(full, ci, cj, half=4):
-    """Outflow patch of 2*half cells around cell (ci, cj) of a periodic state; DOFs and cells
-    at distance >= 2 from the patch edge see exactly the data of the full grid."""
+    """Outflow patch of 2*half cells around cell (ci, cj); DOFs and cells at distance >= 2 from
+    a cut edge of the patch see exactly the data of the full grid.  Periodic grids wrap; on an
+    outflow grid the patch is clipped to the domain, so that its edges on the domain boundary
+    apply the same outflow rule.  Returns the patch and the offsets of its first cell."""
     g = full.grid
+    i0, j0 = ci - half, cj - half
+    if g.bc_x != I.BC_PERIODIC:
+        i0 = min(max(i0, 0), g.nx - 2 * half)
+    if g.bc_y != I.BC_PERIODIC:
+        j0 = min(max(j0, 0), g.ny - 2 * half)
     n = 2 * half
-    ii = (np.arange(ci - half, ci + half) % g.nx)
-    jj = (np.arange(cj - half, cj + half) % g.ny)
-    ik = (np.arange(ci - half, ci + half + 1) % g.nx)
-    jk = (np.arange(cj - half, cj + half + 1) % g.ny)
-    pg = I.Grid(n, n, g.x0 + (ci - half) * g.dx, g.x0 + (ci + half) * g.dx,
-                g.y0 + (cj - half) * g.dy, g.y0 + (cj + half) * g.dy, 1, 1)
+    ii = (np.arange(i0, i0 + n) % g.nx)
+    jj = (np.arange(j0, j0 + n) % g.ny)
+    ik = (np.arange(i0, i0 + n + 1) % g.nkx)
+    jk = (np.arange(j0, j0 + n + 1) % g.nky)
+    pg = I.Grid(n, n, g.x0 + i0 * g.dx, g.x0 + (i0 + n) * g.dx,
+                g.y0 + j0 * g.dy, g.y0 + (j0 + n) * g.dy, 1, 1)
     st = I.State(pg, full.gamma, full.avg[:, jj][:, :, ii].copy(),
                  full.K[:, jk][:, :, ik].copy(), full.X[:, jj][:, :, ik].copy(),
                  full.Y[:, jk][:, :, ii].copy())
-    return st
+    return st, i0, j0
+
+
+def _check_patch_dofs(out, full_grid, p, i0, j0, cells, tol, scale):
+    """Compare the GPU state `out` with the oracle patch `p` at the DOFs of the given cells
+    (global indices) that lie at distance >= 2 from a cut edge of the patch."""
+    g = full_grid
+    n = p.grid.nx
+    for (gi, gj) in cells:
+        pi_, pj = (gi - i0) % g.nx, (gj - j0) % g.ny
+        cut_lo_x = i0 > 0 or g.bc_x == I.BC_PERIODIC
+        cut_hi_x = i0 + n < g.nx or g.bc_x == I.BC_PERIODIC
+        cut_lo_y = j0 > 0 or g.bc_y == I.BC_PERIODIC
+        cut_hi_y = j0 + n < g.ny or g.bc_y == I.BC_PERIODIC
+        if (cut_lo_x and pi_ < 2) or (cut_hi_x and pi_ > n - 3) or \
+                (cut_lo_y and pj < 2) or (cut_hi_y and pj > n - 3):
+            continue
+        assert abs(out["avg"][:, gj, gi] - p.avg[:, pj, pi_]).max() < tol * scale
+        assert abs(out["K"][:, gj, gi] - p.K[:, pj, pi_]).max() < tol * scale
+        assert abs(out["X"][:, gj, gi] - p.X[:, pj, pi_]).max() < tol * scale
+        assert abs(out["Y"][:, gj, gi] - p.Y[:, pj, pi_]).max() < tol * scale
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
@@ -290,16 +317,83 @@ def test_full_size_vortex_sampled(prec, tol):
         [tuple(rng.integers(0, n, 2)) for _ in range(6)]
     scale = 3.0
     for (ci, cj) in cells:
-        p = _patch(st, ci, cj)
+        p, i0, j0 = _patch(st, ci, cj)
         e, _ = oracle.step(p, dt)
         assert e == 0
-        for (a, b) in [(0, 0), (1, 0), (0, 1), (-1, -1)]:
-            gi, gj = (ci + a) % n, (cj + b) % n
-            pi_, pj = 4 + a, 4 + b
-            assert abs(out["avg"][:, gj, gi] - p.avg[:, pj, pi_]).max() < tol * scale
-            assert abs(out["K"][:, gj, gi] - p.K[:, pj, pi_]).max() < tol * scale
-            assert abs(out["X"][:, gj, gi] - p.X[:, pj, pi_]).max() < tol * scale
-            assert abs(out["Y"][:, gj, gi] - p.Y[:, pj, pi_]).max() < tol * scale
+        near = [((ci + a) % n, (cj + b) % n) for (a, b) in [(0, 0), (1, 0), (0, 1), (-1, -1)]]
+        _check_patch_dofs(out, st.grid, p, i0, j0, near, tol, scale)
+
+
+def _sampled_cells(g, rng, k=6):
+    """The domain corners and edge midpoints, the centre, and k random cells."""
+    nx, ny = g.nx, g.ny
+    fixed = [(0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1), (nx // 2, 0), (0, ny // 2),
+             (nx // 2, ny // 2), (nx // 2 - 1, ny // 2 - 1)]
+    return fixed + [tuple(int(v) for v in rng.integers(0, [nx, ny])) for _ in range(k)]
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+def test_full_size_radial_outflow_sampled(prec, tol):
+    """The positivity stress workload at its full size (2048^2, outflow, averaged
+    linearisation, limiter on): one step compared with the oracle on patches at the corners,
+    the edges, the centre (the near-vacuum point) and random cells; then 200 steps keep every
+    point value and average admissible while the limiter starts to act (t = 0.021).  (Around
+    step 226 a cell average at the centre loses positivity: limiting the point values alone
+    does not bound the averages, and the flux limiting that would is not part of this build.)"""
+    n = 2048
+    _flush(f"[gpu] full-size radial outflow {n}^2 prec={prec}")
+    st = I.radial_state(n, n_gl=2)
+    s = gpu_state(st, prec, 1, True, True)
+    t, steps = s.run(1e9, 0.3, 1)
+    out = s.get_state()
+    rng = np.random.default_rng(9)
+    for (ci, cj) in _sampled_cells(st.grid, rng):
+        p, i0, j0 = _patch(st, ci, cj)
+        e, _ = oracle.step(p, t, mode=1, limiter=True)
+        assert e == 0
+        near = [(ci + a, cj + b) for a in (-1, 0, 1) for b in (-1, 0, 1)
+                if 0 <= ci + a < n and 0 <= cj + b < n]
+        _check_patch_dofs(out, st.grid, p, i0, j0, near, tol, 4.0)
+    _flush(f"[gpu] radial outflow {n}^2: 199 more steps")
+    t, steps = s.run(1e9, 0.3, 199)
+    assert steps == 199
+    out = s.get_state()
+    for k in ("K", "X", "Y"):
+        assert (out[k][0] > 0).all() and (out[k][3] > 0).all()
+    r = out["avg"][0]
+    pr = 0.4 * (out["avg"][3] - 0.5 * (out["avg"][1] ** 2 + out["avg"][2] ** 2) / r)
+    assert (r > 0).all() and (pr > 0).all()
+    s.close()
+
+
+_SHEAR = {}  # the 8192^2 input, generated once for both precisions
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+def test_full_size_shear_layer_sampled(prec, tol):
+    """The large shear layer at its full size (8192^2 periodic, averaged linearisation,
+    limiter on): one step compared with the oracle on patches across both jumps, at the
+    periodic seams and at random cells."""
+    n = 8192
+    _flush(f"[gpu] full-size shear layer {n}^2 prec={prec}")
+    if n not in _SHEAR:
+        _SHEAR.clear()
+        _SHEAR[n] = I.shear_state(n)
+    st = _SHEAR[n]
+    s = gpu_state(st, prec, 1, True, True)
+    t, steps = s.run(1e9, 0.3, 1)
+    out = s.get_state()
+    s.close()
+    rng = np.random.default_rng(13)
+    q = n // 4
+    cells = [(0, 0), (n - 1, n - 1), (5, q), (n // 2, q - 1), (100, 3 * q), (n - 3, 3 * q - 1)]
+    cells += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(4)]
+    for (ci, cj) in cells:
+        p, i0, j0 = _patch(st, ci, cj)
+        e, _ = oracle.step(p, t, mode=1, limiter=True)
+        assert e == 0
+        near = [((ci + a) % n, (cj + b) % n) for a in (-1, 0, 1) for b in (-1, 0, 1)]
+        _check_patch_dofs(out, st.grid, p, i0, j0, near, tol, 8.0)
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-7)])
