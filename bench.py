@@ -192,6 +192,45 @@ def run_batched(prec, steps, warmup, stream, n_gl=2):
 run_batched.states = None
 
 
+def accuracy_ladder(sizes, t_end, stream):
+    """Vortex convergence ladder: L1/Linf per conserved variable against the exact translated
+    vortex at t_end, FP64 and FP32-bulk, with the observed order between successive sizes."""
+    from paper_2508_06273_amd import af, inputs as I
+    out = {"t_end": t_end, "cfl": 0.3, "variables": "rho, rho u, rho v, E", "sizes": {}}
+    prev = None
+    for n in sizes:
+        print(f"[bench] ladder {n}^2", file=sys.stderr, flush=True)
+        st = I.shu_vortex(n, n_gl=3)
+        ex = I.cell_average(I.shu_vortex_field(t_end), st.grid, n_gl=3)
+        rec = {}
+        for prec, name in ((af.AF_PREC_FP64, "fp64"), (af.AF_PREC_FP32, "fp32")):
+            s = af.Solver.for_state(st, precision=prec)
+            s.set_stream(stream)
+            t, steps = s.run(t_end, 0.3)
+            avg = s.get_state()["avg"]
+            s.close()
+            l1, linf = I.norms(avg, ex, st.grid)
+            # the window [2.5, 7.5]^2, away from the seams where the vortex's Gaussian tail is
+            # not periodic
+            w = slice(n // 4, 3 * n // 4)
+            l1w = np.abs(avg[:, w, w] - ex[:, w, w]).reshape(4, -1).sum(axis=1) * \
+                st.grid.dx * st.grid.dy
+            rec[name] = {"steps": steps, "L1": [float(v) for v in l1],
+                         "Linf": [float(v) for v in linf],
+                         "L1_window": [float(v) for v in l1w]}
+        if prev is not None:
+            r = math.log(n / prev[0])
+            rec["order_fp64"] = [float(math.log(a / b) / r)
+                                 for a, b in zip(prev[1]["fp64"]["L1"], rec["fp64"]["L1"])]
+            rec["order_fp64_window"] = [
+                float(math.log(a / b) / r)
+                for a, b in zip(prev[1]["fp64"]["L1_window"], rec["fp64"]["L1_window"])]
+        out["sizes"][str(n)] = rec
+        prev = (n, rec)
+        del st, ex
+    return out
+
+
 def cpu_baseline(seconds: float, n_cpu: int):
     import oracle
     from paper_2508_06273_amd import inputs as I
@@ -235,6 +274,9 @@ def main():
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="profiling aid: write profiles/traffic.json from two rocprofv3 --pmc "
                          "result databases of a --calibrate-copy run, then exit")
+    ap.add_argument("--ladder", action="store_true",
+                    help="accuracy aid: vortex convergence ladder (256^2, 1024^2, 4096^2 to "
+                         "t = 0.1), printed as JSON instead of the benchmark line")
     args = ap.parse_args()
     if args.record_traffic:
         record_traffic(args.record_traffic[0], args.record_traffic[1],
@@ -263,6 +305,10 @@ def main():
         print(f"[bench] copy calibration: 3 elementwise copies of {nb} bytes", file=sys.stderr,
               flush=True)
         del src, dst
+
+    if args.ladder:
+        print(json.dumps(accuracy_ladder([256, 1024, 4096], 0.1, stream)), flush=True)
+        return
 
     n = args.n
     print(f"[bench] generating the {n}x{n} vortex", file=sys.stderr, flush=True)

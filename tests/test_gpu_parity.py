@@ -413,3 +413,30 @@ def test_radial_outflow_limiter_multitile(prec, tol):
         assert list(cnt[:4]) == list(ocnt[:4])
     for k in ("K", "X", "Y"):
         assert (out[k][0] > 0).all() and (out[k][3] > 0).all()
+
+
+def test_vortex_error_matches_oracle(golden_dir):
+    """The vortex accuracy gate: after t = 0.25 at 128^2 and 256^2 (Algorithm 1, CFL 0.3), the
+    FP64 path's L1 error against the exact translated vortex equals the FP64 oracle's error
+    (tests/golden/vortex_t025_oracle.txt, written by make_vortex_t025.py from the oracle) to
+    1e-5 relative; the FP32-bulk path's error differs from it by at most 1e-5 of the L1 norm of
+    the solution."""
+    from conftest import load_table
+    tab = {int(r[0]): r for r in load_table(f"{golden_dir}/vortex_t025_oracle.txt")}
+    for n in (128, 256):
+        st = I.shu_vortex(n, n_gl=3)
+        ex = I.cell_average(I.shu_vortex_field(0.25), st.grid, n_gl=3)
+        ref_l1 = np.array(tab[n][2:6])
+        norm_l1 = np.abs(ex).reshape(4, -1).sum(axis=1) * st.grid.dx * st.grid.dy
+        for prec in (0, 1):
+            _flush(f"[gpu] vortex {n}^2 to t=0.25 prec={prec}")
+            s = gpu_state(st, prec)
+            t, steps = s.run(0.25, 0.3)
+            assert t == 0.25 and steps == int(tab[n][1])
+            l1, _ = I.norms(s.get_state()["avg"], ex, st.grid)
+            s.close()
+            if prec == 0:
+                assert np.all(np.abs(l1 - ref_l1) <= 1e-5 * ref_l1), (n, l1, ref_l1)
+            else:
+                assert np.all(np.abs(l1 - ref_l1) <= 1e-5 * norm_l1), (n, l1, ref_l1)
+
