@@ -37,20 +37,21 @@ PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
 # Algorithmic FLOPs of the point kernel per cell and step (add, sub, mul, div, sqrt, acos,
 # asin = 1; FMA = 2), counted operation by operation from the exact-moment formulation that
 # each path evaluates, for the generic subsonic DOF (one arc piece per arc set):
-#   EG2 set-up, foot point and outputs                                   82
-#   corner, FP32 (full circle + two half circles + one quadrant arc set) 1689
-#   corner, FP64 (one general arc set per cell, four cells)              2006
-#   x-edge (full circle + one half circle)                                579
-#   y-edge                                                                584
+#   EG2 set-up, foot point and outputs                                    82
+#   corner, FP32 (full circle + two half circles + one quadrant arc set) 1631
+#   corner, FP64 (one general arc set per cell, four cells)              1975
+#   x-edge (full circle + one half circle)                                575
+#   y-edge                                                                580
 #   per DOF: derivatives 16, correction 74, assembly 31, Simpson-in-time
 #            fluxes 54 + sums (K 32, X/Y 16), wave speed 4               213 / 197 / 197
 #   per cell: inverse Simpson 197, centre value 25, Simpson average 72,
 #             monomials 120 + aspect 24, constants 2                       440
-# (the EG2 figures include the set-up).  Algorithm 1 evaluates EG2 three times per DOF, the
-# averaged linearisation twice (plus 32 for the mean of the adjacent averages).
+# (the EG2 figures include the set-up; the moments are those of the circle of radius c' tau,
+# from scaled arc end points).  Algorithm 1 evaluates EG2 three times per DOF, the averaged
+# linearisation twice (plus 32 for the mean of the adjacent averages).
 # ------------------------------------------------------------------------------------------
-EG2_K = {"fp32": 1689, "fp64": 2006}
-EG2_X, EG2_Y = 579, 584
+EG2_K = {"fp32": 1631, "fp64": 1975}
+EG2_X, EG2_Y = 575, 580
 PER_DOF = 213 + 197 + 197
 PER_CELL = 440
 PEAK_NONPACKED = 78.6  # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz

@@ -1,6 +1,6 @@
 // af_kernels.hpp -- kernels of one Active Flux step (gfx950).
 //
-// One step = two launches:
+// One step = three launches (plus the positivity fix-up pass when the limiter is on):
 //   k_points : per 8x8 tile of DOF sites, stage the t_n point values of a one-cell halo in
 //              LDS, build the cell reconstructions of the 9x9 halo cells (inverse Simpson for
 //              the centre value, primitive Simpson average, monomial coefficients), then evolve
@@ -9,8 +9,8 @@
 //              need the positivity limiter to the fix-up pass, write U^{n+1} and
 //              the per-site Simpson-in-time flux sums f(U^n) + 4 f(U^{n+1/2}) + f(U^{n+1}).
 //   k_update : per cell, Simpson space-time face fluxes from the site sums and the
-//              conservative FP64 update of the cell average (paper eqs. F and 2dfvm); the
-//              last block commits t and the step counter.
+//              conservative FP64 update of the cell average (paper eqs. F and 2dfvm);
+//   k_commit : one thread advances t and the step counter if the step ran without error.
 // Both accumulate the largest wave speed of the new state for the next step's time step.
 #pragma once
 #include "af_device.hpp"
@@ -39,8 +39,8 @@ struct DevState {
   long long steps;
   long long steps_limit;  // no step runs once steps reaches this
   unsigned long long cnt[8];
-  unsigned int done_blocks;
   unsigned int fix_count;  // tiles listed for the positivity fix-up pass of this step
+  unsigned int pad2;
   int cur;                 // batched grids: buffer index of the current state
   int pad1;
 };

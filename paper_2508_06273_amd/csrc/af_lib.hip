@@ -66,8 +66,8 @@ __global__ __launch_bounds__(PT_THREADS) void k_fixup_f64(Params P, Bufs B, DevS
 
 // ------------------------------------------------------------------------------------------
 // Kernel 2: Simpson space-time fluxes and the conservative update of the averages.  Rows of
-// cells, UP_THREADS consecutive cells of a row per pass (coalesced); the last block to finish
-// commits t, the step counter and the wave-speed slot.
+// cells, UP_THREADS consecutive cells of a row per work item (coalesced), about one item per
+// workgroup.  Kernel 3 (one thread) then commits the step.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* __restrict__ A_in,
                                                       double* __restrict__ A_out,
@@ -76,7 +76,6 @@ __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* _
                                                       const double* __restrict__ FY,
                                                       DevState* dev, int slot) {
   __shared__ double red[UP_THREADS / 64];
-  __shared__ int last_block;
   const bool run = !dev->err && dev->active;
   const double dt = dev->dt;
   const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
@@ -92,30 +91,24 @@ __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* _
     }
   }
   if (bad) set_err(dev, ERR_NONPHYS);
-  {
-    double v = speed;
-    for (int off = 32; off > 0; off >>= 1) v = mx(v, __shfl_xor(v, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  }
+  for (int off = 32; off > 0; off >>= 1) speed = mx(speed, __shfl_xor(speed, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = speed;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && run) {
     double m = red[0];
     for (int k = 1; k < UP_THREADS / 64; ++k) m = mx(m, red[k]);
-    if (run) atomic_max_pos(&dev->smax[slot ^ 1], m);
-    __threadfence();
-    const unsigned int ticket = atomicAdd(&dev->done_blocks, 1u);
-    last_block = (ticket == gridDim.x - 1);
+    atomic_max_pos(&dev->smax[slot ^ 1], m);
   }
-  __syncthreads();
-  if (last_block && threadIdx.x == 0) {
-    __threadfence();
-    dev->done_blocks = 0;
-    dev->fix_count = 0u;
-    if (run && !atomicAdd(&dev->err, 0)) {
-      dev->t = dev->last ? dev->t_end : dev->t + dt;
-      dev->steps += 1;
-      dev->smax[slot] = 0ull;
-    }
+}
+
+// Commit of a step (one thread): a step that ran without error advances t and the step
+// counter and clears the wave-speed slot of the old state.
+__global__ void k_commit(DevState* dev, int slot) {
+  dev->fix_count = 0u;
+  if (!dev->err && dev->active) {
+    dev->t = dev->last ? dev->t_end : dev->t + dev->dt;
+    dev->steps += 1;
+    dev->smax[slot] = 0ull;
   }
 }
 
@@ -529,6 +522,7 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
   hipLaunchKernelGGL(k_update, dim3(gu), dim3(UP_THREADS), 0, h->stream, P, (const double*)h->A[in],
                      h->A[out], (const double*)h->FK, (const double*)h->FX,
                      (const double*)h->FY, h->dev, in);
+  hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, h->stream, h->dev, in);
   if (h->timing) {
     (void)hipEventRecord(e2, h->stream);
     h->ev.push_back(e0);
@@ -609,7 +603,6 @@ extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
   ds.t_end = t_end;
   ds.cfl = cfl;
   ds.smax[0] = ds.smax[1] = 0ull;
-  ds.done_blocks = 0;
   ds.steps_limit = max_steps > 0 ? steps0 + max_steps : LLONG_MAX;
   HIP_OK(hipMemcpyAsync(h->dev, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
   {

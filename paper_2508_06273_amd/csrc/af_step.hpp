@@ -29,7 +29,7 @@ namespace af {
 
 constexpr int FIX_BLOCKS = 1024;     // fix-up workgroups (grid-stride over the listed tiles)
 constexpr int UP_THREADS = 256;      // update kernel workgroup
-constexpr int UP_MAX_BLOCKS = 1024;  // update kernel grid cap (grid-stride)
+constexpr int UP_MAX_BLOCKS = 65536;  // update kernel grid cap (grid-stride beyond it)
 
 // ------------------------------------------------------------------------------------------
 // Kernel 1: point values of one tile of 8x8 sites.
