@@ -440,3 +440,53 @@ def test_vortex_error_matches_oracle(golden_dir):
             else:
                 assert np.all(np.abs(l1 - ref_l1) <= 1e-5 * norm_l1), (n, l1, ref_l1)
 
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-4)])
+@pytest.mark.parametrize("dims", [(16, 12, 1.0, 3.0), (10, 24, 2.5, 0.6)])
+def test_anisotropic_cells(prec, tol, dims):
+    """Cells with dy = 4 dx and dx = 10 dy: the circle integrals use dx as the unit length in
+    both directions, with the y-coefficients premultiplied by (dx/dy)^n."""
+    nx, ny, lx, ly = dims
+    _flush(f"[gpu] anisotropic {nx}x{ny} on {lx}x{ly} prec={prec}")
+    g = I.Grid(nx, ny, 0.0, lx, 0.0, ly)
+    st = I.fourier_state(77, g, I.GAMMA, 3)
+    s = gpu_state(st, prec)
+    t, n = s.run(1e9, 0.3, 5)
+    out = s.get_state()
+    s.close()
+    e, n2, _ = oracle.run(st, 1e9, 0.3, max_steps=5)
+    assert e == 0 and n == n2 == 5
+    assert_close(out, st, tol, f"anisotropic {dims}")
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(2, 2, (0, 0)), (2, 3, (1, 1)), (3, 2, (0, 1)),
+                                      (2, 5, (1, 0))])
+def test_minimal_grids(nx, ny, bc):
+    """Grids narrower than a tile: the halo wraps several times (periodic) or repeats the
+    boundary DOFs (outflow)."""
+    _flush(f"[gpu] minimal grid {nx}x{ny} bc={bc}")
+    g = I.Grid(nx, ny, 0.0, 1.0, 0.0, 1.0, bc[0], bc[1])
+    st = I.fourier_state(5, g, I.GAMMA, 3)
+    s = gpu_state(st, 0)
+    t, n = s.run(1e9, 0.2, 3)
+    out = s.get_state()
+    s.close()
+    e, n2, _ = oracle.run(st, 1e9, 0.2, max_steps=3)
+    assert e == 0 and n == n2 == 3
+    assert_close(out, st, 1e-12, f"minimal {nx}x{ny}")
+
+
+def test_widest_grid():
+    """The largest nx the library accepts (65536) on a grid two cells high (periodic in x,
+    outflow in y): many tiles in one row, the widest pitch."""
+    _flush("[gpu] widest grid 65536x2")
+    g = I.Grid(65536, 2, 0.0, 65536.0 / 64, 0.0, 2.0 / 64, 0, 1)
+    st = I.fourier_state(9, g, I.GAMMA, 2)
+    s = gpu_state(st, 0)
+    t, n = s.run(1e9, 0.3, 2)
+    out = s.get_state()
+    s.close()
+    e, n2, _ = oracle.run(st, 1e9, 0.3, max_steps=2)
+    assert e == 0 and n == n2 == 2
+    assert_close(out, st, 1e-12, "widest")
+
