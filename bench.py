@@ -232,6 +232,44 @@ def accuracy_ladder(sizes, t_end, stream):
     return out
 
 
+def extra_workloads(stream):
+    """Throughput of the two limiter workloads (averaged linearisation, positivity limiter on):
+    the 2048^2 radial outflow (outflow boundaries; 10 + 190 steps, before the step where an
+    average loses positivity) and the 8192^2 shear layer (10 warm-up + 100 timed steps)."""
+    from paper_2508_06273_amd import af, inputs as I
+    import torch
+    out = {}
+    for name, make, warm, steps in (("radial_outflow_2048", lambda: I.radial_state(2048, n_gl=2),
+                                     10, 190),
+                                    ("shear_layer_8192", lambda: I.shear_state(8192), 10, 100)):
+        print(f"[bench] {name}", file=sys.stderr, flush=True)
+        st = make()
+        rec = {}
+        for prec, pname in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64")):
+            s = af.Solver.for_state(st, precision=prec, linearisation=af.AF_LIN_AVG, limiter=True)
+            s.set_stream(stream)
+            s.run(1e9, 0.3, warm)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            t, n = s.run(1e9, 0.3, steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            assert n == steps
+            cnt = s.counters()
+            rec[pname] = {"value": s.dof_count() * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+                          "t": t, "eg1_fallbacks": int(cnt[0]), "lf_fallbacks": int(cnt[1]),
+                          "centre_fallbacks": int(cnt[2])}
+            s.close()
+        rec["speedup_fp32_vs_fp64"] = rec["fp32"]["value"] / rec["fp64"]["value"]
+        rec["steps"] = steps
+        out[name] = rec
+        del st
+    return out
+
+
 def cpu_baseline(seconds: float, n_cpu: int):
     import oracle
     from paper_2508_06273_amd import inputs as I
@@ -278,6 +316,9 @@ def main():
     ap.add_argument("--ladder", action="store_true",
                     help="accuracy aid: vortex convergence ladder (256^2, 1024^2, 4096^2 to "
                          "t = 0.1), printed as JSON instead of the benchmark line")
+    ap.add_argument("--extra", action="store_true",
+                    help="throughput of the limiter workloads (2048^2 radial outflow, 8192^2 "
+                         "shear layer), printed as JSON instead of the benchmark line")
     args = ap.parse_args()
     if args.record_traffic:
         record_traffic(args.record_traffic[0], args.record_traffic[1],
@@ -307,6 +348,9 @@ def main():
               flush=True)
         del src, dst
 
+    if args.extra:
+        print(json.dumps(extra_workloads(stream)), flush=True)
+        return
     if args.ladder:
         print(json.dumps(accuracy_ladder([256, 1024, 4096], 0.1, stream)), flush=True)
         return
