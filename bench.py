@@ -65,9 +65,13 @@ def flops_per_cell(mode: int, prec: str) -> float:
 
 
 def source_hash() -> str:
+    """Hash of the sources of the single-grid kernels (every file of the library except the
+    batched-grids translation unit)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2508_06273_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if f == "af_batch.hip":
+            continue
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -161,7 +165,8 @@ def run_gpu(st, prec, steps, warmup, stream):
 
 def run_batched(prec, steps, warmup, stream, n_gl=2):
     """The batched workload (256 periodic grids, N ~ U{64..512}, own dt per grid): DOF-updates/s
-    of one graph-captured launch sequence per step for all grids."""
+    of one graph-captured launch sequence per step for all grids, on the schedule the
+    autotuner picks during the warm-up run."""
     from paper_2508_06273_amd import af, inputs as I
     import torch
     states = run_batched.states
@@ -169,7 +174,10 @@ def run_batched(prec, steps, warmup, stream, n_gl=2):
         states = run_batched.states = I.batched_states(n_gl=n_gl)
     b = af.BatchSolver.for_states(states, precision=prec)
     b.set_stream(stream)
+    b.set_option(af.AF_OPT_AUTOTUNE, 1)  # the warm-up run picks the schedule
     b.run(1e9, 0.3, warmup)
+    schedule = {"tile_order": ["xcd", "linear", "grids"][b.get_option(af.AF_OPT_TILE_ORDER)],
+                "update_threads": b.get_option(af.AF_OPT_UPDATE_THREADS)}
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -186,7 +194,7 @@ def run_batched(prec, steps, warmup, stream, n_gl=2):
     dofs = b.dof_count()
     b.close()
     return dict(value=dofs * steps / (ms * 1e-3), ms_per_step=ms / steps,
-                ms_points=kp / nt, ms_update=ku / nt, dofs=dofs,
+                ms_points=kp / nt, ms_update=ku / nt, dofs=dofs, schedule=schedule,
                 cells=sum(st.grid.nx * st.grid.ny for st in states), grids=len(states))
 
 
@@ -432,7 +440,7 @@ def main():
     }
     if not args.no_batched:
         print("[bench] batched workload: 256 grids", file=sys.stderr, flush=True)
-        bres = {name: run_batched(prec, args.batched_steps, 16, stream)
+        bres = {name: run_batched(prec, args.batched_steps, 32, stream)
                 for prec, name in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64"))}
         line["batched"] = {
             "workload": "256 periodic grids N x N on [0,1]^2, N ~ U{64..512} (seeded), random "
@@ -440,9 +448,9 @@ def main():
             "grids": bres["fp32"]["grids"], "cells": bres["fp32"]["cells"],
             "dof_sites": bres["fp32"]["dofs"], "steps": args.batched_steps,
             "fp32": {k: bres["fp32"][k] for k in ("value", "ms_per_step", "ms_points",
-                                                   "ms_update")},
+                                                   "ms_update", "schedule")},
             "fp64": {k: bres["fp64"][k] for k in ("value", "ms_per_step", "ms_points",
-                                                   "ms_update")},
+                                                   "ms_update", "schedule")},
             "speedup_fp32_vs_fp64": bres["fp32"]["value"] / bres["fp64"]["value"],
             "unit": "DOF-updates/s"}
     if not args.no_cpu_baseline:

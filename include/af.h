@@ -69,9 +69,22 @@ enum {
   AF_OPT_CORRECTION = 3,    /* 1 (default): add C of Corollary 1; 0: drop it              */
   AF_OPT_LIMITER = 4,       /* 0 (default): none; 1: bound-preserving point values (Alg.3)*/
   AF_OPT_GRAPH_STEPS = 5,   /* steps per captured HIP graph in af_run (even, 0 = no graph) */
-  AF_OPT_TIMING = 6         /* 1: launch eagerly and time every kernel with HIP events on the
+  AF_OPT_TIMING = 6,        /* 1: launch eagerly and time every kernel with HIP events on the
                                handle's stream (af_get_timing); 0 (default): off           */
+  AF_OPT_AUTOTUNE = 7,      /* batched handles: 1 = the next af_run times every tile order
+                               and update workgroup size on its first steps (2 steps each)
+                               and keeps the fastest; the results do not depend on the
+                               schedule.  0 (default): keep the current schedule.  No effect
+                               on single-grid handles.                                    */
+  AF_OPT_TILE_ORDER = 8,    /* batched handles: order in which the point kernel's workgroups
+                               take the tiles of all grids (AF_ORDER_*; default XCD)      */
+  AF_OPT_UPDATE_THREADS = 9 /* batched handles: workgroup size of the update kernel, one
+                               row of cells per workgroup: 64, 128 (default) or 256        */
 };
+/* Tile orders of the batched point kernel.  Workgroups are dealt to the GPU's 8 XCDs in turn;
+ * AF_ORDER_XCD gives each XCD a contiguous range of the global tile index, AF_ORDER_LINEAR
+ * takes the tiles in index order, AF_ORDER_GRIDS packs whole grids onto the XCDs. */
+enum { AF_ORDER_XCD = 0, AF_ORDER_LINEAR = 1, AF_ORDER_GRIDS = 2 };
 /* AF_PREC_FP64: every operation in FP64.  AF_PREC_FP32 (FP32 bulk): the evolution operators
  * (moment recurrences, circle shifts and contractions of EG2 and EG1) and the correction term
  * run in FP32 on deviations from the linearisation state; point values and cell averages are
@@ -103,6 +116,11 @@ int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_handle** ou
 
 /* Set an option (keys and values above). */
 int af_set_option(af_handle* h, int key, int64_t value);
+
+/* Current value of an option (for AF_OPT_TILE_ORDER and AF_OPT_UPDATE_THREADS after an
+ * autotuned run: the schedule the tuner kept).  The tile order and update threads are
+ * AF_ERR_INVALID_ARG on single-grid handles. */
+int af_get_option(const af_handle* h, int key, int64_t* value);
 
 /* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) for all
  * device work of this handle.  NULL selects the handle's own (non-blocking) stream. */

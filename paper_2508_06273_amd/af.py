@@ -18,7 +18,9 @@ AF_OK, AF_ERR_INVALID_ARG, AF_ERR_NONPHYSICAL, AF_ERR_CFL, AF_ERR_DEVICE, AF_ERR
     0, -1, -2, -3, -4, -5
 AF_BC_PERIODIC, AF_BC_OUTFLOW = 0, 1
 AF_OPT_PRECISION, AF_OPT_LINEARISATION, AF_OPT_CORRECTION, AF_OPT_LIMITER, \
-    AF_OPT_GRAPH_STEPS, AF_OPT_TIMING = 1, 2, 3, 4, 5, 6
+    AF_OPT_GRAPH_STEPS, AF_OPT_TIMING, AF_OPT_AUTOTUNE, AF_OPT_TILE_ORDER, \
+    AF_OPT_UPDATE_THREADS = 1, 2, 3, 4, 5, 6, 7, 8, 9
+AF_ORDER_XCD, AF_ORDER_LINEAR, AF_ORDER_GRIDS = 0, 1, 2
 AF_PREC_FP64, AF_PREC_FP32 = 0, 1
 AF_LIN_AF3, AF_LIN_AVG, AF_LIN_SIMPLE = 0, 1, 2
 AF_CNT_EG1, AF_CNT_LF, AF_CNT_CENTRE, AF_CNT_INNER, AF_CNT_STEPS = 0, 1, 2, 3, 4
@@ -28,7 +30,7 @@ AF_NCOUNTERS = 8
 EXPORTS = ["af_create", "af_set_option", "af_set_stream", "af_set_state", "af_get_state",
            "af_step", "af_run", "af_get_counters", "af_destroy", "af_last_error",
            "af_dof_count", "af_get_timing", "af_create_batch", "af_batch_size",
-           "af_set_state_grid", "af_get_state_grid", "af_get_grid_info"]
+           "af_set_state_grid", "af_get_state_grid", "af_get_grid_info", "af_get_option"]
 
 
 class AfError(RuntimeError):
@@ -84,9 +86,11 @@ def load(path: str = LIB_PATH):
     L.af_set_state_grid.argtypes = [_H, ct.c_int32, _D, _D, _D, _D, ct.c_double]
     L.af_get_state_grid.argtypes = [_H, ct.c_int32, _D, _D, _D, _D, _D]
     L.af_get_grid_info.argtypes = [_H, ct.c_int32, _D, ct.POINTER(ct.c_int64)]
+    L.af_get_option.argtypes = [_H, ct.c_int, ct.POINTER(ct.c_int64)]
     for name in ("af_create", "af_set_option", "af_set_stream", "af_set_state",
                  "af_get_state", "af_step", "af_run", "af_get_counters", "af_create_batch",
-                 "af_set_state_grid", "af_get_state_grid", "af_get_grid_info"):
+                 "af_set_state_grid", "af_get_state_grid", "af_get_grid_info",
+                 "af_get_option"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -132,6 +136,11 @@ class _Handle:
 
     def set_option(self, key, value):
         self._check(self.L.af_set_option(self.h, key, int(value)))
+
+    def get_option(self, key):
+        v = ct.c_int64(0)
+        self._check(self.L.af_get_option(self.h, key, ct.byref(v)))
+        return v.value
 
     def set_stream(self, stream):
         """stream: a torch.cuda.Stream (its .cuda_stream handle is used) or a raw handle."""

@@ -31,15 +31,16 @@ struct GridDesc {
   int row_base;   // first global row of cells of the grid
 };
 
-constexpr int BU_THREADS = 128;  // batched update: cells of one row per pass
 
-// Point kernel over the tiles of all grids.  Tile order: XCD-aware over the global tile index.
+// Point kernel over the tiles of all grids.  Workgroup b evolves tile block_tile[b] (a
+// permutation of the global tiles: the schedule, see set_order).
 template <class R>
 __device__ __forceinline__ void batch_points(Smem<R>& S, const GridDesc* __restrict__ desc,
-                                             const int* __restrict__ tile_grid, int total_tiles,
+                                             const int* __restrict__ tile_grid,
+                                             const int* __restrict__ block_tile,
                                              DevState* devs, double dt_host) {
   __shared__ int s_g, s_cur;
-  const int t = tile_of_block(blockIdx.x, total_tiles);
+  const int t = block_tile[blockIdx.x];
   if (threadIdx.x == 0) {
     const int g = tile_grid[t];
     s_g = g;
@@ -55,16 +56,16 @@ __device__ __forceinline__ void batch_points(Smem<R>& S, const GridDesc* __restr
 }
 
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
-void kb_points_f32(const GridDesc* desc, const int* tile_grid, int total_tiles, DevState* devs,
-                   double dt_host) {
+void kb_points_f32(const GridDesc* desc, const int* tile_grid, const int* block_tile,
+                   DevState* devs, double dt_host) {
   __shared__ Smem<float> S;
-  batch_points<float>(S, desc, tile_grid, total_tiles, devs, dt_host);
+  batch_points<float>(S, desc, tile_grid, block_tile, devs, dt_host);
 }
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
-void kb_points_f64(const GridDesc* desc, const int* tile_grid, int total_tiles, DevState* devs,
-                   double dt_host) {
+void kb_points_f64(const GridDesc* desc, const int* tile_grid, const int* block_tile,
+                   DevState* devs, double dt_host) {
   __shared__ Smem<double> S;
-  batch_points<double>(S, desc, tile_grid, total_tiles, devs, dt_host);
+  batch_points<double>(S, desc, tile_grid, block_tile, devs, dt_host);
 }
 
 // Positivity fix-up over the global list of flagged tiles (entries are global tile indices).
@@ -115,12 +116,13 @@ __global__ __launch_bounds__(PT_THREADS) void kb_fixup_f64(const GridDesc* desc,
   batch_fixup<double>(S, desc, tile_grid, devs, fix_list, fix_count);
 }
 
-// Update kernel: one workgroup per row of cells of any grid (XCD-aware row order), the
-// grid's largest new wave speed by one atomic per row.
-__global__ __launch_bounds__(BU_THREADS) void kb_update(const GridDesc* __restrict__ desc,
-                                                       const int* __restrict__ row_grid,
-                                                       int total_rows, DevState* devs) {
-  __shared__ double red[BU_THREADS / 64];
+// Update kernel: one workgroup of T threads per row of cells of any grid (XCD-aware row
+// order), the grid's largest new wave speed by one atomic per row.
+template <int T>
+__global__ __launch_bounds__(T) void kb_update(const GridDesc* __restrict__ desc,
+                                              const int* __restrict__ row_grid, int total_rows,
+                                              DevState* devs) {
+  __shared__ double red[(T + 63) / 64];
   const int r = tile_of_block(blockIdx.x, total_rows);
   const int g = __builtin_amdgcn_readfirstlane(row_grid[r]);
   const Params& P = desc[g].P;
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(BU_THREADS) void kb_update(const GridDesc* __restri
   double speed = 0.0;
   bool bad = false;
   if (run)
-    for (int i = threadIdx.x; i < P.nx; i += BU_THREADS)
+    for (int i = threadIdx.x; i < P.nx; i += T)
       if (!update_cell(P, B.A_in, B.A_out, B.FK, B.FX, B.FY, lx, ly, i, j, speed)) bad = true;
   if (bad) set_err(dev, ERR_NONPHYS);
   for (int off = 32; off > 0; off >>= 1) speed = mx(speed, __shfl_xor(speed, off, 64));
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(BU_THREADS) void kb_update(const GridDesc* __restri
   __syncthreads();
   if (threadIdx.x == 0 && run) {
     double m = red[0];
-    for (int k = 1; k < BU_THREADS / 64; ++k) m = mx(m, red[k]);
+    for (int k = 1; k < (T + 63) / 64; ++k) m = mx(m, red[k]);
     atomic_max_pos(&dev->smax[cur ^ 1], m);
   }
 }
@@ -209,6 +211,11 @@ struct Batch {
   DevState* d_devs = nullptr;
   int total_tiles = 0, total_rows = 0;
   bool desc_valid = false;
+  // schedule: tile order of the point kernel (AF_ORDER_*), workgroup size of the update kernel
+  int order = -1;
+  int bu_threads = 128;
+  int* d_block_tile = nullptr;
+  std::vector<long long> grid_tiles;  // tiles per grid (host copy for the orders)
   hipGraphExec_t gexec = nullptr;
   int gexec_steps = 0;
 };
@@ -222,7 +229,8 @@ static void batch_free(Batch* b) {
   }
   for (void* p : {(void*)b->FK, (void*)b->FX, (void*)b->FY, (void*)b->fix_mask,
                   (void*)b->fix_list, (void*)b->fix_count, (void*)b->d_desc,
-                  (void*)b->d_tile_grid, (void*)b->d_row_grid, (void*)b->d_devs})
+                  (void*)b->d_tile_grid, (void*)b->d_row_grid, (void*)b->d_devs,
+                  (void*)b->d_block_tile})
     if (p) (void)hipFree(p);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   delete b;
@@ -303,11 +311,83 @@ int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af
     std::fill(tg.begin() + q.tile_base, tg.begin() + q.tile_base + q.tiles_x * q.tiles_y, k);
     std::fill(rg.begin() + q.row_base, rg.begin() + q.row_base + q.ny, k);
   }
+  b->grid_tiles.resize(n);
+  for (int k = 0; k < n; ++k) b->grid_tiles[k] = (long long)b->g[k].tiles_x * b->g[k].tiles_y;
+  HIP_OK(hipMalloc(&b->d_block_tile, tg.size() * sizeof(int)), h);
   HIP_OK(hipMalloc(&b->d_tile_grid, tg.size() * sizeof(int)), h);
   HIP_OK(hipMalloc(&b->d_row_grid, rg.size() * sizeof(int)), h);
   HIP_OK(hipMemcpy(b->d_tile_grid, tg.data(), tg.size() * sizeof(int), hipMemcpyHostToDevice), h);
   HIP_OK(hipMemcpy(b->d_row_grid, rg.data(), rg.size() * sizeof(int), hipMemcpyHostToDevice), h);
   (void)gamma;
+  return batch_set_schedule(h, AF_ORDER_XCD, 128);
+}
+
+// Workgroup-to-tile table of the point kernel for a tile order:
+//   AF_ORDER_XCD     workgroups are dealt to the 8 XCDs in turn; XCD x takes the contiguous
+//                    global tile range [x T/8, (x+1) T/8) (neighbouring tiles share its L2);
+//   AF_ORDER_LINEAR  workgroup b takes tile b;
+//   AF_ORDER_GRIDS   whole grids are packed onto the XCDs (largest first onto the least loaded),
+//                    each XCD working through its grids' tiles in order; a short XCD queue is
+//                    topped up from the longest.
+static std::vector<int> block_tile_table(const Batch* b, int order) {
+  const int T = b->total_tiles;
+  std::vector<int> tab((size_t)T);
+  if (order == AF_ORDER_LINEAR) {
+    for (int k = 0; k < T; ++k) tab[k] = k;
+  } else if (order == AF_ORDER_XCD) {
+    const int per = T >> 3;
+    for (int k = 0; k < T; ++k) tab[k] = k >= (per << 3) ? k : (k & 7) * per + (k >> 3);
+  } else {
+    std::vector<int> idx((size_t)b->n);
+    for (int k = 0; k < b->n; ++k) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](int x, int y) { return b->grid_tiles[x] > b->grid_tiles[y]; });
+    std::vector<std::vector<int>> q(8);
+    long long load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int gi : idx) {
+      const int x = (int)(std::min_element(load, load + 8) - load);
+      load[x] += b->grid_tiles[gi];
+      const int base = b->g[gi].tile_base;
+      for (long long t = 0; t < b->grid_tiles[gi]; ++t) q[x].push_back(base + (int)t);
+    }
+    size_t head[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < T; ++k) {
+      int x = k & 7;
+      if (head[x] >= q[x].size()) {
+        size_t best = 0;
+        for (int y = 0; y < 8; ++y)
+          if (q[y].size() - head[y] > best) { best = q[y].size() - head[y]; x = y; }
+      }
+      tab[k] = q[x][head[x]++];
+    }
+  }
+  return tab;
+}
+
+int batch_set_schedule(af_handle* h, int order, int bu_threads) {
+  Batch* b = h->batch;
+  if (order != AF_ORDER_XCD && order != AF_ORDER_LINEAR && order != AF_ORDER_GRIDS)
+    return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown tile order");
+  if (bu_threads != 64 && bu_threads != 128 && bu_threads != 256)
+    return fail(h, AF_ERR_INVALID_ARG, "af_set_option: update threads must be 64, 128 or 256");
+  if (order != b->order) {
+    const std::vector<int> tab = block_tile_table(b, order);
+    HIP_OK(hipMemcpy(b->d_block_tile, tab.data(), tab.size() * sizeof(int),
+                     hipMemcpyHostToDevice), h);
+    b->order = order;
+  }
+  b->bu_threads = bu_threads;
+  if (b->gexec) {
+    (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->gexec_steps = 0;
+  }
+  return AF_OK;
+}
+
+int batch_get_schedule(const af_handle* h, int* order, int* bu_threads) {
+  *order = h->batch->order;
+  *bu_threads = h->batch->bu_threads;
   return AF_OK;
 }
 
@@ -451,22 +531,18 @@ int batch_get_counters(const af_handle* h, int64_t* out) {
 }
 
 // One step of every grid: point kernel, fix-up (limiter on), update, commit.
+// `ev` (nullable): three events recorded before the point kernel, between the fix-up and the
+// update, and after the commit.
 template <class R>
-static void enqueue_batch_step(af_handle* h, double dt_host) {
+static void enqueue_batch_step(af_handle* h, double dt_host, hipEvent_t* ev) {
   Batch* b = h->batch;
-  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-  if (h->timing) {
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    (void)hipEventCreate(&e2);
-    (void)hipEventRecord(e0, h->stream);
-  }
+  if (ev) (void)hipEventRecord(ev[0], h->stream);
   if constexpr (sizeof(R) == 4)
     hipLaunchKernelGGL(kb_points_f32, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
-                       b->d_desc, b->d_tile_grid, b->total_tiles, b->d_devs, dt_host);
+                       b->d_desc, b->d_tile_grid, b->d_block_tile, b->d_devs, dt_host);
   else
     hipLaunchKernelGGL(kb_points_f64, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
-                       b->d_desc, b->d_tile_grid, b->total_tiles, b->d_devs, dt_host);
+                       b->d_desc, b->d_tile_grid, b->d_block_tile, b->d_devs, dt_host);
   if (h->limiter) {
     const int nb = std::min(b->total_tiles, FIX_BLOCKS);
     if constexpr (sizeof(R) == 4)
@@ -476,21 +552,78 @@ static void enqueue_batch_step(af_handle* h, double dt_host) {
       hipLaunchKernelGGL(kb_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, h->stream, b->d_desc,
                          b->d_tile_grid, b->d_devs, b->fix_list, b->fix_count);
   }
-  if (h->timing) (void)hipEventRecord(e1, h->stream);
-  hipLaunchKernelGGL(kb_update, dim3(b->total_rows), dim3(BU_THREADS), 0, h->stream, b->d_desc,
-                     b->d_row_grid, b->total_rows, b->d_devs);
+  if (ev) (void)hipEventRecord(ev[1], h->stream);
+  if (b->bu_threads == 64)
+    hipLaunchKernelGGL(kb_update<64>, dim3(b->total_rows), dim3(64), 0, h->stream, b->d_desc,
+                       b->d_row_grid, b->total_rows, b->d_devs);
+  else if (b->bu_threads == 256)
+    hipLaunchKernelGGL(kb_update<256>, dim3(b->total_rows), dim3(256), 0, h->stream, b->d_desc,
+                       b->d_row_grid, b->total_rows, b->d_devs);
+  else
+    hipLaunchKernelGGL(kb_update<128>, dim3(b->total_rows), dim3(128), 0, h->stream, b->d_desc,
+                       b->d_row_grid, b->total_rows, b->d_devs);
   hipLaunchKernelGGL(kb_commit, dim3((b->n + 63) / 64), dim3(64), 0, h->stream, b->d_devs, b->n,
                      b->fix_count);
-  if (h->timing) {
-    (void)hipEventRecord(e2, h->stream);
-    h->ev.push_back(e0);
-    h->ev.push_back(e1);
-    h->ev.push_back(e2);
-  }
+  if (ev) (void)hipEventRecord(ev[2], h->stream);
 }
 static void enqueue_batch(af_handle* h, double dt_host) {
-  if (h->prec == AF_PREC_FP32) enqueue_batch_step<float>(h, dt_host);
-  else enqueue_batch_step<double>(h, dt_host);
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  if (h->timing) {
+    for (hipEvent_t& e : ev) (void)hipEventCreate(&e);
+  }
+  if (h->prec == AF_PREC_FP32) enqueue_batch_step<float>(h, dt_host, h->timing ? ev : nullptr);
+  else enqueue_batch_step<double>(h, dt_host, h->timing ? ev : nullptr);
+  if (h->timing)
+    for (hipEvent_t e : ev) h->ev.push_back(e);
+}
+
+// Mean times of the point and of the update kernel (ms) over `steps` eager steps of the run.
+static int time_steps(af_handle* h, int steps, double* ms_points, double* ms_update) {
+  std::vector<hipEvent_t> ev((size_t)3 * steps);
+  for (hipEvent_t& e : ev) HIP_OK(hipEventCreate(&e), h);
+  for (int s = 0; s < steps; ++s) {
+    if (h->prec == AF_PREC_FP32) enqueue_batch_step<float>(h, 0.0, &ev[3 * s]);
+    else enqueue_batch_step<double>(h, 0.0, &ev[3 * s]);
+  }
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  double a = 0.0, c = 0.0;
+  for (int s = 0; s < steps; ++s) {
+    float x = 0.f, y = 0.f;
+    (void)hipEventElapsedTime(&x, ev[3 * s], ev[3 * s + 1]);
+    (void)hipEventElapsedTime(&y, ev[3 * s + 1], ev[3 * s + 2]);
+    a += x;
+    c += y;
+  }
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  *ms_points = a / steps;
+  *ms_update = c / steps;
+  return AF_OK;
+}
+
+// Autotuner: time each tile order of the point kernel, then each workgroup size of the update
+// kernel, on `per` steps of the run each (every schedule computes the same values), and keep
+// the fastest.
+static int autotune(af_handle* h, int per) {
+  Batch* b = h->batch;
+  const int orders[3] = {AF_ORDER_XCD, AF_ORDER_LINEAR, AF_ORDER_GRIDS};
+  const int threads[3] = {64, 128, 256};
+  double best = INFINITY, mp = 0.0, mu = 0.0;
+  int best_order = b->order;
+  if (int e = time_steps(h, 1, &mp, &mu)) return e;  // warm-up
+  for (int o : orders) {
+    if (int e = batch_set_schedule(h, o, b->bu_threads)) return e;
+    if (int e = time_steps(h, per, &mp, &mu)) return e;
+    if (mp < best) { best = mp; best_order = o; }
+  }
+  if (int e = batch_set_schedule(h, best_order, b->bu_threads)) return e;
+  best = INFINITY;
+  int best_threads = b->bu_threads;
+  for (int t : threads) {
+    if (int e = batch_set_schedule(h, best_order, t)) return e;
+    if (int e = time_steps(h, per, &mp, &mu)) return e;
+    if (mu < best) { best = mu; best_threads = t; }
+  }
+  return batch_set_schedule(h, best_order, best_threads);
 }
 
 static void collect_batch_timing(af_handle* h) {
@@ -574,6 +707,10 @@ int batch_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double*
   const int per = 16;
   hipLaunchKernelGGL(kb_cfl, dim3(b->n * per), dim3(256), 0, h->stream, b->d_desc, b->d_devs, per);
   HIP_OK(hipGetLastError(), h);
+  if (h->autotune == 1) {
+    if (int e = autotune(h, 2)) return e;
+    h->autotune = 2;  // done; the chosen schedule stays
+  }
   const long long chunk = h->graph_steps > 0 ? h->graph_steps : 8;
   while (true) {
     // every grid stops by itself at t_end or at its step limit; the host only checks between

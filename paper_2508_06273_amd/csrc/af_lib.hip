@@ -340,12 +340,49 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
         return fail(h, AF_ERR_INVALID_ARG, "af_set_option: graph steps must be even, 0..4096");
       h->graph_steps = (int)value;
       break;
+    case AF_OPT_AUTOTUNE:
+      if (value != 0 && value != 1) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: 0 or 1");
+      h->autotune = (int)value;
+      break;
+    case AF_OPT_TILE_ORDER:
+    case AF_OPT_UPDATE_THREADS: {
+      if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: batched handles only");
+      int order = 0, threads = 0;
+      batch_get_schedule(h, &order, &threads);
+      if (key == AF_OPT_TILE_ORDER) order = (int)value;
+      else threads = (int)value;
+      if (value < 0 || value > 4096)
+        return fail(h, AF_ERR_INVALID_ARG, "af_set_option: bad schedule value");
+      return batch_set_schedule(h, order, threads);
+    }
     default:
       return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown key");
   }
   if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
   batch_invalidate(h);
   return AF_OK;
+}
+
+extern "C" int af_get_option(const af_handle* h, int key, int64_t* value) {
+  if (!h || !value) return fail(h, AF_ERR_INVALID_ARG, "af_get_option: NULL argument");
+  int order = 0, threads = 0;
+  switch (key) {
+    case AF_OPT_PRECISION: *value = h->prec; return AF_OK;
+    case AF_OPT_LINEARISATION: *value = h->mode; return AF_OK;
+    case AF_OPT_CORRECTION: *value = h->correction; return AF_OK;
+    case AF_OPT_LIMITER: *value = h->limiter; return AF_OK;
+    case AF_OPT_GRAPH_STEPS: *value = h->graph_steps; return AF_OK;
+    case AF_OPT_TIMING: *value = h->timing; return AF_OK;
+    case AF_OPT_AUTOTUNE: *value = h->autotune == 1; return AF_OK;
+    case AF_OPT_TILE_ORDER:
+    case AF_OPT_UPDATE_THREADS:
+      if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_get_option: batched handles only");
+      batch_get_schedule(h, &order, &threads);
+      *value = key == AF_OPT_TILE_ORDER ? order : threads;
+      return AF_OK;
+    default:
+      return fail(h, AF_ERR_INVALID_ARG, "af_get_option: unknown key");
+  }
 }
 
 extern "C" int af_set_stream(af_handle* h, void* s) {

@@ -190,3 +190,47 @@ def test_batched_workload_full_size_sampled(prec):
     for k in ("avg", "K", "X", "Y"):
         assert np.abs(out[k] - getattr(st, k)).max() < tol * scale, k
     b.close()
+
+
+def test_batch_schedules_give_identical_results():
+    """Every tile order and update workgroup size, and the autotuned choice, compute the same
+    bits (the schedule only maps workgroups to tiles and rows)."""
+    _flush("[gpu] batch schedules and autotuner")
+    states = _mixed_states()
+    ref = None
+    for order in (af.AF_ORDER_XCD, af.AF_ORDER_LINEAR, af.AF_ORDER_GRIDS):
+        for threads in (64, 128, 256):
+            b = af.BatchSolver.for_states(states, precision=1)
+            b.set_option(af.AF_OPT_TILE_ORDER, order)
+            b.set_option(af.AF_OPT_UPDATE_THREADS, threads)
+            assert b.get_option(af.AF_OPT_TILE_ORDER) == order
+            assert b.get_option(af.AF_OPT_UPDATE_THREADS) == threads
+            b.run(1e9, 0.3, 20)
+            out = [b.get_state(g) for g in range(len(states))]
+            b.close()
+            if ref is None:
+                ref = out
+            for g in range(len(states)):
+                for k in ("avg", "K", "X", "Y"):
+                    assert np.array_equal(out[g][k], ref[g][k]), (order, threads, g, k)
+    b = af.BatchSolver.for_states(states, precision=1)
+    b.set_option(af.AF_OPT_AUTOTUNE, 1)
+    t, n = b.run(1e9, 0.3, 20)
+    assert n == 20
+    assert b.get_option(af.AF_OPT_TILE_ORDER) in (0, 1, 2)
+    assert b.get_option(af.AF_OPT_UPDATE_THREADS) in (64, 128, 256)
+    assert b.get_option(af.AF_OPT_AUTOTUNE) == 0  # tuned once
+    for g in range(len(states)):
+        out = b.get_state(g)
+        for k in ("avg", "K", "X", "Y"):
+            assert np.array_equal(out[k], ref[g][k]), ("autotuned", g, k)
+    with pytest.raises(af.AfError):
+        b.set_option(af.AF_OPT_UPDATE_THREADS, 96)
+    with pytest.raises(af.AfError):
+        b.set_option(af.AF_OPT_TILE_ORDER, 3)
+    b.close()
+    s = af.Solver.for_state(states[0])
+    with pytest.raises(af.AfError):
+        s.set_option(af.AF_OPT_TILE_ORDER, 0)
+    s.close()
+
