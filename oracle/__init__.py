@@ -38,7 +38,7 @@ class Cfg(ct.Structure):
                 ("dx", ct.c_double), ("dy", ct.c_double), ("gamma", ct.c_double),
                 ("per_x", ct.c_int), ("per_y", ct.c_int), ("mode", ct.c_int),
                 ("correction", ct.c_int), ("limiter", ct.c_int), ("gl_n", ct.c_int),
-                ("nthreads", ct.c_int)]
+                ("nthreads", ct.c_int), ("bc", ct.c_int * 4), ("inflow", (ct.c_double * 4) * 4)]
 
 
 FIELD_CB = ct.CFUNCTYPE(None, ct.c_double, ct.c_double, ct.POINTER(ct.c_double))
@@ -99,8 +99,15 @@ def _v(x) -> np.ndarray:
 
 def cfg_for(state, mode=MODE_AF3, correction=True, limiter=False, gl_n=10, nthreads=0) -> Cfg:
     g = state.grid
-    return Cfg(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, state.gamma, int(g.bc_x == 0),
-               int(g.bc_y == 0), mode, int(correction), int(limiter), gl_n, nthreads)
+    c = Cfg(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, state.gamma, int(g.bc_x == 0),
+            int(g.bc_y == 0), mode, int(correction), int(limiter), gl_n, nthreads)
+    for s, k in enumerate(g.side_kinds()):
+        c.bc[s] = k
+        w = g.inflow_state(s)
+        if w is not None:
+            for v in range(4):
+                c.inflow[s][v] = float(w[v])
+    return c
 
 
 def _arrays(state):

@@ -120,11 +120,18 @@ void or_gl(int n, double* x, double* w) {
 
 /* ------------------------------------------------------------------------------------ */
 /* Grid access with boundary treatment (paper Sec. 4, implementation of boundary          */
-/* conditions): periodic = index wrap; outflow = piecewise constant extrapolation, read  */
-/* as a DOF-wise copy of the nearest boundary value into one ghost layer.               */
+/* conditions), one ghost layer:                                                          */
+/*   periodic: index wrap;                                                               */
+/*   outflow:  piecewise constant extrapolation, read as a DOF-wise copy of the nearest    */
+/*             boundary value;                                                            */
+/*   wall:     the ghost DOF is the mirror image of the interior DOF at the same distance  */
+/*             from the wall line, with the normal velocity (momentum) negated;           */
+/*   inflow:   the ghost DOF holds the given inflow state.                                */
+/* At a domain corner the x rule is applied first, then the y rule.                        */
 /* ------------------------------------------------------------------------------------ */
 typedef struct {
-  const or_cfg* c;
+  const or_cfg* c; /* points at cn */
+  or_cfg cn;       /* the caller's configuration with the side kinds completed */
   const double *A, *K, *X, *Y;
   int nkx, nky;
   double* Uc; /* centre values of cells -1..nx x -1..ny */
@@ -134,9 +141,47 @@ typedef struct {
   double glx[64], glw[64];
 } ctx;
 
-static int wrap_cell(int i, int n, int per) {
-  if (per) return ((i % n) + n) % n;
-  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+/* index i on an axis of n cells (line = 1: the grid lines 0..n, else the cells 0..n-1) with
+ * boundary kinds lo, hi: the interior index that supplies the value, and in *side the side
+ * whose rule then applies (-1: none, 0: lo, 1: hi) */
+static int axis_map(int i, int n, int line, int lo, int hi, int* side) {
+  const int last = line ? n : n - 1;
+  *side = -1;
+  if (lo == OR_BC_PERIODIC) return ((i % n) + n) % n;
+  if (i < 0) {
+    *side = 0;
+    i = (lo == OR_BC_WALL) ? (line ? -i : -1 - i) : 0;
+  } else if (i > last) {
+    *side = 1;
+    i = (hi == OR_BC_WALL) ? (line ? 2 * n - i : 2 * n - 1 - i) : last;
+  }
+  if (i < 0) i = 0;
+  if (i > last) i = last;
+  return i;
+}
+
+/* rule of side (axis 0: x, 1: y; side 0: low, 1: high) on a primitive (or conserved) value */
+static void apply_side(const or_cfg* c, int axis, int side, int conserved, double o[4]) {
+  if (side < 0) return;
+  const int s = 2 * axis + side;
+  if (c->bc[s] == OR_BC_WALL) {
+    o[1 + axis] = -o[1 + axis];
+  } else if (c->bc[s] == OR_BC_INFLOW) {
+    if (conserved) or_p2c(c->inflow[s], c->gamma, o);
+    else memcpy(o, c->inflow[s], sizeof(double) * 4);
+  }
+}
+
+/* value of array `a` (4 variables of rows x width) at (i, j); xl, yl: lines or cells */
+static void get_dof(const ctx* C, const double* a, int width, int rows, int i, int j, int xl,
+                    int yl, int conserved, double o[4]) {
+  const or_cfg* c = C->c;
+  int sx, sy;
+  const int ii = axis_map(i, c->nx, xl, c->bc[0], c->bc[1], &sx);
+  const int jj = axis_map(j, c->ny, yl, c->bc[2], c->bc[3], &sy);
+  for (int v = 0; v < 4; ++v) o[v] = a[(size_t)v * rows * width + (size_t)jj * width + ii];
+  apply_side(c, 0, sx, conserved, o);
+  apply_side(c, 1, sy, conserved, o);
 }
 static int wrap_line(int i, int n, int per) {
   if (per) return ((i % n) + n) % n;
@@ -144,27 +189,16 @@ static int wrap_line(int i, int n, int per) {
 }
 
 static void getA(const ctx* C, int i, int j, double o[4]) {
-  const or_cfg* c = C->c;
-  int ii = wrap_cell(i, c->nx, c->per_x), jj = wrap_cell(j, c->ny, c->per_y);
-  for (int v = 0; v < 4; ++v) o[v] = C->A[(size_t)v * c->ny * c->nx + (size_t)jj * c->nx + ii];
+  get_dof(C, C->A, C->c->nx, C->c->ny, i, j, 0, 0, 1, o);
 }
 static void getK(const ctx* C, int i, int j, double o[4]) {
-  const or_cfg* c = C->c;
-  int ii = wrap_line(i, c->nx, c->per_x), jj = wrap_line(j, c->ny, c->per_y);
-  for (int v = 0; v < 4; ++v)
-    o[v] = C->K[(size_t)v * C->nky * C->nkx + (size_t)jj * C->nkx + ii];
+  get_dof(C, C->K, C->nkx, C->nky, i, j, 1, 1, 0, o);
 }
 static void getX(const ctx* C, int i, int j, double o[4]) {
-  const or_cfg* c = C->c;
-  int ii = wrap_line(i, c->nx, c->per_x), jj = wrap_cell(j, c->ny, c->per_y);
-  for (int v = 0; v < 4; ++v)
-    o[v] = C->X[(size_t)v * c->ny * C->nkx + (size_t)jj * C->nkx + ii];
+  get_dof(C, C->X, C->nkx, C->c->ny, i, j, 1, 0, 0, o);
 }
 static void getY(const ctx* C, int i, int j, double o[4]) {
-  const or_cfg* c = C->c;
-  int ii = wrap_cell(i, c->nx, c->per_x), jj = wrap_line(j, c->ny, c->per_y);
-  for (int v = 0; v < 4; ++v)
-    o[v] = C->Y[(size_t)v * C->nky * c->nx + (size_t)jj * c->nx + ii];
+  get_dof(C, C->Y, C->c->nx, C->nky, i, j, 0, 1, 0, o);
 }
 static size_t ghost_index(const ctx* C, int i, int j) {
   return (size_t)(j + 1) * (C->c->nx + 2) + (i + 1);
@@ -188,9 +222,27 @@ static void cell_nodes(const ctx* C, int i, int j, double W[3][3][4], int with_c
  * its primitive value U_c, and the primitive cell average U-bar by Simpson's rule.
  * Reading: if U_c is not admissible, the centre node falls back to C2P(Q-bar). */
 static int prep_cell(ctx* C, int i, int j, double Uc[4], double Ub[4], int count) {
-  double g = C->c->gamma, W[3][3][4], Qn[3][3][4], Qb[4], Qc[4];
-  getA(C, i, j, Qb);
+  const or_cfg* c = C->c;
+  double g = c->gamma, W[3][3][4], Qn[3][3][4], Qb[4], Qc[4];
   cell_nodes(C, i, j, W, 0);
+  /* a ghost cell beyond an inflow side: its point values, the centre included, are the
+   * inflow state (Sec. 4.3); its average is then the Simpson average of its nodes */
+  int sx, sy;
+  axis_map(i, c->nx, 0, c->bc[0], c->bc[1], &sx);
+  axis_map(j, c->ny, 0, c->bc[2], c->bc[3], &sy);
+  if ((sx >= 0 && c->bc[sx] == OR_BC_INFLOW) || (sy >= 0 && c->bc[2 + sy] == OR_BC_INFLOW)) {
+    double o[4] = {0, 0, 0, 0};
+    apply_side(c, 0, sx, 0, o);
+    apply_side(c, 1, sy, 0, o);
+    memcpy(Uc, o, sizeof(o));
+    for (int v = 0; v < 4; ++v) {
+      double corners = W[0][0][v] + W[2][0][v] + W[0][2][v] + W[2][2][v];
+      double edges = W[0][1][v] + W[2][1][v] + W[1][0][v] + W[1][2][v];
+      Ub[v] = (corners + 4.0 * edges + 16.0 * Uc[v]) / 36.0;
+    }
+    return 0;
+  }
+  getA(C, i, j, Qb);
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
       if (!(a == 1 && b == 1)) or_p2c(W[a][b], g, Qn[a][b]);
@@ -511,6 +563,19 @@ static int limit_point(ctx* C, int kind, int i, int j, double tau, double U[4],
   return OR_OK;
 }
 
+/* Does the DOF lie on a grid line that is a solid wall? */
+static int on_wall(const or_cfg* c, int kind, int i, int j) {
+  if (kind != OR_KIND_Y) {
+    if (i == 0 && c->bc[0] == OR_BC_WALL) return 1;
+    if (i == c->nx && c->bc[1] == OR_BC_WALL) return 1;
+  }
+  if (kind != OR_KIND_X) {
+    if (j == 0 && c->bc[2] == OR_BC_WALL) return 1;
+    if (j == c->ny && c->bc[3] == OR_BC_WALL) return 1;
+  }
+  return 0;
+}
+
 /* One point-value DOF: intermediate and new time level (Algorithm 1; Sec. 3.1 averaged
  * linearisation; simplified method eq. 1stStep), plus Algorithm 3 when the limiter is on. */
 static int dof_update(ctx* C, int kind, int i, int j, double dt, double half[4],
@@ -535,7 +600,10 @@ static int dof_update(ctx* C, int kind, int i, int j, double dt, double half[4],
     if (admissible(q)) memcpy(lin, q, sizeof(q));
     else { memcpy(lin, U0, sizeof(U0)); cnt[3]++; }
   } else if (c->mode == 1) {
-    dof_avg_lin(C, kind, i, j, lin);
+    /* on a solid wall the mean of the cell averages on both sides of the wall is replaced by
+     * the point value itself (Sec. 4.3) */
+    if (on_wall(c, kind, i, j)) memcpy(lin, U0, sizeof(U0));
+    else dof_avg_lin(C, kind, i, j, lin);
   } else {
     memcpy(lin, U0, sizeof(U0));
   }
@@ -564,7 +632,15 @@ static int dof_update(ctx* C, int kind, int i, int j, double dt, double half[4],
 static int ctx_init(ctx* C, const or_cfg* c, const double* A, const double* K,
                     const double* X, const double* Y) {
   memset(C, 0, sizeof(*C));
-  C->c = c;
+  C->cn = *c;
+  /* periodicity follows per_x / per_y; on a non-periodic axis a side left at
+   * OR_BC_PERIODIC is outflow */
+  for (int s = 0; s < 4; ++s) {
+    int per = s < 2 ? c->per_x : c->per_y;
+    if (per) C->cn.bc[s] = OR_BC_PERIODIC;
+    else if (C->cn.bc[s] == OR_BC_PERIODIC) C->cn.bc[s] = OR_BC_OUTFLOW;
+  }
+  C->c = &C->cn;
   C->A = A; C->K = K; C->X = X; C->Y = Y;
   C->nkx = c->nx + (c->per_x ? 0 : 1);
   C->nky = c->ny + (c->per_y ? 0 : 1);

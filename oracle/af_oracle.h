@@ -21,13 +21,19 @@ typedef struct {
   int nx, ny;
   double x0, y0, dx, dy;
   double gamma;
-  int per_x, per_y;    /* 1: periodic, 0: outflow (piecewise constant extrapolation) */
+  int per_x, per_y;    /* 1: periodic; 0: the sides of the axis follow bc[] */
   int mode;            /* 0: Algorithm 1; 1: averaged linearisation (Sec. 3.1); 2: simplified */
   int correction;      /* 1: add the Corollary 1 correction C */
   int limiter;         /* 1: bound-preserving point values (Algorithm 3) */
   int gl_n;            /* Gauss-Legendre nodes per sub-arc (0: default 10) */
   int nthreads;        /* OpenMP threads (0: runtime default) */
+  /* boundary kind per side (left, right, bottom, top), OR_BC_* (Sec. 4.3).  On a periodic
+   * axis bc[] is ignored; on a non-periodic axis OR_BC_PERIODIC (0) reads as outflow.
+   * inflow[s]: primitive inflow state of side s (used when bc[s] == OR_BC_INFLOW). */
+  int bc[4];
+  double inflow[4][4];
 } or_cfg;
+enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_WALL = 2, OR_BC_INFLOW = 3 };
 
 enum { OR_OK = 0, OR_ERR_ARG = -1, OR_ERR_NONPHYSICAL = -2, OR_ERR_CFL = -3 };
 enum { OR_KIND_K = 0, OR_KIND_X = 1, OR_KIND_Y = 2 };

@@ -28,6 +28,8 @@ import numpy as np
 GAMMA = 1.4
 BC_PERIODIC = 0
 BC_OUTFLOW = 1
+BC_WALL = 2
+BC_INFLOW = 3
 SEED_BASE = 250806273
 
 # --------------------------------------------------------------------------------------
@@ -68,6 +70,37 @@ class Grid:
     y1: float
     bc_x: int = BC_PERIODIC
     bc_y: int = BC_PERIODIC
+    # optional kind per side (left, right, bottom, top); None: bc_x on both x sides, bc_y on
+    # both y sides.  A non-periodic axis needs bc_x / bc_y != BC_PERIODIC.
+    sides: tuple | None = None
+    # optional primitive inflow state per side (None where the side is not inflow)
+    inflow: tuple | None = None
+
+    def __post_init__(self):
+        if self.sides is not None:
+            s = tuple(int(k) for k in self.sides)
+            assert len(s) == 4
+            for ax, (lo, hi) in enumerate(((s[0], s[1]), (s[2], s[3]))):
+                assert (lo == BC_PERIODIC) == (hi == BC_PERIODIC), "periodic must pair"
+                kind = BC_PERIODIC if lo == BC_PERIODIC else BC_OUTFLOW
+                if ax == 0:
+                    self.bc_x = kind
+                else:
+                    self.bc_y = kind
+            self.sides = s
+            for k, kind in enumerate(s):
+                if kind == BC_INFLOW:
+                    assert self.inflow is not None and self.inflow[k] is not None
+
+    def side_kinds(self) -> tuple:
+        if self.sides is not None:
+            return self.sides
+        return (self.bc_x, self.bc_x, self.bc_y, self.bc_y)
+
+    def inflow_state(self, side: int):
+        if self.inflow is None:
+            return None
+        return self.inflow[side]
 
     @property
     def dx(self) -> float:
@@ -414,6 +447,76 @@ def batched_states(n_grids: int = 256, seed: int = SEED_BASE + 4000, lo: int = 6
         grid = Grid(int(N), int(N), 0.0, 1.0, 0.0, 1.0)
         out.append(fourier_state(seed + 100 * (g + 1), grid, GAMMA, n_gl, f"batch{g}_{N}"))
     return out
+
+
+# Closed box [0,1]^2: a smooth field that is even about x = 0, 1 (rho, v, p) or odd (u), and
+# likewise in y with v odd, so that it is the restriction of a mirror-symmetric field of
+# period 2; random amplitudes of the modes cos / sin (k pi x) cos / sin (l pi y), k, l <= 2.
+def mirror_field(seed: int):
+    u = uniform01(seed, 36) - 0.5
+
+    def fn(x, y):
+        cx = [np.cos(k * math.pi * x) for k in range(3)]
+        sx = [np.sin(k * math.pi * x) for k in range(3)]
+        cy = [np.cos(l * math.pi * y) for l in range(3)]
+        sy = [np.sin(l * math.pi * y) for l in range(3)]
+        rho = 1.0 + 0.0 * x
+        p = 1.0 + 0.0 * x
+        uu = 0.0 * x
+        vv = 0.0 * x
+        q = 0
+        for k in range(3):
+            for l in range(3):
+                if k + l > 0:
+                    rho = rho + 0.15 * u[q] * cx[k] * cy[l]
+                    p = p + 0.15 * u[q + 9] * cx[k] * cy[l]
+                uu = uu + 0.3 * u[q + 18] * sx[k] * cy[l]
+                vv = vv + 0.3 * u[q + 27] * cx[k] * sy[l]
+                q += 1
+        return np.stack([rho, uu, vv, p])
+    return fn
+
+
+def box_state(n: int, seed: int = SEED_BASE + 6000, sides=(2, 2, 2, 2), n_gl: int = 4,
+              ny: int | None = None) -> State:
+    """mirror_field(seed) on [0,1]^2 with the given side kinds (wall, or periodic pairs).  On a
+    wall line the normal velocity of the point values is set to exactly 0."""
+    ny = n if ny is None else ny
+    grid = Grid(n, ny, 0.0, 1.0, 0.0, 1.0, sides=tuple(sides))
+    st = state_from_field(mirror_field(seed), grid, GAMMA, n_gl, f"box{n}")
+    if sides[0] == BC_WALL:
+        st.K[1, :, 0] = 0.0
+        st.X[1, :, 0] = 0.0
+    if sides[1] == BC_WALL:
+        st.K[1, :, -1] = 0.0
+        st.X[1, :, -1] = 0.0
+    if sides[2] == BC_WALL:
+        st.K[2, 0, :] = 0.0
+        st.Y[2, 0, :] = 0.0
+    if sides[3] == BC_WALL:
+        st.K[2, -1, :] = 0.0
+        st.Y[2, -1, :] = 0.0
+    st.meta.update(seed=seed)
+    return st
+
+
+# Shock reflection (Sec. 4.3): [0,4] x [0,1]; the state (1, 2.9, 0, 1/1.4) everywhere except
+# on the top line y = 1, which holds the post-shock state; inflow at the left (the upstream
+# state) and at the top (the post-shock state), a solid wall at the bottom, outflow at the
+# right.  Point values on y = 1 and the top inflow take the post-shock state.
+SRP_UP = (1.0, 2.9, 0.0, 1.0 / 1.4)
+SRP_POST = (1.69997, 2.61934, -0.50632, 1.52819)
+
+
+def shock_reflection_state(nx: int = 120, ny: int = 30) -> State:
+    grid = Grid(nx, ny, 0.0, 4.0, 0.0, 1.0,
+                sides=(BC_INFLOW, BC_OUTFLOW, BC_WALL, BC_INFLOW),
+                inflow=(SRP_UP, None, None, SRP_POST))
+    st = uniform_state(grid, SRP_UP)
+    st.K[:, -1, :] = np.asarray(SRP_POST)[:, None]
+    st.Y[:, -1, :] = np.asarray(SRP_POST)[:, None]
+    st.name = f"shock_reflection_{nx}x{ny}"
+    return st
 
 
 # Shear layer on [0,1]^2: inner strip |y-1/2| < 1/4 has rho = 2, u = -0.5; outside rho = 1,

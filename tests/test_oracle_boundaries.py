@@ -1,0 +1,222 @@
+"""Pins of the oracle's solid-wall and inflow boundaries (paper Sec. 4.3).
+
+* A closed box with solid walls is the restriction of a periodic domain of twice the size whose
+  data are mirror images about the walls (normal velocity odd, everything else even): the wall
+  ghost rule (ghost averages and point values are the mirror images of the interior ones, with
+  the normal velocity negated) must reproduce that periodic run on the box, DOF by DOF, in the
+  linearisations whose intermediate state is built from point values (Algorithm 1 and the
+  simplified method).  The periodic run shares none of the boundary code.
+* With the averaged linearisation, a DOF on a wall line is linearised at its own point value
+  (the paper's remark on reflecting boundaries): there it must coincide with the simplified
+  method, and only there.
+* Inflow: a uniform state whose inflow sides carry the same state stays uniform; and one step
+  with inflow ghost data equals one step on a domain extended upstream by a region that holds
+  the inflow state (the ghost point values, the ghost cells' centre values and averages are
+  then the same numbers).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06273_amd import inputs as I
+
+G = I.GAMMA
+WALL, INFLOW, OUTFLOW, PER = I.BC_WALL, I.BC_INFLOW, I.BC_OUTFLOW, I.BC_PERIODIC
+
+
+def _mirror(a, axis, n, line, var):
+    """Extend array `a` (variable axis 0) across index n on `axis` by its mirror image with
+    variable `var` negated; the result has period 2n."""
+    a = np.moveaxis(a, axis, -1)
+    if line:
+        ext = a[..., n - 1:0:-1].copy()
+        base = a[..., :n + 1]
+    else:
+        ext = a[..., ::-1].copy()
+        base = a
+    ext[var] = -ext[var]
+    out = np.concatenate([base, ext], axis=-1)
+    return np.ascontiguousarray(np.moveaxis(out, -1, axis))
+
+
+def _doubled(st, mx, my):
+    """The periodic mirror-symmetric state on [0, 2] in each mirrored axis."""
+    g = st.grid
+    avg, K, X, Y = st.avg, st.K, st.X, st.Y
+    if mx:
+        avg = _mirror(avg, 2, g.nx, False, 1)
+        K = _mirror(K, 2, g.nx, True, 1)
+        X = _mirror(X, 2, g.nx, True, 1)
+        Y = _mirror(Y, 2, g.nx, False, 1)
+    if my:
+        avg = _mirror(avg, 1, g.ny, False, 2)
+        K = _mirror(K, 1, g.ny, True, 2)
+        X = _mirror(X, 1, g.ny, False, 2)
+        Y = _mirror(Y, 1, g.ny, True, 2)
+    grid = I.Grid(g.nx * (2 if mx else 1), g.ny * (2 if my else 1), g.x0,
+                  g.x1 + (g.x1 - g.x0) * (1 if mx else 0), g.y0,
+                  g.y1 + (g.y1 - g.y0) * (1 if my else 0))
+    return I.State(grid, st.gamma, avg, K, X, Y)
+
+
+def _quadrant(big, st):
+    g = st.grid
+    return dict(avg=big.avg[:, :g.ny, :g.nx], K=big.K[:, :g.nky, :g.nkx],
+                X=big.X[:, :g.ny, :g.nkx], Y=big.Y[:, :g.nky, :g.nx])
+
+
+def _advance(st, dt, steps, **kw):
+    for _ in range(steps):
+        e, _ = oracle.step(st, dt, **kw)
+        assert e == oracle.OK
+    return st
+
+
+@pytest.mark.parametrize("sides,n,ny,mode", [
+    ((WALL, WALL, WALL, WALL), 10, 10, oracle.MODE_AF3),
+    ((WALL, WALL, WALL, WALL), 9, 7, oracle.MODE_SIMPLE),
+    ((WALL, WALL, PER, PER), 8, 6, oracle.MODE_AF3),
+    ((PER, PER, WALL, WALL), 6, 9, oracle.MODE_AF3),
+])
+def test_closed_box_equals_mirrored_periodic_domain(sides, n, ny, mode):
+    st = I.box_state(n, sides=sides, ny=ny)
+    mx, my = sides[0] == WALL, sides[2] == WALL
+    big = _doubled(st, mx, my)
+    # the doubled data really are mirror images (checked on the constructed arrays)
+    q = _quadrant(big, st)
+    for k in ("avg", "K", "X", "Y"):
+        assert np.array_equal(q[k], getattr(st, k))
+    dt = 0.3 * min(st.grid.dx, st.grid.dy) / oracle.max_speed(st)
+    assert dt == 0.3 * min(big.grid.dx, big.grid.dy) / oracle.max_speed(big)
+    _advance(st, dt, 4, mode=mode)
+    _advance(big, dt, 4, mode=mode)
+    q = _quadrant(big, st)
+    scale = max(np.abs(st.avg).max(), np.abs(st.K).max())
+    for k in ("avg", "K", "X", "Y"):
+        err = np.abs(getattr(st, k) - q[k]).max()
+        assert err < 1e-12 * scale, (k, err)
+    # the evolved normal velocity on the walls stays zero up to rounding
+    if mx:
+        assert np.abs(st.K[1, :, 0]).max() < 1e-13 and np.abs(st.X[1, :, -1]).max() < 1e-13
+    if my:
+        assert np.abs(st.K[2, 0, :]).max() < 1e-13 and np.abs(st.Y[2, -1, :]).max() < 1e-13
+
+
+def test_closed_box_conserves_mass_and_energy():
+    """Walls let no mass or energy through: the face fluxes on a wall line carry only the
+    pressure term, so the totals of rho and E stay constant to rounding."""
+    st = I.box_state(12, seed=I.SEED_BASE + 6100)
+    m0 = st.avg.sum(axis=(1, 2))
+    e, n, _ = oracle.run(st, 1e9, 0.3, max_steps=12, mode=oracle.MODE_AVG)
+    assert e == oracle.OK and n == 12
+    m1 = st.avg.sum(axis=(1, 2))
+    assert abs(m1[0] - m0[0]) < 1e-12 * abs(m0[0])
+    assert abs(m1[3] - m0[3]) < 1e-12 * abs(m0[3])
+
+
+@pytest.mark.parametrize("kind,i,j,on_wall", [
+    (oracle.KIND_K, 0, 3, True), (oracle.KIND_K, 10, 0, True), (oracle.KIND_K, 0, 0, True),
+    (oracle.KIND_X, 10, 4, True), (oracle.KIND_Y, 5, 0, True), (oracle.KIND_Y, 2, 10, True),
+    (oracle.KIND_K, 4, 5, False), (oracle.KIND_X, 1, 4, False), (oracle.KIND_Y, 0, 1, False),
+    (oracle.KIND_X, 5, 0, False), (oracle.KIND_Y, 0, 4, False),
+])
+def test_averaged_linearisation_on_wall_uses_point_value(kind, i, j, on_wall):
+    """Mode AVG on a wall line is the simplified method (intermediate state linearised at
+    U^n); everywhere else it is the mean of the adjacent averages, which differs.  X sites on
+    the bottom wall row and Y sites on the left wall column are not on a wall line."""
+    st = I.box_state(10, seed=I.SEED_BASE + 6200)
+    dt = 0.2 * st.grid.dx / oracle.max_speed(st)
+    e1, h1, f1, _ = oracle.dof_update(st, kind, i, j, dt, mode=oracle.MODE_AVG)
+    e2, h2, f2, _ = oracle.dof_update(st, kind, i, j, dt, mode=oracle.MODE_SIMPLE)
+    assert e1 == e2 == oracle.OK
+    if on_wall:
+        assert np.array_equal(h1, h2) and np.array_equal(f1, f2)
+    else:
+        assert np.abs(h1 - h2).max() > 1e-9
+
+
+def test_inflow_preserves_matching_uniform_state():
+    W0 = (1.0, 2.9, 0.0, 1.0 / 1.4)
+    grid = I.Grid(12, 6, 0.0, 4.0, 0.0, 1.0, sides=(INFLOW, OUTFLOW, WALL, INFLOW),
+                  inflow=(W0, None, None, W0))
+    st = I.uniform_state(grid, W0)
+    ref = st.copy()
+    e, n, _ = oracle.run(st, 1e9, 0.4, max_steps=6)
+    assert e == oracle.OK and n == 6
+    for k in ("avg", "K", "X", "Y"):
+        assert np.abs(getattr(st, k) - getattr(ref, k)).max() < 1e-13, k
+
+
+def _ramp_field(W_in):
+    W_in = np.asarray(W_in, dtype=np.float64)
+
+    def fn(x, y):
+        b = np.where(x > 0.4, ((x - 0.4) / 0.6) ** 4, 0.0)
+        out = np.stack([np.full_like(x, W_in[k]) for k in range(4)])
+        out[0] = out[0] + 0.3 * b * (1.0 + 0.5 * np.sin(2 * np.pi * y))
+        out[1] = out[1] - 0.4 * b * np.cos(2 * np.pi * y)
+        out[2] = out[2] + 0.2 * b * np.sin(2 * np.pi * y)
+        out[3] = out[3] + 0.2 * b
+        return out
+    return fn
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_AF3, oracle.MODE_AVG, oracle.MODE_SIMPLE])
+def test_inflow_step_equals_upstream_extended_domain(mode):
+    W_in = (1.0, 2.0, 0.1, 0.5)
+    n, ext = 16, 4
+    fn = _ramp_field(W_in)
+    grid = I.Grid(n, 8, 0.0, 1.0, 0.0, 1.0, sides=(INFLOW, OUTFLOW, PER, PER),
+                  inflow=(W_in, None, None, None))
+    st = I.state_from_field(fn, grid, G, 4)
+    gx = I.Grid(n + ext, 8, -ext / n, 1.0, 0.0, 1.0, sides=(OUTFLOW, OUTFLOW, PER, PER))
+    big = I.state_from_field(fn, gx, G, 4)
+    # the upstream region holds the inflow state (point values exactly, averages to rounding)
+    assert np.array_equal(big.K[:, :, :ext + 2], np.broadcast_to(
+        np.asarray(W_in)[:, None, None], big.K[:, :, :ext + 2].shape))
+    dt = 0.3 * grid.dx / oracle.max_speed(big)
+    _advance(st, dt, 1, mode=mode)
+    _advance(big, dt, 1, mode=mode)
+    scale = max(np.abs(st.avg).max(), np.abs(st.K).max())
+    for k, sl in (("avg", np.s_[:, :, ext:]), ("K", np.s_[:, :, ext:]),
+                  ("X", np.s_[:, :, ext:]), ("Y", np.s_[:, :, ext:])):
+        err = np.abs(getattr(st, k) - getattr(big, k)[sl]).max()
+        assert err < 1e-13 * scale, (k, err)
+    # the step did change the interior
+    assert np.abs(st.K - I.state_from_field(fn, grid, G, 4).K).max() > 1e-4
+
+
+def test_inflow_ghost_cell_centre_is_inflow_state():
+    """The centre value of a ghost cell beyond an inflow side is the inflow state itself, also
+    where the boundary point values differ from it; the ghost's primitive average is the
+    Simpson average of its nine nodes."""
+    W_in = np.array([1.3, 0.7, -0.2, 0.9])
+    grid = I.Grid(6, 5, 0.0, 1.0, 0.0, 1.0, sides=(INFLOW, OUTFLOW, WALL, OUTFLOW),
+                  inflow=(tuple(W_in), None, None, None))
+    st = I.fourier_state(I.SEED_BASE + 6300, grid, G, 3)
+    e, Uc, Ub = oracle.prep_cell(st, -1, 2)
+    assert np.array_equal(Uc, W_in)
+    K, X, Y = st.K, st.X, st.Y
+    corners = 2 * W_in + K[:, 2, 0] + K[:, 3, 0]
+    edges = W_in + X[:, 2, 0] + 2 * W_in
+    nodes = (corners + 4 * edges + 16 * W_in) / 36
+    assert np.allclose(Ub, nodes, rtol=0, atol=1e-15)
+    # a corner ghost below the inflow side and beyond the bottom wall: inflow state, then the
+    # wall's mirror rule (normal velocity negated)
+    e, Uc, _ = oracle.prep_cell(st, -1, -1)
+    assert np.array_equal(Uc, W_in * np.array([1, 1, -1, 1]))
+
+
+def test_wall_ghost_cell_is_mirror_of_first_cell():
+    """With zero normal velocity on the wall line, the centre value and primitive average of
+    the ghost cell beyond a wall are those of the first interior cell with the normal velocity
+    negated (to rounding: the node sums run in mirrored order)."""
+    st = I.box_state(8, seed=I.SEED_BASE + 6400)
+    for (gi, gj), (ii, jj), var in (((-1, 3), (0, 3), 1), ((8, 5), (7, 5), 1),
+                                    ((2, -1), (2, 0), 2), ((4, 8), (4, 7), 2)):
+        _, Ucg, Ubg = oracle.prep_cell(st, gi, gj)
+        _, Uci, Ubi = oracle.prep_cell(st, ii, jj)
+        f = np.ones(4)
+        f[var] = -1
+        assert np.allclose(Ucg, f * Uci, rtol=0, atol=1e-14)
+        assert np.allclose(Ubg, f * Ubi, rtol=0, atol=1e-14)
