@@ -160,13 +160,17 @@ static int axis_map(int i, int n, int line, int lo, int hi, int* side) {
   return i;
 }
 
-/* rule of side (axis 0: x, 1: y; side 0: low, 1: high) on a primitive (or conserved) value */
-static void apply_side(const or_cfg* c, int axis, int side, int conserved, double o[4]) {
-  if (side < 0) return;
-  const int s = 2 * axis + side;
-  if (c->bc[s] == OR_BC_WALL) {
-    o[1 + axis] = -o[1 + axis];
-  } else if (c->bc[s] == OR_BC_INFLOW) {
+/* ghost rules on a value fetched through axis_map (sx, sy: the sides that apply, -1: none):
+ * solid walls first (the normal velocity, or momentum, negated), then inflow (the side's
+ * state replaces the value; the y side's if both apply) */
+static void apply_sides(const or_cfg* c, int sx, int sy, int conserved, double o[4]) {
+  if (sx >= 0 && c->bc[sx] == OR_BC_WALL) o[1] = -o[1];
+  if (sy >= 0 && c->bc[2 + sy] == OR_BC_WALL) o[2] = -o[2];
+  for (int axis = 0; axis < 2; ++axis) {
+    const int side = axis ? sy : sx;
+    if (side < 0) continue;
+    const int s = 2 * axis + side;
+    if (c->bc[s] != OR_BC_INFLOW) continue;
     if (conserved) or_p2c(c->inflow[s], c->gamma, o);
     else memcpy(o, c->inflow[s], sizeof(double) * 4);
   }
@@ -180,8 +184,27 @@ static void get_dof(const ctx* C, const double* a, int width, int rows, int i, i
   const int ii = axis_map(i, c->nx, xl, c->bc[0], c->bc[1], &sx);
   const int jj = axis_map(j, c->ny, yl, c->bc[2], c->bc[3], &sy);
   for (int v = 0; v < 4; ++v) o[v] = a[(size_t)v * rows * width + (size_t)jj * width + ii];
-  apply_side(c, 0, sx, conserved, o);
-  apply_side(c, 1, sy, conserved, o);
+  apply_sides(c, sx, sy, conserved, o);
+}
+
+/* Kind of cell (i, j), one layer of ghosts:
+ *   CELL_OWN    interior, or a ghost beyond outflow (reconstructed from its own nodes);
+ *   CELL_INFLOW a ghost beyond an inflow side: every point value, the centre included, is
+ *               the inflow state;
+ *   CELL_MIRROR a ghost beyond a solid wall (and no inflow side): the mirror image about the
+ *               wall line of the cell (*si, *sj), whose velocity components in *flips (bit 0:
+ *               u, bit 1: v) are negated. */
+enum { CELL_OWN = 0, CELL_INFLOW = 1, CELL_MIRROR = 2 };
+static int cell_kind(const or_cfg* c, int i, int j, int* si, int* sj, int* flips) {
+  int sx, sy;
+  const int mi = axis_map(i, c->nx, 0, c->bc[0], c->bc[1], &sx);
+  const int mj = axis_map(j, c->ny, 0, c->bc[2], c->bc[3], &sy);
+  *si = i; *sj = j; *flips = 0;
+  if ((sx >= 0 && c->bc[sx] == OR_BC_INFLOW) || (sy >= 0 && c->bc[2 + sy] == OR_BC_INFLOW))
+    return CELL_INFLOW;
+  if (sx >= 0 && c->bc[sx] == OR_BC_WALL) { *si = mi; *flips |= 1; }
+  if (sy >= 0 && c->bc[2 + sy] == OR_BC_WALL) { *sj = mj; *flips |= 2; }
+  return *flips ? CELL_MIRROR : CELL_OWN;
 }
 static int wrap_line(int i, int n, int per) {
   if (per) return ((i % n) + n) % n;
@@ -227,13 +250,13 @@ static int prep_cell(ctx* C, int i, int j, double Uc[4], double Ub[4], int count
   cell_nodes(C, i, j, W, 0);
   /* a ghost cell beyond an inflow side: its point values, the centre included, are the
    * inflow state (Sec. 4.3); its average is then the Simpson average of its nodes */
-  int sx, sy;
-  axis_map(i, c->nx, 0, c->bc[0], c->bc[1], &sx);
-  axis_map(j, c->ny, 0, c->bc[2], c->bc[3], &sy);
-  if ((sx >= 0 && c->bc[sx] == OR_BC_INFLOW) || (sy >= 0 && c->bc[2 + sy] == OR_BC_INFLOW)) {
+  int si, sj, fl;
+  if (cell_kind(c, i, j, &si, &sj, &fl) == CELL_INFLOW) {
+    int sx, sy;
     double o[4] = {0, 0, 0, 0};
-    apply_side(c, 0, sx, 0, o);
-    apply_side(c, 1, sy, 0, o);
+    axis_map(i, c->nx, 0, c->bc[0], c->bc[1], &sx);
+    axis_map(j, c->ny, 0, c->bc[2], c->bc[3], &sy);
+    apply_sides(c, sx, sy, 0, o);
     memcpy(Uc, o, sizeof(o));
     for (int v = 0; v < 4; ++v) {
       double corners = W[0][0][v] + W[2][0][v] + W[0][2][v] + W[2][2][v];
@@ -273,6 +296,16 @@ static void lagr(double s, double l[3]) {
 }
 static void recon_eval(const ctx* C, int i, int j, double x, double y, double out[4]) {
   const or_cfg* c = C->c;
+  int si, sj, fl;
+  if (cell_kind(c, i, j, &si, &sj, &fl) == CELL_MIRROR) {
+    /* the reflected point in the mirrored cell; the wall lines are x0, x0 + nx dx, ... */
+    if (fl & 1) x = 2.0 * (c->x0 + (i < 0 ? 0 : c->nx) * c->dx) - x;
+    if (fl & 2) y = 2.0 * (c->y0 + (j < 0 ? 0 : c->ny) * c->dy) - y;
+    recon_eval(C, si, sj, x, y, out);
+    if (fl & 1) out[1] = -out[1];
+    if (fl & 2) out[2] = -out[2];
+    return;
+  }
   double W[3][3][4], lx[3], ly[3];
   cell_nodes(C, i, j, W, 1);
   double xc = c->x0 + (i + 0.5) * c->dx, yc = c->y0 + (j + 0.5) * c->dy;
@@ -656,6 +689,8 @@ static int ctx_init(ctx* C, const or_cfg* c, const double* A, const double* K,
 #pragma omp parallel for reduction(+ : bad, ccount) schedule(static)
   for (int j = -1; j <= c->ny; ++j) {
     for (int i = -1; i <= c->nx; ++i) {
+      int si, sj, fl;
+      if (cell_kind(C->c, i, j, &si, &sj, &fl) == CELL_MIRROR) continue;
       int phys = (i >= 0 && i < c->nx && j >= 0 && j < c->ny);
       ctx local = *C;
       memset(local.cnt, 0, sizeof(local.cnt));
@@ -666,6 +701,18 @@ static int ctx_init(ctx* C, const or_cfg* c, const double* A, const double* K,
     }
   }
   C->cnt[2] += ccount;
+  /* ghost cells beyond solid walls: the mirror images of the cells they face */
+  for (int j = -1; j <= c->ny; ++j)
+    for (int i = -1; i <= c->nx; ++i) {
+      int si, sj, fl;
+      if (cell_kind(C->c, i, j, &si, &sj, &fl) != CELL_MIRROR) continue;
+      double* uc = C->Uc + 4 * ghost_index(C, i, j);
+      double* ub = C->Ub + 4 * ghost_index(C, i, j);
+      memcpy(uc, C->Uc + 4 * ghost_index(C, si, sj), sizeof(double) * 4);
+      memcpy(ub, C->Ub + 4 * ghost_index(C, si, sj), sizeof(double) * 4);
+      if (fl & 1) { uc[1] = -uc[1]; ub[1] = -ub[1]; }
+      if (fl & 2) { uc[2] = -uc[2]; ub[2] = -ub[2]; }
+    }
   return bad ? OR_ERR_NONPHYSICAL : OR_OK;
 }
 

@@ -201,22 +201,58 @@ def test_inflow_ghost_cell_centre_is_inflow_state():
     edges = W_in + X[:, 2, 0] + 2 * W_in
     nodes = (corners + 4 * edges + 16 * W_in) / 36
     assert np.allclose(Ub, nodes, rtol=0, atol=1e-15)
-    # a corner ghost below the inflow side and beyond the bottom wall: inflow state, then the
-    # wall's mirror rule (normal velocity negated)
+    # a corner ghost beyond the inflow side and the bottom wall: inflow wins
     e, Uc, _ = oracle.prep_cell(st, -1, -1)
-    assert np.array_equal(Uc, W_in * np.array([1, 1, -1, 1]))
+    assert np.array_equal(Uc, W_in)
 
 
 def test_wall_ghost_cell_is_mirror_of_first_cell():
-    """With zero normal velocity on the wall line, the centre value and primitive average of
-    the ghost cell beyond a wall are those of the first interior cell with the normal velocity
-    negated (to rounding: the node sums run in mirrored order)."""
-    st = I.box_state(8, seed=I.SEED_BASE + 6400)
+    """A ghost cell beyond a wall is the mirror image of the cell it faces: its centre value
+    and primitive average are that cell's with the normal velocity negated, exactly, and its
+    reconstruction at a point is the facing cell's at the reflected point (also with a
+    non-zero normal velocity on the wall line, where the two differ from a reconstruction
+    through the ghost's own nodes)."""
+    st = I.fourier_state(I.SEED_BASE + 6400, I.Grid(8, 7, 0.0, 1.0, 0.0, 0.7,
+                                                    sides=(WALL, WALL, WALL, WALL)), G, 3)
+    g = st.grid
     for (gi, gj), (ii, jj), var in (((-1, 3), (0, 3), 1), ((8, 5), (7, 5), 1),
-                                    ((2, -1), (2, 0), 2), ((4, 8), (4, 7), 2)):
+                                    ((2, -1), (2, 0), 2), ((4, 7), (4, 6), 2)):
         _, Ucg, Ubg = oracle.prep_cell(st, gi, gj)
         _, Uci, Ubi = oracle.prep_cell(st, ii, jj)
         f = np.ones(4)
         f[var] = -1
-        assert np.allclose(Ucg, f * Uci, rtol=0, atol=1e-14)
-        assert np.allclose(Ubg, f * Ubi, rtol=0, atol=1e-14)
+        assert np.array_equal(Ucg, f * Uci) and np.array_equal(Ubg, f * Ubi)
+        # a point of the ghost cell and its reflection about the wall line
+        xg = g.x0 + (gi + 0.3) * g.dx
+        yg = g.y0 + (gj + 0.8) * g.dy
+        if var == 1:
+            xw = g.x0 if gi < 0 else g.x1
+            xr, yr = 2 * xw - xg, yg
+        else:
+            yw = g.y0 if gj < 0 else g.y1
+            xr, yr = xg, 2 * yw - yg
+        _, vg = oracle.eval_recon(st, gi, gj, xg, yg)
+        _, vi = oracle.eval_recon(st, ii, jj, xr, yr)
+        assert np.array_equal(vg, f * vi)
+    # corner ghost beyond two walls: both velocity components negated
+    _, Ucg, _ = oracle.prep_cell(st, -1, -1)
+    _, Uci, _ = oracle.prep_cell(st, 0, 0)
+    assert np.array_equal(Ucg, Uci * np.array([1, -1, -1, 1]))
+
+
+def test_shock_reflection_states_are_consistent():
+    """The shock-reflection problem's two given states are linked by an oblique shock at
+    29 degrees (the exact solution's incident shock); the reflected state behind the second
+    shock, which turns the flow back parallel to the wall, is the standard one."""
+    import math
+    import exact_shock as ES
+    up = np.array(I.SRP_UP)
+    post = ES.turned_state(up, math.radians(29.0), -1)
+    assert np.allclose(post, I.SRP_POST, rtol=2e-5, atol=2e-5), post
+    theta = -math.atan2(I.SRP_POST[2], I.SRP_POST[1])
+    beta = ES.weak_shock_angle(np.array(I.SRP_POST), theta)
+    refl = ES.turned_state(np.array(I.SRP_POST), beta, +1)
+    assert abs(refl[2]) < 1e-12
+    # reflected shock at about 23.3 degrees to the wall; region 3 about (2.687, 2.401, 0, 2.934)
+    assert abs(math.degrees(beta - theta) - 23.28) < 0.02
+    assert np.allclose(refl, [2.687, 2.401, 0.0, 2.934], atol=2e-3), refl
