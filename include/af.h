@@ -11,7 +11,8 @@
  *     (Sec. 2, eqs. 2dfvm and F);
  *   - optionally, point values with negative density or pressure are replaced by EG1 on
  *     piecewise constant data and, failing that, by a Lax-Friedrichs update (Algorithm 3);
- *   - boundaries are periodic or outflow (piecewise constant extrapolation, Sec. 4).
+ *   - boundaries are periodic, outflow (piecewise constant extrapolation, Sec. 4), solid wall
+ *     or inflow (Sec. 4.3), chosen per side.
  *
  * Degrees of freedom and host array layout (all host arrays are FP64, variable-major,
  * unpadded, C order):
@@ -47,11 +48,26 @@ typedef struct {
   double x0, x1, y0, y1;
 } af_grid;
 
-/* Boundary condition per side.  Periodic must be set on both sides of an axis. */
-enum { AF_BC_PERIODIC = 0, AF_BC_OUTFLOW = 1 };
+/* Boundary condition per side (Sec. 4 and 4.3).  Periodic must be set on both sides of an
+ * axis.  The DOFs on a non-periodic boundary line are evolved like interior ones; the data
+ * beyond the side (one layer of ghost cells and their point values) are:
+ *   AF_BC_OUTFLOW : copies of the nearest boundary cell average / point value;
+ *   AF_BC_WALL    : the mirror image about the boundary line of the interior at the same
+ *                   distance, with the normal velocity (and momentum) negated: ghost point
+ *                   values are the reflected point values, a ghost cell is the reflection
+ *                   of the cell it faces (average, reconstruction, centre value).  With
+ *                   AF_LIN_AVG a DOF on a wall line is linearised at its own point value
+ *                   instead of the mean of the adjacent averages;
+ *   AF_BC_INFLOW  : the side's inflow state (af_set_inflow) for every ghost point value, the
+ *                   ghost cells' centre values included.
+ * Beyond a domain corner the walls' reflections apply first, then an inflow side's state
+ * replaces the value (the y side's if both sides are inflow). */
+enum { AF_BC_PERIODIC = 0, AF_BC_OUTFLOW = 1, AF_BC_WALL = 2, AF_BC_INFLOW = 3 };
 typedef struct {
   int32_t left, right, bottom, top;
 } af_bc;
+/* Side numbers of af_set_inflow. */
+enum { AF_SIDE_LEFT = 0, AF_SIDE_RIGHT = 1, AF_SIDE_BOTTOM = 2, AF_SIDE_TOP = 3 };
 
 enum {
   AF_OK = 0,
@@ -194,6 +210,13 @@ int af_get_state_grid(const af_handle* h, int32_t g, double* avg, double* K, dou
 
 /* Time and steps taken (since af_set_state_grid) of grid g (nullable outputs). */
 int af_get_grid_info(const af_handle* h, int32_t g, double* t, int64_t* steps);
+
+/* Inflow state W = (rho, u, v, p) (primitive, rho > 0, p > 0; copied) of side `side`
+ * (AF_SIDE_*) of grid g (0 on single handles), which must have been created AF_BC_INFLOW
+ * (Sec. 4.3).  Every inflow side needs its state before af_step or af_run
+ * (AF_ERR_INVALID_ARG otherwise); it applies from the next step on and may be changed
+ * between steps. */
+int af_set_inflow(af_handle* h, int32_t g, int32_t side, const double* W);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libaf.so")
 
 AF_OK, AF_ERR_INVALID_ARG, AF_ERR_NONPHYSICAL, AF_ERR_CFL, AF_ERR_DEVICE, AF_ERR_OOM = \
     0, -1, -2, -3, -4, -5
-AF_BC_PERIODIC, AF_BC_OUTFLOW = 0, 1
+AF_BC_PERIODIC, AF_BC_OUTFLOW, AF_BC_WALL, AF_BC_INFLOW = 0, 1, 2, 3
+AF_SIDE_LEFT, AF_SIDE_RIGHT, AF_SIDE_BOTTOM, AF_SIDE_TOP = 0, 1, 2, 3
 AF_OPT_PRECISION, AF_OPT_LINEARISATION, AF_OPT_CORRECTION, AF_OPT_LIMITER, \
     AF_OPT_GRAPH_STEPS, AF_OPT_TIMING, AF_OPT_AUTOTUNE, AF_OPT_TILE_ORDER, \
     AF_OPT_UPDATE_THREADS = 1, 2, 3, 4, 5, 6, 7, 8, 9
@@ -30,7 +31,8 @@ AF_NCOUNTERS = 8
 EXPORTS = ["af_create", "af_set_option", "af_set_stream", "af_set_state", "af_get_state",
            "af_step", "af_run", "af_get_counters", "af_destroy", "af_last_error",
            "af_dof_count", "af_get_timing", "af_create_batch", "af_batch_size",
-           "af_set_state_grid", "af_get_state_grid", "af_get_grid_info", "af_get_option"]
+           "af_set_state_grid", "af_get_state_grid", "af_get_grid_info", "af_get_option",
+           "af_set_inflow"]
 
 
 class AfError(RuntimeError):
@@ -87,10 +89,11 @@ def load(path: str = LIB_PATH):
     L.af_get_state_grid.argtypes = [_H, ct.c_int32, _D, _D, _D, _D, _D]
     L.af_get_grid_info.argtypes = [_H, ct.c_int32, _D, ct.POINTER(ct.c_int64)]
     L.af_get_option.argtypes = [_H, ct.c_int, ct.POINTER(ct.c_int64)]
+    L.af_set_inflow.argtypes = [_H, ct.c_int32, ct.c_int32, _D]
     for name in ("af_create", "af_set_option", "af_set_stream", "af_set_state",
                  "af_get_state", "af_step", "af_run", "af_get_counters", "af_create_batch",
                  "af_set_state_grid", "af_get_state_grid", "af_get_grid_info",
-                 "af_get_option"):
+                 "af_get_option", "af_set_inflow"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -103,6 +106,22 @@ def _ptr(a: np.ndarray):
 
 def _shapes(nx, ny, nkx, nky):
     return dict(avg=(4, ny, nx), K=(4, nky, nkx), X=(4, ny, nkx), Y=(4, nky, nx))
+
+
+def _sides(bc_x, bc_y, sides):
+    """Side kinds (left, right, bottom, top): `sides` if given, else bc_x twice, bc_y twice."""
+    if sides is None:
+        return (int(bc_x), int(bc_x), int(bc_y), int(bc_y))
+    return tuple(int(k) for k in sides)
+
+
+def _grid_sides(grid):
+    """Side kinds and inflow states of an inputs.Grid."""
+    kinds = grid.side_kinds() if hasattr(grid, "side_kinds") else \
+        (grid.bc_x, grid.bc_x, grid.bc_y, grid.bc_y)
+    inflow = {s: grid.inflow_state(s) for s in range(4)
+              if hasattr(grid, "inflow_state") and grid.inflow_state(s) is not None}
+    return kinds, inflow
 
 
 class _Handle:
@@ -186,6 +205,10 @@ class _Handle:
         out["t"] = t.value
         return out
 
+    def _set_inflow(self, g, side, W):
+        w = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(4))
+        self._check(self.L.af_set_inflow(self.h, int(g), int(side), _ptr(w)))
+
     def grid_info(self, g=0):
         """(t, steps taken) of grid g."""
         t = ct.c_double(0.0)
@@ -199,24 +222,33 @@ class Solver(_Handle):
 
     def __init__(self, nx, ny, x0, x1, y0, y1, gamma=1.4, bc_x=AF_BC_PERIODIC,
                  bc_y=AF_BC_PERIODIC, precision=AF_PREC_FP64, linearisation=AF_LIN_AF3,
-                 correction=True, limiter=False, graph_steps=None):
+                 correction=True, limiter=False, graph_steps=None, sides=None, inflow=None):
+        """sides: optional kinds (left, right, bottom, top) instead of bc_x / bc_y;
+        inflow: optional {side: (rho, u, v, p)} for the inflow sides."""
         self.L = load()
         self.nx, self.ny = int(nx), int(ny)
-        self.nkx = self.nx + (0 if bc_x == AF_BC_PERIODIC else 1)
-        self.nky = self.ny + (0 if bc_y == AF_BC_PERIODIC else 1)
+        k = _sides(bc_x, bc_y, sides)
+        self.nkx = self.nx + (0 if k[0] == AF_BC_PERIODIC else 1)
+        self.nky = self.ny + (0 if k[2] == AF_BC_PERIODIC else 1)
         self.h = _H()
         g = Grid(self.nx, self.ny, x0, x1, y0, y1)
-        bc = Bc(bc_x, bc_x, bc_y, bc_y)
+        bc = Bc(*k)
         self._check(self.L.af_create(ct.byref(g), gamma, ct.byref(bc), ct.byref(self.h)),
                     create=True)
         self._options(precision, linearisation, correction, limiter, graph_steps)
+        for side, W in (inflow or {}).items():
+            self.set_inflow(side, W)
 
     @classmethod
     def for_state(cls, st, **kw):
         g = st.grid
-        s = cls(g.nx, g.ny, g.x0, g.x1, g.y0, g.y1, st.gamma, g.bc_x, g.bc_y, **kw)
+        kinds, inflow = _grid_sides(g)
+        s = cls(g.nx, g.ny, g.x0, g.x1, g.y0, g.y1, st.gamma, sides=kinds, inflow=inflow, **kw)
         s.set_state(st.avg, st.K, st.X, st.Y, st.t)
         return s
+
+    def set_inflow(self, side, W):
+        self._set_inflow(0, side, W)
 
     def shapes(self):
         return _shapes(self.nx, self.ny, self.nkx, self.nky)
@@ -244,17 +276,21 @@ class BatchSolver(_Handle):
 
     def __init__(self, grids, gamma=1.4, precision=AF_PREC_FP64, linearisation=AF_LIN_AF3,
                  correction=True, limiter=False, graph_steps=None):
-        """grids: sequence of (nx, ny, x0, x1, y0, y1, bc_x, bc_y)."""
+        """grids: sequence of (nx, ny, x0, x1, y0, y1, bc_x, bc_y) or
+        (nx, ny, x0, x1, y0, y1, (left, right, bottom, top))."""
         self.L = load()
         n = len(grids)
         G = (Grid * n)()
         B = (Bc * n)()
         self.dims = []
-        for k, (nx, ny, x0, x1, y0, y1, bx, by) in enumerate(grids):
+        for k, spec in enumerate(grids):
+            nx, ny, x0, x1, y0, y1 = spec[:6]
+            kinds = _sides(0, 0, spec[6]) if len(spec) == 7 else _sides(spec[6], spec[7], None)
             G[k] = Grid(int(nx), int(ny), x0, x1, y0, y1)
-            B[k] = Bc(bx, bx, by, by)
-            self.dims.append((int(nx), int(ny), int(nx) + (0 if bx == AF_BC_PERIODIC else 1),
-                              int(ny) + (0 if by == AF_BC_PERIODIC else 1)))
+            B[k] = Bc(*kinds)
+            self.dims.append((int(nx), int(ny),
+                              int(nx) + (0 if kinds[0] == AF_BC_PERIODIC else 1),
+                              int(ny) + (0 if kinds[2] == AF_BC_PERIODIC else 1)))
         self.h = _H()
         self._check(self.L.af_create_batch(n, G, gamma, B, ct.byref(self.h)), create=True)
         self._options(precision, linearisation, correction, limiter, graph_steps)
@@ -262,11 +298,16 @@ class BatchSolver(_Handle):
     @classmethod
     def for_states(cls, states, **kw):
         grids = [(st.grid.nx, st.grid.ny, st.grid.x0, st.grid.x1, st.grid.y0, st.grid.y1,
-                  st.grid.bc_x, st.grid.bc_y) for st in states]
+                  _grid_sides(st.grid)[0]) for st in states]
         s = cls(grids, states[0].gamma, **kw)
         for g, st in enumerate(states):
+            for side, W in _grid_sides(st.grid)[1].items():
+                s.set_inflow(g, side, W)
             s.set_state(g, st.avg, st.K, st.X, st.Y, st.t)
         return s
+
+    def set_inflow(self, g, side, W):
+        self._set_inflow(g, side, W)
 
     def __len__(self):
         return int(self.L.af_batch_size(self.h))

@@ -408,6 +408,7 @@ static int upload_desc(af_handle* h) {
     P.pA = q.pA; P.sA = q.pA * q.ny;
     P.pP = q.pP; P.sP = q.pP * q.nky;
     P.pF = q.pP; P.sF = q.pP * q.nky;
+    fill_sides(h, k, P);
     for (int in = 0; in < 2; ++in) {
       Bufs& B = d[k].B[in];
       const int out = in ^ 1;

@@ -13,6 +13,14 @@ using namespace af;
 
 struct Batch;  // batched grids (af_batch.hip)
 
+// Boundary of one grid: kind per side (left, right, bottom, top; a periodic axis has
+// AF_BC_PERIODIC on both sides) and the inflow states (`set`: bit s = inflow[s] given).
+struct Sides {
+  int bc[4] = {0, 0, 0, 0};
+  double inflow[4][4] = {};
+  unsigned set = 0;
+};
+
 struct af_handle {
   int nx = 0, ny = 0, per_x = 1, per_y = 1, nkx = 0, nky = 0;
   double x0 = 0, x1 = 1, y0 = 0, y1 = 1, dx = 1, dy = 1, gamma = 1.4;
@@ -44,6 +52,7 @@ struct af_handle {
   double* stage = nullptr;  // pinned host staging buffer of host <-> device copies
   Batch* batch = nullptr;   // several grids (af_create_batch); nullptr for one grid
   int autotune = 0;         // batched: 1 = tune the schedule at the next af_run, 2 = tuned
+  std::vector<Sides> sides;  // per grid
   std::string err;
 };
 
@@ -67,6 +76,9 @@ int copy2d(const af_handle* h, bool to_device, double* dev, long long pitch, int
            double* host);
 int copy4(const af_handle* h, bool to_device, void* dev, long long pitch, int rows_alloc,
           int rows, int cols, double* host);
+
+// Boundary kinds and inflow states of grid g into P.
+void fill_sides(const af_handle* h, int g, Params& P);
 
 // Batched handles (af_batch.hip): the public entry points hand over to these when h->batch.
 int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af_handle* h);

@@ -20,6 +20,7 @@ namespace af {
 enum { ERR_NONPHYS = -2, ERR_CFL = -3 };
 enum { KIND_K = 0, KIND_X = 1, KIND_Y = 2 };
 enum { LIN_AF3 = 0, LIN_AVG = 1, LIN_SIMPLE = 2 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_WALL = 2, BC_INFLOW = 3 };
 
 constexpr int TILE = 8;        // sites per tile edge
 constexpr int HS = TILE + 2;   // halo sites per edge (local -1 .. TILE)
@@ -53,6 +54,8 @@ struct Params {
   long long pA, sA;  // pitch and variable stride of the cell-average arrays (doubles)
   long long pP, sP;  // pitch and variable stride of the point-value arrays
   long long pF, sF;  // pitch and variable stride of the flux-sum arrays (doubles)
+  int bc[4];         // boundary kind per side (left, right, bottom, top): BC_*
+  double inflow[4][4];  // primitive inflow state per side (sides of kind BC_INFLOW)
 };
 
 // Point values are stored in FP64 in both precisions (the bulk type only sets the arithmetic
@@ -77,8 +80,8 @@ struct Bufs {
   int tile_base;
 };
 
-// Index of a (possibly ghost) cell or grid line, i >= -n: periodic wrap, or the outflow
-// copy of the nearest boundary cell (line).  The common case needs no integer division.
+// Periodic index of a (possibly ghost) cell or grid line, i >= -n.  The common case needs no
+// integer division.
 __device__ __forceinline__ int wrap_per(int i, int n) {
   if (i < 0) return i + n;
   if (i >= n) {
@@ -87,13 +90,62 @@ __device__ __forceinline__ int wrap_per(int i, int n) {
   }
   return i;
 }
-__device__ __forceinline__ int wrap_cell(int i, int n, int per) {
-  if (per) return wrap_per(i, n);
-  return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
 __device__ __forceinline__ int wrap_line(int i, int n, int per) {
   if (per) return wrap_per(i, n);
   return i < 0 ? 0 : (i > n ? n : i);
+}
+
+// Ghost data (Sec. 4 and 4.3).  map_axis gives, for a possibly ghost index i on an axis of n
+// cells (LINE: the grid lines 0..n, else the cells 0..n-1), the index of the stored value that
+// supplies it and, in `side`, the side whose rule then applies (-1: none, 0: low, 1: high).
+// Periodic: wrap.  Outflow and inflow: the nearest boundary value (inflow then replaces it).
+// Wall: the mirror image about the boundary line (line n - k <-> n + k, cell n - 1 - k <->
+// n + k).  Indices stay in range for any i (grids narrower than a tile).
+template <bool LINE>
+__device__ __forceinline__ int map_axis(int i, int n, int per, int lo, int hi, int& side) {
+  side = -1;
+  if (per) return wrap_per(i, n);
+  const int last = LINE ? n : n - 1;
+  if (i < 0) {
+    side = 0;
+    i = (lo == BC_WALL) ? (LINE ? -i : -1 - i) : 0;
+  } else if (i > last) {
+    side = 1;
+    i = (hi == BC_WALL) ? (LINE ? 2 * n - i : 2 * n - 1 - i) : last;
+  }
+  return i < 0 ? 0 : (i > last ? last : i);
+}
+
+// Ghost rules on a value fetched through map_axis (sx, sy: the sides that apply, -1: none):
+// solid walls first (the normal velocity, or momentum, negated), then inflow (the side's state
+// replaces a primitive value; the y side's if both apply).
+__device__ __forceinline__ void apply_sides(const Params& P, int sx, int sy, double o[4]) {
+  if (sx >= 0 && P.bc[sx] == BC_WALL) o[1] = -o[1];
+  if (sy >= 0 && P.bc[2 + sy] == BC_WALL) o[2] = -o[2];
+  if (sx >= 0 && P.bc[sx] == BC_INFLOW) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) o[v] = P.inflow[sx][v];
+  }
+  if (sy >= 0 && P.bc[2 + sy] == BC_INFLOW) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) o[v] = P.inflow[2 + sy][v];
+  }
+}
+
+// Is side `side` of axis `axis` an inflow side?
+__device__ __forceinline__ bool inflow_side(const Params& P, int axis, int side) {
+  return side >= 0 && P.bc[2 * axis + side] == BC_INFLOW;
+}
+
+// Does a DOF of kind KIND at (i, j) lie on a solid-wall line?
+template <int KIND>
+__device__ __forceinline__ bool on_wall(const Params& P, int i, int j) {
+  bool w = false;
+  if (KIND != KIND_Y)
+    w = w || (i == 0 && P.bc[0] == BC_WALL) || (i == P.nx && P.bc[1] == BC_WALL);
+  if (KIND != KIND_X)
+    w = w || (j == 0 && P.bc[2] == BC_WALL) || (j == P.ny && P.bc[3] == BC_WALL);
+  return w;
 }
 
 // Errors are negative; when several DOFs fail in one step the most negative code wins

@@ -149,7 +149,33 @@ static Params make_params(const af_handle* h) {
   P.pA = h->pA; P.sA = h->pA * h->ny;
   P.pP = h->pP; P.sP = h->pP * h->nky;
   P.pF = h->pF; P.sF = h->pF * h->nky;
+  fill_sides(h, 0, P);
   return P;
+}
+
+void fill_sides(const af_handle* h, int g, Params& P) {
+  const Sides& q = h->sides[g];
+  for (int s = 0; s < 4; ++s) {
+    P.bc[s] = q.bc[s];
+    for (int v = 0; v < 4; ++v) P.inflow[s][v] = q.inflow[s][v];
+  }
+}
+
+static Sides make_sides(const af_bc* bc) {
+  Sides q;
+  q.bc[0] = bc->left; q.bc[1] = bc->right; q.bc[2] = bc->bottom; q.bc[3] = bc->top;
+  return q;
+}
+
+// Every inflow side of every grid has its state.
+static int check_inflow(af_handle* h, const char* fn) {
+  for (size_t g = 0; g < h->sides.size(); ++g)
+    for (int s = 0; s < 4; ++s)
+      if (h->sides[g].bc[s] == AF_BC_INFLOW && !((h->sides[g].set >> s) & 1u))
+        return fail(h, AF_ERR_INVALID_ARG,
+                    std::string(fn) + ": no inflow state for side " + std::to_string(s) +
+                        " of grid " + std::to_string(g) + " (af_set_inflow)");
+  return AF_OK;
 }
 
 static void free_buffers(af_handle* h) {
@@ -203,7 +229,7 @@ static int check_grid(const af_grid* grid, const af_bc* bc, const char* fn) {
     return fail(nullptr, AF_ERR_INVALID_ARG, f + ": nx, ny must be in [2, 65536]");
   if (!(grid->x1 > grid->x0) || !(grid->y1 > grid->y0))
     return fail(nullptr, AF_ERR_INVALID_ARG, f + ": empty domain");
-  auto okbc = [](int k) { return k == AF_BC_PERIODIC || k == AF_BC_OUTFLOW; };
+  auto okbc = [](int k) { return k >= AF_BC_PERIODIC && k <= AF_BC_INFLOW; };
   if (!okbc(bc->left) || !okbc(bc->right) || !okbc(bc->bottom) || !okbc(bc->top))
     return fail(nullptr, AF_ERR_INVALID_ARG, f + ": unknown boundary kind");
   if ((bc->left == AF_BC_PERIODIC) != (bc->right == AF_BC_PERIODIC) ||
@@ -238,6 +264,7 @@ extern "C" int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_
   h->per_x = bc->left == AF_BC_PERIODIC; h->per_y = bc->bottom == AF_BC_PERIODIC;
   h->nkx = h->nx + (h->per_x ? 0 : 1); h->nky = h->ny + (h->per_y ? 0 : 1);
   h->gamma = gamma;
+  h->sides.assign(1, make_sides(bc));
   int e = AF_OK;
   if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
     e = fail(h, AF_ERR_DEVICE, "af_create: hipStreamCreate");
@@ -272,6 +299,7 @@ extern "C" int af_create_batch(int32_t n, const af_grid* grids, double gamma, co
     return fail(nullptr, AF_ERR_DEVICE, "af_create_batch: no HIP device");
   af_handle* h = new af_handle();
   h->gamma = gamma;
+  for (int k = 0; k < n; ++k) h->sides.push_back(make_sides(&bcs[k]));
   int e = AF_OK;
   if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
     e = fail(h, AF_ERR_DEVICE, "af_create_batch: hipStreamCreate");
@@ -605,6 +633,7 @@ static const char* err_text(int code) {
 
 extern "C" int af_step(af_handle* h, double dt) {
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step: NULL handle");
+  if (int e = check_inflow(h, "af_step")) return e;
   if (h->batch) return batch_step(h, dt);
   if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_step: no state set");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, AF_ERR_INVALID_ARG, "af_step: dt must be > 0");
@@ -628,6 +657,7 @@ extern "C" int af_step(af_handle* h, double dt) {
 extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
                       double* t_reached, int64_t* steps_taken) {
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_run: NULL handle");
+  if (int e = check_inflow(h, "af_run")) return e;
   if (h->batch) return batch_run(h, t_end, cfl, max_steps, t_reached, steps_taken);
   if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_run: no state set");
   if (!(cfl > 0.0) || !(cfl < 0.5)) return fail(h, AF_ERR_INVALID_ARG, "af_run: cfl must be in (0, 0.5)");
@@ -726,5 +756,23 @@ extern "C" int af_get_grid_info(const af_handle* h, int32_t g, double* t, int64_
   HIP_OK(hipStreamSynchronize(h->stream), h);
   if (t) *t = ds.t;
   if (steps) *steps = ds.steps;
+  return AF_OK;
+}
+
+extern "C" int af_set_inflow(af_handle* h, int32_t g, int32_t side, const double* W) {
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_inflow: NULL handle");
+  if (g < 0 || g >= (int)h->sides.size())
+    return fail(h, AF_ERR_INVALID_ARG, "af_set_inflow: grid index out of range");
+  if (side < 0 || side > 3) return fail(h, AF_ERR_INVALID_ARG, "af_set_inflow: bad side");
+  if (h->sides[g].bc[side] != AF_BC_INFLOW)
+    return fail(h, AF_ERR_INVALID_ARG, "af_set_inflow: side is not an inflow boundary");
+  if (!W || !(W[0] > 0.0) || !(W[3] > 0.0) || !std::isfinite(W[0]) || !std::isfinite(W[1]) ||
+      !std::isfinite(W[2]) || !std::isfinite(W[3]))
+    return fail(h, AF_ERR_INVALID_ARG, "af_set_inflow: need finite W with rho > 0 and p > 0");
+  for (int v = 0; v < 4; ++v) h->sides[g].inflow[side][v] = W[v];
+  h->sides[g].set |= 1u << side;
+  // the parameters are baked into captured graphs and the batched descriptors
+  if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
+  batch_invalidate(h);
   return AF_OK;
 }

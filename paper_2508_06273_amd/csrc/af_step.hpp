@@ -143,9 +143,9 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
       for (int v = 0; v < 4; ++v) lin[v] = U0[v];
       if (!FIX) atomicAdd(&dev->cnt[AF_CNT_INNER], 1ull);
     }
-  } else if (P.mode == LIN_AVG) {
+  } else if (P.mode == LIN_AVG && !on_wall<KIND>(P, gi, gj)) {
     avg_lin(lin);
-  } else {
+  } else {  // simplified method; and the averaged linearisation on a wall line (Sec. 4.3)
 #pragma unroll
     for (int v = 0; v < 4; ++v) lin[v] = U0[v];
   }
@@ -286,32 +286,55 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
     const int kind = e / NS, s = e % NS;
     const int a = s % HS - 1, b = s / HS - 1;
     const int gi = i0 + a, gj = j0 + b;
-    int si, sj;
+    int si, sj, sx, sy;
     const double* src;
     double* dst;
     if (kind == 0) {
-      si = wrap_line(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.K_in; dst = S.sk;
+      si = map_axis<true>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+      sj = map_axis<true>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+      src = B.K_in; dst = S.sk;
     } else if (kind == 1) {
-      si = wrap_line(gi, P.nx, P.per_x); sj = wrap_cell(gj, P.ny, P.per_y); src = B.X_in; dst = S.sx;
+      si = map_axis<true>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+      sj = map_axis<false>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+      src = B.X_in; dst = S.sx;
     } else {
-      si = wrap_cell(gi, P.nx, P.per_x); sj = wrap_line(gj, P.ny, P.per_y); src = B.Y_in; dst = S.sy;
+      si = map_axis<false>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+      sj = map_axis<true>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+      src = B.Y_in; dst = S.sy;
     }
     const long long o = (long long)sj * P.pP + si;
+    double W[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) dst[v * NS + s] = src[v * P.sP + o];
+    for (int v = 0; v < 4; ++v) W[v] = src[v * P.sP + o];
+    if (sx >= 0 || sy >= 0) apply_sides(P, sx, sy, W);  // a ghost site
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[v * NS + s] = W[v];
   }
   __syncthreads();
 
   // 2. cell reconstructions of the halo cells (local cells -1 .. TILE-1)
   for (int c = tid; c < NC; c += PT_THREADS) {
     const int a = c % HC - 1, b = c / HC - 1;
-    const int gi = wrap_cell(i0 + a, P.nx, P.per_x), gj = wrap_cell(j0 + b, P.ny, P.per_y);
+    int sx, sy;
+    const int gi = map_axis<false>(i0 + a, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+    const int gj = map_axis<false>(j0 + b, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+    // A ghost cell beyond an inflow side holds the inflow state (centre value below).  A ghost
+    // cell beyond a solid wall is the mirror image of the cell (gi, gj) it faces: that cell's
+    // reconstruction is built from its own nodes and average, then reflected (fx, fy).  Halo
+    // cells more than one layer beyond the grid are never read; their node cell is only kept
+    // inside the halo.
+    const bool inflow = inflow_side(P, 0, sx) || inflow_side(P, 1, sy);
+    const bool fx = !inflow && sx >= 0 && P.bc[sx] == BC_WALL;
+    const bool fy = !inflow && sy >= 0 && P.bc[2 + sy] == BC_WALL;
+    const int an = fx ? min(max(gi - i0, -1), TILE - 1) : a;
+    const int bn = fy ? min(max(gj - j0, -1), TILE - 1) : b;
     const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
     // node k of the cell: 0..3 corners K(a,b) K(a+1,b) K(a,b+1) K(a+1,b+1),
     // 4,5 X(a,b) X(a+1,b), 6,7 Y(a,b) Y(a,b+1)
-    const double* nptr[8] = {S.sk + sidx(a, b), S.sk + sidx(a + 1, b), S.sk + sidx(a, b + 1),
-                        S.sk + sidx(a + 1, b + 1), S.sx + sidx(a, b), S.sx + sidx(a + 1, b),
-                        S.sy + sidx(a, b), S.sy + sidx(a, b + 1)};
+    const double* nptr[8] = {S.sk + sidx(an, bn), S.sk + sidx(an + 1, bn),
+                             S.sk + sidx(an, bn + 1), S.sk + sidx(an + 1, bn + 1),
+                             S.sx + sidx(an, bn), S.sx + sidx(an + 1, bn),
+                             S.sy + sidx(an, bn), S.sy + sidx(an, bn + 1)};
     auto node = [&](int k, double W[4]) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) W[v] = (double)nptr[k][v * NS];
@@ -348,7 +371,12 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
       for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Q[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
     }
     c2p_dev(Wr, dQ, gm1, Uc);
-    if (!admissible(Uc[0], Uc[3])) {
+    if (inflow) {
+      // every point value of the ghost cell, the centre included, is the inflow state
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Uc[v] = 0.0;
+      apply_sides(P, sx, sy, Uc);
+    } else if (!admissible(Uc[0], Uc[3])) {
       c2p_plain(Qb, gm1, Uc);
       const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
       if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
@@ -363,17 +391,23 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
       const double u = Uc[v];
       const double sK4 = ((w[0] - u) + (w[1] - u)) + ((w[2] - u) + (w[3] - u));
       const double sE4 = ((w[4] - u) + (w[5] - u)) + ((w[6] - u) + (w[7] - u));
-      S.ub[v * NC + c] = u + (sK4 + 4.0 * sE4) * (1.0 / 36.0);
+      // reflection of a wall ghost: the normal velocity negated, and in the monomial
+      // coefficients c_mn (of xi^m eta^n, k = 3m + n) the odd powers of the normal coordinate
+      const double sv = ((fx && v == 1) || (fy && v == 2)) ? -1.0 : 1.0;
+      S.ub[v * NC + c] = sv * (u + (sK4 + 4.0 * sE4) * (1.0 / 36.0));
       const double N[3][3] = {{w[0], w[4], w[2]}, {w[6], u, w[7]}, {w[1], w[5], w[3]}};
       double cm[9];
       nodes_to_monomials(N, cm);
-      S.c0[v * NC + c] = cm[0];
+      S.c0[v * NC + c] = sv * cm[0];
       // c_mn of xi^m eta^n -> coefficient of xi^m (eta dy/dx)^n: the circle integrals use
       // dx as the unit length in both directions
 #pragma unroll
-      for (int k = 1; k < 9; ++k)
-        S.ch[(v * 8 + k - 1) * NC + c] = (R)(k % 3 == 0 ? cm[k] : (k % 3 == 1 ? cm[k] * rho
-                                                                              : cm[k] * rho2));
+      for (int k = 1; k < 9; ++k) {
+        const double sk = sv * ((fx && ((k / 3) & 1)) ? -1.0 : 1.0) *
+                          ((fy && ((k % 3) & 1)) ? -1.0 : 1.0);
+        S.ch[(v * 8 + k - 1) * NC + c] =
+            (R)(sk * (k % 3 == 0 ? cm[k] : (k % 3 == 1 ? cm[k] * rho : cm[k] * rho2)));
+      }
     }
   }
   __syncthreads();
