@@ -275,6 +275,49 @@ def extra_workloads(stream):
         rec["steps"] = steps
         out[name] = rec
         del st
+    out.update(shock_reflection(stream))
+    return out
+
+
+def _region_mean(avg, grid, box):
+    """Mean primitive state of the cells whose centres lie in box = (x0, x1, y0, y1)."""
+    xc, yc = grid.cell_centres()
+    m = (xc > box[0]) & (xc < box[1]) & (yc > box[2]) & (yc < box[3])
+    Q = avg[:, m]
+    rho = Q[0]
+    u, v = Q[1] / rho, Q[2] / rho
+    p = 0.4 * (Q[3] - 0.5 * rho * (u * u + v * v))
+    return [float(rho.mean()), float(u.mean()), float(v.mean()), float(p.mean())]
+
+
+def shock_reflection(stream):
+    """The shock-reflection problem of Sec. 4.3 (inflow left and top, wall below, outflow
+    right) run to t = 6 without limiter, FP64 and FP32 bulk, averaged linearisation: wall time,
+    steps, and the mean states upstream of the incident shock, between the shocks and between
+    the reflected shock and the wall (boxes 0.1 away from the shocks)."""
+    from paper_2508_06273_amd import af, inputs as I
+    import torch
+    boxes = {"upstream": (0.2, 0.9, 0.05, 0.3), "between_shocks": (1.8, 2.6, 0.75, 0.95),
+             "reflected": (3.0, 3.9, 0.05, 0.3)}
+    out = {}
+    for nx, ny in ((120, 30), (240, 60)):
+        print(f"[bench] shock reflection {nx}x{ny}", file=sys.stderr, flush=True)
+        st = I.shock_reflection_state(nx, ny)
+        rec = {}
+        for prec, pname in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64")):
+            s = af.Solver.for_state(st, precision=prec, linearisation=af.AF_LIN_AVG)
+            s.set_stream(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t, n = s.run(6.0, 0.3)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            o = s.get_state()
+            s.close()
+            rec[pname] = {"seconds_to_t6": el, "steps": n, "ms_per_step": 1e3 * el / n,
+                          "regions": {k: _region_mean(o["avg"], st.grid, b)
+                                      for k, b in boxes.items()}}
+        out[f"shock_reflection_{nx}x{ny}"] = rec
     return out
 
 
