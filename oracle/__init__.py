@@ -38,7 +38,8 @@ class Cfg(ct.Structure):
                 ("dx", ct.c_double), ("dy", ct.c_double), ("gamma", ct.c_double),
                 ("per_x", ct.c_int), ("per_y", ct.c_int), ("mode", ct.c_int),
                 ("correction", ct.c_int), ("limiter", ct.c_int), ("gl_n", ct.c_int),
-                ("nthreads", ct.c_int), ("bc", ct.c_int * 4), ("inflow", (ct.c_double * 4) * 4)]
+                ("nthreads", ct.c_int), ("bc", ct.c_int * 4), ("inflow", (ct.c_double * 4) * 4),
+                ("tsw", ct.c_int), ("shock", ct.c_int)]
 
 
 FIELD_CB = ct.CFUNCTYPE(None, ct.c_double, ct.c_double, ct.POINTER(ct.c_double))
@@ -80,6 +81,9 @@ def lib():
             L.or_dof_update.restype = ct.c_int
             L.or_lf_point.argtypes = [P, _D, _D, _D, _D, ct.c_int, ct.c_int, ct.c_int,
                                       ct.c_double, _D]
+            L.or_indicators.argtypes = [P, _D, _D, _D, _D, ct.c_int, ct.c_int, ct.c_int, _D,
+                                        ct.POINTER(ct.c_int)]
+            L.or_indicators.restype = ct.c_int
             L.or_lf_point.restype = ct.c_int
             L.or_eg_cb.argtypes = [ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.c_int, _D,
                                    ct.c_double, ct.c_double, FIELD_CB, ct.c_int, _D]
@@ -97,7 +101,9 @@ def _v(x) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
 
 
-def cfg_for(state, mode=MODE_AF3, correction=True, limiter=False, gl_n=10, nthreads=0) -> Cfg:
+def cfg_for(state, mode=MODE_AF3, correction=True, limiter=False, gl_n=10, nthreads=0,
+            tsw=False, shock=False) -> Cfg:
+    """tsw: Algorithm 2; shock: the shock-indicator blend of Sec. 3.4."""
     g = state.grid
     c = Cfg(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, state.gamma, int(g.bc_x == 0),
             int(g.bc_y == 0), mode, int(correction), int(limiter), gl_n, nthreads)
@@ -107,6 +113,8 @@ def cfg_for(state, mode=MODE_AF3, correction=True, limiter=False, gl_n=10, nthre
         if w is not None:
             for v in range(4):
                 c.inflow[s][v] = float(w[v])
+    c.tsw = int(bool(tsw))
+    c.shock = int(bool(shock))
     return c
 
 
@@ -221,6 +229,17 @@ def lf_point(state, kind, ci, cj, tau, **kw):
     e = lib().or_lf_point(ct.byref(c), _p(A), _p(K), _p(X), _p(Y), kind, ci, cj, float(tau),
                           _p(o))
     return e, o
+
+
+def indicators(state, kind, ci, cj, **kw):
+    """(theta of Sec. 3.4, transonic flag of Algorithm 2) of one DOF from the state."""
+    c = cfg_for(state, **kw)
+    A, K, X, Y = _arrays(state)
+    th = ct.c_double(0.0)
+    f = ct.c_int(0)
+    e = lib().or_indicators(ct.byref(c), _p(A), _p(K), _p(X), _p(Y), kind, ci, cj,
+                            ct.byref(th), ct.byref(f))
+    return e, th.value, f.value
 
 
 def eg_field(order, xb, yb, vline, hline, lin, tau, field, gamma=1.4, gl_n=10):

@@ -223,8 +223,9 @@ static void getX(const ctx* C, int i, int j, double o[4]) {
 static void getY(const ctx* C, int i, int j, double o[4]) {
   get_dof(C, C->Y, C->c->nx, C->nky, i, j, 0, 1, 0, o);
 }
+/* cells -2 .. n+1 in each direction: the shock indicators reach two cells beyond a DOF */
 static size_t ghost_index(const ctx* C, int i, int j) {
-  return (size_t)(j + 1) * (C->c->nx + 2) + (i + 1);
+  return (size_t)(j + 2) * (C->c->nx + 4) + (i + 2);
 }
 
 /* The nine nodes of cell (i,j): W[a][b], a = x-position (0 left, 1 centre, 2 right),
@@ -536,6 +537,72 @@ static void dof_avg_lin(const ctx* C, int kind, int i, int j, double o[4]) {
   }
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* Indicators from the primitive cell averages U-bar at t_n                               */
+/* ------------------------------------------------------------------------------------ */
+/* Algorithm 2: across the cell pair (L, R) in the direction of velocity component `comp`
+ * (1: u, x; 2: v, y) a characteristic speed w + c or w - c changes from positive to
+ * negative (the same sign choice on both sides). */
+static int transonic_pair(const double* L, const double* R, int comp, double gamma) {
+  const double cl = sound(L, gamma), cr = sound(R, gamma);
+  if (L[comp] + cl > 0.0 && R[comp] + cr < 0.0) return 1;
+  if (L[comp] - cl > 0.0 && R[comp] - cr < 0.0) return 1;
+  return 0;
+}
+
+/* Algorithm 2: indicator of the corner at (x0 + I dx, y0 + J dy), from the four cells around
+ * it: the two rows in x, the two columns in y. */
+static int transonic_corner(const ctx* C, int I, int J) {
+  const double g = C->c->gamma;
+  return transonic_pair(Ubcell(C, I - 1, J), Ubcell(C, I, J), 1, g) ||
+         transonic_pair(Ubcell(C, I - 1, J - 1), Ubcell(C, I, J - 1), 1, g) ||
+         transonic_pair(Ubcell(C, I - 1, J - 1), Ubcell(C, I - 1, J), 2, g) ||
+         transonic_pair(Ubcell(C, I, J - 1), Ubcell(C, I, J), 2, g);
+}
+
+/* Algorithm 2: a corner uses its own indicator, an edge midpoint the larger of its two end
+ * corners' indicators. */
+static int transonic_dof(const ctx* C, int kind, int i, int j) {
+  if (kind == OR_KIND_K) return transonic_corner(C, i, j);
+  if (kind == OR_KIND_X) return transonic_corner(C, i, j) || transonic_corner(C, i, j + 1);
+  return transonic_corner(C, i, j) || transonic_corner(C, i + 1, j);
+}
+
+/* Sec. 3.4: theta = exp(-phi1 phi2) of the edge-midpoint DOF between the cells k-1 and k of a
+ * line of cells (axis 0: X site (k, j), the cells k-2 .. k+1 of row j; axis 1: Y site (i, k),
+ * the cells k-2 .. k+1 of column i).  phi1: the larger of the two pressure sensors
+ * |p_{m+1} - 2 p_m + p_{m-1}| / (p_{m+1} + 2 p_m + p_{m-1}) centred on the cells m = k and
+ * m = k-1; phi2 = 2^max(|w| + c) over the cells k-1 and k, w the velocity component along the
+ * axis.  Reading: with a non-admissible average among the four cells theta is 0. */
+static double theta_edge(const ctx* C, int axis, int i, int j) {
+  const double g = C->c->gamma;
+  const double* U[4];
+  for (int m = 0; m < 4; ++m)
+    U[m] = axis == 0 ? Ubcell(C, i - 2 + m, j) : Ubcell(C, i, j - 2 + m);
+  for (int m = 0; m < 4; ++m)
+    if (!admissible(U[m])) return 0.0;
+  const double p0 = U[0][3], p1 = U[1][3], p2 = U[2][3], p3 = U[3][3];
+  double s_hi = fabs((p3 - 2.0 * p2 + p1) / (p3 + 2.0 * p2 + p1));  /* centred on cell k */
+  double s_lo = fabs((p2 - 2.0 * p1 + p0) / (p2 + 2.0 * p1 + p0));  /* centred on cell k-1 */
+  const double phi1 = s_hi > s_lo ? s_hi : s_lo;
+  const int comp = 1 + axis;
+  const double a = fabs(U[2][comp]) + sound(U[2], g), b = fabs(U[1][comp]) + sound(U[1], g);
+  const double phi2 = pow(2.0, a > b ? a : b);
+  return exp(-phi1 * phi2);
+}
+
+/* Sec. 3.4: theta of a DOF.  Edge midpoints: theta_edge; a corner: the smallest theta of the
+ * four edge midpoints next to it (the x-edges above and below, the y-edges right and left). */
+static double theta_dof(const ctx* C, int kind, int i, int j) {
+  if (kind == OR_KIND_X) return theta_edge(C, 0, i, j);
+  if (kind == OR_KIND_Y) return theta_edge(C, 1, i, j);
+  double t = theta_edge(C, 0, i, j), u;
+  u = theta_edge(C, 0, i, j - 1); if (u < t) t = u;
+  u = theta_edge(C, 1, i, j);     if (u < t) t = u;
+  u = theta_edge(C, 1, i - 1, j); if (u < t) t = u;
+  return t;
+}
+
 /* Lax-Friedrichs point update (Algorithm 3, last resort), in conservative variables, on the
  * lattice of DOFs of the same kind: a dual cell of size dx x dy centred at the DOF, with
  * Rusanov fluxes between the DOF and its four same-kind neighbours; the time increment is
@@ -596,6 +663,22 @@ static int limit_point(ctx* C, int kind, int i, int j, double tau, double U[4],
   return OR_OK;
 }
 
+/* Sec. 3.4: U := theta U + (1 - theta) U_lo, with U_lo the EG1 value on piecewise constant
+ * data over tau, linearised at the mean of the adjacent averages (as in Algorithm 3).
+ * Reading: where that mean is not admissible, or EG1 fails for a reason other than the CFL
+ * condition, U is kept (Algorithm 3 then takes care of its positivity). */
+static int shock_blend(const ctx* C, int kind, int i, int j, double tau, double theta,
+                       double U[4]) {
+  double Ut[4], lo[4];
+  dof_avg_lin(C, kind, i, j, Ut);
+  if (!admissible(Ut)) return OR_OK;
+  int e = dof_eg(C, 1, 1, kind, i, j, Ut, tau, lo);
+  if (e == OR_ERR_CFL) return e;
+  if (e != OR_OK) return OR_OK;
+  for (int v = 0; v < 4; ++v) U[v] = theta * U[v] + (1.0 - theta) * lo[v];
+  return OR_OK;
+}
+
 /* Does the DOF lie on a grid line that is a solid wall? */
 static int on_wall(const or_cfg* c, int kind, int i, int j) {
   if (kind != OR_KIND_Y) {
@@ -640,18 +723,36 @@ static int dof_update(ctx* C, int kind, int i, int j, double dt, double half[4],
   } else {
     memcpy(lin, U0, sizeof(U0));
   }
+  const double theta = c->shock ? theta_dof(C, kind, i, j) : 1.0;
   e = dof_eg(C, 2, 0, kind, i, j, lin, 0.5 * dt, half);
   if (e != OR_OK) return e;
   for (int v = 0; v < 4; ++v) half[v] += Ch[v];
+  if (theta < 1.0) {
+    e = shock_blend(C, kind, i, j, 0.5 * dt, theta, half);
+    if (e != OR_OK) return e;
+  }
   if (c->limiter) {
     e = limit_point(C, kind, i, j, 0.5 * dt, half, cnt);
     if (e != OR_OK) return e;
   } else if (!admissible(half)) {
     return OR_ERR_NONPHYSICAL;
   }
-  e = dof_eg(C, 2, 0, kind, i, j, half, dt, full);
+  /* full step: linearised at U^{n+1/2}, or near a transonic shock at the mean of the adjacent
+   * averages (Algorithm 2) */
+  double linf[4];
+  if (c->tsw && transonic_dof(C, kind, i, j)) {
+    dof_avg_lin(C, kind, i, j, linf);
+    cnt[5]++;
+  } else {
+    memcpy(linf, half, sizeof(linf));
+  }
+  e = dof_eg(C, 2, 0, kind, i, j, linf, dt, full);
   if (e != OR_OK) return e;
   for (int v = 0; v < 4; ++v) full[v] += Cf[v];
+  if (theta < 1.0) {
+    e = shock_blend(C, kind, i, j, dt, theta, full);
+    if (e != OR_OK) return e;
+  }
   if (c->limiter) {
     e = limit_point(C, kind, i, j, dt, full, cnt);
     if (e != OR_OK) return e;
@@ -680,15 +781,15 @@ static int ctx_init(ctx* C, const or_cfg* c, const double* A, const double* K,
   C->gl_n = c->gl_n > 0 ? c->gl_n : 10;
   if (C->gl_n > 64) C->gl_n = 64;
   or_gl(C->gl_n, C->glx, C->glw);
-  size_t nc = (size_t)(c->nx + 2) * (c->ny + 2);
+  size_t nc = (size_t)(c->nx + 4) * (c->ny + 4);
   C->Uc = (double*)malloc(sizeof(double) * 4 * nc);
   C->Ub = (double*)malloc(sizeof(double) * 4 * nc);
   if (!C->Uc || !C->Ub) return OR_ERR_ARG;
   int bad = 0;
   long long ccount = 0;
 #pragma omp parallel for reduction(+ : bad, ccount) schedule(static)
-  for (int j = -1; j <= c->ny; ++j) {
-    for (int i = -1; i <= c->nx; ++i) {
+  for (int j = -2; j <= c->ny + 1; ++j) {
+    for (int i = -2; i <= c->nx + 1; ++i) {
       int si, sj, fl;
       if (cell_kind(C->c, i, j, &si, &sj, &fl) == CELL_MIRROR) continue;
       int phys = (i >= 0 && i < c->nx && j >= 0 && j < c->ny);
@@ -702,8 +803,8 @@ static int ctx_init(ctx* C, const or_cfg* c, const double* A, const double* K,
   }
   C->cnt[2] += ccount;
   /* ghost cells beyond solid walls: the mirror images of the cells they face */
-  for (int j = -1; j <= c->ny; ++j)
-    for (int i = -1; i <= c->nx; ++i) {
+  for (int j = -2; j <= c->ny + 1; ++j)
+    for (int i = -2; i <= c->nx + 1; ++i) {
       int si, sj, fl;
       if (cell_kind(C->c, i, j, &si, &sj, &fl) != CELL_MIRROR) continue;
       double* uc = C->Uc + 4 * ghost_index(C, i, j);
@@ -747,9 +848,9 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
   long long cnt[OR_NCOUNTERS] = {0};
   cnt[2] = C.cnt[2];
   for (int kind = 0; kind < 3; ++kind) {
-    long long c0 = 0, c1 = 0, c3 = 0;
+    long long c0 = 0, c1 = 0, c3 = 0, c5 = 0;
     int kerr = 0;
-#pragma omp parallel for reduction(+ : c0, c1, c3) schedule(dynamic, 16)
+#pragma omp parallel for reduction(+ : c0, c1, c3, c5) schedule(dynamic, 16)
     for (int s = 0; s < nsite[kind]; ++s) {
       int i = s % wid[kind], j = s / wid[kind];
       double h[4], f[4];
@@ -760,13 +861,13 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
 #pragma omp critical
         { if (e < kerr) kerr = e; }
       }
-      c0 += lc[0]; c1 += lc[1]; c3 += lc[3];
+      c0 += lc[0]; c1 += lc[1]; c3 += lc[3]; c5 += lc[5];
       for (int v = 0; v < 4; ++v) {
         half[kind][(size_t)v * nsite[kind] + s] = h[v];
         full[kind][(size_t)v * nsite[kind] + s] = f[v];
       }
     }
-    cnt[0] += c0; cnt[1] += c1; cnt[3] += c3;
+    cnt[0] += c0; cnt[1] += c1; cnt[3] += c3; cnt[5] += c5;
     if (kerr < err) err = kerr;
   }
   if (err == OR_OK) {
@@ -920,6 +1021,16 @@ int or_dof_update(const or_cfg* c, const double* A, const double* K, const doubl
   if (e == OR_OK) e = dof_update(&C, kind, ci, cj, dt, half, full, lc);
   if (counters)
     for (int k = 0; k < OR_NCOUNTERS; ++k) counters[k] += lc[k] + (k == 2 ? C.cnt[2] : 0);
+  ctx_free(&C);
+  return e;
+}
+
+int or_indicators(const or_cfg* c, const double* A, const double* K, const double* X,
+                  const double* Y, int kind, int ci, int cj, double* theta, int* tsw) {
+  ctx C;
+  int e = ctx_init(&C, c, A, K, X, Y);
+  *theta = theta_dof(&C, kind, ci, cj);
+  *tsw = transonic_dof(&C, kind, ci, cj);
   ctx_free(&C);
   return e;
 }

@@ -32,13 +32,16 @@ typedef struct {
    * inflow[s]: primitive inflow state of side s (used when bc[s] == OR_BC_INFLOW). */
   int bc[4];
   double inflow[4][4];
+  int tsw;             /* 1: Algorithm 2 (full step linearised at averages near transonic shocks) */
+  int shock;           /* 1: shock-indicator blend of high- and low-order point values (Sec. 3.4) */
 } or_cfg;
 enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_WALL = 2, OR_BC_INFLOW = 3 };
 
 enum { OR_OK = 0, OR_ERR_ARG = -1, OR_ERR_NONPHYSICAL = -2, OR_ERR_CFL = -3 };
 enum { OR_KIND_K = 0, OR_KIND_X = 1, OR_KIND_Y = 2 };
 /* counters[0] EG1 fallbacks, [1] LF fallbacks, [2] centre-value fallbacks,
- * [3] Algorithm 1 inner-state fallbacks, [4..7] unused */
+ * [3] Algorithm 1 inner-state fallbacks, [4] unused, [5] DOFs whose full step took the
+ * transonic-shock linearisation (Algorithm 2), [6..7] unused */
 #define OR_NCOUNTERS 8
 
 int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double dt,
@@ -65,6 +68,10 @@ int or_dof_eg(const or_cfg* c, const double* A, const double* K, const double* X
 int or_dof_update(const or_cfg* c, const double* A, const double* K, const double* X,
                   const double* Y, int kind, int ci, int cj, double dt, double half[4],
                   double full[4], long long* counters);
+/* Shock-indicator weight theta of a DOF (Sec. 3.4) and its transonic-shock flag
+ * (Algorithm 2) from the t_n state. */
+int or_indicators(const or_cfg* c, const double* A, const double* K, const double* X,
+                  const double* Y, int kind, int ci, int cj, double* theta, int* tsw);
 int or_lf_point(const or_cfg* c, const double* A, const double* K, const double* X,
                 const double* Y, int kind, int ci, int cj, double tau, double out[4]);
 typedef void (*or_field_cb)(double x, double y, double* out4);
