@@ -94,8 +94,30 @@ enum {
                                on single-grid handles.                                    */
   AF_OPT_TILE_ORDER = 8,    /* batched handles: order in which the point kernel's workgroups
                                take the tiles of all grids (AF_ORDER_*; default XCD)      */
-  AF_OPT_UPDATE_THREADS = 9 /* batched handles: workgroup size of the update kernel, one
+  AF_OPT_UPDATE_THREADS = 9, /* batched handles: workgroup size of the update kernel, one
                                row of cells per workgroup: 64, 128 (default) or 256        */
+  AF_OPT_TRANSONIC = 10,    /* 1: Algorithm 2.  A corner is flagged when, across its two
+                               rows (columns) of cells, u + c or u - c (v + c or v - c) of
+                               the primitive averages goes from positive to negative; a
+                               flagged corner, or an edge midpoint with a flagged end
+                               corner, linearises its new time level at the mean of the
+                               adjacent primitive averages instead of U^{n+1/2}.  Meant
+                               with AF_LIN_AVG (Sec. 3.1).  0 (default): off.  Single-grid
+                               handles only.                                               */
+  AF_OPT_SHOCK_LIMITER = 11 /* 1: shock-indicator limiting of point values (Sec. 3.4): the
+                               intermediate and the new value become theta U + (1 - theta)
+                               U_lo, U_lo being EG1 on piecewise constant data linearised at
+                               the mean of the adjacent primitive averages (as in
+                               Algorithm 3), theta = exp(-phi1 phi2), phi1 the larger of the
+                               two pressure sensors |p(k+1) - 2p(k) + p(k-1)| / (p(k+1) +
+                               2p(k) + p(k-1)) centred on the two cells next to an edge
+                               midpoint, phi2 = 2^max(|w| + c) over those cells (w: the
+                               velocity along the edge normal); a corner takes the smallest
+                               theta of its four edges.  A non-admissible average in a
+                               sensor's stencil gives theta = 0; where the mean of the
+                               averages is not admissible the value is not blended.
+                               Algorithm 3 (AF_OPT_LIMITER) then runs on the blended value.
+                               0 (default): off.  Single-grid handles only.                */
 };
 /* Tile orders of the batched point kernel.  Workgroups are dealt to the GPU's 8 XCDs in turn;
  * AF_ORDER_XCD gives each XCD a contiguous range of the global tile index, AF_ORDER_LINEAR
@@ -123,6 +145,8 @@ enum {
   AF_CNT_INNER = 3,      /* Algorithm 1 inner states not admissible (the intermediate
                             value was then linearised at U^n)                          */
   AF_CNT_STEPS = 4,      /* steps taken                                               */
+  AF_CNT_TSW = 5,        /* DOFs whose new time level took the transonic-shock
+                            linearisation (AF_OPT_TRANSONIC)                           */
   AF_NCOUNTERS = 8
 };
 

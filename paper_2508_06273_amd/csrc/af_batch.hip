@@ -52,7 +52,7 @@ __device__ __forceinline__ void batch_points(Smem<R>& S, const GridDesc* __restr
   const Params P = desc[g].P;
   const Bufs B = desc[g].B[cur];
   const int local = t - desc[g].tile_base;
-  points_body<R>(S, P, B, devs + g, dt_host, cur, local, local == 0);
+  points_body<R>(S, nullptr, P, B, devs + g, dt_host, cur, local, local == 0);
 }
 
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
@@ -96,7 +96,7 @@ __device__ __forceinline__ void batch_fixup(Smem<R>& S, const GridDesc* __restri
     const Params P = desc[g].P;
     const Bufs B = desc[g].B[cur];
     double speed = 0.0;
-    fixup_tile<R>(S, P, B, devs + g, s_tile, s_dt, s_run != 0, mask, speed);
+    fixup_tile<R>(S, nullptr, P, B, devs + g, s_tile, s_dt, s_run != 0, mask, speed);
     block_max_atomic(speed, &devs[g].smax[cur ^ 1], S.red);
     __syncthreads();  // the next entry overwrites the shared values
   }

@@ -53,6 +53,9 @@ struct af_handle {
   Batch* batch = nullptr;   // several grids (af_create_batch); nullptr for one grid
   int autotune = 0;         // batched: 1 = tune the schedule at the next af_run, 2 = tuned
   std::vector<Sides> sides;  // per grid
+  int tsw = 0, shock = 0;    // Algorithm 2; the shock-indicator blend (single grids)
+  double* UB = nullptr;      // padded primitive averages for the indicators
+  long long pU = 0;
   std::string err;
 };
 

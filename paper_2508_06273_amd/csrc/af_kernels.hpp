@@ -56,6 +56,8 @@ struct Params {
   long long pF, sF;  // pitch and variable stride of the flux-sum arrays (doubles)
   int bc[4];         // boundary kind per side (left, right, bottom, top): BC_*
   double inflow[4][4];  // primitive inflow state per side (sides of kind BC_INFLOW)
+  int tsw, shock;    // Algorithm 2; the shock-indicator blend of Sec. 3.4
+  long long pU, sU;  // pitch and variable stride of the padded primitive averages
 };
 
 // Point values are stored in FP64 in both precisions (the bulk type only sets the arithmetic
@@ -78,6 +80,9 @@ struct Bufs {
   int* fix_list;
   unsigned int* fix_count;
   int tile_base;
+  // primitive Simpson averages of the cells -2 .. nx+1 x -2 .. ny+1 (cell (i, j) at
+  // (j + 2) * pU + i + 2), written before the point kernel when an indicator is on
+  double* UB;
 };
 
 // Periodic index of a (possibly ghost) cell or grid line, i >= -n.  The common case needs no
@@ -194,6 +199,22 @@ template <class R> struct Smem {
   double sy[4 * NS];
   double red[4];
 };
+
+// Indicators of a tile (Algorithm 2, Sec. 3.4): the primitive averages of the cells -2 .. TILE
+// around it, theta of its x-edges (sites 0..TILE-1 x -1..TILE-1) and y-edges (-1..TILE-1 x
+// 0..TILE-1), and the transonic flags of the corners 0..TILE x 0..TILE.
+constexpr int RC = TILE + 3;  // ring cells per edge (local -2 .. TILE)
+constexpr int NR = RC * RC;
+struct Ind {
+  double ring[4 * NR];
+  double thx[TILE * (TILE + 1)];
+  double thy[(TILE + 1) * TILE];
+  unsigned char flag[(TILE + 1) * (TILE + 1)];
+};
+__device__ __forceinline__ int ridx(int a, int b) { return (a + 2) + (b + 2) * RC; }
+__device__ __forceinline__ int thx_idx(int a, int b) { return a + (b + 1) * TILE; }
+__device__ __forceinline__ int thy_idx(int a, int b) { return (a + 1) + b * (TILE + 1); }
+__device__ __forceinline__ int flag_idx(int a, int b) { return a + b * (TILE + 1); }
 
 __device__ __forceinline__ int sidx(int a, int b) { return (a + 1) + (b + 1) * HS; }
 __device__ __forceinline__ int cidx(int a, int b) { return (a + 1) + (b + 1) * HC; }

@@ -18,24 +18,48 @@
 namespace af {
 
 // ------------------------------------------------------------------------------------------
-// Kernel 1: point values, one workgroup per 8x8-site tile (XCD-aware tile order).
+// Kernel 1: point values, one workgroup per 8x8-site tile (XCD-aware tile order).  The _ind
+// variants add the indicators of Algorithm 2 and Sec. 3.4.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
 void k_points_f32(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
   __shared__ Smem<float> S;
-  points_body<float>(S, P, B, dev, dt_host, slot,
+  points_body<float>(S, nullptr, P, B, dev, dt_host, slot,
                      tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y), blockIdx.x == 0);
 }
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
 void k_points_f64(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
   __shared__ Smem<double> S;
-  points_body<double>(S, P, B, dev, dt_host, slot,
+  points_body<double>(S, nullptr, P, B, dev, dt_host, slot,
                       tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y), blockIdx.x == 0);
+}
+template <class R>
+__global__ __launch_bounds__(PT_THREADS) void k_points_ind(Params P, Bufs B, DevState* dev,
+                                                           double dt_host, int slot) {
+  __shared__ Smem<R> S;
+  __shared__ Ind I;
+  points_body<R, true>(S, &I, P, B, dev, dt_host, slot,
+                       tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y), blockIdx.x == 0);
+}
+
+// Primitive Simpson averages of the cells -2 .. nx+1 x -2 .. ny+1 for the indicators, one
+// thread per cell (row-major, coalesced).
+__global__ __launch_bounds__(256) void k_avgprim(Params P, Bufs B) {
+  const int W = P.nx + 4;
+  const long long n = (long long)W * (P.ny + 4);
+  for (long long e = blockIdx.x * 256ll + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    const int i = (int)(e % W) - 2, j = (int)(e / W) - 2;
+    double ub[4];
+    prim_average(P, B, i, j, ub);
+    const long long o = (long long)(j + 2) * P.pU + (i + 2);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) B.UB[v * P.sU + o] = ub[v];
+  }
 }
 
 // Positivity fix-up pass over the tiles the point kernel listed.  Cheap when the list is empty.
-template <class R>
-__device__ __forceinline__ void fixup_body(Smem<R>& S, const Params& P, const Bufs& B,
+template <class R, bool IND>
+__device__ __forceinline__ void fixup_body(Smem<R>& S, Ind* I, const Params& P, const Bufs& B,
                                            DevState* dev, int slot) {
   __shared__ unsigned long long mask[3];
   __shared__ int s_run;
@@ -50,18 +74,25 @@ __device__ __forceinline__ void fixup_body(Smem<R>& S, const Params& P, const Bu
   const unsigned int n = s_n;
   double speed = 0.0;
   for (unsigned int k = blockIdx.x; k < n; k += gridDim.x)
-    fixup_tile<R>(S, P, B, dev, B.fix_list[k], s_dt, s_run != 0, mask, speed);
+    fixup_tile<R, IND>(S, I, P, B, dev, B.fix_list[k], s_dt, s_run != 0, mask, speed);
   if (n > blockIdx.x) block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
 }
 __global__ __launch_bounds__(PT_THREADS) void k_fixup_f32(Params P, Bufs B, DevState* dev,
                                                          int slot) {
   __shared__ Smem<float> S;
-  fixup_body<float>(S, P, B, dev, slot);
+  fixup_body<float, false>(S, nullptr, P, B, dev, slot);
 }
 __global__ __launch_bounds__(PT_THREADS) void k_fixup_f64(Params P, Bufs B, DevState* dev,
                                                          int slot) {
   __shared__ Smem<double> S;
-  fixup_body<double>(S, P, B, dev, slot);
+  fixup_body<double, false>(S, nullptr, P, B, dev, slot);
+}
+template <class R>
+__global__ __launch_bounds__(PT_THREADS) void k_fixup_ind(Params P, Bufs B, DevState* dev,
+                                                          int slot) {
+  __shared__ Smem<R> S;
+  __shared__ Ind I;
+  fixup_body<R, true>(S, &I, P, B, dev, slot);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -150,6 +181,8 @@ static Params make_params(const af_handle* h) {
   P.pP = h->pP; P.sP = h->pP * h->nky;
   P.pF = h->pF; P.sF = h->pF * h->nky;
   fill_sides(h, 0, P);
+  P.tsw = h->tsw; P.shock = h->shock;
+  P.pU = h->pU; P.sU = h->pU * (h->ny + 4);
   return P;
 }
 
@@ -243,6 +276,7 @@ static void destroy_handle(af_handle* h) {
   batch_destroy(h);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->dev) (void)hipFree(h->dev);
+  if (h->UB) (void)hipFree(h->UB);
   if (h->stage) (void)hipHostFree(h->stage);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   delete h;
@@ -372,6 +406,19 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
       if (value != 0 && value != 1) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: 0 or 1");
       h->autotune = (int)value;
       break;
+    case AF_OPT_TRANSONIC:
+    case AF_OPT_SHOCK_LIMITER:
+      if (value != 0 && value != 1) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: 0 or 1");
+      if (h->batch && value)
+        return fail(h, AF_ERR_INVALID_ARG,
+                    "af_set_option: the shock indicators are for single-grid handles");
+      if (value && !h->UB) {
+        h->pU = (h->nx + 4 + 31) / 32 * 32;
+        HIP_OK(hipMalloc(&h->UB, (size_t)4 * h->pU * (h->ny + 4) * sizeof(double)), h);
+      }
+      if (key == AF_OPT_TRANSONIC) h->tsw = (int)value;
+      else h->shock = (int)value;
+      break;
     case AF_OPT_TILE_ORDER:
     case AF_OPT_UPDATE_THREADS: {
       if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: batched handles only");
@@ -402,6 +449,8 @@ extern "C" int af_get_option(const af_handle* h, int key, int64_t* value) {
     case AF_OPT_GRAPH_STEPS: *value = h->graph_steps; return AF_OK;
     case AF_OPT_TIMING: *value = h->timing; return AF_OK;
     case AF_OPT_AUTOTUNE: *value = h->autotune == 1; return AF_OK;
+    case AF_OPT_TRANSONIC: *value = h->tsw; return AF_OK;
+    case AF_OPT_SHOCK_LIMITER: *value = h->shock; return AF_OK;
     case AF_OPT_TILE_ORDER:
     case AF_OPT_UPDATE_THREADS:
       if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_get_option: batched handles only");
@@ -560,6 +609,7 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
   B.FK = h->FK; B.FX = h->FX; B.FY = h->FY;
   B.fix_mask = h->fix_mask; B.fix_list = h->fix_list;
   B.fix_count = &h->dev->fix_count; B.tile_base = 0;
+  B.UB = h->UB;
   const int ntiles = P.tiles_x * P.tiles_y;
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (h->timing) {
@@ -568,15 +618,26 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
     (void)hipEventCreate(&e2);
     (void)hipEventRecord(e0, h->stream);
   }
-  if constexpr (sizeof(R) == 4)
+  const bool ind = h->tsw || h->shock;
+  if (ind) {
+    const long long n = (long long)(h->nx + 4) * (h->ny + 4);
+    const int gb = (int)std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_avgprim, dim3(gb), dim3(256), 0, h->stream, P, B);
+    hipLaunchKernelGGL(k_points_ind<R>, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B,
+                       h->dev, dt_host, in);
+  } else if constexpr (sizeof(R) == 4) {
     hipLaunchKernelGGL(k_points_f32, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
                        dt_host, in);
-  else
+  } else {
     hipLaunchKernelGGL(k_points_f64, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
                        dt_host, in);
+  }
   if (h->limiter) {
     const int nb = std::min(ntiles, FIX_BLOCKS);
-    if constexpr (sizeof(R) == 4)
+    if (ind)
+      hipLaunchKernelGGL(k_fixup_ind<R>, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
+                         in);
+    else if constexpr (sizeof(R) == 4)
       hipLaunchKernelGGL(k_fixup_f32, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev, in);
     else
       hipLaunchKernelGGL(k_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev, in);

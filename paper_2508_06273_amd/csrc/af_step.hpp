@@ -72,10 +72,27 @@ __device__ __forceinline__ void mark_fix(const Bufs& B, int tile, int kind, int 
 // FIX = false (main pass): a DOF whose value needs the positivity limiter is left to the
 // fix-up pass, which keeps the rare limiter code out of the main kernel's registers.
 // FIX = true (fix-up pass): the same computation with Algorithm 3 applied.
-template <class R, int KIND, bool FIX>
-__device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bufs& B,
-                                           DevState* dev, int tile, int a, int b, int gi,
-                                           int gj, double dt, double& speed) {
+// Sec. 3.4: U := theta U + (1 - theta) U_lo, U_lo = EG1 on the piecewise constant data over tau
+// linearised at the mean of the adjacent primitive averages Ut.  Where Ut is not admissible, or
+// EG1 fails other than by the CFL condition, U is kept.  Returns 0 or ERR_CFL.
+template <class R, int KIND>
+__device__ __forceinline__ int shock_blend(const Smem<R>& S, const Geo<R>& G, int cb,
+                                           const double Ut[4], double tau, double theta,
+                                           double U[4]) {
+  if (!admissible(Ut[0], Ut[3])) return 0;
+  R d[4];
+  const int e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(tau), G, d);
+  if (e == ERR_CFL) return e;
+  if (e) return 0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) U[v] = theta * U[v] + (1.0 - theta) * (Ut[v] + (double)d[v]);
+  return 0;
+}
+
+template <class R, int KIND, bool FIX, bool IND>
+__device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Params& P,
+                                           const Bufs& B, DevState* dev, int tile, int a, int b,
+                                           int gi, int gj, double dt, double& speed) {
   const Geo<R> G = {R(P.idx), R(0.5 * P.dy * P.idx), R(P.gamma), R(0.5 * P.hmin)};
   const double* site = (KIND == KIND_K) ? S.sk : (KIND == KIND_X ? S.sx : S.sy);
   const int s0 = sidx(a, b);
@@ -150,6 +167,29 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
     for (int v = 0; v < 4; ++v) lin[v] = U0[v];
   }
 
+  // indicators of this DOF (Sec. 3.4 theta; Algorithm 2 flag)
+  double theta = 1.0;
+  bool tsw = false;
+  if constexpr (IND) {
+    if (P.shock) {
+      if constexpr (KIND == KIND_K)
+        theta = mn(mn(I->thx[thx_idx(a, b)], I->thx[thx_idx(a, b - 1)]),
+                   mn(I->thy[thy_idx(a, b)], I->thy[thy_idx(a - 1, b)]));
+      else if constexpr (KIND == KIND_X)
+        theta = I->thx[thx_idx(a, b)];
+      else
+        theta = I->thy[thy_idx(a, b)];
+    }
+    if (P.tsw) {
+      if constexpr (KIND == KIND_K)
+        tsw = I->flag[flag_idx(a, b)] != 0;
+      else if constexpr (KIND == KIND_X)
+        tsw = (I->flag[flag_idx(a, b)] | I->flag[flag_idx(a, b + 1)]) != 0;
+      else
+        tsw = (I->flag[flag_idx(a, b)] | I->flag[flag_idx(a + 1, b)]) != 0;
+    }
+  }
+
   double Uh[4], U1[4];
   {
     R d[4];
@@ -157,6 +197,12 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
     if (e) { set_err(dev, e); return; }
 #pragma unroll
     for (int v = 0; v < 4; ++v) Uh[v] = lin[v] + (double)d[v] + h2 * (double)Cv[v];
+  }
+  if (IND && theta < 1.0) {
+    double Ut[4];
+    avg_lin(Ut);
+    e = shock_blend<R, KIND>(S, G, cb, Ut, 0.5 * dt, theta, Uh);
+    if (e) { set_err(dev, e); return; }
   }
   // positivity of the intermediate value (Algorithm 3)
   if (!admissible(Uh[0], Uh[3])) {
@@ -172,11 +218,26 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
     }
   }
   {
+    // the new time level is linearised at U^{n+1/2}, or next to a transonic shock at the mean
+    // of the adjacent averages (Algorithm 2)
+    double lf[4];
+    if (IND && tsw) {
+      avg_lin(lf);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lf[v] = Uh[v];
+    }
     R d[4];
-    e = eg2<R, KIND>(S, cb, Uh, R(dt), G, d);
+    e = eg2<R, KIND>(S, cb, lf, R(dt), G, d);
     if (e) { set_err(dev, e); return; }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) U1[v] = Uh[v] + (double)d[v] + f2 * (double)Cv[v];
+    for (int v = 0; v < 4; ++v) U1[v] = lf[v] + (double)d[v] + f2 * (double)Cv[v];
+  }
+  if (IND && theta < 1.0) {
+    double Ut[4];
+    avg_lin(Ut);
+    e = shock_blend<R, KIND>(S, G, cb, Ut, dt, theta, U1);
+    if (e) { set_err(dev, e); return; }
   }
   if (P.limiter && !admissible(U1[0], U1[3])) {
     if constexpr (!FIX) {
@@ -191,6 +252,7 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Params& P, const Bu
   }
 
   // outputs: new point value, Simpson-in-time flux sums, wave speed
+  if (IND && tsw) atomicAdd(&dev->cnt[AF_CNT_TSW], 1ull);
   double* out = (KIND == KIND_K) ? B.K_out : (KIND == KIND_X ? B.X_out : B.Y_out);
   const long long o = (long long)gj * P.pP + gi;
 #pragma unroll
@@ -273,6 +335,179 @@ __device__ __forceinline__ bool step_dt(const Params& P, DevState* dev, double d
   return s_run != 0;
 }
 
+// t_n point value of kind `kind` (0 K, 1 X, 2 Y) at the possibly ghost site (gi, gj), through
+// the boundary rules.
+__device__ __forceinline__ void fetch_site(const Params& P, const Bufs& B, int kind, int gi,
+                                           int gj, double W[4]) {
+  int si, sj, sx, sy;
+  const double* src;
+  if (kind == 0) {
+    si = map_axis<true>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+    sj = map_axis<true>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+    src = B.K_in;
+  } else if (kind == 1) {
+    si = map_axis<true>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+    sj = map_axis<false>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+    src = B.X_in;
+  } else {
+    si = map_axis<false>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+    sj = map_axis<true>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+    src = B.Y_in;
+  }
+  const long long o = (long long)sj * P.pP + si;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) W[v] = src[v * P.sP + o];
+  if (sx >= 0 || sy >= 0) apply_sides(P, sx, sy, W);  // a ghost site
+}
+
+// Primitive Simpson average of the (possibly ghost, up to two layers) cell (i, j), with the
+// cell preparation's rules and arithmetic: inverse Simpson for the centre value (deviation
+// form, falling back to C2P of the average), inflow ghosts centred at the inflow state, wall
+// ghosts the reflection of the cell they face.
+__device__ __forceinline__ void prim_average(const Params& P, const Bufs& B, int i, int j,
+                                             double ub[4]) {
+  int sx, sy;
+  const int gi = map_axis<false>(i, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+  const int gj = map_axis<false>(j, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+  const bool inflow = inflow_side(P, 0, sx) || inflow_side(P, 1, sy);
+  const bool fx = !inflow && sx >= 0 && P.bc[sx] == BC_WALL;
+  const bool fy = !inflow && sy >= 0 && P.bc[2 + sy] == BC_WALL;
+  const int ci = fx ? gi : i, cj = fy ? gj : j;
+  const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
+  double w[8][4];
+  fetch_site(P, B, 0, ci, cj, w[0]);
+  fetch_site(P, B, 0, ci + 1, cj, w[1]);
+  fetch_site(P, B, 0, ci, cj + 1, w[2]);
+  fetch_site(P, B, 0, ci + 1, cj + 1, w[3]);
+  fetch_site(P, B, 1, ci, cj, w[4]);
+  fetch_site(P, B, 1, ci + 1, cj, w[5]);
+  fetch_site(P, B, 2, ci, cj, w[6]);
+  fetch_site(P, B, 2, ci, cj + 1, w[7]);
+  double Uc[4];
+  if (inflow) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Uc[v] = 0.0;
+    apply_sides(P, sx, sy, Uc);
+  } else {
+    double Qb[4];
+    const long long oa = (long long)gj * P.pA + gi;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Qb[v] = B.A_in[v * P.sA + oa];
+    double Wr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      Wr[v] = (((w[0][v] + w[1][v]) + (w[2][v] + w[3][v])) +
+               ((w[4][v] + w[5][v]) + (w[6][v] + w[7][v]))) * 0.125;
+    double dQ[4];
+    {
+      double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, Q[4];
+      for (int k = 0; k < 8; ++k) {
+        p2c(w[k], g1inv, Q);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (k < 4) sK[v] += Qb[v] - Q[v];
+          else sE[v] += Qb[v] - Q[v];
+        }
+      }
+      p2c(Wr, g1inv, Q);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Q[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
+    }
+    c2p_dev(Wr, dQ, gm1, Uc);
+    if (!admissible(Uc[0], Uc[3])) c2p_plain(Qb, gm1, Uc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double u = Uc[v];
+    const double sK4 = ((w[0][v] - u) + (w[1][v] - u)) + ((w[2][v] - u) + (w[3][v] - u));
+    const double sE4 = ((w[4][v] - u) + (w[5][v] - u)) + ((w[6][v] - u) + (w[7][v] - u));
+    const double sv = ((fx && v == 1) || (fy && v == 2)) ? -1.0 : 1.0;
+    ub[v] = sv * (u + (sK4 + 4.0 * sE4) * (1.0 / 36.0));
+  }
+}
+
+// Algorithm 2: across the cells L -> R (ring indices) in the direction of velocity component
+// comp (1: x, 2: y), w + c or w - c goes from positive to negative.
+__device__ __forceinline__ bool transonic_pair(const double* ring, int l, int r, int comp,
+                                               double gamma) {
+  const double cl = sqrt(gamma * ring[3 * NR + l] / ring[l]);
+  const double cr = sqrt(gamma * ring[3 * NR + r] / ring[r]);
+  const double wl = ring[comp * NR + l], wr = ring[comp * NR + r];
+  return (wl + cl > 0.0 && wr + cr < 0.0) || (wl - cl > 0.0 && wr - cr < 0.0);
+}
+
+// Sec. 3.4: theta of the edge midpoint between ring cells c1 and c2 of the line of ring cells
+// c0, c1, c2, c3 (spacing `st`), velocity component comp along the line.
+__device__ __forceinline__ double theta_edge(const double* ring, int c0, int st, int comp,
+                                             double gamma) {
+  double p[4], a[2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int c = c0 + m * st;
+    if (!admissible(ring[c], ring[3 * NR + c])) return 0.0;
+    p[m] = ring[3 * NR + c];
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int c = c0 + (2 - m) * st;  // cell k, then k-1
+    a[m] = fabs(ring[comp * NR + c]) + sqrt(gamma * ring[3 * NR + c] / ring[c]);
+  }
+  const double s_hi = fabs((p[3] - 2.0 * p[2] + p[1]) / (p[3] + 2.0 * p[2] + p[1]));
+  const double s_lo = fabs((p[2] - 2.0 * p[1] + p[0]) / (p[2] + 2.0 * p[1] + p[0]));
+  const double phi1 = s_hi > s_lo ? s_hi : s_lo;
+  const double phi2 = exp2(a[0] > a[1] ? a[0] : a[1]);
+  return exp(-phi1 * phi2);
+}
+
+// Stage the primitive averages of the ring of cells -2 .. TILE around a tile (from the padded
+// array written by the averaging pass; they replace the prep's own, so that one set of averages
+// serves the linearisations and the indicators), then theta of the tile's edge midpoints and the
+// transonic flags of its corners.  Ends with a barrier.
+template <class R>
+__device__ __forceinline__ void stage_indicators(Smem<R>& S, Ind& I, const Params& P,
+                                                 const Bufs& B, int tile) {
+  const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
+  const int tid = threadIdx.x;
+  for (int c = tid; c < NR; c += PT_THREADS) {
+    const int a = c % RC - 2, b = c / RC - 2;
+    // cells beyond the padded range are never read by a DOF of the grid
+    const int gi = min(i0 + a, P.nx + 1), gj = min(j0 + b, P.ny + 1);
+    const long long o = (long long)(gj + 2) * P.pU + (gi + 2);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double u = B.UB[v * P.sU + o];
+      I.ring[v * NR + c] = u;
+      if (a >= -1 && a < TILE && b >= -1 && b < TILE) S.ub[v * NC + cidx(a, b)] = u;
+    }
+  }
+  __syncthreads();
+  const double g = P.gamma;
+  for (int e = tid; e < (TILE + 1) * (TILE + 1) + 2 * TILE * (TILE + 1); e += PT_THREADS) {
+    if (e < (TILE + 1) * (TILE + 1)) {
+      // corner (a, b): cells (a-1 .. a) x (b-1 .. b)
+      const int a = e % (TILE + 1), b = e / (TILE + 1);
+      bool f = false;
+      if (P.tsw)
+        f = transonic_pair(I.ring, ridx(a - 1, b), ridx(a, b), 1, g) ||
+            transonic_pair(I.ring, ridx(a - 1, b - 1), ridx(a, b - 1), 1, g) ||
+            transonic_pair(I.ring, ridx(a - 1, b - 1), ridx(a - 1, b), 2, g) ||
+            transonic_pair(I.ring, ridx(a, b - 1), ridx(a, b), 2, g);
+      I.flag[flag_idx(a, b)] = f ? 1 : 0;
+    } else if (e < (TILE + 1) * (TILE + 1) + TILE * (TILE + 1)) {
+      // x-edge (a, b), a in 0..TILE-1, b in -1..TILE-1: cells a-2 .. a+1 of row b
+      const int q = e - (TILE + 1) * (TILE + 1);
+      const int a = q % TILE, b = q / TILE - 1;
+      I.thx[thx_idx(a, b)] = P.shock ? theta_edge(I.ring, ridx(a - 2, b), 1, 1, g) : 1.0;
+    } else {
+      // y-edge (a, b), a in -1..TILE-1, b in 0..TILE-1: cells b-2 .. b+1 of column a
+      const int q = e - (TILE + 1) * (TILE + 1) - TILE * (TILE + 1);
+      const int a = q % (TILE + 1) - 1, b = q / (TILE + 1);
+      I.thy[thy_idx(a, b)] = P.shock ? theta_edge(I.ring, ridx(a, b - 2), RC, 2, g) : 1.0;
+    }
+  }
+  __syncthreads();
+}
+
 // Stage the t_n point values of a tile's halo in LDS and build the halo cells'
 // reconstructions.  Ends with a barrier.
 template <class R>
@@ -285,28 +520,9 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
   for (int e = tid; e < 3 * NS; e += PT_THREADS) {
     const int kind = e / NS, s = e % NS;
     const int a = s % HS - 1, b = s / HS - 1;
-    const int gi = i0 + a, gj = j0 + b;
-    int si, sj, sx, sy;
-    const double* src;
-    double* dst;
-    if (kind == 0) {
-      si = map_axis<true>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
-      sj = map_axis<true>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
-      src = B.K_in; dst = S.sk;
-    } else if (kind == 1) {
-      si = map_axis<true>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
-      sj = map_axis<false>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
-      src = B.X_in; dst = S.sx;
-    } else {
-      si = map_axis<false>(gi, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
-      sj = map_axis<true>(gj, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
-      src = B.Y_in; dst = S.sy;
-    }
-    const long long o = (long long)sj * P.pP + si;
     double W[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) W[v] = src[v * P.sP + o];
-    if (sx >= 0 || sy >= 0) apply_sides(P, sx, sy, W);  // a ghost site
+    fetch_site(P, B, kind, i0 + a, j0 + b, W);
+    double* dst = kind == 0 ? S.sk : (kind == 1 ? S.sx : S.sy);
 #pragma unroll
     for (int v = 0; v < 4; ++v) dst[v * NS + s] = W[v];
   }
@@ -416,9 +632,9 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
 // Evolve the tile's own DOFs: wavefront 0 -> K; wavefront 1 -> X, then Y (an edge EG2 costs
 // well under half of a corner EG2, so the two waves are about equally loaded).  In the fix-up
 // pass only the lanes listed in `mask` (per kind) run.
-template <class R, bool FIX>
-__device__ __forceinline__ void evolve_tile(Smem<R>& S, const Params& P, const Bufs& B,
-                                            DevState* dev, int tile, double dt,
+template <class R, bool FIX, bool IND>
+__device__ __forceinline__ void evolve_tile(Smem<R>& S, const Ind* I, const Params& P,
+                                            const Bufs& B, DevState* dev, int tile, double dt,
                                             const unsigned long long* mask, double& speed) {
   const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -428,12 +644,12 @@ __device__ __forceinline__ void evolve_tile(Smem<R>& S, const Params& P, const B
   auto listed = [&](int kind) { return !FIX || ((mask[kind] >> lane) & 1ull); };
   if (wave == 0) {
     if (listed(KIND_K) && gi < P.nkx && gj < P.nky)
-      evolve_dof<R, KIND_K, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
+      evolve_dof<R, KIND_K, FIX, IND>(S, I, P, B, dev, tile, a, b, gi, gj, dt, speed);
   } else {
     if (listed(KIND_X) && gi < P.nkx && gj < P.ny)
-      evolve_dof<R, KIND_X, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
+      evolve_dof<R, KIND_X, FIX, IND>(S, I, P, B, dev, tile, a, b, gi, gj, dt, speed);
     if (listed(KIND_Y) && gi < P.nx && gj < P.nky)
-      evolve_dof<R, KIND_Y, FIX>(S, P, B, dev, tile, a, b, gi, gj, dt, speed);
+      evolve_dof<R, KIND_Y, FIX, IND>(S, I, P, B, dev, tile, a, b, gi, gj, dt, speed);
   }
 }
 
@@ -449,29 +665,31 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles) {
 
 // One tile of the point kernel.  `slot` is the buffer index of the t_n state (its wave-speed
 // maximum is smax[slot]; the new state's goes to smax[slot ^ 1]).
-template <class R>
-__device__ __forceinline__ void points_body(Smem<R>& S, const Params& P, const Bufs& B,
+template <class R, bool IND = false>
+__device__ __forceinline__ void points_body(Smem<R>& S, Ind* I, const Params& P, const Bufs& B,
                                             DevState* dev, double dt_host, int slot, int tile,
                                             bool leader) {
   double dt;
   if (!step_dt(P, dev, dt_host, slot, leader, &dt)) return;
   stage_and_prep(S, P, B, dev, tile, true);
+  if constexpr (IND) stage_indicators(S, *I, P, B, tile);
   double speed = 0.0;
-  evolve_tile<R, false>(S, P, B, dev, tile, dt, nullptr, speed);
+  evolve_tile<R, false, IND>(S, I, P, B, dev, tile, dt, nullptr, speed);
   block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
 }
 
 // Positivity fix-up of one listed tile: stage and prepare it again and recompute only the
 // lanes flagged in its masks with Algorithm 3; then clear the masks.  Block-uniform `run`.
-template <class R>
-__device__ __forceinline__ void fixup_tile(Smem<R>& S, const Params& P, const Bufs& B,
+template <class R, bool IND = false>
+__device__ __forceinline__ void fixup_tile(Smem<R>& S, Ind* I, const Params& P, const Bufs& B,
                                            DevState* dev, int tile, double dt, bool run,
                                            unsigned long long* mask, double& speed) {
   if (threadIdx.x < 3) mask[threadIdx.x] = B.fix_mask[4 * (long long)tile + threadIdx.x];
   __syncthreads();
   if (run) {
     stage_and_prep(S, P, B, dev, tile, false);
-    evolve_tile<R, true>(S, P, B, dev, tile, dt, mask, speed);
+    if constexpr (IND) stage_indicators(S, *I, P, B, tile);
+    evolve_tile<R, true, IND>(S, I, P, B, dev, tile, dt, mask, speed);
   }
   __syncthreads();
   if (threadIdx.x < 4) B.fix_mask[4 * (long long)tile + threadIdx.x] = 0ull;
