@@ -243,7 +243,9 @@ def accuracy_ladder(sizes, t_end, stream):
 def extra_workloads(stream):
     """Throughput of the two limiter workloads (averaged linearisation, positivity limiter on):
     the 2048^2 radial outflow (outflow boundaries; 10 + 190 steps, before the step where an
-    average loses positivity) and the 8192^2 shear layer (10 warm-up + 100 timed steps)."""
+    average loses positivity) and the 8192^2 shear layer (10 warm-up + 100 timed steps), the
+    latter also with Algorithm 2 and the shock-indicator blend; then the shock-reflection
+    problem."""
     from paper_2508_06273_amd import af, inputs as I
     import torch
     out = {}
@@ -253,8 +255,14 @@ def extra_workloads(stream):
         print(f"[bench] {name}", file=sys.stderr, flush=True)
         st = make()
         rec = {}
-        for prec, pname in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64")):
-            s = af.Solver.for_state(st, precision=prec, linearisation=af.AF_LIN_AVG, limiter=True)
+        legs = [(af.AF_PREC_FP32, "fp32", False), (af.AF_PREC_FP64, "fp64", False)]
+        if name.startswith("shear"):
+            # the same run with Algorithm 2 and the shock-indicator blend of Sec. 3.4 on
+            legs += [(af.AF_PREC_FP32, "fp32_indicators", True),
+                     (af.AF_PREC_FP64, "fp64_indicators", True)]
+        for prec, pname, ind in legs:
+            s = af.Solver.for_state(st, precision=prec, linearisation=af.AF_LIN_AVG, limiter=True,
+                                    transonic=ind, shock_limiter=ind)
             s.set_stream(stream)
             s.run(1e9, 0.3, warm)
             torch.cuda.synchronize()
@@ -269,7 +277,7 @@ def extra_workloads(stream):
             cnt = s.counters()
             rec[pname] = {"value": s.dof_count() * steps / (ms * 1e-3), "ms_per_step": ms / steps,
                           "t": t, "eg1_fallbacks": int(cnt[0]), "lf_fallbacks": int(cnt[1]),
-                          "centre_fallbacks": int(cnt[2])}
+                          "centre_fallbacks": int(cnt[2]), "transonic_flags": int(cnt[5])}
             s.close()
         rec["speedup_fp32_vs_fp64"] = rec["fp32"]["value"] / rec["fp64"]["value"]
         rec["steps"] = steps

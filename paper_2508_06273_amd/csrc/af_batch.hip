@@ -49,8 +49,8 @@ __device__ __forceinline__ void batch_points(Smem<R>& S, const GridDesc* __restr
   __syncthreads();
   const int g = __builtin_amdgcn_readfirstlane(s_g);
   const int cur = __builtin_amdgcn_readfirstlane(s_cur);
-  const Params P = desc[g].P;
-  const Bufs B = desc[g].B[cur];
+  const Params& P = desc[g].P;
+  const Bufs& B = desc[g].B[cur];
   const int local = t - desc[g].tile_base;
   points_body<R>(S, nullptr, P, B, devs + g, dt_host, cur, local, local == 0);
 }
@@ -93,8 +93,8 @@ __device__ __forceinline__ void batch_fixup(Smem<R>& S, const GridDesc* __restri
     __syncthreads();
     const int g = __builtin_amdgcn_readfirstlane(s_g);
     const int cur = __builtin_amdgcn_readfirstlane(s_cur);
-    const Params P = desc[g].P;
-    const Bufs B = desc[g].B[cur];
+    const Params& P = desc[g].P;
+    const Bufs& B = desc[g].B[cur];
     double speed = 0.0;
     fixup_tile<R>(S, nullptr, P, B, devs + g, s_tile, s_dt, s_run != 0, mask, speed);
     block_max_atomic(speed, &devs[g].smax[cur ^ 1], S.red);

@@ -72,21 +72,29 @@ __device__ __forceinline__ void mark_fix(const Bufs& B, int tile, int kind, int 
 // FIX = false (main pass): a DOF whose value needs the positivity limiter is left to the
 // fix-up pass, which keeps the rare limiter code out of the main kernel's registers.
 // FIX = true (fix-up pass): the same computation with Algorithm 3 applied.
-// Sec. 3.4: U := theta U + (1 - theta) U_lo, U_lo = EG1 on the piecewise constant data over tau
-// linearised at the mean of the adjacent primitive averages Ut.  Where Ut is not admissible, or
-// EG1 fails other than by the CFL condition, U is kept.  Returns 0 or ERR_CFL.
+// Sec. 3.4: the low-order value U_lo = EG1 on the piecewise constant data, linearised at the mean
+// Ut of the adjacent primitive averages.  On data constant in the four quadrants around the DOF
+// the circle's centre and radius both scale with tau, so every arc angle, and EG1's value, is
+// the same for tau = dt/2 and tau = dt: one evaluation serves both time levels; only the CFL
+// check depends on tau.  Returns 0 (lo valid), 1 (no blend: Ut not admissible) or ERR_CFL.
 template <class R, int KIND>
-__device__ __forceinline__ int shock_blend(const Smem<R>& S, const Geo<R>& G, int cb,
-                                           const double Ut[4], double tau, double theta,
-                                           double U[4]) {
-  if (!admissible(Ut[0], Ut[3])) return 0;
+__device__ __forceinline__ int shock_low(const Smem<R>& S, const Geo<R>& G, int cb,
+                                         const double Ut[4], double tau, double lo[4]) {
+  if (!admissible(Ut[0], Ut[3])) return 1;
   R d[4];
   const int e = eg1_pc<R, KIND>(S.ub, cb, Ut, R(tau), G, d);
-  if (e == ERR_CFL) return e;
-  if (e) return 0;
+  if (e) return e;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) U[v] = theta * U[v] + (1.0 - theta) * (Ut[v] + (double)d[v]);
+  for (int v = 0; v < 4; ++v) lo[v] = Ut[v] + (double)d[v];
   return 0;
+}
+
+// eg1_pc's CFL condition for the linearisation state Ut over tau.
+template <class R>
+__device__ __forceinline__ bool eg1_cfl_fails(const Geo<R>& G, const double Ut[4], double tau) {
+  const R rp = R(Ut[0]), up = R(Ut[1]), vp = R(Ut[2]), pp = R(Ut[3]);
+  const R c = Math<R>::sqrt_(G.gamma * pp / rp);
+  return (mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * R(tau) >= G.half_h;
 }
 
 template <class R, int KIND, bool FIX, bool IND>
@@ -198,11 +206,17 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Param
 #pragma unroll
     for (int v = 0; v < 4; ++v) Uh[v] = lin[v] + (double)d[v] + h2 * (double)Cv[v];
   }
+  // Sec. 3.4 blend of the intermediate value (U_lo is kept for the new time level)
+  double lo[4], Ut[4];
+  int lo_state = 1;  // 0: lo valid, 1: no blend
   if (IND && theta < 1.0) {
-    double Ut[4];
     avg_lin(Ut);
-    e = shock_blend<R, KIND>(S, G, cb, Ut, 0.5 * dt, theta, Uh);
-    if (e) { set_err(dev, e); return; }
+    lo_state = shock_low<R, KIND>(S, G, cb, Ut, 0.5 * dt, lo);
+    if (lo_state == ERR_CFL) { set_err(dev, ERR_CFL); return; }
+    if (lo_state == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Uh[v] = theta * Uh[v] + (1.0 - theta) * lo[v];
+    }
   }
   // positivity of the intermediate value (Algorithm 3)
   if (!admissible(Uh[0], Uh[3])) {
@@ -233,11 +247,10 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Param
 #pragma unroll
     for (int v = 0; v < 4; ++v) U1[v] = lf[v] + (double)d[v] + f2 * (double)Cv[v];
   }
-  if (IND && theta < 1.0) {
-    double Ut[4];
-    avg_lin(Ut);
-    e = shock_blend<R, KIND>(S, G, cb, Ut, dt, theta, U1);
-    if (e) { set_err(dev, e); return; }
+  if (IND && lo_state == 0) {
+    if (eg1_cfl_fails<R>(G, Ut, dt)) { set_err(dev, ERR_CFL); return; }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) U1[v] = theta * U1[v] + (1.0 - theta) * lo[v];
   }
   if (P.limiter && !admissible(U1[0], U1[3])) {
     if constexpr (!FIX) {
