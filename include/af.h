@@ -102,8 +102,7 @@ enum {
                                flagged corner, or an edge midpoint with a flagged end
                                corner, linearises its new time level at the mean of the
                                adjacent primitive averages instead of U^{n+1/2}.  Meant
-                               with AF_LIN_AVG (Sec. 3.1).  0 (default): off.  Single-grid
-                               handles only.                                               */
+                               with AF_LIN_AVG (Sec. 3.1).  0 (default): off.              */
   AF_OPT_SHOCK_LIMITER = 11 /* 1: shock-indicator limiting of point values (Sec. 3.4): the
                                intermediate and the new value become theta U + (1 - theta)
                                U_lo, U_lo being EG1 on piecewise constant data linearised at
@@ -117,7 +116,7 @@ enum {
                                sensor's stencil gives theta = 0; where the mean of the
                                averages is not admissible the value is not blended.
                                Algorithm 3 (AF_OPT_LIMITER) then runs on the blended value.
-                               0 (default): off.  Single-grid handles only.                */
+                               0 (default): off.                                          */
 };
 /* Tile orders of the batched point kernel.  Workgroups are dealt to the GPU's 8 XCDs in turn;
  * AF_ORDER_XCD gives each XCD a contiguous range of the global tile index, AF_ORDER_LINEAR

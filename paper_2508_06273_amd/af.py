@@ -285,7 +285,8 @@ class BatchSolver(_Handle):
     per step for all grids, each grid with its own time step."""
 
     def __init__(self, grids, gamma=1.4, precision=AF_PREC_FP64, linearisation=AF_LIN_AF3,
-                 correction=True, limiter=False, graph_steps=None):
+                 correction=True, limiter=False, graph_steps=None, transonic=False,
+                 shock_limiter=False):
         """grids: sequence of (nx, ny, x0, x1, y0, y1, bc_x, bc_y) or
         (nx, ny, x0, x1, y0, y1, (left, right, bottom, top))."""
         self.L = load()
@@ -303,7 +304,8 @@ class BatchSolver(_Handle):
                               int(ny) + (0 if kinds[2] == AF_BC_PERIODIC else 1)))
         self.h = _H()
         self._check(self.L.af_create_batch(n, G, gamma, B, ct.byref(self.h)), create=True)
-        self._options(precision, linearisation, correction, limiter, graph_steps)
+        self._options(precision, linearisation, correction, limiter, graph_steps, transonic,
+                      shock_limiter)
 
     @classmethod
     def for_states(cls, states, **kw):

@@ -68,9 +68,52 @@ void kb_points_f64(const GridDesc* desc, const int* tile_grid, const int* block_
   batch_points<double>(S, desc, tile_grid, block_tile, devs, dt_host);
 }
 
-// Positivity fix-up over the global list of flagged tiles (entries are global tile indices).
+// With the shock indicators (Algorithm 2, Sec. 3.4): the point kernel's indicator variant.
 template <class R>
-__device__ __forceinline__ void batch_fixup(Smem<R>& S, const GridDesc* __restrict__ desc,
+__global__ __launch_bounds__(PT_THREADS) void kb_points_ind(const GridDesc* desc,
+                                                            const int* tile_grid,
+                                                            const int* block_tile,
+                                                            DevState* devs, double dt_host) {
+  __shared__ Smem<R> S;
+  __shared__ Ind I;
+  __shared__ int s_g, s_cur;
+  const int t = block_tile[blockIdx.x];
+  if (threadIdx.x == 0) {
+    const int g = tile_grid[t];
+    s_g = g;
+    s_cur = devs[g].cur;
+  }
+  __syncthreads();
+  const int g = __builtin_amdgcn_readfirstlane(s_g);
+  const int cur = __builtin_amdgcn_readfirstlane(s_cur);
+  const Params& P = desc[g].P;
+  const Bufs& B = desc[g].B[cur];
+  const int local = t - desc[g].tile_base;
+  points_body<R, true>(S, &I, P, B, devs + g, dt_host, cur, local, local == 0);
+}
+
+// Primitive Simpson averages of every grid's padded cells (-2 .. nx+1 x -2 .. ny+1) from its
+// current state: one workgroup per padded row (prow_grid: the grid of each padded row).
+__global__ __launch_bounds__(256) void kb_avgprim(const GridDesc* __restrict__ desc,
+                                                  const int* __restrict__ prow_grid,
+                                                  const int* __restrict__ prow_base,
+                                                  DevState* devs) {
+  const int g = prow_grid[blockIdx.x];
+  const Params& P = desc[g].P;
+  const Bufs& B = desc[g].B[devs[g].cur];
+  const int j = blockIdx.x - prow_base[g] - 2;
+  for (int i = (int)threadIdx.x - 2; i < P.nx + 2; i += 256) {
+    double ub[4];
+    prim_average(P, B, i, j, ub);
+    const long long o = (long long)(j + 2) * P.pU + (i + 2);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) B.UB[v * P.sU + o] = ub[v];
+  }
+}
+
+// Positivity fix-up over the global list of flagged tiles (entries are global tile indices).
+template <class R, bool IND = false>
+__device__ __forceinline__ void batch_fixup(Smem<R>& S, Ind* I, const GridDesc* __restrict__ desc,
                                             const int* __restrict__ tile_grid, DevState* devs,
                                             const int* fix_list, const unsigned int* fix_count) {
   __shared__ unsigned long long mask[3];
@@ -96,7 +139,7 @@ __device__ __forceinline__ void batch_fixup(Smem<R>& S, const GridDesc* __restri
     const Params& P = desc[g].P;
     const Bufs& B = desc[g].B[cur];
     double speed = 0.0;
-    fixup_tile<R>(S, nullptr, P, B, devs + g, s_tile, s_dt, s_run != 0, mask, speed);
+    fixup_tile<R, IND>(S, I, P, B, devs + g, s_tile, s_dt, s_run != 0, mask, speed);
     block_max_atomic(speed, &devs[g].smax[cur ^ 1], S.red);
     __syncthreads();  // the next entry overwrites the shared values
   }
@@ -106,14 +149,24 @@ __global__ __launch_bounds__(PT_THREADS) void kb_fixup_f32(const GridDesc* desc,
                                                           const int* fix_list,
                                                           const unsigned int* fix_count) {
   __shared__ Smem<float> S;
-  batch_fixup<float>(S, desc, tile_grid, devs, fix_list, fix_count);
+  batch_fixup<float>(S, nullptr, desc, tile_grid, devs, fix_list, fix_count);
 }
 __global__ __launch_bounds__(PT_THREADS) void kb_fixup_f64(const GridDesc* desc,
                                                           const int* tile_grid, DevState* devs,
                                                           const int* fix_list,
                                                           const unsigned int* fix_count) {
   __shared__ Smem<double> S;
-  batch_fixup<double>(S, desc, tile_grid, devs, fix_list, fix_count);
+  batch_fixup<double>(S, nullptr, desc, tile_grid, devs, fix_list, fix_count);
+}
+
+template <class R>
+__global__ __launch_bounds__(PT_THREADS) void kb_fixup_ind(const GridDesc* desc,
+                                                           const int* tile_grid, DevState* devs,
+                                                           const int* fix_list,
+                                                           const unsigned int* fix_count) {
+  __shared__ Smem<R> S;
+  __shared__ Ind I;
+  batch_fixup<R, true>(S, &I, desc, tile_grid, devs, fix_list, fix_count);
 }
 
 // Update kernel: one workgroup of T threads per row of cells of any grid (XCD-aware row
@@ -188,6 +241,8 @@ struct BatchGrid {
   double x0, y0, dx, dy;
   long long pA, pP;        // row pitches (elements)
   size_t oA, oP, oF;       // element offsets of the grid in the packed arrays
+  long long pU;            // row pitch of the padded primitive averages (indicators)
+  size_t oU;               // element offset of those
   int tile_base, tiles_x, tiles_y, row_base;
   bool has_state;
 };
@@ -208,6 +263,10 @@ struct Batch {
   GridDesc* d_desc = nullptr;
   int* d_tile_grid = nullptr;
   int* d_row_grid = nullptr;
+  double* UB = nullptr;          // padded primitive averages (allocated with the indicators)
+  int* d_prow_grid = nullptr;    // grid of every padded row
+  int* d_prow_base = nullptr;    // first padded row of every grid
+  int total_prows = 0;
   DevState* d_devs = nullptr;
   int total_tiles = 0, total_rows = 0;
   bool desc_valid = false;
@@ -230,6 +289,7 @@ static void batch_free(Batch* b) {
   for (void* p : {(void*)b->FK, (void*)b->FX, (void*)b->FY, (void*)b->fix_mask,
                   (void*)b->fix_list, (void*)b->fix_count, (void*)b->d_desc,
                   (void*)b->d_tile_grid, (void*)b->d_row_grid, (void*)b->d_devs,
+                  (void*)b->UB, (void*)b->d_prow_grid, (void*)b->d_prow_base,
                   (void*)b->d_block_tile})
     if (p) (void)hipFree(p);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -247,6 +307,30 @@ void batch_invalidate(af_handle* h) {
 }
 
 int batch_count(const af_handle* h) { return h->batch ? h->batch->n : 1; }
+
+// Padded primitive averages of every grid and the padded-row tables (the shock indicators).
+int batch_alloc_indicators(af_handle* h) {
+  Batch* b = h->batch;
+  if (b->UB) return AF_OK;
+  size_t nU = 0;
+  std::vector<int> pg, pb((size_t)b->n);
+  for (int k = 0; k < b->n; ++k) {
+    BatchGrid& q = b->g[k];
+    q.pU = (q.nx + 4 + 31) / 32 * 32;
+    q.oU = nU;
+    nU += round_up((size_t)4 * q.pU * (q.ny + 4), 64);
+    pb[k] = (int)pg.size();
+    pg.insert(pg.end(), (size_t)(q.ny + 4), k);
+  }
+  HIP_OK(hipMalloc(&b->UB, nU * sizeof(double)), h);
+  HIP_OK(hipMalloc(&b->d_prow_grid, pg.size() * sizeof(int)), h);
+  HIP_OK(hipMalloc(&b->d_prow_base, pb.size() * sizeof(int)), h);
+  HIP_OK(hipMemcpy(b->d_prow_grid, pg.data(), pg.size() * sizeof(int), hipMemcpyHostToDevice), h);
+  HIP_OK(hipMemcpy(b->d_prow_base, pb.data(), pb.size() * sizeof(int), hipMemcpyHostToDevice), h);
+  b->total_prows = (int)pg.size();
+  batch_invalidate(h);
+  return AF_OK;
+}
 
 void batch_destroy(af_handle* h) {
   if (h->batch) batch_free(h->batch);
@@ -279,6 +363,8 @@ int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af
     q.tiles_y = (q.nky + TILE - 1) / TILE;
     q.tile_base = (int)tiles;
     q.row_base = (int)rows;
+    q.pU = 0;
+    q.oU = 0;
     tiles += (long long)q.tiles_x * q.tiles_y;
     rows += q.ny;
     q.has_state = false;
@@ -409,6 +495,8 @@ static int upload_desc(af_handle* h) {
     P.pP = q.pP; P.sP = q.pP * q.nky;
     P.pF = q.pP; P.sF = q.pP * q.nky;
     fill_sides(h, k, P);
+    P.tsw = h->tsw; P.shock = h->shock;
+    P.pU = q.pU; P.sU = q.pU * (q.ny + 4);
     for (int in = 0; in < 2; ++in) {
       Bufs& B = d[k].B[in];
       const int out = in ^ 1;
@@ -419,6 +507,7 @@ static int upload_desc(af_handle* h) {
       B.fix_mask = b->fix_mask + 4 * (size_t)q.tile_base;
       B.fix_list = b->fix_list;
       B.fix_count = b->fix_count;
+      B.UB = b->UB ? b->UB + q.oU : nullptr;
       B.tile_base = q.tile_base;
     }
     d[k].tile_base = q.tile_base;
@@ -538,15 +627,25 @@ template <class R>
 static void enqueue_batch_step(af_handle* h, double dt_host, hipEvent_t* ev) {
   Batch* b = h->batch;
   if (ev) (void)hipEventRecord(ev[0], h->stream);
-  if constexpr (sizeof(R) == 4)
+  const bool ind = h->tsw || h->shock;
+  if (ind) {
+    hipLaunchKernelGGL(kb_avgprim, dim3(b->total_prows), dim3(256), 0, h->stream, b->d_desc,
+                       b->d_prow_grid, b->d_prow_base, b->d_devs);
+    hipLaunchKernelGGL(kb_points_ind<R>, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
+                       b->d_desc, b->d_tile_grid, b->d_block_tile, b->d_devs, dt_host);
+  } else if constexpr (sizeof(R) == 4) {
     hipLaunchKernelGGL(kb_points_f32, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
                        b->d_desc, b->d_tile_grid, b->d_block_tile, b->d_devs, dt_host);
-  else
+  } else {
     hipLaunchKernelGGL(kb_points_f64, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
                        b->d_desc, b->d_tile_grid, b->d_block_tile, b->d_devs, dt_host);
+  }
   if (h->limiter) {
     const int nb = std::min(b->total_tiles, FIX_BLOCKS);
-    if constexpr (sizeof(R) == 4)
+    if (ind)
+      hipLaunchKernelGGL(kb_fixup_ind<R>, dim3(nb), dim3(PT_THREADS), 0, h->stream, b->d_desc,
+                         b->d_tile_grid, b->d_devs, b->fix_list, b->fix_count);
+    else if constexpr (sizeof(R) == 4)
       hipLaunchKernelGGL(kb_fixup_f32, dim3(nb), dim3(PT_THREADS), 0, h->stream, b->d_desc,
                          b->d_tile_grid, b->d_devs, b->fix_list, b->fix_count);
     else

@@ -53,7 +53,7 @@ struct af_handle {
   Batch* batch = nullptr;   // several grids (af_create_batch); nullptr for one grid
   int autotune = 0;         // batched: 1 = tune the schedule at the next af_run, 2 = tuned
   std::vector<Sides> sides;  // per grid
-  int tsw = 0, shock = 0;    // Algorithm 2; the shock-indicator blend (single grids)
+  int tsw = 0, shock = 0;    // Algorithm 2; the shock-indicator blend
   double* UB = nullptr;      // padded primitive averages for the indicators
   long long pU = 0;
   std::string err;
@@ -87,6 +87,7 @@ void fill_sides(const af_handle* h, int g, Params& P);
 int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af_handle* h);
 void batch_destroy(af_handle* h);
 int batch_count(const af_handle* h);
+int batch_alloc_indicators(af_handle* h);
 void batch_invalidate(af_handle* h);
 int64_t batch_dof_count(const af_handle* h);
 int batch_set_state(af_handle* h, int g, const double* avg, const double* K, const double* X,

@@ -409,10 +409,9 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
     case AF_OPT_TRANSONIC:
     case AF_OPT_SHOCK_LIMITER:
       if (value != 0 && value != 1) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: 0 or 1");
-      if (h->batch && value)
-        return fail(h, AF_ERR_INVALID_ARG,
-                    "af_set_option: the shock indicators are for single-grid handles");
-      if (value && !h->UB) {
+      if (value && h->batch) {
+        if (int e = batch_alloc_indicators(h)) return e;
+      } else if (value && !h->UB) {
         h->pU = (h->nx + 4 + 31) / 32 * 32;
         HIP_OK(hipMalloc(&h->UB, (size_t)4 * h->pU * (h->ny + 4) * sizeof(double)), h);
       }

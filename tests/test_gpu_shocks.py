@@ -167,7 +167,29 @@ def test_indicator_options():
     s2.close()
     for k in ("avg", "K", "X", "Y"):
         assert np.array_equal(a[k], b[k])
-    bt = af.BatchSolver.for_states([st, st])
-    with pytest.raises(af.AfError):
-        bt.set_option(af.AF_OPT_TRANSONIC, 1)
-    bt.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_indicators_equal_single_handles(prec):
+    """Batched grids with both indicators on (uneven sizes, outflow, walls and inflow) give
+    the single-grid results bit for bit."""
+    _flush(f"[gpu] batched indicators prec={prec}")
+    states = [_riemann_state(), CASES["transonic_shock"](), I.shock_reflection_state(48, 12),
+              _riemann_state(19, 23)]
+    kw = dict(precision=prec, linearisation=af.AF_LIN_AVG, limiter=True, transonic=True,
+              shock_limiter=True)
+    b = af.BatchSolver.for_states(states, **kw)
+    b.run(1e9, 0.3, 10)
+    cb = b.counters()
+    tot = np.zeros(8, dtype=np.int64)
+    for g, st in enumerate(states):
+        s = af.Solver.for_state(st, **kw)
+        s.run(1e9, 0.3, 10)
+        ref = s.get_state()
+        tot += s.counters()
+        s.close()
+        out = b.get_state(g)
+        for k in ("avg", "K", "X", "Y"):
+            assert np.array_equal(out[k], ref[k]), (g, k)
+    assert cb[af.AF_CNT_TSW] == tot[af.AF_CNT_TSW] > 0
+    b.close()
