@@ -189,8 +189,8 @@ __global__ __launch_bounds__(T) void kb_update(const GridDesc* __restrict__ desc
   double speed = 0.0;
   bool bad = false;
   if (run)
-    for (int i = threadIdx.x; i < P.nx; i += T)
-      if (!update_cell(P, B.A_in, B.A_out, B.FK, B.FX, B.FY, lx, ly, i, j, speed)) bad = true;
+    for (int i = 2 * threadIdx.x; i < P.nx; i += 2 * T)
+      if (!update_pair(P, B.A_in, B.A_out, B.FK, B.FX, B.FY, lx, ly, i, j, speed)) bad = true;
   if (bad) set_err(dev, ERR_NONPHYS);
   for (int off = 32; off > 0; off >>= 1) speed = mx(speed, __shfl_xor(speed, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = speed;

@@ -97,8 +97,9 @@ __global__ __launch_bounds__(PT_THREADS) void k_fixup_ind(Params P, Bufs B, DevS
 
 // ------------------------------------------------------------------------------------------
 // Kernel 2: Simpson space-time fluxes and the conservative update of the averages.  Rows of
-// cells, UP_THREADS consecutive cells of a row per work item (coalesced), about one item per
-// workgroup.  Kernel 3 (one thread) then commits the step.
+// cells, 2 UP_THREADS consecutive cells of a row per work item, two neighbouring cells per
+// thread (16-byte loads), about one item per workgroup.  Kernel 3 (one thread) then commits
+// the step.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* __restrict__ A_in,
                                                       double* __restrict__ A_out,
@@ -113,12 +114,12 @@ __global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* _
   double speed = 0.0;
   bool bad = false;
   if (run) {
-    const int chunks_x = (P.nx + UP_THREADS - 1) / UP_THREADS;
+    const int chunks_x = (P.nx + 2 * UP_THREADS - 1) / (2 * UP_THREADS);
     const long long nwork = (long long)chunks_x * P.ny;
     for (long long w = blockIdx.x; w < nwork; w += gridDim.x) {
       const int j = (int)(w / chunks_x);
-      const int i = (int)(w % chunks_x) * UP_THREADS + threadIdx.x;
-      if (i < P.nx && !update_cell(P, A_in, A_out, FK, FX, FY, lx, ly, i, j, speed)) bad = true;
+      const int i = (int)(w % chunks_x) * 2 * UP_THREADS + 2 * threadIdx.x;
+      if (i < P.nx && !update_pair(P, A_in, A_out, FK, FX, FY, lx, ly, i, j, speed)) bad = true;
     }
   }
   if (bad) set_err(dev, ERR_NONPHYS);
@@ -642,7 +643,7 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
       hipLaunchKernelGGL(k_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev, in);
   }
   if (h->timing) (void)hipEventRecord(e1, h->stream);
-  const long long nwork = (long long)((h->nx + UP_THREADS - 1) / UP_THREADS) * h->ny;
+  const long long nwork = (long long)((h->nx + 2 * UP_THREADS - 1) / (2 * UP_THREADS)) * h->ny;
   const int gu = (int)std::min<long long>(nwork, UP_MAX_BLOCKS);
   hipLaunchKernelGGL(k_update, dim3(gu), dim3(UP_THREADS), 0, h->stream, P, (const double*)h->A[in],
                      h->A[out], (const double*)h->FK, (const double*)h->FX,

@@ -708,36 +708,88 @@ __device__ __forceinline__ void fixup_tile(Smem<R>& S, Ind* I, const Params& P, 
   if (threadIdx.x < 4) B.fix_mask[4 * (long long)tile + threadIdx.x] = 0ull;
 }
 
-// Conservative update of cell (i, j) (eqs. F and 2dfvm): the four Simpson face fluxes from the
-// per-site Simpson-in-time sums, then the FP64 update.  lx = dt / (36 dx), ly = dt / (36 dy).
-// Returns false if the new average is not admissible; else raises `speed` to its wave speed.
-__device__ __forceinline__ bool update_cell(const Params& P, const double* __restrict__ A_in,
+// Conservative update (eqs. F and 2dfvm) of the two cells (i, j) and (i + 1, j), i even (the
+// second only if i + 1 < nx): per cell the four Simpson face fluxes from the per-site
+// Simpson-in-time sums, F = (f_K + 4 f_X + f_K') sums, then the FP64 update with
+// lx = dt / (36 dx), ly = dt / (36 dy).  The east face of the first cell is the west face of
+// the second, and site pairs (i, i + 1) are read with 16-byte loads (rows are aligned to 32
+// doubles or more).  Returns false if a new average is not admissible; else raises `speed` to
+// the new averages' wave speeds.
+__device__ __forceinline__ bool update_pair(const Params& P, const double* __restrict__ A_in,
                                             double* __restrict__ A_out,
                                             const double* __restrict__ FK,
                                             const double* __restrict__ FX,
                                             const double* __restrict__ FY, double lx, double ly,
                                             int i, int j, double& speed) {
-  const int ip = wrap_line(i + 1, P.nx, P.per_x), jp = wrap_line(j + 1, P.ny, P.per_y);
-  const long long kw0 = (long long)j * P.pF + i, kw1 = (long long)jp * P.pF + i;
-  const long long ke0 = (long long)j * P.pF + ip, ke1 = (long long)jp * P.pF + ip;
-  const long long oa = (long long)j * P.pA + i;
-  double Q[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const double* fk = FK + v * P.sF;
-    const double* gk = FK + (4 + v) * P.sF;
-    const double Fw = fk[kw0] + 4.0 * FX[v * P.sF + kw0] + fk[kw1];
-    const double Fe = fk[ke0] + 4.0 * FX[v * P.sF + ke0] + fk[ke1];
-    const double Gs = gk[kw0] + 4.0 * FY[v * P.sF + kw0] + gk[ke0];
-    const double Gn = gk[kw1] + 4.0 * FY[v * P.sF + kw1] + gk[ke1];
-    Q[v] = A_in[v * P.sA + oa] - lx * (Fe - Fw) - ly * (Gn - Gs);
-    A_out[v * P.sA + oa] = Q[v];
+  const bool two = i + 1 < P.nx;
+  const int jp = wrap_line(j + 1, P.ny, P.per_y);
+  const int s1 = wrap_line(i + 1, P.nx, P.per_x);
+  const int s2 = two ? wrap_line(i + 2, P.nx, P.per_x) : s1;
+  const long long r0 = (long long)j * P.pF, r1 = (long long)jp * P.pF;
+  const long long ra = (long long)j * P.pA;
+  double Q0[4], Q1[4];
+  if (two && s1 == i + 1) {
+    // sites i, i + 1 adjacent in memory: 16-byte loads of the pairs
+    auto ld = [](const double* a, long long o) {
+      return *reinterpret_cast<const double2*>(a + o);
+    };
+#pragma unroll 1
+    for (int v = 0; v < 4; ++v) {
+      const double* fk = FK + v * P.sF;
+      const double* gk = FK + (4 + v) * P.sF;
+      const double* fx = FX + v * P.sF;
+      const double* fy = FY + v * P.sF;
+      const double2 f0 = ld(fk, r0 + i), f1 = ld(fk, r1 + i);
+      const double2 g0 = ld(gk, r0 + i), g1 = ld(gk, r1 + i);
+      const double2 x = ld(fx, r0 + i), y0 = ld(fy, r0 + i), y1 = ld(fy, r1 + i);
+      const double2 a = ld(A_in + v * P.sA, ra + i);
+      const double f20 = fk[r0 + s2], f21 = fk[r1 + s2], g20 = gk[r0 + s2], x2 = fx[r0 + s2];
+      const double g21 = gk[r1 + s2];
+      const double Fw = f0.x + 4.0 * x.x + f1.x;
+      const double Fe = f0.y + 4.0 * x.y + f1.y;
+      const double Gs = g0.x + 4.0 * y0.x + g0.y;
+      const double Gn = g1.x + 4.0 * y1.x + g1.y;
+      Q0[v] = a.x - lx * (Fe - Fw) - ly * (Gn - Gs);
+      const double Fe1 = f20 + 4.0 * x2 + f21;
+      const double Gs1 = g0.y + 4.0 * y0.y + g20;
+      const double Gn1 = g1.y + 4.0 * y1.y + g21;
+      Q1[v] = a.y - lx * (Fe1 - Fe) - ly * (Gn1 - Gs1);
+      *reinterpret_cast<double2*>(A_out + v * P.sA + ra + i) = make_double2(Q0[v], Q1[v]);
+    }
+  } else {
+    // the last cell of a row (one cell, or a periodic wrap between the two sites)
+#pragma unroll 1
+    for (int v = 0; v < 4; ++v) {
+      const double* fk = FK + v * P.sF;
+      const double* gk = FK + (4 + v) * P.sF;
+      const double* fx = FX + v * P.sF;
+      const double* fy = FY + v * P.sF;
+      const double Fw = fk[r0 + i] + 4.0 * fx[r0 + i] + fk[r1 + i];
+      const double Fe = fk[r0 + s1] + 4.0 * fx[r0 + s1] + fk[r1 + s1];
+      const double Gs = gk[r0 + i] + 4.0 * fy[r0 + i] + gk[r0 + s1];
+      const double Gn = gk[r1 + i] + 4.0 * fy[r1 + i] + gk[r1 + s1];
+      Q0[v] = A_in[v * P.sA + ra + i] - lx * (Fe - Fw) - ly * (Gn - Gs);
+      A_out[v * P.sA + ra + i] = Q0[v];
+      if (two) {
+        const double Fe1 = fk[r0 + s2] + 4.0 * fx[r0 + s2] + fk[r1 + s2];
+        const double Gs1 = gk[r0 + s1] + 4.0 * fy[r0 + i + 1] + gk[r0 + s2];
+        const double Gn1 = gk[r1 + s1] + 4.0 * fy[r1 + i + 1] + gk[r1 + s2];
+        Q1[v] = A_in[v * P.sA + ra + i + 1] - lx * (Fe1 - Fe) - ly * (Gn1 - Gs1);
+        A_out[v * P.sA + ra + i + 1] = Q1[v];
+      }
+    }
   }
+  bool ok = true;
   double U[4];
-  c2p_plain(Q, P.gamma - 1.0, U);
+  if (two) {
+    c2p_plain(Q1, P.gamma - 1.0, U);
+    if (!admissible(U[0], U[3])) ok = false;
+    else speed = mx(speed, wave_speed(U, P.gamma));
+  }
+  c2p_plain(Q0, P.gamma - 1.0, U);
   if (!admissible(U[0], U[3])) return false;
   speed = mx(speed, wave_speed(U, P.gamma));
-  return true;
+  return ok;
 }
 
 // Largest wave speed over the DOFs e0, e0 + stride, ... of a state (averages, then K, X, Y in
