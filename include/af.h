@@ -234,6 +234,16 @@ int af_get_state_grid(const af_handle* h, int32_t g, double* avg, double* K, dou
 /* Time and steps taken (since af_set_state_grid) of grid g (nullable outputs). */
 int af_get_grid_info(const af_handle* h, int32_t g, double* t, int64_t* steps);
 
+/* af_set_state_grid / af_get_state_grid for arrays in device memory of the handle's GPU (for
+ * instance torch tensors), in the host layout above (FP64, variable-major, unpadded): copied
+ * device to device on the handle's stream, synchronously, with no host staging; the caller
+ * keeps ownership.  The averages are checked on the device (AF_ERR_NONPHYSICAL if one is not
+ * admissible).  g = 0 on single-grid handles.  Output pointers may be NULL. */
+int af_set_state_device(af_handle* h, int32_t g, const double* avg, const double* K,
+                        const double* X, const double* Y, double t);
+int af_get_state_device(const af_handle* h, int32_t g, double* avg, double* K, double* X,
+                        double* Y, double* t);
+
 /* Inflow state W = (rho, u, v, p) (primitive, rho > 0, p > 0; copied) of side `side`
  * (AF_SIDE_*) of grid g (0 on single handles), which must have been created AF_BC_INFLOW
  * (Sec. 4.3).  Every inflow side needs its state before af_step or af_run

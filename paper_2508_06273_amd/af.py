@@ -34,7 +34,7 @@ EXPORTS = ["af_create", "af_set_option", "af_set_stream", "af_set_state", "af_ge
            "af_step", "af_run", "af_get_counters", "af_destroy", "af_last_error",
            "af_dof_count", "af_get_timing", "af_create_batch", "af_batch_size",
            "af_set_state_grid", "af_get_state_grid", "af_get_grid_info", "af_get_option",
-           "af_set_inflow"]
+           "af_set_inflow", "af_set_state_device", "af_get_state_device"]
 
 
 class AfError(RuntimeError):
@@ -92,10 +92,15 @@ def load(path: str = LIB_PATH):
     L.af_get_grid_info.argtypes = [_H, ct.c_int32, _D, ct.POINTER(ct.c_int64)]
     L.af_get_option.argtypes = [_H, ct.c_int, ct.POINTER(ct.c_int64)]
     L.af_set_inflow.argtypes = [_H, ct.c_int32, ct.c_int32, _D]
+    L.af_set_state_device.argtypes = [_H, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                      ct.c_void_p, ct.c_double]
+    L.af_get_state_device.argtypes = [_H, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                      ct.c_void_p, _D]
     for name in ("af_create", "af_set_option", "af_set_stream", "af_set_state",
                  "af_get_state", "af_step", "af_run", "af_get_counters", "af_create_batch",
                  "af_set_state_grid", "af_get_state_grid", "af_get_grid_info",
-                 "af_get_option", "af_set_inflow"):
+                 "af_get_option", "af_set_inflow", "af_set_state_device",
+                 "af_get_state_device"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -216,6 +221,27 @@ class _Handle:
         w = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(4))
         self._check(self.L.af_set_inflow(self.h, int(g), int(side), _ptr(w)))
 
+    def set_state_device(self, g, avg, K, X, Y, t=0.0):
+        """State from device tensors (torch, FP64, contiguous, on the handle's GPU)."""
+        shapes = self._shapes_of(g)
+        arrs = (avg, K, X, Y)
+        for a, (name, shp) in zip(arrs, shapes.items()):
+            if tuple(a.shape) != shp or not a.is_contiguous() or str(a.dtype) != "torch.float64":
+                raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shp}")
+        self._check(self.L.af_set_state_device(self.h, g, *[a.data_ptr() for a in arrs],
+                                               float(t)))
+
+    def get_state_device(self, g, avg, K, X, Y):
+        """Copy the current state into device tensors (as for set_state_device); returns t."""
+        shapes = self._shapes_of(g)
+        for a, (name, shp) in zip((avg, K, X, Y), shapes.items()):
+            if tuple(a.shape) != shp or not a.is_contiguous() or str(a.dtype) != "torch.float64":
+                raise ValueError(f"{name}: need a contiguous float64 tensor of shape {shp}")
+        t = ct.c_double(0.0)
+        self._check(self.L.af_get_state_device(self.h, g, avg.data_ptr(), K.data_ptr(),
+                                               X.data_ptr(), Y.data_ptr(), ct.byref(t)))
+        return t.value
+
     def grid_info(self, g=0):
         """(t, steps taken) of grid g."""
         t = ct.c_double(0.0)
@@ -262,6 +288,9 @@ class Solver(_Handle):
 
     def shapes(self):
         return _shapes(self.nx, self.ny, self.nkx, self.nky)
+
+    def _shapes_of(self, g):
+        return self.shapes()
 
     def set_state(self, avg, K, X, Y, t=0.0):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (avg, K, X, Y)]
@@ -326,6 +355,9 @@ class BatchSolver(_Handle):
 
     def shapes(self, g):
         return _shapes(*self.dims[g])
+
+    def _shapes_of(self, g):
+        return self.shapes(g)
 
     def set_state(self, g, avg, K, X, Y, t=0.0):
         self._set(g, self.shapes(g), avg, K, X, Y, t)

@@ -544,27 +544,35 @@ static int write_devs(af_handle* h, const std::vector<DevState>& ds) {
 }
 
 int batch_set_state(af_handle* h, int g, const double* avg, const double* K, const double* X,
-                    const double* Y, double t) {
+                    const double* Y, double t, bool user_dev) {
   Batch* b = h->batch;
   if (g < 0 || g >= b->n) return fail(h, AF_ERR_INVALID_ARG, "af_set_state_grid: bad grid index");
   if (!avg || !K || !X || !Y) return fail(h, AF_ERR_INVALID_ARG, "af_set_state_grid: NULL array");
   if (!std::isfinite(t)) return fail(h, AF_ERR_INVALID_ARG, "af_set_state_grid: t not finite");
   BatchGrid& q = b->g[g];
-  const size_t nc = (size_t)q.nx * q.ny;
-  for (size_t k = 0; k < nc; ++k) {
-    const double r = avg[k], E = avg[3 * nc + k];
-    const double kin = 0.5 * (avg[nc + k] * avg[nc + k] + avg[2 * nc + k] * avg[2 * nc + k]) / r;
-    if (!(r > 0.0) || !((h->gamma - 1.0) * (E - kin) > 0.0))
-      return fail(h, AF_ERR_NONPHYSICAL, "af_set_state_grid: non-admissible cell average");
+  if (user_dev) {
+    if (int e = check_avg_device(h, avg, q.nx, q.ny, "af_set_state_device")) return e;
+  } else {
+    const size_t nc = (size_t)q.nx * q.ny;
+    for (size_t k = 0; k < nc; ++k) {
+      const double r = avg[k], E = avg[3 * nc + k];
+      const double kin = 0.5 * (avg[nc + k] * avg[nc + k] + avg[2 * nc + k] * avg[2 * nc + k]) / r;
+      if (!(r > 0.0) || !((h->gamma - 1.0) * (E - kin) > 0.0))
+        return fail(h, AF_ERR_NONPHYSICAL, "af_set_state_grid: non-admissible cell average");
+    }
   }
   int e;
-  if ((e = copy4(h, true, b->A[0] + q.oA, q.pA, q.ny, q.ny, q.nx, const_cast<double*>(avg))))
+  if ((e = copy4(h, true, b->A[0] + q.oA, q.pA, q.ny, q.ny, q.nx, const_cast<double*>(avg),
+                 user_dev)))
     return e;
-  if ((e = copy4(h, true, b->K[0] + q.oP, q.pP, q.nky, q.nky, q.nkx, const_cast<double*>(K))))
+  if ((e = copy4(h, true, b->K[0] + q.oP, q.pP, q.nky, q.nky, q.nkx, const_cast<double*>(K),
+                 user_dev)))
     return e;
-  if ((e = copy4(h, true, b->X[0] + q.oP, q.pP, q.nky, q.ny, q.nkx, const_cast<double*>(X))))
+  if ((e = copy4(h, true, b->X[0] + q.oP, q.pP, q.nky, q.ny, q.nkx, const_cast<double*>(X),
+                 user_dev)))
     return e;
-  if ((e = copy4(h, true, b->Y[0] + q.oP, q.pP, q.nky, q.nky, q.nx, const_cast<double*>(Y))))
+  if ((e = copy4(h, true, b->Y[0] + q.oP, q.pP, q.nky, q.nky, q.nx, const_cast<double*>(Y),
+                 user_dev)))
     return e;
   DevState ds;
   std::memset(&ds, 0, sizeof(ds));
@@ -579,7 +587,7 @@ int batch_set_state(af_handle* h, int g, const double* avg, const double* K, con
 }
 
 int batch_get_state(const af_handle* h, int g, double* avg, double* K, double* X, double* Y,
-                    double* t) {
+                    double* t, bool user_dev) {
   const Batch* b = h->batch;
   if (g < 0 || g >= b->n) return fail(h, AF_ERR_INVALID_ARG, "af_get_state_grid: bad grid index");
   const BatchGrid& q = b->g[g];
@@ -589,10 +597,14 @@ int batch_get_state(const af_handle* h, int g, double* avg, double* K, double* X
   HIP_OK(hipStreamSynchronize(h->stream), h);
   const int c = ds.cur;
   int e;
-  if (avg && (e = copy4(h, false, b->A[c] + q.oA, q.pA, q.ny, q.ny, q.nx, avg))) return e;
-  if (K && (e = copy4(h, false, b->K[c] + q.oP, q.pP, q.nky, q.nky, q.nkx, K))) return e;
-  if (X && (e = copy4(h, false, b->X[c] + q.oP, q.pP, q.nky, q.ny, q.nkx, X))) return e;
-  if (Y && (e = copy4(h, false, b->Y[c] + q.oP, q.pP, q.nky, q.nky, q.nx, Y))) return e;
+  if (avg && (e = copy4(h, false, b->A[c] + q.oA, q.pA, q.ny, q.ny, q.nx, avg, user_dev)))
+    return e;
+  if (K && (e = copy4(h, false, b->K[c] + q.oP, q.pP, q.nky, q.nky, q.nkx, K, user_dev)))
+    return e;
+  if (X && (e = copy4(h, false, b->X[c] + q.oP, q.pP, q.nky, q.ny, q.nkx, X, user_dev)))
+    return e;
+  if (Y && (e = copy4(h, false, b->Y[c] + q.oP, q.pP, q.nky, q.nky, q.nx, Y, user_dev)))
+    return e;
   if (t) *t = ds.t;
   return AF_OK;
 }

@@ -53,6 +53,7 @@ struct af_handle {
   Batch* batch = nullptr;   // several grids (af_create_batch); nullptr for one grid
   int autotune = 0;         // batched: 1 = tune the schedule at the next af_run, 2 = tuned
   std::vector<Sides> sides;  // per grid
+  int* d_flag = nullptr;     // device flag of check_avg_device
   int tsw = 0, shock = 0;    // Algorithm 2; the shock-indicator blend
   double* UB = nullptr;      // padded primitive averages for the indicators
   long long pU = 0;
@@ -75,10 +76,13 @@ int fail(const af_handle* h, int code, const std::string& msg);
 // Host <-> device copies through the handle's pinned staging buffer (synchronous on the
 // handle's stream): one variable of rows x cols (host unpadded, device with a row pitch), or
 // the four variables of a padded array (variable v at offset v * rows_alloc * pitch).
+// `user_dev`: the caller's array is in device memory (copied device to device, no staging).
 int copy2d(const af_handle* h, bool to_device, double* dev, long long pitch, int rows, int cols,
-           double* host);
+           double* host, bool user_dev = false);
 int copy4(const af_handle* h, bool to_device, void* dev, long long pitch, int rows_alloc,
-          int rows, int cols, double* host);
+          int rows, int cols, double* host, bool user_dev = false);
+// Are all nx * ny conserved averages of the caller's device array (4 x ny x nx) admissible?
+int check_avg_device(const af_handle* h, const double* avg, int nx, int ny, const char* fn);
 
 // Boundary kinds and inflow states of grid g into P.
 void fill_sides(const af_handle* h, int g, Params& P);
@@ -91,9 +95,9 @@ int batch_alloc_indicators(af_handle* h);
 void batch_invalidate(af_handle* h);
 int64_t batch_dof_count(const af_handle* h);
 int batch_set_state(af_handle* h, int g, const double* avg, const double* K, const double* X,
-                    const double* Y, double t);
+                    const double* Y, double t, bool user_dev = false);
 int batch_get_state(const af_handle* h, int g, double* avg, double* K, double* X, double* Y,
-                    double* t);
+                    double* t, bool user_dev = false);
 int batch_grid_info(const af_handle* h, int g, double* t, int64_t* steps);
 int batch_get_counters(const af_handle* h, int64_t* out);
 int batch_step(af_handle* h, double dt);

@@ -144,6 +144,16 @@ __global__ void k_commit(DevState* dev, int slot) {
   }
 }
 
+// Admissibility of n conserved averages (variable-major, unpadded): sets *bad if any is not.
+__global__ void k_check_avg(const double* __restrict__ avg, long long n, double gamma, int* bad) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    double Q[4] = {avg[k], avg[n + k], avg[2 * n + k], avg[3 * n + k]}, U[4];
+    c2p_plain(Q, gamma - 1.0, U);
+    if (!admissible(U[0], U[3])) atomicOr(bad, 1);
+  }
+}
+
 // Largest wave speed of the current state (averages and point values) into smax[slot].
 __global__ void k_cfl(Params P, const double* __restrict__ A, const double* __restrict__ K,
                       const double* __restrict__ X, const double* __restrict__ Y, DevState* dev,
@@ -278,6 +288,7 @@ static void destroy_handle(af_handle* h) {
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->dev) (void)hipFree(h->dev);
   if (h->UB) (void)hipFree(h->UB);
+  if (h->d_flag) (void)hipFree(h->d_flag);
   if (h->stage) (void)hipHostFree(h->stage);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   delete h;
@@ -485,8 +496,19 @@ static int ensure_stage(const af_handle* hc) {
 // One variable: host FP64 rows x cols (unpadded, row-major) <-> device FP64 rows x cols with
 // a row pitch of `pitch` elements.
 int copy2d(const af_handle* h, bool to_device, double* dev, long long pitch, int rows,
-                  int cols, double* host) {
+                  int cols, double* host, bool user_dev) {
   if (cols > pitch) return fail(h, AF_ERR_INVALID_ARG, "copy2d: cols exceed pitch");
+  if (user_dev) {
+    const size_t row_bytes = (size_t)cols * 8;
+    if (to_device)
+      HIP_OK(hipMemcpy2DAsync(dev, pitch * 8, host, row_bytes, row_bytes, (size_t)rows,
+                              hipMemcpyDeviceToDevice, h->stream), h);
+    else
+      HIP_OK(hipMemcpy2DAsync(host, row_bytes, dev, pitch * 8, row_bytes, (size_t)rows,
+                              hipMemcpyDeviceToDevice, h->stream), h);
+    HIP_OK(hipStreamSynchronize(h->stream), h);
+    return AF_OK;
+  }
   if (int e = ensure_stage(h)) return e;
   const size_t row_bytes = (size_t)cols * 8;
   const int block = (int)std::max<size_t>(1, STAGE_BYTES / row_bytes);
@@ -512,42 +534,66 @@ int copy2d(const af_handle* h, bool to_device, double* dev, long long pitch, int
 // The padded arrays store variable v at offset v * rows_alloc * pitch: copy one variable at a
 // time.
 int copy4(const af_handle* h, bool to_device, void* dev, long long pitch, int rows_alloc,
-                 int rows, int cols, double* host) {
+                 int rows, int cols, double* host, bool user_dev) {
   if (rows > rows_alloc) return fail(h, AF_ERR_INVALID_ARG, "copy4: rows exceed allocation");
   for (int v = 0; v < 4; ++v) {
     double* d = (double*)dev + (size_t)v * rows_alloc * pitch;
-    if (int e = copy2d(h, to_device, d, pitch, rows, cols, host + (size_t)v * rows * cols))
+    if (int e = copy2d(h, to_device, d, pitch, rows, cols, host + (size_t)v * rows * cols,
+                       user_dev))
       return e;
   }
   return AF_OK;
 }
 
-extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, const double* X,
-                            const double* Y, double t) {
-  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_state: NULL handle");
-  if (h->batch) {
-    if (batch_count(h) != 1)
-      return fail(h, AF_ERR_INVALID_ARG, "af_set_state: batched handle, use af_set_state_grid");
-    return batch_set_state(h, 0, avg, K, X, Y, t);
-  }
-  if (!avg || !K || !X || !Y) return fail(h, AF_ERR_INVALID_ARG, "af_set_state: NULL array");
-  if (!std::isfinite(t)) return fail(h, AF_ERR_INVALID_ARG, "af_set_state: t not finite");
-  const size_t nc = (size_t)h->nx * h->ny;
-  for (size_t k = 0; k < nc; ++k) {
-    const double r = avg[k], E = avg[3 * nc + k];
-    const double kin = 0.5 * (avg[nc + k] * avg[nc + k] + avg[2 * nc + k] * avg[2 * nc + k]) / r;
-    if (!(r > 0.0) || !((h->gamma - 1.0) * (E - kin) > 0.0))
-      return fail(h, AF_ERR_NONPHYSICAL, "af_set_state: non-admissible cell average");
+int check_avg_device(const af_handle* h, const double* avg, int nx, int ny, const char* fn) {
+  af_handle* hm = const_cast<af_handle*>(h);
+  if (!hm->d_flag) HIP_OK(hipMalloc(&hm->d_flag, sizeof(int)), h);
+  HIP_OK(hipMemsetAsync(hm->d_flag, 0, sizeof(int), h->stream), h);
+  const long long n = (long long)nx * ny;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_check_avg, dim3(blocks), dim3(256), 0, h->stream, avg, n, h->gamma,
+                     hm->d_flag);
+  HIP_OK(hipGetLastError(), h);
+  int bad = 0;
+  HIP_OK(hipMemcpyAsync(&bad, hm->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  if (bad) return fail(h, AF_ERR_NONPHYSICAL, std::string(fn) + ": non-admissible cell average");
+  return AF_OK;
+}
+
+static int set_state_impl(af_handle* h, int g, const double* avg, const double* K,
+                          const double* X, const double* Y, double t, bool user_dev,
+                          const char* fn) {
+  const std::string f(fn);
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, f + ": NULL handle");
+  if (h->batch) return batch_set_state(h, g, avg, K, X, Y, t, user_dev);
+  if (g != 0) return fail(h, AF_ERR_INVALID_ARG, f + ": grid index must be 0");
+  if (!avg || !K || !X || !Y) return fail(h, AF_ERR_INVALID_ARG, f + ": NULL array");
+  if (!std::isfinite(t)) return fail(h, AF_ERR_INVALID_ARG, f + ": t not finite");
+  if (user_dev) {
+    if (int e = check_avg_device(h, avg, h->nx, h->ny, fn)) return e;
+  } else {
+    const size_t nc = (size_t)h->nx * h->ny;
+    for (size_t k = 0; k < nc; ++k) {
+      const double r = avg[k], E = avg[3 * nc + k];
+      const double kin = 0.5 * (avg[nc + k] * avg[nc + k] + avg[2 * nc + k] * avg[2 * nc + k]) / r;
+      if (!(r > 0.0) || !((h->gamma - 1.0) * (E - kin) > 0.0))
+        return fail(h, AF_ERR_NONPHYSICAL, f + ": non-admissible cell average");
+    }
   }
   h->cur = 0;
   int e;
-  if ((e = copy4(h, true, h->A[0], h->pA, h->ny, h->ny, h->nx, const_cast<double*>(avg))))
+  if ((e = copy4(h, true, h->A[0], h->pA, h->ny, h->ny, h->nx, const_cast<double*>(avg),
+                 user_dev)))
     return e;
-  if ((e = copy4(h, true, h->K[0], h->pP, h->nky, h->nky, h->nkx, const_cast<double*>(K))))
+  if ((e = copy4(h, true, h->K[0], h->pP, h->nky, h->nky, h->nkx, const_cast<double*>(K),
+                 user_dev)))
     return e;
-  if ((e = copy4(h, true, h->X[0], h->pP, h->nky, h->ny, h->nkx, const_cast<double*>(X))))
+  if ((e = copy4(h, true, h->X[0], h->pP, h->nky, h->ny, h->nkx, const_cast<double*>(X),
+                 user_dev)))
     return e;
-  if ((e = copy4(h, true, h->Y[0], h->pP, h->nky, h->nky, h->nx, const_cast<double*>(Y))))
+  if ((e = copy4(h, true, h->Y[0], h->pP, h->nky, h->nky, h->nx, const_cast<double*>(Y),
+                 user_dev)))
     return e;
   DevState ds;
   std::memset(&ds, 0, sizeof(ds));
@@ -561,21 +607,19 @@ extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, co
   return AF_OK;
 }
 
-extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* X, double* Y,
-                            double* t) {
-  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_get_state: NULL handle");
-  if (h->batch) {
-    if (batch_count(h) != 1)
-      return fail(h, AF_ERR_INVALID_ARG, "af_get_state: batched handle, use af_get_state_grid");
-    return batch_get_state(h, 0, avg, K, X, Y, t);
-  }
-  if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_get_state: no state set");
+static int get_state_impl(const af_handle* h, int g, double* avg, double* K, double* X,
+                          double* Y, double* t, bool user_dev, const char* fn) {
+  const std::string f(fn);
+  if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, f + ": NULL handle");
+  if (h->batch) return batch_get_state(h, g, avg, K, X, Y, t, user_dev);
+  if (g != 0) return fail(h, AF_ERR_INVALID_ARG, f + ": grid index must be 0");
+  if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, f + ": no state set");
   const int c = h->cur;
   int e;
-  if (avg && (e = copy4(h, false, h->A[c], h->pA, h->ny, h->ny, h->nx, avg))) return e;
-  if (K && (e = copy4(h, false, h->K[c], h->pP, h->nky, h->nky, h->nkx, K))) return e;
-  if (X && (e = copy4(h, false, h->X[c], h->pP, h->nky, h->ny, h->nkx, X))) return e;
-  if (Y && (e = copy4(h, false, h->Y[c], h->pP, h->nky, h->nky, h->nx, Y))) return e;
+  if (avg && (e = copy4(h, false, h->A[c], h->pA, h->ny, h->ny, h->nx, avg, user_dev))) return e;
+  if (K && (e = copy4(h, false, h->K[c], h->pP, h->nky, h->nky, h->nkx, K, user_dev))) return e;
+  if (X && (e = copy4(h, false, h->X[c], h->pP, h->nky, h->ny, h->nkx, X, user_dev))) return e;
+  if (Y && (e = copy4(h, false, h->Y[c], h->pP, h->nky, h->nky, h->nx, Y, user_dev))) return e;
   if (t) {
     DevState ds;
     HIP_OK(hipMemcpyAsync(&ds, h->dev, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
@@ -583,6 +627,30 @@ extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* 
     *t = ds.t;
   }
   return AF_OK;
+}
+
+extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, const double* X,
+                            const double* Y, double t) {
+  if (h && h->batch && batch_count(h) != 1)
+    return fail(h, AF_ERR_INVALID_ARG, "af_set_state: batched handle, use af_set_state_grid");
+  return set_state_impl(h, 0, avg, K, X, Y, t, false, "af_set_state");
+}
+
+extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* X, double* Y,
+                            double* t) {
+  if (h && h->batch && batch_count(h) != 1)
+    return fail(h, AF_ERR_INVALID_ARG, "af_get_state: batched handle, use af_get_state_grid");
+  return get_state_impl(h, 0, avg, K, X, Y, t, false, "af_get_state");
+}
+
+extern "C" int af_set_state_device(af_handle* h, int32_t g, const double* avg, const double* K,
+                                   const double* X, const double* Y, double t) {
+  return set_state_impl(h, g, avg, K, X, Y, t, true, "af_set_state_device");
+}
+
+extern "C" int af_get_state_device(const af_handle* h, int32_t g, double* avg, double* K,
+                                   double* X, double* Y, double* t) {
+  return get_state_impl(h, g, avg, K, X, Y, t, true, "af_get_state_device");
 }
 
 extern "C" int af_get_counters(const af_handle* h, int64_t* out) {
