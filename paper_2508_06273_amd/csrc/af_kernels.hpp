@@ -477,38 +477,47 @@ __device__ __noinline__ int eg1_pc(const double* __restrict__ ub, int cb, const 
   const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
   const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
   const R al = MA::acos_(cMx), be = MA::asin_(cMy);
-  const R twopi = R(2 * kPi), pi = R(kPi);
   R Ip = 0, IpC = 0, IpS = 0, Jr = 0, Ku = 0, Kv = 0;
-  const int nq = (KIND == KIND_K) ? 4 : 2;
-  for (int q = 0; q < nq; ++q) {
-    int sx, sy;
-    if (KIND == KIND_K) { sx = q & 1; sy = q >> 1; }
-    else if (KIND == KIND_X) { sx = q; sy = 0; }
-    else { sx = 0; sy = q; }
-    R m[6] = {0, 0, 0, 0, 0, 0};
-    // x-interval of side sx (whole circle for Y), y-interval of side sy (whole for X)
-    R a1, b1, c1a, s1a, c1b, s1b, a2, b2, c2a, s2a, c2b, s2b;
-    if (KIND == KIND_Y) { a1 = -pi; b1 = pi; c1a = -1; s1a = 0; c1b = -1; s1b = 0; }
-    else if (sx) { a1 = -al; b1 = al; c1a = cMx; s1a = -sxx; c1b = cMx; s1b = sxx; }
-    else { a1 = al; b1 = twopi - al; c1a = cMx; s1a = sxx; c1b = cMx; s1b = -sxx; }
-    if (KIND == KIND_X) { a2 = -pi; b2 = pi; c2a = -1; s2a = 0; c2b = -1; s2b = 0; }
-    else if (sy) { a2 = be; b2 = pi - be; c2a = syy; s2a = cMy; c2b = -syy; s2b = cMy; }
-    else { a2 = pi - be; b2 = twopi + be; c2a = -syy; s2a = cMy; c2b = syy; s2b = cMy; }
+  // The data are constant on the quadrants (K) or halves (X, Y) around the DOF.  As for EG2,
+  // split them into the low-side value on the full circle plus differences on the right half,
+  // the upper half and their intersection: the full circle's moments are closed form, and only
+  // the half circles (one arc each) and the quadrant need arc moments.
+  auto piece = [&](double dp, double du, double dv, const R m[6]) {
+    const R p = R(dp), u = R(du), v = R(dv);
+    Ip += p * m[0];
+    IpC += p * m[1];
+    IpS += p * m[2];
+    Jr += u * m[1] + v * m[2];
+    Ku += u * (R(3) * m[3] - m[0]) + R(3) * v * m[4];
+    Kv += R(3) * u * m[4] + v * (R(3) * m[5] - m[0]);
+  };
+  auto dev = [&](int cell, int var) { return ub[var * NC + cell] - lin64[var]; };
+  const R twopi = R(2 * kPi), pi = R(kPi);
+  const R mfull[6] = {twopi, R(0), R(0), pi, R(0), pi};
+  R mr[6], mu[6];
+  if (KIND != KIND_Y) low_moments(cMx, -sxx, cMx, sxx, R(2) * al, mr);   // right: (-al, al)
+  if (KIND != KIND_X) low_moments(syy, cMy, -syy, cMy, pi - R(2) * be, mu);  // up: (be, pi-be)
+  const int c00 = cb;                                 // low-side cell (left / lower)
+  const int c10 = cb + 1, c01 = cb + HC, c11 = cb + HC + 1;
+  piece(dev(c00, 3), dev(c00, 1), dev(c00, 2), mfull);
+  if constexpr (KIND == KIND_X) {
+    piece(dev(c10, 3) - dev(c00, 3), dev(c10, 1) - dev(c00, 1), dev(c10, 2) - dev(c00, 2), mr);
+  } else if constexpr (KIND == KIND_Y) {
+    piece(dev(c01, 3) - dev(c00, 3), dev(c01, 1) - dev(c00, 1), dev(c01, 2) - dev(c00, 2), mu);
+  } else {
+    piece(dev(c10, 3) - dev(c00, 3), dev(c10, 1) - dev(c00, 1), dev(c10, 2) - dev(c00, 2), mr);
+    piece(dev(c01, 3) - dev(c00, 3), dev(c01, 1) - dev(c00, 1), dev(c01, 2) - dev(c00, 2), mu);
+    // the upper right quadrant: (-al, al) and (be, pi - be), up to one turn apart
+    R mq[6] = {0, 0, 0, 0, 0, 0};
     for (int k = -1; k <= 1; ++k) {
       R n[6];
-      low_piece(a1, c1a, s1a, b1, c1b, s1b, a2 + R(k) * twopi, c2a, s2a, b2 + R(k) * twopi,
-                c2b, s2b, n);
-      for (int t = 0; t < 6; ++t) m[t] += n[t];
+      low_piece(-al, cMx, -sxx, al, cMx, sxx, be + R(k) * twopi, syy, cMy,
+                pi - be + R(k) * twopi, -syy, cMy, n);
+      for (int t = 0; t < 6; ++t) mq[t] += n[t];
     }
-    const int cell = cb + (KIND == KIND_Y ? 0 : sx) + (KIND == KIND_X ? 0 : sy * HC);
-    const R dpq = R(ub[3 * NC + cell] - lin64[3]), duq = R(ub[1 * NC + cell] - lin64[1]),
-            dvq = R(ub[2 * NC + cell] - lin64[2]);
-    Ip += dpq * m[0];
-    IpC += dpq * m[1];
-    IpS += dpq * m[2];
-    Jr += duq * m[1] + dvq * m[2];
-    Ku += duq * (R(3) * m[3] - m[0]) + R(3) * dvq * m[4];
-    Kv += R(3) * duq * m[4] + dvq * (R(3) * m[5] - m[0]);
+    auto d4 = [&](int var) { return ((ub[var * NC + c11] - ub[var * NC + c01]) -
+                                     (ub[var * NC + c10] - ub[var * NC + c00])); };
+    piece(d4(3), d4(1), d4(2), mq);
   }
   // foot point values (mean over the cells whose closure contains P')
   double P[4] = {0, 0, 0, 0};
