@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -70,11 +71,14 @@ def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2508_06273_amd", "csrc")
     for f in ("af_device.hpp", "af_kernels.hpp", "af_step.hpp", "af_lib.hip"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            data = fh.read()
+        with open(os.path.join(csrc, f), "r") as fh:
+            text = fh.read()
         if f == "af_lib.hip":
-            data = data.split(b"// Host runtime")[0]
-        h.update(data)
+            text = text.split("// Host runtime")[0]
+        # comments and layout do not change the code
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -11,7 +11,9 @@
 //   k_update : per cell, Simpson space-time face fluxes from the site sums and the
 //              conservative FP64 update of the cell average (paper eqs. F and 2dfvm);
 //   k_commit : one thread advances t and the step counter if the step ran without error.
-// Both accumulate the largest wave speed of the new state for the next step's time step.
+// The point and update kernels accumulate the largest wave speed of the new state for the next
+// step's time step.  With the shock indicators (Algorithm 2, Sec. 3.4) an averaging pass
+// (k_avgprim) runs first and the point kernel's indicator variant replaces the default one.
 #pragma once
 #include "af_device.hpp"
 
