@@ -237,3 +237,18 @@ def test_shock_reflection_reaches_exact_states(nx, ny, mode):
         assert err[0] < 0.01 * ex[0] and err[3] < 0.01 * ex[3], (lab, r, ex)
         assert err[1] < 0.01 * abs(ex[1]) and err[2] < 0.01 * max(abs(ex[1]), 1.0), \
             (lab, r, ex)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-4)])
+def test_shock_reflection_benchmark_grid_matches_oracle(prec, tol):
+    """The 240 x 60 shock-reflection grid the benchmark's extra workloads time (averaged
+    linearisation, no limiter): 6 steps against the oracle, every DOF."""
+    _flush(f"[gpu] shock reflection 240x60 vs oracle prec={prec}")
+    st = I.shock_reflection_state(240, 60)
+    s = af.Solver.for_state(st, precision=prec, linearisation=af.AF_LIN_AVG)
+    t, n = s.run(1e9, 0.3, 6)
+    out = s.get_state()
+    s.close()
+    e, n2, _ = oracle.run(st, 1e9, 0.3, max_steps=6, mode=oracle.MODE_AVG)
+    assert e == 0 and n == n2 == 6
+    _assert_close(out, st, tol, f"240x60 prec {prec}")
