@@ -29,6 +29,11 @@ constexpr int HS = TILE + 2;   // halo sites per edge (local -1 .. TILE)
 constexpr int HC = TILE + 1;   // halo cells per edge (local -1 .. TILE-1)
 constexpr int NS = HS * HS;    // 100
 constexpr int NC = HC * HC;    // 81
+// LDS words (of the bulk type) per halo cell of the monomial coefficients: 4 variables x 8,
+// plus one so that lanes reading neighbouring cells fall into different banks.  All the
+// coefficients of a cell and of its right neighbour then lie within reach of the
+// immediate offsets of one paired LDS read: one address per cell pair, not per coefficient.
+constexpr int CS = 4 * 8 + 1;
 constexpr int PT_THREADS = 128;  // two wavefronts: corners; edges
 
 // Device-resident step control.
@@ -123,25 +128,35 @@ __device__ __forceinline__ int map_axis(int i, int n, int per, int lo, int hi, i
   return i < 0 ? 0 : (i > last ? last : i);
 }
 
+// Kind and inflow state of side s (0 left, 1 right, 2 bottom, 3 top), by selects: indexing the
+// kernel parameters with a runtime value makes the compiler copy them to scratch memory.
+__device__ __forceinline__ int side_kind(const Params& P, int s) {
+  return s == 0 ? P.bc[0] : (s == 1 ? P.bc[1] : (s == 2 ? P.bc[2] : P.bc[3]));
+}
+__device__ __forceinline__ double side_inflow(const Params& P, int s, int v) {
+  return s == 0 ? P.inflow[0][v]
+                : (s == 1 ? P.inflow[1][v] : (s == 2 ? P.inflow[2][v] : P.inflow[3][v]));
+}
+
 // Ghost rules on a value fetched through map_axis (sx, sy: the sides that apply, -1: none):
 // solid walls first (the normal velocity, or momentum, negated), then inflow (the side's state
 // replaces a primitive value; the y side's if both apply).
 __device__ __forceinline__ void apply_sides(const Params& P, int sx, int sy, double o[4]) {
-  if (sx >= 0 && P.bc[sx] == BC_WALL) o[1] = -o[1];
-  if (sy >= 0 && P.bc[2 + sy] == BC_WALL) o[2] = -o[2];
-  if (sx >= 0 && P.bc[sx] == BC_INFLOW) {
+  if (sx >= 0 && side_kind(P, sx) == BC_WALL) o[1] = -o[1];
+  if (sy >= 0 && side_kind(P, 2 + sy) == BC_WALL) o[2] = -o[2];
+  if (sx >= 0 && side_kind(P, sx) == BC_INFLOW) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) o[v] = P.inflow[sx][v];
+    for (int v = 0; v < 4; ++v) o[v] = side_inflow(P, sx, v);
   }
-  if (sy >= 0 && P.bc[2 + sy] == BC_INFLOW) {
+  if (sy >= 0 && side_kind(P, 2 + sy) == BC_INFLOW) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) o[v] = P.inflow[2 + sy][v];
+    for (int v = 0; v < 4; ++v) o[v] = side_inflow(P, 2 + sy, v);
   }
 }
 
 // Is side `side` of axis `axis` an inflow side?
 __device__ __forceinline__ bool inflow_side(const Params& P, int axis, int side) {
-  return side >= 0 && P.bc[2 * axis + side] == BC_INFLOW;
+  return side >= 0 && side_kind(P, 2 * axis + side) == BC_INFLOW;
 }
 
 // Does a DOF of kind KIND at (i, j) lie on a solid-wall line?
@@ -194,7 +209,7 @@ __device__ __forceinline__ void block_max_atomic(double v, unsigned long long* t
 // ------------------------------------------------------------------------------------------
 template <class R> struct Smem {
   double c0[4 * NC];  // centre values U_c (constant monomial coefficient) [var][cell]
-  R ch[4 * 8 * NC];   // other monomial coefficients c_01 .. c_22 [var][coef-1][cell]
+  R ch[NC * CS];      // other monomial coefficients c_01 .. c_22 [cell][var][coef-1]
   double ub[4 * NC];  // primitive Simpson averages [var][cell]
   double sk[4 * NS];  // t_n point values [var][site], local site (a,b) -> (a+1) + (b+1)*HS
   double sx[4 * NS];
@@ -223,6 +238,15 @@ __device__ __forceinline__ int cidx(int a, int b) { return (a + 1) + (b + 1) * H
 
 // idx = 1/dx; hy = dy / (2 dx): half a cell in y in units of dx (the local frame of the circle
 // integrals uses dx in both directions).
+// An LDS pointer whose value the compiler cannot see through.  Reads at constant offsets from
+// it fold the offsets into the LDS instructions; from a visible base computation the compiler
+// instead rebuilds the full address for every read.
+template <class T> __device__ __forceinline__ const T* lds_base(const T* p) {
+  auto q = (__attribute__((address_space(3))) const T*)p;
+  asm("" : "+v"(q));
+  return (const T*)q;
+}
+
 template <class R> struct Geo {
   R idx, hy, gamma, half_h;
 };
@@ -247,7 +271,10 @@ template <class R, int KIND>
 __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[4], R tau,
                                    const Geo<R>& G, R dU[4]) {
   using MA = Math<R>;
-  const R* __restrict__ ch = S.ch;
+  // the coefficients of the lower-left cell and of the cell above it; their right neighbours
+  // are constant offsets from them
+  const R* __restrict__ chc = lds_base(S.ch + cb * CS);
+  const R* __restrict__ chu = lds_base(S.ch + (cb + HC) * CS);
   const double* __restrict__ c0 = S.c0;
   const R rp = R(lin64[0]), up = R(lin64[1]), vp = R(lin64[2]), pp = R(lin64[3]);
   if (!admissible(rp, pp)) return ERR_NONPHYS;
@@ -260,7 +287,6 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const R hy = G.hy;
   const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
   const R pi = R(kPi);
-  constexpr int VS = 8 * NC;  // variable stride in ch
   // deviation of a cell's centre value from the linearisation state, formed in FP64
   auto dev0 = [&](int var, int cell) { return R(c0[var * NC + cell] - lin64[var]); };
   Acc<R> A = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
@@ -308,14 +334,14 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
         R t[9], r[9], w[9];
         Mom<R> Mx;
         moments_sym_x(m1, s1, a1, r2, Mx);
-        circle_shift(dev0(var, cLL), ch + var * VS + cLL, NC, xl, yb, t);
-        circle_shift(dev0(var, cLR), ch + var * VS + cLR, NC, xr, yb, r);
+        circle_shift(dev0(var, cLL), chc + var * 8, 1, xl, yb, t);
+        circle_shift(dev0(var, cLR), chc + CS + var * 8, 1, xr, yb, r);
 #pragma unroll
         for (int i = 0; i < 9; ++i) w[i] = r[i] - t[i];  // P_LR - P_LL
         if (var == 3) { contract_p<3>(t, Mf, A); contract_p<1>(w, Mx, A); }
         if (var == 1) { contract_u<3>(t, Mf, A); contract_u<1>(w, Mx, A); }
         if (var == 2) { contract_v<3>(t, Mf, A); contract_v<1>(w, Mx, A); }
-        circle_shift(dev0(var, cUL), ch + var * VS + cUL, NC, xl, yt, w);
+        circle_shift(dev0(var, cUL), chu + var * 8, 1, xl, yt, w);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
           const R d = w[i] - t[i];  // P_UL - P_LL
@@ -327,7 +353,7 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
         if (var == 3) contract_p<2>(w, My, A);
         if (var == 1) contract_u<2>(w, My, A);
         if (var == 2) contract_v<2>(w, My, A);
-        circle_shift(dev0(var, cUR), ch + var * VS + cUR, NC, xr, yt, w);
+        circle_shift(dev0(var, cUR), chu + CS + var * 8, 1, xr, yt, w);
 #pragma unroll
         for (int i = 0; i < 9; ++i) w[i] -= r[i];  // P_UR - P_UL - P_LR + P_LL
         if (var == 3) contract_p<0>(w, Mq, A);
@@ -369,13 +395,14 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
         Mom<R> M;
         moments(B, ar2, M);
         const int cell = cb + sx + sy * HC;
+        const R* chq = (sy ? chu : chc) + sx * CS;
         const R xi0 = px + R(0.5) - R(sx), eta0 = py + (sy ? -hy : hy);
         R d[9];
-        circle_shift(dev0(3, cell), ch + 3 * VS + cell, NC, xi0, eta0, d);
+        circle_shift(dev0(3, cell), chq + 3 * 8, 1, xi0, eta0, d);
         contract_p<0>(d, M, A);
-        circle_shift(dev0(1, cell), ch + 1 * VS + cell, NC, xi0, eta0, d);
+        circle_shift(dev0(1, cell), chq + 1 * 8, 1, xi0, eta0, d);
         contract_u<0>(d, M, A);
-        circle_shift(dev0(2, cell), ch + 2 * VS + cell, NC, xi0, eta0, d);
+        circle_shift(dev0(2, cell), chq + 2 * 8, 1, xi0, eta0, d);
         contract_v<0>(d, M, A);
       }
     }
@@ -401,8 +428,8 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
     for (int var = 1; var < 4; ++var) {
       R lo[9], hi[9];
       const R dl = dev0(var, cl);
-      circle_shift(dl, ch + var * VS + cl, NC, xl, yl, lo);
-      circle_shift(dev0(var, chh), ch + var * VS + chh, NC, xh, yh, hi);
+      circle_shift(dl, chc + var * 8, 1, xl, yl, lo);
+      circle_shift(dev0(var, chh), (KIND == KIND_X ? chc + CS : chu) + var * 8, 1, xh, yh, hi);
 #pragma unroll
       for (int i = 0; i < 9; ++i) hi[i] -= lo[i];
       if (var == 3) { contract_p<3>(lo, Mf, A); contract_p<SYM>(hi, M, A); }
@@ -415,10 +442,11 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const int sxP = (KIND == KIND_Y) ? 0 : (up <= R(0) ? 1 : 0);
   const int syP = (KIND == KIND_X) ? 0 : (vp <= R(0) ? 1 : 0);
   const int cellP = cb + sxP + syP * HC;
+  const R* chP = (syP ? chu : chc) + sxP * CS;
   const R xiP = (KIND == KIND_Y) ? px : px + R(0.5) - R(sxP);
   const R etaP = (KIND == KIND_X) ? py : py + (syP ? -hy : hy);
-  const R drP = poly_eval(dev0(0, cellP), ch + 0 * VS + cellP, NC, xiP, etaP);
-  const R dpP = poly_eval(dev0(3, cellP), ch + 3 * VS + cellP, NC, xiP, etaP);
+  const R drP = poly_eval(dev0(0, cellP), chP, 1, xiP, etaP);
+  const R dpP = poly_eval(dev0(3, cellP), chP + 3 * 8, 1, xiP, etaP);
 
   // undo the moment scaling: first-order integrals carry a factor ar, second-order ar^2
   const R ia = qdiv(R(1), ar), ia2 = ia * ia;

@@ -383,8 +383,8 @@ __device__ __forceinline__ void prim_average(const Params& P, const Bufs& B, int
   const int gi = map_axis<false>(i, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
   const int gj = map_axis<false>(j, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
   const bool inflow = inflow_side(P, 0, sx) || inflow_side(P, 1, sy);
-  const bool fx = !inflow && sx >= 0 && P.bc[sx] == BC_WALL;
-  const bool fy = !inflow && sy >= 0 && P.bc[2 + sy] == BC_WALL;
+  const bool fx = !inflow && sx >= 0 && side_kind(P, sx) == BC_WALL;
+  const bool fy = !inflow && sy >= 0 && side_kind(P, 2 + sy) == BC_WALL;
   const int ci = fx ? gi : i, cj = fy ? gj : j;
   const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
   double w[8][4];
@@ -414,6 +414,7 @@ __device__ __forceinline__ void prim_average(const Params& P, const Bufs& B, int
     double dQ[4];
     {
       double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, Q[4];
+#pragma unroll
       for (int k = 0; k < 8; ++k) {
         p2c(w[k], g1inv, Q);
 #pragma unroll
@@ -521,6 +522,112 @@ __device__ __forceinline__ void stage_indicators(Smem<R>& S, Ind& I, const Param
   __syncthreads();
 }
 
+// Reconstruction of the halo cell c of the tile with corner (i0, j0): centre value, primitive
+// Simpson average and monomial coefficients into LDS.  GHOST: the cell or its nodes may lie
+// beyond the grid (boundary rules apply); otherwise every index is a plain interior one.
+template <class R, bool GHOST>
+__device__ __forceinline__ void prep_cell(Smem<R>& S, const Params& P, const Bufs& B,
+                                          DevState* dev, int i0, int j0, int c, bool count) {
+  const int a = c % HC - 1, b = c / HC - 1;
+  int sx = -1, sy = -1, gi = i0 + a, gj = j0 + b;
+  if constexpr (GHOST) {
+    gi = map_axis<false>(i0 + a, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+    gj = map_axis<false>(j0 + b, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+  }
+  // A ghost cell beyond an inflow side holds the inflow state (centre value below).  A ghost
+  // cell beyond a solid wall is the mirror image of the cell (gi, gj) it faces: that cell's
+  // reconstruction is built from its own nodes and average, then reflected (fx, fy).  Halo
+  // cells more than one layer beyond the grid are never read; their node cell is only kept
+  // inside the halo.
+  const bool inflow = inflow_side(P, 0, sx) || inflow_side(P, 1, sy);
+  const bool fx = !inflow && sx >= 0 && side_kind(P, sx) == BC_WALL;
+  const bool fy = !inflow && sy >= 0 && side_kind(P, 2 + sy) == BC_WALL;
+  const int an = fx ? min(max(gi - i0, -1), TILE - 1) : a;
+  const int bn = fy ? min(max(gj - j0, -1), TILE - 1) : b;
+  const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
+  // node k of the cell: 0..3 corners K(a,b) K(a+1,b) K(a,b+1) K(a+1,b+1),
+  // 4,5 X(a,b) X(a+1,b), 6,7 Y(a,b) Y(a,b+1)
+  const double* nptr[8] = {S.sk + sidx(an, bn), S.sk + sidx(an + 1, bn),
+                           S.sk + sidx(an, bn + 1), S.sk + sidx(an + 1, bn + 1),
+                           S.sx + sidx(an, bn), S.sx + sidx(an + 1, bn),
+                           S.sy + sidx(an, bn), S.sy + sidx(an, bn + 1)};
+  auto node = [&](int k, double W[4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) W[v] = (double)nptr[k][v * NS];
+  };
+  double Qb[4];
+  const long long oa = (long long)gj * P.pA + gi;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Qb[v] = B.A_in[v * P.sA + oa];
+  // reference state: mean of the eight nodes (exact for equal nodes)
+  double Wr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    Wr[v] = ((((double)nptr[0][v * NS] + (double)nptr[1][v * NS]) +
+              ((double)nptr[2][v * NS] + (double)nptr[3][v * NS])) +
+             (((double)nptr[4][v * NS] + (double)nptr[5][v * NS]) +
+              ((double)nptr[6][v * NS] + (double)nptr[7][v * NS]))) * 0.125;
+  }
+  // inverse Simpson for the centre value: Q_c = Q-bar + [sum_K (Q-bar - Q_k)
+  //                                          + 4 sum_E (Q-bar - Q_e)] / 16
+  double dQ[4], Uc[4];
+  {
+    double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, W[4], Q[4];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      node(k, W);
+      p2c(W, g1inv, Q);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (k < 4) sK[v] += Qb[v] - Q[v];
+        else sE[v] += Qb[v] - Q[v];
+      }
+    }
+    p2c(Wr, g1inv, Q);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Q[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
+  }
+  c2p_dev(Wr, dQ, gm1, Uc);
+  if (inflow) {
+    // every point value of the ghost cell, the centre included, is the inflow state
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Uc[v] = 0.0;
+    apply_sides(P, sx, sy, Uc);
+  } else if (!admissible(Uc[0], Uc[3])) {
+    c2p_plain(Qb, gm1, Uc);
+    const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
+    if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
+  }
+  const double rho = P.dx / P.dy, rho2 = rho * rho;
+  // primitive Simpson average and monomial coefficients, one variable at a time
+#pragma unroll 1
+  for (int v = 0; v < 4; ++v) {
+    double w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) w[k] = (double)nptr[k][v * NS];
+    const double u = Uc[v];
+    const double sK4 = ((w[0] - u) + (w[1] - u)) + ((w[2] - u) + (w[3] - u));
+    const double sE4 = ((w[4] - u) + (w[5] - u)) + ((w[6] - u) + (w[7] - u));
+    // reflection of a wall ghost: the normal velocity negated, and in the monomial
+    // coefficients c_mn (of xi^m eta^n, k = 3m + n) the odd powers of the normal coordinate
+    const double sv = ((fx && v == 1) || (fy && v == 2)) ? -1.0 : 1.0;
+    S.ub[v * NC + c] = sv * (u + (sK4 + 4.0 * sE4) * (1.0 / 36.0));
+    const double N[3][3] = {{w[0], w[4], w[2]}, {w[6], u, w[7]}, {w[1], w[5], w[3]}};
+    double cm[9];
+    nodes_to_monomials(N, cm);
+    S.c0[v * NC + c] = sv * cm[0];
+    // c_mn of xi^m eta^n -> coefficient of xi^m (eta dy/dx)^n: the circle integrals use
+    // dx as the unit length in both directions
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {
+      const double sk = sv * ((fx && ((k / 3) & 1)) ? -1.0 : 1.0) *
+                        ((fy && ((k % 3) & 1)) ? -1.0 : 1.0);
+      S.ch[c * CS + v * 8 + k - 1] =
+          (R)(sk * (k % 3 == 0 ? cm[k] : (k % 3 == 1 ? cm[k] * rho : cm[k] * rho2)));
+    }
+  }
+}
+
 // Stage the t_n point values of a tile's halo in LDS and build the halo cells'
 // reconstructions.  Ends with a barrier.
 template <class R>
@@ -528,13 +635,27 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
                                                DevState* dev, int tile, bool count) {
   const int i0 = (tile % P.tiles_x) * TILE, j0 = (tile / P.tiles_x) * TILE;
   const int tid = threadIdx.x;
+  // a tile whose halo (sites i0-1 .. i0+TILE, cells i0-1 .. i0+TILE-1, likewise in y) lies
+  // inside the grid needs no boundary rule: the same for the whole block
+  const bool inner = i0 >= 1 && j0 >= 1 && i0 + TILE <= P.nx - 1 && j0 + TILE <= P.ny - 1;
+  // the three source arrays as opaque values: a select among the fields of the kernel
+  // arguments would otherwise become an indexed load from a scratch copy of them
+  const double *srcK = B.K_in, *srcX = B.X_in, *srcY = B.Y_in;
+  asm("" : "+v"(srcK), "+v"(srcX), "+v"(srcY));
 
   // 1. stage the t_n point values of the halo (local sites -1 .. TILE) in LDS
   for (int e = tid; e < 3 * NS; e += PT_THREADS) {
     const int kind = e / NS, s = e % NS;
     const int a = s % HS - 1, b = s / HS - 1;
     double W[4];
-    fetch_site(P, B, kind, i0 + a, j0 + b, W);
+    if (inner) {
+      const double* src = kind == 0 ? srcK : (kind == 1 ? srcX : srcY);
+      const long long o = (long long)(j0 + b) * P.pP + (i0 + a);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[v] = src[v * P.sP + o];
+    } else {
+      fetch_site(P, B, kind, i0 + a, j0 + b, W);
+    }
     double* dst = kind == 0 ? S.sk : (kind == 1 ? S.sx : S.sy);
 #pragma unroll
     for (int v = 0; v < 4; ++v) dst[v * NS + s] = W[v];
@@ -543,101 +664,10 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
 
   // 2. cell reconstructions of the halo cells (local cells -1 .. TILE-1)
   for (int c = tid; c < NC; c += PT_THREADS) {
-    const int a = c % HC - 1, b = c / HC - 1;
-    int sx, sy;
-    const int gi = map_axis<false>(i0 + a, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
-    const int gj = map_axis<false>(j0 + b, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
-    // A ghost cell beyond an inflow side holds the inflow state (centre value below).  A ghost
-    // cell beyond a solid wall is the mirror image of the cell (gi, gj) it faces: that cell's
-    // reconstruction is built from its own nodes and average, then reflected (fx, fy).  Halo
-    // cells more than one layer beyond the grid are never read; their node cell is only kept
-    // inside the halo.
-    const bool inflow = inflow_side(P, 0, sx) || inflow_side(P, 1, sy);
-    const bool fx = !inflow && sx >= 0 && P.bc[sx] == BC_WALL;
-    const bool fy = !inflow && sy >= 0 && P.bc[2 + sy] == BC_WALL;
-    const int an = fx ? min(max(gi - i0, -1), TILE - 1) : a;
-    const int bn = fy ? min(max(gj - j0, -1), TILE - 1) : b;
-    const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
-    // node k of the cell: 0..3 corners K(a,b) K(a+1,b) K(a,b+1) K(a+1,b+1),
-    // 4,5 X(a,b) X(a+1,b), 6,7 Y(a,b) Y(a,b+1)
-    const double* nptr[8] = {S.sk + sidx(an, bn), S.sk + sidx(an + 1, bn),
-                             S.sk + sidx(an, bn + 1), S.sk + sidx(an + 1, bn + 1),
-                             S.sx + sidx(an, bn), S.sx + sidx(an + 1, bn),
-                             S.sy + sidx(an, bn), S.sy + sidx(an, bn + 1)};
-    auto node = [&](int k, double W[4]) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) W[v] = (double)nptr[k][v * NS];
-    };
-    double Qb[4];
-    const long long oa = (long long)gj * P.pA + gi;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Qb[v] = B.A_in[v * P.sA + oa];
-    // reference state: mean of the eight nodes (exact for equal nodes)
-    double Wr[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Wr[v] = ((((double)nptr[0][v * NS] + (double)nptr[1][v * NS]) +
-                ((double)nptr[2][v * NS] + (double)nptr[3][v * NS])) +
-               (((double)nptr[4][v * NS] + (double)nptr[5][v * NS]) +
-                ((double)nptr[6][v * NS] + (double)nptr[7][v * NS]))) * 0.125;
-    }
-    // inverse Simpson for the centre value: Q_c = Q-bar + [sum_K (Q-bar - Q_k)
-    //                                          + 4 sum_E (Q-bar - Q_e)] / 16
-    double dQ[4], Uc[4];
-    {
-      double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, W[4], Q[4];
-      for (int k = 0; k < 8; ++k) {
-        node(k, W);
-        p2c(W, g1inv, Q);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (k < 4) sK[v] += Qb[v] - Q[v];
-          else sE[v] += Qb[v] - Q[v];
-        }
-      }
-      p2c(Wr, g1inv, Q);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Q[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
-    }
-    c2p_dev(Wr, dQ, gm1, Uc);
-    if (inflow) {
-      // every point value of the ghost cell, the centre included, is the inflow state
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Uc[v] = 0.0;
-      apply_sides(P, sx, sy, Uc);
-    } else if (!admissible(Uc[0], Uc[3])) {
-      c2p_plain(Qb, gm1, Uc);
-      const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
-      if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
-    }
-    const double rho = P.dx / P.dy, rho2 = rho * rho;
-    // primitive Simpson average and monomial coefficients, one variable at a time
-#pragma unroll 1
-    for (int v = 0; v < 4; ++v) {
-      double w[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) w[k] = (double)nptr[k][v * NS];
-      const double u = Uc[v];
-      const double sK4 = ((w[0] - u) + (w[1] - u)) + ((w[2] - u) + (w[3] - u));
-      const double sE4 = ((w[4] - u) + (w[5] - u)) + ((w[6] - u) + (w[7] - u));
-      // reflection of a wall ghost: the normal velocity negated, and in the monomial
-      // coefficients c_mn (of xi^m eta^n, k = 3m + n) the odd powers of the normal coordinate
-      const double sv = ((fx && v == 1) || (fy && v == 2)) ? -1.0 : 1.0;
-      S.ub[v * NC + c] = sv * (u + (sK4 + 4.0 * sE4) * (1.0 / 36.0));
-      const double N[3][3] = {{w[0], w[4], w[2]}, {w[6], u, w[7]}, {w[1], w[5], w[3]}};
-      double cm[9];
-      nodes_to_monomials(N, cm);
-      S.c0[v * NC + c] = sv * cm[0];
-      // c_mn of xi^m eta^n -> coefficient of xi^m (eta dy/dx)^n: the circle integrals use
-      // dx as the unit length in both directions
-#pragma unroll
-      for (int k = 1; k < 9; ++k) {
-        const double sk = sv * ((fx && ((k / 3) & 1)) ? -1.0 : 1.0) *
-                          ((fy && ((k % 3) & 1)) ? -1.0 : 1.0);
-        S.ch[(v * 8 + k - 1) * NC + c] =
-            (R)(sk * (k % 3 == 0 ? cm[k] : (k % 3 == 1 ? cm[k] * rho : cm[k] * rho2)));
-      }
-    }
+    if (inner)
+      prep_cell<R, false>(S, P, B, dev, i0, j0, c, count);
+    else
+      prep_cell<R, true>(S, P, B, dev, i0, j0, c, count);
   }
   __syncthreads();
 }
