@@ -257,12 +257,6 @@ template <> __device__ __forceinline__ float qdiv<float>(float a, float b) {
   return a * __builtin_amdgcn_rcpf(b);
 }
 
-// Corner EG2 formulation.  Split (FP32): the lower-left cell on the full circle plus cell
-// differences on two half circles and one quadrant arc set -- about a quarter fewer
-// operations, but three moment sets live at once.  Quadrants (FP64): one general arc set per
-// cell, one moment set live at a time, which keeps the FP64 kernel within its registers.
-template <class R> constexpr bool kCornerSplit = sizeof(R) == 4;
-
 // ------------------------------------------------------------------------------------------
 // EG2 at one DOF.  cb: LDS index of the lower-left cell around the DOF (K: cell (a-1,b-1);
 // X: cell (a-1,b); Y: cell (a,b-1)).  Returns the deviation dU = EG2[U] - lin.
@@ -294,117 +288,65 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   full_moments(Mf, ar);
 
   if constexpr (KIND == KIND_K) {
-    if constexpr (kCornerSplit<R>) {
-      // corner: the lower-left cell's polynomial P_LL on the full circle, plus (P_LR - P_LL) on
-      // the right half (cos > u'/c'), (P_UL - P_LL) on the upper half (sin > v'/c') and
-      // (P_UR - P_UL - P_LR + P_LL) on their intersection; in every cell the terms sum to the
-      // cell's own polynomial.  The two halves are symmetric arcs (half their moments vanish);
-      // only the upper-right arc set needs the general moments.
-      const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
-      const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
-      const R al = MA::acos_(cMx), be = MA::asin_(cMy);
-      const R Ly = pi - R(2) * be;
-      // end points of the arcs on the circle of radius ar (the moments are those of that circle)
-      const R cxa = ar * cMx, sxa = ar * sxx, sya = ar * syy, cya = ar * cMy, a2 = ar * ar;
-      Mom<R> Mq;
-      {
-        // upper-right arc set: (-al, al) cap (be, pi - be), pieces for the shifts 0 and -2 pi
-        Br<R> B;
-        br_zero(B);
+    // corner: the lower-left cell's polynomial P_LL on the full circle, plus (P_LR - P_LL) on
+    // the right half (cos > u'/c'), (P_UL - P_LL) on the upper half (sin > v'/c') and
+    // (P_UR - P_UL - P_LR + P_LL) on their intersection; in every cell the terms sum to the
+    // cell's own polynomial.  The two halves are symmetric arcs (half their moments vanish);
+    // only the upper-right arc set needs the general moments.
+    const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
+    const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
+    const R al = MA::acos_(cMx), be = MA::asin_(cMy);
+    const R Ly = pi - R(2) * be;
+    // end points of the arcs on the circle of radius ar (the moments are those of that circle)
+    const R cxa = ar * cMx, sxa = ar * sxx, sya = ar * syy, cya = ar * cMy, a2 = ar * ar;
+    Mom<R> Mq;
+    {
+      // upper-right arc set: (-al, al) cap (be, pi - be), pieces for the shifts 0 and -2 pi
+      Br<R> B;
+      br_zero(B);
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const R sh = t ? R(-2 * kPi) : R(0);
-          const R lo2 = be + sh, hi2 = pi - be + sh;
-          const bool l1 = -al >= lo2, h1 = al <= hi2;
-          const R lo = l1 ? -al : lo2, hi = h1 ? al : hi2;
-          const R Ca = l1 ? cxa : sya, Sa = l1 ? -sxa : cya;
-          const R Cb = h1 ? cxa : -sya, Sb = h1 ? sxa : cya;
-          br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
-        }
-        moments(B, a2, Mq);
+      for (int t = 0; t < 2; ++t) {
+        const R sh = t ? R(-2 * kPi) : R(0);
+        const R lo2 = be + sh, hi2 = pi - be + sh;
+        const bool l1 = -al >= lo2, h1 = al <= hi2;
+        const R lo = l1 ? -al : lo2, hi = h1 ? al : hi2;
+        const R Ca = l1 ? cxa : sya, Sa = l1 ? -sxa : cya;
+        const R Cb = h1 ? cxa : -sya, Sb = h1 ? sxa : cya;
+        br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
       }
-      const int cLL = cb, cLR = cb + 1, cUL = cb + HC, cUR = cb + HC + 1;
-      const R xl = px + R(0.5), xr = px - R(0.5), yb = py + hy, yt = py - hy;
+      moments(B, a2, Mq);
+    }
+    const int cLL = cb, cLR = cb + 1, cUL = cb + HC, cUR = cb + HC + 1;
+    const R xl = px + R(0.5), xr = px - R(0.5), yb = py + hy, yt = py - hy;
+    Mom<R> Mx, My;
+    moments_sym_x(cxa, sxa, al, a2, Mx);
+    moments_sym_y(sya, cya, Ly, a2, My);
 #pragma unroll
-      for (int var = 1; var < 4; ++var) {
-        // the half-circle moments are cheap: they are formed again for each variable (an
-        // empty asm keeps the compiler from hoisting them and holding 26 more registers)
-        R m1 = cxa, s1 = sxa, a1 = al, q2 = sya, w2 = cya, l2 = Ly, r2 = a2;
-        asm volatile("" : "+v"(m1), "+v"(s1), "+v"(a1), "+v"(q2), "+v"(w2), "+v"(l2), "+v"(r2));
-        R t[9], r[9], w[9];
-        Mom<R> Mx;
-        moments_sym_x(m1, s1, a1, r2, Mx);
-        circle_shift(dev0(var, cLL), chc + var * 8, 1, xl, yb, t);
-        circle_shift(dev0(var, cLR), chc + CS + var * 8, 1, xr, yb, r);
+    for (int var = 1; var < 4; ++var) {
+      R t[9], r[9], w[9];
+      circle_shift(dev0(var, cLL), chc + var * 8, 1, xl, yb, t);
+      circle_shift(dev0(var, cLR), chc + CS + var * 8, 1, xr, yb, r);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) w[i] = r[i] - t[i];  // P_LR - P_LL
-        if (var == 3) { contract_p<3>(t, Mf, A); contract_p<1>(w, Mx, A); }
-        if (var == 1) { contract_u<3>(t, Mf, A); contract_u<1>(w, Mx, A); }
-        if (var == 2) { contract_v<3>(t, Mf, A); contract_v<1>(w, Mx, A); }
-        circle_shift(dev0(var, cUL), chu + var * 8, 1, xl, yt, w);
+      for (int i = 0; i < 9; ++i) w[i] = r[i] - t[i];  // P_LR - P_LL
+      if (var == 3) { contract_p<3>(t, Mf, A); contract_p<1>(w, Mx, A); }
+      if (var == 1) { contract_u<3>(t, Mf, A); contract_u<1>(w, Mx, A); }
+      if (var == 2) { contract_v<3>(t, Mf, A); contract_v<1>(w, Mx, A); }
+      circle_shift(dev0(var, cUL), chu + var * 8, 1, xl, yt, w);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          const R d = w[i] - t[i];  // P_UL - P_LL
-          w[i] = d;
-          r[i] += d;  // P_LR + P_UL - P_LL
-        }
-        Mom<R> My;
-        moments_sym_y(q2, w2, l2, r2, My);
-        if (var == 3) contract_p<2>(w, My, A);
-        if (var == 1) contract_u<2>(w, My, A);
-        if (var == 2) contract_v<2>(w, My, A);
-        circle_shift(dev0(var, cUR), chu + CS + var * 8, 1, xr, yt, w);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) w[i] -= r[i];  // P_UR - P_UL - P_LR + P_LL
-        if (var == 3) contract_p<0>(w, Mq, A);
-        if (var == 1) contract_u<0>(w, Mq, A);
-        if (var == 2) contract_v<0>(w, Mq, A);
+      for (int i = 0; i < 9; ++i) {
+        const R d = w[i] - t[i];  // P_UL - P_LL
+        w[i] = d;
+        r[i] += d;  // P_LR + P_UL - P_LL
       }
-    } else {
-      // corner: for each of the four cells, the arc set where the circle lies in that cell
-      // (the intersection of the x-interval of its side with the y-interval of its side)
-      const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
-      const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
-      const R al = MA::acos_(cMx), be = MA::asin_(cMy);
-      const R twopi = R(2 * kPi);
-      // end points of the arcs on the circle of radius ar (the moments are those of that circle)
-      const R cxa = ar * cMx, sxa = ar * sxx, sya = ar * syy, cya = ar * cMy, ar2 = ar * ar;
-#pragma unroll 1
-      for (int q = 0; q < 4; ++q) {
-        const int sx = q & 1, sy = q >> 1;
-        // x interval of side sx: right (-al, al), left (al, 2pi - al)
-        const R a1 = sx ? -al : al, b1 = sx ? al : twopi - al;
-        const R sa1 = sx ? -sxa : sxa;  // a sin at a1 (a cos is cxa at both ends)
-        // y interval of side sy: top (be, pi - be), bottom (pi - be, 2pi + be)
-        const R a2 = sy ? be : pi - be, b2 = sy ? pi - be : twopi + be;
-        const R ca2 = sy ? sya : -sya;  // a cos at a2 (a sin is cya at both ends)
-        Br<R> B;
-        br_zero(B);
-        // the intersection is made of the pieces I_x cap (I_y + 2 pi k), k = 0 and one k = +-1
-        const R kB = (sx == 0 && sy == 1) ? twopi : -twopi;
+      if (var == 3) contract_p<2>(w, My, A);
+      if (var == 1) contract_u<2>(w, My, A);
+      if (var == 2) contract_v<2>(w, My, A);
+      circle_shift(dev0(var, cUR), chu + CS + var * 8, 1, xr, yt, w);
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const R sh = t ? kB : R(0);
-          const R lo2 = a2 + sh, hi2 = b2 + sh;
-          const bool l1 = a1 >= lo2, h1 = b1 <= hi2;
-          const R lo = l1 ? a1 : lo2, hi = h1 ? b1 : hi2;
-          const R Ca = l1 ? cxa : ca2, Sa = l1 ? sa1 : cya;
-          const R Cb = h1 ? cxa : -ca2, Sb = h1 ? -sa1 : cya;
-          br_piece(B, Ca, Sa, Cb, Sb, hi - lo);
-        }
-        Mom<R> M;
-        moments(B, ar2, M);
-        const int cell = cb + sx + sy * HC;
-        const R* chq = (sy ? chu : chc) + sx * CS;
-        const R xi0 = px + R(0.5) - R(sx), eta0 = py + (sy ? -hy : hy);
-        R d[9];
-        circle_shift(dev0(3, cell), chq + 3 * 8, 1, xi0, eta0, d);
-        contract_p<0>(d, M, A);
-        circle_shift(dev0(1, cell), chq + 1 * 8, 1, xi0, eta0, d);
-        contract_u<0>(d, M, A);
-        circle_shift(dev0(2, cell), chq + 2 * 8, 1, xi0, eta0, d);
-        contract_v<0>(d, M, A);
-      }
+      for (int i = 0; i < 9; ++i) w[i] -= r[i];  // P_UR - P_UL - P_LR + P_LL
+      if (var == 3) contract_p<0>(w, Mq, A);
+      if (var == 1) contract_u<0>(w, Mq, A);
+      if (var == 2) contract_v<0>(w, Mq, A);
     }
   } else {
     // edge: the low-side cell on the full circle plus, on the high-side arc, the difference of
