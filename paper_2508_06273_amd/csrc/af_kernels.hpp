@@ -217,18 +217,26 @@ template <class R> struct Smem {
   double red[4];
 };
 
-// Indicators of a tile (Algorithm 2, Sec. 3.4): the primitive averages of the cells -2 .. TILE
-// around it, theta of its x-edges (sites 0..TILE-1 x -1..TILE-1) and y-edges (-1..TILE-1 x
-// 0..TILE-1), and the transonic flags of the corners 0..TILE x 0..TILE.
+// Indicators of a tile (Algorithm 2, Sec. 3.4): the primitive averages of the ring of cells
+// -2 .. TILE around it, theta of its x-edges (sites 0..TILE-1 x -1..TILE-1) and y-edges
+// (-1..TILE-1 x 0..TILE-1), and the transonic flags of the corners 0..TILE x 0..TILE.  The ring
+// cells -1 .. TILE-1 are the halo cells, whose averages live in Smem::ub; `outer` holds the
+// layer around them.
 constexpr int RC = TILE + 3;  // ring cells per edge (local -2 .. TILE)
 constexpr int NR = RC * RC;
+constexpr int NO = NR - NC;   // outer layer: 4 (TILE + 2) cells
 struct Ind {
-  double ring[4 * NR];
+  double outer[4 * NO];
   double thx[TILE * (TILE + 1)];
   double thy[(TILE + 1) * TILE];
   unsigned char flag[(TILE + 1) * (TILE + 1)];
 };
-__device__ __forceinline__ int ridx(int a, int b) { return (a + 2) + (b + 2) * RC; }
+// outer-layer index of ring cell (a, b): bottom row, top row, then the left and right columns
+__device__ __forceinline__ int oidx(int a, int b) {
+  if (b == -2) return a + 2;
+  if (b == TILE) return RC + a + 2;
+  return 2 * RC + (a == -2 ? 0 : TILE + 1) + (b + 1);
+}
 __device__ __forceinline__ int thx_idx(int a, int b) { return a + (b + 1) * TILE; }
 __device__ __forceinline__ int thy_idx(int a, int b) { return (a + 1) + b * (TILE + 1); }
 __device__ __forceinline__ int flag_idx(int a, int b) { return a + b * (TILE + 1); }

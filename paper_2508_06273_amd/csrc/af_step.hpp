@@ -440,31 +440,42 @@ __device__ __forceinline__ void prim_average(const Params& P, const Bufs& B, int
   }
 }
 
-// Algorithm 2: across the cells L -> R (ring indices) in the direction of velocity component
-// comp (1: x, 2: y), w + c or w - c goes from positive to negative.
-__device__ __forceinline__ bool transonic_pair(const double* ring, int l, int r, int comp,
-                                               double gamma) {
-  const double cl = sqrt(gamma * ring[3 * NR + l] / ring[l]);
-  const double cr = sqrt(gamma * ring[3 * NR + r] / ring[r]);
-  const double wl = ring[comp * NR + l], wr = ring[comp * NR + r];
+// Primitive average of ring cell (a, b), -2 <= a, b <= TILE, component v.
+template <class R>
+__device__ __forceinline__ double ring_at(const Smem<R>& S, const Ind& I, int v, int a, int b) {
+  const bool halo = a >= -1 && a < TILE && b >= -1 && b < TILE;
+  const double* p = halo ? S.ub + (v * NC + cidx(a, b)) : I.outer + (v * NO + oidx(a, b));
+  return *p;
+}
+
+// Algorithm 2: across the ring cells L = (al, bl) -> R = (ar, br) in the direction of velocity
+// component comp (1: x, 2: y), w + c or w - c goes from positive to negative.
+template <class R>
+__device__ __forceinline__ bool transonic_pair(const Smem<R>& S, const Ind& I, int al, int bl,
+                                               int ar, int br, int comp, double gamma) {
+  const double cl = sqrt(gamma * ring_at(S, I, 3, al, bl) / ring_at(S, I, 0, al, bl));
+  const double cr = sqrt(gamma * ring_at(S, I, 3, ar, br) / ring_at(S, I, 0, ar, br));
+  const double wl = ring_at(S, I, comp, al, bl), wr = ring_at(S, I, comp, ar, br);
   return (wl + cl > 0.0 && wr + cr < 0.0) || (wl - cl > 0.0 && wr - cr < 0.0);
 }
 
-// Sec. 3.4: theta of the edge midpoint between ring cells c1 and c2 of the line of ring cells
-// c0, c1, c2, c3 (spacing `st`), velocity component comp along the line.
-__device__ __forceinline__ double theta_edge(const double* ring, int c0, int st, int comp,
-                                             double gamma) {
-  double p[4], a[2];
+// Sec. 3.4: theta of the edge midpoint between ring cells 1 and 2 of the line of ring cells
+// (a0, b0) + m (da, db), m = 0..3, velocity component comp along the line.
+template <class R>
+__device__ __forceinline__ double theta_edge(const Smem<R>& S, const Ind& I, int a0, int b0,
+                                             int da, int db, int comp, double gamma) {
+  double p[4], rho[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const int c = c0 + m * st;
-    if (!admissible(ring[c], ring[3 * NR + c])) return 0.0;
-    p[m] = ring[3 * NR + c];
+    rho[m] = ring_at(S, I, 0, a0 + m * da, b0 + m * db);
+    p[m] = ring_at(S, I, 3, a0 + m * da, b0 + m * db);
+    if (!admissible(rho[m], p[m])) return 0.0;
   }
+  double a[2];
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
-    const int c = c0 + (2 - m) * st;  // cell k, then k-1
-    a[m] = fabs(ring[comp * NR + c]) + sqrt(gamma * ring[3 * NR + c] / ring[c]);
+    const int k = 2 - m;  // cell k, then k-1
+    a[m] = fabs(ring_at(S, I, comp, a0 + k * da, b0 + k * db)) + sqrt(gamma * p[k] / rho[k]);
   }
   const double s_hi = fabs((p[3] - 2.0 * p[2] + p[1]) / (p[3] + 2.0 * p[2] + p[1]));
   const double s_lo = fabs((p[2] - 2.0 * p[1] + p[0]) / (p[2] + 2.0 * p[1] + p[0]));
@@ -487,11 +498,14 @@ __device__ __forceinline__ void stage_indicators(Smem<R>& S, Ind& I, const Param
     // cells beyond the padded range are never read by a DOF of the grid
     const int gi = min(i0 + a, P.nx + 1), gj = min(j0 + b, P.ny + 1);
     const long long o = (long long)(gj + 2) * P.pU + (gi + 2);
+    const bool halo = a >= -1 && a < TILE && b >= -1 && b < TILE;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const double u = B.UB[v * P.sU + o];
-      I.ring[v * NR + c] = u;
-      if (a >= -1 && a < TILE && b >= -1 && b < TILE) S.ub[v * NC + cidx(a, b)] = u;
+      if (halo)
+        S.ub[v * NC + cidx(a, b)] = u;
+      else
+        I.outer[v * NO + oidx(a, b)] = u;
     }
   }
   __syncthreads();
@@ -502,21 +516,21 @@ __device__ __forceinline__ void stage_indicators(Smem<R>& S, Ind& I, const Param
       const int a = e % (TILE + 1), b = e / (TILE + 1);
       bool f = false;
       if (P.tsw)
-        f = transonic_pair(I.ring, ridx(a - 1, b), ridx(a, b), 1, g) ||
-            transonic_pair(I.ring, ridx(a - 1, b - 1), ridx(a, b - 1), 1, g) ||
-            transonic_pair(I.ring, ridx(a - 1, b - 1), ridx(a - 1, b), 2, g) ||
-            transonic_pair(I.ring, ridx(a, b - 1), ridx(a, b), 2, g);
+        f = transonic_pair(S, I, a - 1, b, a, b, 1, g) ||
+            transonic_pair(S, I, a - 1, b - 1, a, b - 1, 1, g) ||
+            transonic_pair(S, I, a - 1, b - 1, a - 1, b, 2, g) ||
+            transonic_pair(S, I, a, b - 1, a, b, 2, g);
       I.flag[flag_idx(a, b)] = f ? 1 : 0;
     } else if (e < (TILE + 1) * (TILE + 1) + TILE * (TILE + 1)) {
       // x-edge (a, b), a in 0..TILE-1, b in -1..TILE-1: cells a-2 .. a+1 of row b
       const int q = e - (TILE + 1) * (TILE + 1);
       const int a = q % TILE, b = q / TILE - 1;
-      I.thx[thx_idx(a, b)] = P.shock ? theta_edge(I.ring, ridx(a - 2, b), 1, 1, g) : 1.0;
+      I.thx[thx_idx(a, b)] = P.shock ? theta_edge(S, I, a - 2, b, 1, 0, 1, g) : 1.0;
     } else {
       // y-edge (a, b), a in -1..TILE-1, b in 0..TILE-1: cells b-2 .. b+1 of column a
       const int q = e - (TILE + 1) * (TILE + 1) - TILE * (TILE + 1);
       const int a = q % (TILE + 1) - 1, b = q / (TILE + 1);
-      I.thy[thy_idx(a, b)] = P.shock ? theta_edge(I.ring, ridx(a, b - 2), RC, 2, g) : 1.0;
+      I.thy[thy_idx(a, b)] = P.shock ? theta_edge(S, I, a, b - 2, 0, 1, 2, g) : 1.0;
     }
   }
   __syncthreads();
