@@ -39,8 +39,8 @@ PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
 # asin = 1; FMA = 2), counted operation by operation from the exact-moment formulation that
 # each path evaluates, for the generic subsonic DOF (one arc piece per arc set):
 #   EG2 set-up, foot point and outputs                                    82
-#   corner, FP32 (full circle + two half circles + one quadrant arc set) 1631
-#   corner, FP64 (one general arc set per cell, four cells)              1975
+#   corner (full circle + two half circles + one quadrant arc set; the
+#           half-circle moments 46 + 48 formed once per evaluation)      1443
 #   x-edge (full circle + one half circle)                                575
 #   y-edge                                                                580
 #   per DOF: derivatives 16, correction 74, assembly 31, Simpson-in-time
@@ -51,7 +51,7 @@ PEAK_FP64 = 78.6   # TFLOP/s, MI355X vector FP64 (published)
 # from scaled arc end points).  Algorithm 1 evaluates EG2 three times per DOF, the averaged
 # linearisation twice (plus 32 for the mean of the adjacent averages).
 # ------------------------------------------------------------------------------------------
-EG2_K = {"fp32": 1631, "fp64": 1975}
+EG2_K = {"fp32": 1443, "fp64": 1443}
 EG2_X, EG2_Y = 575, 580
 PER_DOF = 213 + 197 + 197
 PER_CELL = 440
