@@ -91,16 +91,20 @@ __device__ __forceinline__ void c2p_plain(const double Q[4], double gm1, double 
 // f(q), g(q) evaluated from primitive values, FP64.
 __device__ __forceinline__ void flux_fg(const double U[4], double g1inv, double F[4],
                                         double G[4]) {
-  double r = U[0], u = U[1], v = U[2], p = U[3];
-  double H = p * g1inv + 0.5 * r * (u * u + v * v) + p;  // E + p
-  double ru = r * u, rv = r * v;
+  // fused multiply-adds written out and no other contraction: every kernel that inlines this
+  // gets the same bits (the batched and single-grid paths agree exactly)
+#pragma clang fp contract(off)
+  const double r = U[0], u = U[1], v = U[2], p = U[3];
+  const double q = __builtin_fma(u, u, v * v);
+  const double H = __builtin_fma(p, g1inv, __builtin_fma(0.5 * r, q, p));  // E + p
+  const double ru = r * u, rv = r * v;
   F[0] = ru;
-  F[1] = ru * u + p;
+  F[1] = __builtin_fma(ru, u, p);
   F[2] = ru * v;
   F[3] = u * H;
   G[0] = rv;
   G[1] = rv * u;
-  G[2] = rv * v + p;
+  G[2] = __builtin_fma(rv, v, p);
   G[3] = v * H;
 }
 

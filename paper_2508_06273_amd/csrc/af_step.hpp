@@ -264,28 +264,30 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Param
     }
   }
 
-  // outputs: new point value, Simpson-in-time flux sums, wave speed
+  // outputs: new point value, Simpson-in-time flux sums (weights 1, 4, 1 at t_n, t_n+1/2,
+  // t_n+1), wave speed
   if (IND && tsw) atomicAdd(&dev->cnt[AF_CNT_TSW], 1ull);
   double* out = (KIND == KIND_K) ? B.K_out : (KIND == KIND_X ? B.X_out : B.Y_out);
   const long long o = (long long)gj * P.pP + gi;
 #pragma unroll
   for (int v = 0; v < 4; ++v) out[v * P.sP + o] = U1[v];
   const double g1inv = 1.0 / (P.gamma - 1.0);
-  double Fs[4] = {0, 0, 0, 0}, Gs[4] = {0, 0, 0, 0};
+  double Fs[4], Gs[4];
   {
-    double Ul[4], F[4], Gq[4];
-#pragma unroll 1
-    for (int lvl = 0; lvl < 3; ++lvl) {
+#pragma clang fp contract(off)
+    double F0[4], G0[4], F[4], Gq[4];
+    flux_fg(U0, g1inv, F0, G0);
+    flux_fg(Uh, g1inv, F, Gq);
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        Ul[v] = lvl == 0 ? site[v * NS + s0] : (lvl == 1 ? Uh[v] : U1[v]);
-      flux_fg(Ul, g1inv, F, Gq);
-      const double w = lvl == 1 ? 4.0 : 1.0;
+    for (int v = 0; v < 4; ++v) {
+      Fs[v] = __builtin_fma(4.0, F[v], F0[v]);
+      Gs[v] = __builtin_fma(4.0, Gq[v], G0[v]);
+    }
+    flux_fg(U1, g1inv, F, Gq);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Fs[v] += w * F[v];
-        Gs[v] += w * Gq[v];
-      }
+    for (int v = 0; v < 4; ++v) {
+      Fs[v] += F[v];
+      Gs[v] += Gq[v];
     }
   }
   const long long of = (long long)gj * P.pF + gi;
@@ -777,7 +779,7 @@ __device__ __forceinline__ bool update_pair(const Params& P, const double* __res
     auto ld = [](const double* a, long long o) {
       return *reinterpret_cast<const double2*>(a + o);
     };
-#pragma unroll 1
+#pragma unroll
     for (int v = 0; v < 4; ++v) {
       const double* fk = FK + v * P.sF;
       const double* gk = FK + (4 + v) * P.sF;
