@@ -246,9 +246,10 @@ __device__ __forceinline__ int cidx(int a, int b) { return (a + 1) + (b + 1) * H
 
 // idx = 1/dx; hy = dy / (2 dx): half a cell in y in units of dx (the local frame of the circle
 // integrals uses dx in both directions).
-// An LDS pointer whose value the compiler cannot see through.  Reads at constant offsets from
-// it fold the offsets into the LDS instructions; from a visible base computation the compiler
-// instead rebuilds the full address for every read.
+// An LDS pointer whose value the compiler cannot see through (p must point into LDS: it is
+// converted to the LDS address space).  Reads at constant offsets from it fold the offsets into
+// the LDS instructions; from a visible base computation the compiler instead rebuilds the full
+// address for every read.
 template <class T> __device__ __forceinline__ const T* lds_base(const T* p) {
   auto q = (__attribute__((address_space(3))) const T*)p;
   asm("" : "+v"(q));
