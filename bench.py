@@ -390,7 +390,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the Active Flux step on one GPU only; "
+        print("bench.py: this library runs the Active Flux step on one GPU only; "
               f"--gpus {args.gpus} (WORLD_SIZE={world}) is not supported.", file=sys.stderr)
         sys.exit(2)
 

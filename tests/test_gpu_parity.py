@@ -339,7 +339,7 @@ def test_full_size_radial_outflow_sampled(prec, tol):
     the edges, the centre (the near-vacuum point) and random cells; then 200 steps keep every
     point value and average admissible while the limiter starts to act (t = 0.021).  (Around
     step 226 a cell average at the centre loses positivity: limiting the point values alone
-    does not bound the averages, and the flux limiting that would is not part of this build.)"""
+    does not bound the averages, and the flux limiting that would is not implemented.)"""
     n = 2048
     _flush(f"[gpu] full-size radial outflow {n}^2 prec={prec}")
     st = I.radial_state(n, n_gl=2)
