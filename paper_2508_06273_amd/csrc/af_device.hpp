@@ -33,14 +33,12 @@ template <> struct Math<double> {
   static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
   static __device__ __forceinline__ double acos_(double x) { return ::acos(x); }
   static __device__ __forceinline__ double asin_(double x) { return ::asin(x); }
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 };
 template <> struct Math<float> {
   // hardware square root (1 ulp) rather than the correctly rounded expansion
   static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
   static __device__ __forceinline__ float acos_(float x) { return ::acosf(x); }
   static __device__ __forceinline__ float asin_(float x) { return ::asinf(x); }
-  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 };
 
 template <class T> __device__ __forceinline__ T mx(T a, T b) { return a > b ? a : b; }
