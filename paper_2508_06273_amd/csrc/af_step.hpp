@@ -689,8 +689,8 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
 }
 
 // Evolve the tile's own DOFs: wavefront 0 -> K; wavefront 1 -> X, then Y (an edge EG2 costs
-// well under half of a corner EG2, so the two waves are about equally loaded).  In the fix-up
-// pass only the lanes listed in `mask` (per kind) run.
+// about 40 % of a corner EG2, so the two waves' loads are within about a fifth of each other).
+// In the fix-up pass only the lanes listed in `mask` (per kind) run.
 template <class R, bool FIX, bool IND>
 __device__ __forceinline__ void evolve_tile(Smem<R>& S, const Ind* I, const Params& P,
                                             const Bufs& B, DevState* dev, int tile, double dt,
