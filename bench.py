@@ -292,6 +292,42 @@ def extra_workloads(stream):
     return out
 
 
+def pcie_inclusive(n, stream, steps=(1, 40)):
+    """Whole-job rate when the state is handed over in host memory, as the C ABI's
+    af_set_state / af_get_state do: copy the 4096^2 vortex in (host to device, pageable numpy
+    arrays), run K steps, copy the state out, all timed on the host clock; also the two copies
+    alone.  This is a reported figure beside the benchmark, never its value."""
+    from paper_2508_06273_amd import af, inputs as I
+    import torch
+    st = I.shu_vortex(n, n_gl=3)
+    out = {"workload": f"isentropic vortex {n}x{n}, Algorithm 1, CFL 0.3; state FP64 in host "
+                       "memory (pageable) before and after", "state_bytes": int(
+                           sum(getattr(st, k).nbytes for k in ("avg", "K", "X", "Y")))}
+    for prec, name in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64")):
+        s = af.Solver.for_state(st, precision=prec)
+        s.set_stream(stream)
+        s.run(1e9, 0.3, 2)  # warm-up (graph capture, first launches)
+        rec = {}
+        t0 = time.perf_counter()
+        s.set_state(st.avg, st.K, st.X, st.Y, st.t)
+        t1 = time.perf_counter()
+        s.get_state()
+        t2 = time.perf_counter()
+        rec["set_state_ms"] = (t1 - t0) * 1e3
+        rec["get_state_ms"] = (t2 - t1) * 1e3
+        for k in steps:
+            t0 = time.perf_counter()
+            s.set_state(st.avg, st.K, st.X, st.Y, st.t)
+            s.run(1e9, 0.3, k)
+            s.get_state()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec[f"steps_{k}"] = {"ms": dt * 1e3, "dof_updates_per_s": s.dof_count() * k / dt}
+        s.close()
+        out[name] = rec
+    return out
+
+
 def _region_mean(avg, grid, box):
     """Mean primitive state of the cells whose centres lie in box = (x0, x1, y0, y1)."""
     xc, yc = grid.cell_centres()
@@ -380,6 +416,10 @@ def main():
     ap.add_argument("--ladder", action="store_true",
                     help="accuracy aid: vortex convergence ladder (256^2, 1024^2, 4096^2 to "
                          "t = 0.1), printed as JSON instead of the benchmark line")
+    ap.add_argument("--pcie", action="store_true",
+                    help="whole-job rate with the state copied in from and out to host memory "
+                         "(1 and 40 steps of the vortex), printed as JSON instead of the "
+                         "benchmark line")
     ap.add_argument("--extra", action="store_true",
                     help="throughput of the limiter workloads (2048^2 radial outflow, 8192^2 "
                          "shear layer), printed as JSON instead of the benchmark line")
@@ -414,6 +454,9 @@ def main():
 
     if args.extra:
         print(json.dumps(extra_workloads(stream)), flush=True)
+        return
+    if args.pcie:
+        print(json.dumps(pcie_inclusive(args.n, stream)), flush=True)
         return
     if args.ladder:
         print(json.dumps(accuracy_ladder([256, 1024, 4096], 0.1, stream)), flush=True)
