@@ -446,8 +446,8 @@ __device__ __forceinline__ void low_piece(R a1, R c1a, R s1a, R b1, R c1b, R s1b
 }
 
 template <class R, int KIND>
-__device__ __noinline__ int eg1_pc(const double* __restrict__ ub, int cb, const double* lin64,
-                                   R tau, const Geo<R>& G, R dU[4]) {
+__device__ __forceinline__ int eg1_pc(const double* __restrict__ ub, int cb, const double* lin64,
+                                      R tau, const Geo<R>& G, R dU[4]) {
   using MA = Math<R>;
   const R rp = R(lin64[0]), up = R(lin64[1]), vp = R(lin64[2]), pp = R(lin64[3]);
   if (!admissible(rp, pp)) return ERR_NONPHYS;
