@@ -68,12 +68,13 @@ void kb_points_f64(const GridDesc* desc, const int* tile_grid, const int* block_
   batch_points<double>(S, desc, tile_grid, block_tile, devs, dt_host);
 }
 
-// With the shock indicators (Algorithm 2, Sec. 3.4): the point kernel's indicator variant.
+// With the shock indicators (Algorithm 2, Sec. 3.4): the point kernel's indicator variant.  At
+// least two waves per SIMD: left alone, the FP64 variant takes two registers more than that
+// allows and runs one wave per SIMD.
 template <class R>
-__global__ __launch_bounds__(PT_THREADS) void kb_points_ind(const GridDesc* desc,
-                                                            const int* tile_grid,
-                                                            const int* block_tile,
-                                                            DevState* devs, double dt_host) {
+__global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+void kb_points_ind(const GridDesc* desc, const int* tile_grid, const int* block_tile,
+                   DevState* devs, double dt_host) {
   __shared__ Smem<R> S;
   __shared__ Ind I;
   __shared__ int s_g, s_cur;
