@@ -491,6 +491,7 @@ static int upload_desc(af_handle* h) {
     P.tiles_x = q.tiles_x; P.tiles_y = q.tiles_y;
     P.dx = q.dx; P.dy = q.dy; P.idx = 1.0 / q.dx; P.idy = 1.0 / q.dy;
     P.gamma = h->gamma; P.hmin = std::min(q.dx, q.dy);
+    P.g1inv = 1.0 / (h->gamma - 1.0); P.aspect = q.dx / q.dy;
     P.mode = h->mode; P.correction = h->correction; P.limiter = h->limiter; P.pad = 0;
     P.pA = q.pA; P.sA = q.pA * q.ny;
     P.pP = q.pP; P.sP = q.pP * q.nky;

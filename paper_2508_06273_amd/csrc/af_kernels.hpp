@@ -57,6 +57,7 @@ struct Params {
   int nx, ny, nkx, nky, per_x, per_y;
   int tiles_x, tiles_y;
   double dx, dy, idx, idy, gamma, hmin;
+  double g1inv, aspect;  // 1 / (gamma - 1) and dx / dy, formed on the host
   int mode, correction, limiter, pad;
   long long pA, sA;  // pitch and variable stride of the cell-average arrays (doubles)
   long long pP, sP;  // pitch and variable stride of the point-value arrays
@@ -555,7 +556,7 @@ __device__ __noinline__ void lf_update(const double* __restrict__ site, int a, i
   const int nb[5][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}};
   for (int k = 0; k < 5; ++k)
     for (int v = 0; v < 4; ++v) U[k][v] = site[v * NS + sidx(a + nb[k][0], b + nb[k][1])];
-  const double g1inv = 1.0 / (P.gamma - 1.0);
+  const double g1inv = P.g1inv;
   double Fe[4], Fw[4], Gn[4], Gs[4], Q0[4], Q[4];
   lf_flux(U[0], U[1], 0, P.gamma, g1inv, Fe);
   lf_flux(U[2], U[0], 0, P.gamma, g1inv, Fw);

@@ -187,6 +187,7 @@ static Params make_params(const af_handle* h) {
   P.tiles_y = (h->nky + TILE - 1) / TILE;
   P.dx = h->dx; P.dy = h->dy; P.idx = 1.0 / h->dx; P.idy = 1.0 / h->dy;
   P.gamma = h->gamma; P.hmin = std::min(h->dx, h->dy);
+  P.g1inv = 1.0 / (h->gamma - 1.0); P.aspect = h->dx / h->dy;
   P.mode = h->mode; P.correction = h->correction; P.limiter = h->limiter; P.pad = 0;
   P.pA = h->pA; P.sA = h->pA * h->ny;
   P.pP = h->pP; P.sP = h->pP * h->nky;

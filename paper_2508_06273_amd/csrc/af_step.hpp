@@ -271,7 +271,7 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Param
   const long long o = (long long)gj * P.pP + gi;
 #pragma unroll
   for (int v = 0; v < 4; ++v) out[v * P.sP + o] = U1[v];
-  const double g1inv = 1.0 / (P.gamma - 1.0);
+  const double g1inv = P.g1inv;
   double Fs[4], Gs[4];
   {
 #pragma clang fp contract(off)
@@ -388,7 +388,7 @@ __device__ __forceinline__ void prim_average(const Params& P, const Bufs& B, int
   const bool fx = !inflow && sx >= 0 && side_kind(P, sx) == BC_WALL;
   const bool fy = !inflow && sy >= 0 && side_kind(P, 2 + sy) == BC_WALL;
   const int ci = fx ? gi : i, cj = fy ? gj : j;
-  const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
+  const double g1inv = P.g1inv, gm1 = P.gamma - 1.0;
   double w[8][4];
   fetch_site(P, B, 0, ci, cj, w[0]);
   fetch_site(P, B, 0, ci + 1, cj, w[1]);
@@ -560,7 +560,7 @@ __device__ __forceinline__ void prep_cell(Smem<R>& S, const Params& P, const Buf
   const bool fy = !inflow && sy >= 0 && side_kind(P, 2 + sy) == BC_WALL;
   const int an = fx ? min(max(gi - i0, -1), TILE - 1) : a;
   const int bn = fy ? min(max(gj - j0, -1), TILE - 1) : b;
-  const double g1inv = 1.0 / (P.gamma - 1.0), gm1 = P.gamma - 1.0;
+  const double g1inv = P.g1inv, gm1 = P.gamma - 1.0;
   // node k of the cell: 0..3 corners K(a,b) K(a+1,b) K(a,b+1) K(a+1,b+1),
   // 4,5 X(a,b) X(a+1,b), 6,7 Y(a,b) Y(a,b+1)
   const double* nptr[8] = {S.sk + sidx(an, bn), S.sk + sidx(an + 1, bn),
@@ -614,7 +614,7 @@ __device__ __forceinline__ void prep_cell(Smem<R>& S, const Params& P, const Buf
     const bool owned = a >= 0 && b >= 0 && (i0 + a) < P.nx && (j0 + b) < P.ny;
     if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
   }
-  const double rho = P.dx / P.dy, rho2 = rho * rho;
+  const double rho = P.aspect, rho2 = rho * rho;
   // primitive Simpson average and monomial coefficients, one variable at a time
 #pragma unroll 1
   for (int v = 0; v < 4; ++v) {
