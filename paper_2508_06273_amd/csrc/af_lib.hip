@@ -101,12 +101,12 @@ __global__ __launch_bounds__(PT_THREADS) void k_fixup_ind(Params P, Bufs B, DevS
 // thread (16-byte loads), about one item per workgroup.  Kernel 3 (one thread) then commits
 // the step.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(UP_THREADS) void k_update(Params P, const double* __restrict__ A_in,
-                                                      double* __restrict__ A_out,
-                                                      const double* __restrict__ FK,
-                                                      const double* __restrict__ FX,
-                                                      const double* __restrict__ FY,
-                                                      DevState* dev, int slot) {
+// Two waves per SIMD: the register budget lets every load of a cell pair be in flight before
+// the first use (this HBM-bound kernel gains more from that than from occupancy).
+__global__ __launch_bounds__(UP_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_update(Params P, const double* __restrict__ A_in, double* __restrict__ A_out,
+              const double* __restrict__ FK, const double* __restrict__ FX,
+              const double* __restrict__ FY, DevState* dev, int slot) {
   __shared__ double red[UP_THREADS / 64];
   const bool run = !dev->err && dev->active;
   const double dt = dev->dt;

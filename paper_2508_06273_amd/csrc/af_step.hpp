@@ -779,27 +779,33 @@ __device__ __forceinline__ bool update_pair(const Params& P, const double* __res
     auto ld = [](const double* a, long long o) {
       return *reinterpret_cast<const double2*>(a + o);
     };
+    // every load first, then the arithmetic
+    double2 f0[4], f1[4], g0[4], g1[4], x[4], y0[4], y1[4], a[4];
+    double f20[4], f21[4], g20[4], x2[4], g21[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const double* fk = FK + v * P.sF;
       const double* gk = FK + (4 + v) * P.sF;
       const double* fx = FX + v * P.sF;
       const double* fy = FY + v * P.sF;
-      const double2 f0 = ld(fk, r0 + i), f1 = ld(fk, r1 + i);
-      const double2 g0 = ld(gk, r0 + i), g1 = ld(gk, r1 + i);
-      const double2 x = ld(fx, r0 + i), y0 = ld(fy, r0 + i), y1 = ld(fy, r1 + i);
-      const double2 a = ld(A_in + v * P.sA, ra + i);
-      const double f20 = fk[r0 + s2], f21 = fk[r1 + s2], g20 = gk[r0 + s2], x2 = fx[r0 + s2];
-      const double g21 = gk[r1 + s2];
-      const double Fw = f0.x + 4.0 * x.x + f1.x;
-      const double Fe = f0.y + 4.0 * x.y + f1.y;
-      const double Gs = g0.x + 4.0 * y0.x + g0.y;
-      const double Gn = g1.x + 4.0 * y1.x + g1.y;
-      Q0[v] = a.x - lx * (Fe - Fw) - ly * (Gn - Gs);
-      const double Fe1 = f20 + 4.0 * x2 + f21;
-      const double Gs1 = g0.y + 4.0 * y0.y + g20;
-      const double Gn1 = g1.y + 4.0 * y1.y + g21;
-      Q1[v] = a.y - lx * (Fe1 - Fe) - ly * (Gn1 - Gs1);
+      f0[v] = ld(fk, r0 + i); f1[v] = ld(fk, r1 + i);
+      g0[v] = ld(gk, r0 + i); g1[v] = ld(gk, r1 + i);
+      x[v] = ld(fx, r0 + i); y0[v] = ld(fy, r0 + i); y1[v] = ld(fy, r1 + i);
+      a[v] = ld(A_in + v * P.sA, ra + i);
+      f20[v] = fk[r0 + s2]; f21[v] = fk[r1 + s2]; g20[v] = gk[r0 + s2]; x2[v] = fx[r0 + s2];
+      g21[v] = gk[r1 + s2];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double Fw = f0[v].x + 4.0 * x[v].x + f1[v].x;
+      const double Fe = f0[v].y + 4.0 * x[v].y + f1[v].y;
+      const double Gs = g0[v].x + 4.0 * y0[v].x + g0[v].y;
+      const double Gn = g1[v].x + 4.0 * y1[v].x + g1[v].y;
+      Q0[v] = a[v].x - lx * (Fe - Fw) - ly * (Gn - Gs);
+      const double Fe1 = f20[v] + 4.0 * x2[v] + f21[v];
+      const double Gs1 = g0[v].y + 4.0 * y0[v].y + g20[v];
+      const double Gn1 = g1[v].y + 4.0 * y1[v].y + g21[v];
+      Q1[v] = a[v].y - lx * (Fe1 - Fe) - ly * (Gn1 - Gs1);
       *reinterpret_cast<double2*>(A_out + v * P.sA + ra + i) = make_double2(Q0[v], Q1[v]);
     }
   } else {
