@@ -1,0 +1,145 @@
+"""Accuracy of the HIP path: element by element against the oracle on the 256^2 vortex, the
+vortex convergence ladder, and the paper's Tables 1 and 2 reproduced by the GPU path itself.
+
+Every run goes through the C ABI.  Achieved maxima are printed next to the gates.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_06273_amd import inputs as I
+from conftest import load_table
+
+pytestmark = pytest.mark.gpu
+
+af = pytest.importorskip("paper_2508_06273_amd.af")
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(st, prec, t_end, cfl, mode=0, correction=True, max_steps=0):
+    s = af.Solver.for_state(st, precision=prec, linearisation=mode, correction=correction)
+    t, n = s.run(t_end, cfl, max_steps)
+    out = s.get_state()
+    s.close()
+    return out, t, n
+
+
+_VORTEX256 = {}
+
+
+def _vortex256_oracle():
+    """The FP64 oracle on the 256^2 vortex to t = 0.25 (Algorithm 1 with C, CFL 0.3)."""
+    if not _VORTEX256:
+        st = I.shu_vortex(256, n_gl=3)
+        ref = st.copy()
+        e, n, _ = oracle.run(ref, 0.25, 0.3)
+        assert e == 0
+        _VORTEX256.update(st=st, ref=ref, steps=n)
+    return _VORTEX256["st"], _VORTEX256["ref"], _VORTEX256["steps"]
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
+def test_vortex256_elementwise_against_oracle(prec, tol):
+    """Config 2 at 256^2 to t = 0.25 (63 steps; the growing mode of the near-sonic background
+    limits how far the vortex can run): every average and point value against the FP64
+    oracle, absolute Linf <= 1e-9 in FP64 and <= 1e-5 in FP32 bulk."""
+    _flush(f"[gpu] vortex 256^2 to t=0.25 element-wise prec={prec}")
+    st, ref, steps = _vortex256_oracle()
+    out, t, n = _run(st, prec, 0.25, 0.3)
+    assert n == steps and t == 0.25
+    d = {k: float(np.abs(out[k] - getattr(ref, k)).max()) for k in ("avg", "K", "X", "Y")}
+    _flush(f"    achieved Linf {d} (gate {tol:g})")
+    assert max(d.values()) <= tol, d
+
+
+def _window_l1(avg, ex, grid):
+    n = grid.nx
+    lo, hi = n // 4, 3 * n // 4
+    d = np.abs(avg - ex)[:, lo:hi, lo:hi]
+    return d.reshape(4, -1).sum(axis=1) * grid.dx * grid.dy
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_vortex_ladder_third_order(prec):
+    """The vortex to t = 0.1 at 256^2, 512^2, 1024^2 (Algorithm 1 with C, CFL 0.3): the L1 error
+    of every conserved variable on the window [2.5, 7.5]^2 against the exact translated vortex
+    falls at third order (EOC >= 2.8) in both precisions."""
+    errs = []
+    for n in (256, 512, 1024):
+        _flush(f"[gpu] vortex ladder {n}^2 prec={prec}")
+        st = I.shu_vortex(n, n_gl=3)
+        out, t, _ = _run(st, prec, 0.1, 0.3)
+        assert t == 0.1
+        ex = I.cell_average(I.shu_vortex_field(0.1), st.grid, n_gl=4)
+        errs.append(_window_l1(out["avg"], ex, st.grid))
+    errs = np.array(errs)
+    eoc = np.log2(errs[:-1] / errs[1:])
+    _flush(f"    window L1 {errs.tolist()} EOC {eoc.tolist()}")
+    assert np.all(eoc >= 2.8), (errs, eoc)
+
+
+def _ex1_errors_gpu(prec, mode, correction, sizes):
+    sols = {}
+    for nx in sorted(set(sizes) | {2 * n for n in sizes}):
+        st = I.ex1_state(nx, ny=2)
+        out, t, _ = _run(st, prec, 0.25, 0.279, mode, correction)
+        assert t == 0.25
+        sols[nx] = out["avg"]
+    err = []
+    for nx in sizes:
+        c = sols[nx][0].mean(axis=0)
+        f = sols[2 * nx][0].mean(axis=0)
+        err.append(np.abs(c - 0.5 * (f[0::2] + f[1::2])).sum() / nx)
+    return np.array(err)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("col,mode,correction", [(1, 0, True), (2, 0, False), (3, 2, True)])
+def test_table1_on_gpu(golden_dir, prec, col, mode, correction):
+    """Table 1 (Example 1, t = 0.25, errors against the solution on twice as many cells) from 32
+    to 1024 cells by the GPU path, CFL 0.279 (the paper does not state its CFL): magnitudes
+    within 10 %, EOCs within 0.05 up to 256 cells; beyond, within 0.1."""
+    tab = {int(r[0]): r for r in load_table(f"{golden_dir}/table1_ex1.txt")}
+    sizes = [32, 64, 128, 256, 512, 1024]
+    _flush(f"[gpu] table 1 column {col} prec={prec}")
+    err = _ex1_errors_gpu(prec, mode, correction, sizes)
+    paper = np.array([tab[n][col] for n in sizes])
+    eoc = np.log2(err[:-1] / err[1:])
+    peoc = np.log2(paper[:-1] / paper[1:])
+    _flush(f"    L1 {err.tolist()}\n    ratio to paper {(err / paper).tolist()}\n"
+           f"    EOC {eoc.tolist()} paper {peoc.tolist()}")
+    assert np.all(np.abs(err / paper - 1.0) < 0.10), (err, paper)
+    assert np.all(np.abs(eoc[:3] - peoc[:3]) < 0.05), (eoc, peoc)
+    assert np.all(np.abs(eoc - peoc) < 0.1), (eoc, peoc)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_table2_on_gpu(golden_dir, prec):
+    """Table 2 (Example 2, t = 1, exact solution = initial data), Algorithm 1 with C, from 32^2
+    to 512^2 by the GPU path at CFL 0.279: magnitudes within 25 %, EOCs within 0.05."""
+    tab = {int(r[0]): r for r in load_table(f"{golden_dir}/table2_ex2.txt")}
+    sizes = [32, 64, 128, 256, 512]
+    err = []
+    for n in sizes:
+        _flush(f"[gpu] table 2 {n}^2 prec={prec}")
+        st = I.ex2_state(n, n_gl=6)
+        out, t, _ = _run(st, prec, 1.0, 0.279)
+        assert t == 1.0
+        ex = I.cell_average(I.ex2_field(1.0), st.grid, conserved=True, n_gl=6)
+        l1, _ = I.norms(out["avg"], ex, st.grid)
+        err.append(l1[0])
+    err = np.array(err)
+    paper = np.array([tab[n][1] for n in sizes])
+    eoc = np.log2(err[:-1] / err[1:])
+    peoc = np.log2(paper[:-1] / paper[1:])
+    _flush(f"    L1 {err.tolist()}\n    ratio to paper {(err / paper).tolist()}\n"
+           f"    EOC {eoc.tolist()} paper {peoc.tolist()}")
+    assert np.all(np.abs(err / paper - 1.0) < 0.25), (err, paper)
+    assert np.all(np.abs(eoc - peoc) < 0.05), (eoc, peoc)

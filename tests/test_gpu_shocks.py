@@ -28,6 +28,8 @@ def _flush(msg):
 def _assert_close(out, ref, tol, label=""):
     scale = max(float(np.abs(ref.avg).max()), float(np.abs(ref.K).max()))
     d = {k: float(np.abs(out[k] - getattr(ref, k)).max()) for k in ("avg", "K", "X", "Y")}
+    print(f"    {label}: achieved max|diff|/scale {max(d.values()) / scale:.3e} (gate {tol:g})",
+          flush=True)
     bad = {k: v for k, v in d.items() if v > tol * scale}
     assert not bad, f"{label}: {d} (tol {tol * scale:.3e})"
 

@@ -687,7 +687,7 @@ def test_eg1_pc_matches_brute_force(lin):
 # compared with Corollary 1 evaluated at the exact derivatives of a smooth field: the
 # difference must fall at second order (a wrong spacing, sign or stencil direction is O(1)).
 # ------------------------------------------------------------------------------------------
-def _smooth_field():
+def _smooth_field_c():
     tp = 2 * math.pi
 
     def fn(x, y):
@@ -699,7 +699,7 @@ def _smooth_field():
 
 
 def test_correction_derivative_stencils_second_order():
-    fn = _smooth_field()
+    fn = _smooth_field_c()
     dt_over_h = 0.1
     errs = {kind: [] for kind in (oracle.KIND_K, oracle.KIND_X, oracle.KIND_Y)}
     scale = None
