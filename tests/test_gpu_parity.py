@@ -3,8 +3,8 @@
 Tolerances: the FP64 path and the oracle evaluate the same formulas in different orders and
 with different exact circle integrations (trigonometric moments vs. Gauss-Legendre), so they
 agree to rounding: |diff| <= 1e-12 * scale after the step counts used here.  The FP32 path
-evaluates the evolution operators in FP32 on FP64 deviations; its tolerance is 2e-5 * scale after one
-step and 1e-4 * scale after 20.
+evaluates the evolution operators in FP32 on FP64 deviations; its tolerance is 1e-6 * scale (the
+largest difference measured over these tests is 8e-8 * scale), and 1e-5 absolute on config 1.
 """
 import math
 import sys
@@ -115,7 +115,7 @@ def test_single_step_fp32_bulk():
     s.step(dt)
     out = s.get_state()
     e, _ = oracle.step(st, dt)
-    assert_close(out, st, 2e-5, "fp32 step")
+    assert_close(out, st, 1e-6, "fp32 step")
 
 
 # ------------------------------------------------------------------------------------------
@@ -337,7 +337,7 @@ def _check_patch_dofs(out, full_grid, p, i0, j0, cells, tol, scale, margin=2):
         assert abs(out["Y"][:, gj, gi] - p.Y[:, pj, pi_]).max() < tol * scale
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
 def test_full_size_vortex_sampled(prec, tol):
     n = 4096
     _flush(f"[gpu] full-size {n}^2 sampled parity prec={prec}")
@@ -366,7 +366,7 @@ def _sampled_cells(g, rng, k=6):
     return fixed + [tuple(int(v) for v in rng.integers(0, [nx, ny])) for _ in range(k)]
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
 def test_full_size_radial_outflow_sampled(prec, tol):
     """The positivity stress workload at its full size (2048^2, outflow, averaged
     linearisation, limiter on): one step compared with the oracle on patches at the corners,
@@ -403,7 +403,7 @@ def test_full_size_radial_outflow_sampled(prec, tol):
 _SHEAR = {}  # the 8192^2 input, generated once for both precisions
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
 def test_full_size_shear_layer_sampled(prec, tol):
     """The large shear layer at its full size (8192^2 periodic, averaged linearisation,
     limiter on): one step compared with the oracle on patches across both jumps, at the
@@ -430,7 +430,7 @@ def test_full_size_shear_layer_sampled(prec, tol):
         _check_patch_dofs(out, st.grid, p, i0, j0, near, tol, 8.0)
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
 def test_full_size_shear_layer_indicators_sampled(prec, tol):
     """The large shear layer at its full size with Algorithm 2 and the shock-indicator blend on
     (as timed by the benchmark's extra workloads): two steps (the blend acts from the second,
@@ -485,15 +485,13 @@ def test_vortex_error_matches_oracle(golden_dir):
     """The vortex accuracy gate: after t = 0.25 at 128^2 and 256^2 (Algorithm 1, CFL 0.3), the
     FP64 path's L1 error against the exact translated vortex equals the FP64 oracle's error
     (tests/golden/vortex_t025_oracle.txt, written by make_vortex_t025.py from the oracle) to
-    1e-5 relative; the FP32-bulk path's error differs from it by at most 1e-5 of the L1 norm of
-    the solution."""
+    1e-5 relative; the FP32-bulk path's error equals it to 1e-2 relative."""
     from conftest import load_table
     tab = {int(r[0]): r for r in load_table(f"{golden_dir}/vortex_t025_oracle.txt")}
     for n in (128, 256):
         st = I.shu_vortex(n, n_gl=3)
         ex = I.cell_average(I.shu_vortex_field(0.25), st.grid, n_gl=3)
         ref_l1 = np.array(tab[n][2:6])
-        norm_l1 = np.abs(ex).reshape(4, -1).sum(axis=1) * st.grid.dx * st.grid.dy
         for prec in (0, 1):
             _flush(f"[gpu] vortex {n}^2 to t=0.25 prec={prec}")
             s = gpu_state(st, prec)
@@ -501,13 +499,13 @@ def test_vortex_error_matches_oracle(golden_dir):
             assert t == 0.25 and steps == int(tab[n][1])
             l1, _ = I.norms(s.get_state()["avg"], ex, st.grid)
             s.close()
-            if prec == 0:
-                assert np.all(np.abs(l1 - ref_l1) <= 1e-5 * ref_l1), (n, l1, ref_l1)
-            else:
-                assert np.all(np.abs(l1 - ref_l1) <= 1e-5 * norm_l1), (n, l1, ref_l1)
+            rel = np.abs(l1 - ref_l1) / ref_l1
+            _flush(f"    L1 {l1.tolist()} oracle {ref_l1.tolist()} relative difference "
+                   f"{rel.tolist()}")
+            assert np.all(rel <= (1e-5 if prec == 0 else 1e-2)), (n, prec, l1, ref_l1)
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-4)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
 @pytest.mark.parametrize("dims", [(16, 12, 1.0, 3.0), (10, 24, 2.5, 0.6)])
 def test_anisotropic_cells(prec, tol, dims):
     """Cells with dy = 4 dx and dx = 10 dy: the circle integrals use dx as the unit length in
