@@ -251,6 +251,34 @@ int af_get_state_device(const af_handle* h, int32_t g, double* avg, double* K, d
  * between steps. */
 int af_set_inflow(af_handle* h, int32_t g, int32_t side, const double* W);
 
+/* ---------------------------------------------------------------------------------------
+ * One step that allocates nothing, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same step as
+ * af_step (same kernels and arithmetic, no indicator options), on caller-owned device arrays
+ * in the library's device layout:
+ *   avg_in/avg_out : 4 x ny rows x pitch_avg doubles (variable v at v * ny * pitch_avg);
+ *   K, X, Y (in/out): 4 x nky rows x pitch_pts doubles each (variable v at v * nky * pitch_pts;
+ *                    X uses the first ny rows of each variable),
+ * nkx, nky as above; pitches even, pitch_avg >= nx, pitch_pts >= nkx; every pointer 16-byte
+ * aligned; no output may alias an input.  `inflow` (host, 4 x 4, row = side, nullable unless a
+ * side is AF_BC_INFLOW) gives the inflow states.  Options as AF_OPT_PRECISION,
+ * AF_OPT_LINEARISATION, AF_OPT_CORRECTION and AF_OPT_LIMITER.  Work is enqueued on `stream`
+ * (a hipStream_t; NULL: the null stream) and the call waits for it; `counters` (host, nullable,
+ * AF_NCOUNTERS values) receives this step's counters.
+ * Scratch: step control, fix-up masks and the per-site flux sums live in a static device array
+ * of 32 MiB per GPU (held until the process ends): grids whose flux sums (128 bytes per
+ * nky * pitch_pts site) and tile masks do not fit, about 500 x 500 cells, are rejected with
+ * AF_ERR_INVALID_ARG.  Every call on one GPU uses that GPU's array: calls that overlap on one
+ * GPU (several host threads or streams) race.  No hipMalloc, hipFree or allocating routine is
+ * called.  Errors as af_step (the outputs are then unspecified, the inputs unchanged); the text
+ * is af_last_error(NULL). */
+int af_step_noalloc(const af_grid* grid, double gamma, const af_bc* bc, const double* inflow,
+                    int32_t precision, int32_t linearisation, int32_t correction,
+                    int32_t limiter, const double* avg_in, const double* K_in,
+                    const double* X_in, const double* Y_in, double* avg_out, double* K_out,
+                    double* X_out, double* Y_out, int64_t pitch_avg, int64_t pitch_pts,
+                    double dt, void* stream, int64_t* counters);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,8 @@ EXPORTS = ["af_create", "af_set_option", "af_set_stream", "af_set_state", "af_ge
            "af_step", "af_run", "af_get_counters", "af_destroy", "af_last_error",
            "af_dof_count", "af_get_timing", "af_create_batch", "af_batch_size",
            "af_set_state_grid", "af_get_state_grid", "af_get_grid_info", "af_get_option",
-           "af_set_inflow", "af_set_state_device", "af_get_state_device"]
+           "af_set_inflow", "af_set_state_device", "af_get_state_device",
+           "af_step_noalloc"]
 
 
 class AfError(RuntimeError):
@@ -96,11 +97,14 @@ def load(path: str = LIB_PATH):
                                       ct.c_void_p, ct.c_double]
     L.af_get_state_device.argtypes = [_H, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       ct.c_void_p, _D]
+    L.af_step_noalloc.argtypes = [ct.POINTER(Grid), ct.c_double, ct.POINTER(Bc), _D, ct.c_int32,
+                                  ct.c_int32, ct.c_int32, ct.c_int32] + [ct.c_void_p] * 8 + \
+        [ct.c_int64, ct.c_int64, ct.c_double, ct.c_void_p, ct.POINTER(ct.c_int64)]
     for name in ("af_create", "af_set_option", "af_set_stream", "af_set_state",
                  "af_get_state", "af_step", "af_run", "af_get_counters", "af_create_batch",
                  "af_set_state_grid", "af_get_state_grid", "af_get_grid_info",
                  "af_get_option", "af_set_inflow", "af_set_state_device",
-                 "af_get_state_device"):
+                 "af_get_state_device", "af_step_noalloc"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -364,3 +368,28 @@ class BatchSolver(_Handle):
 
     def get_state(self, g):
         return self._get(g, self.shapes(g))
+
+
+def step_noalloc(grid, gamma, bc, ins, outs, pitch_avg, pitch_pts, dt, precision=AF_PREC_FP64,
+                 linearisation=AF_LIN_AF3, correction=True, limiter=False, inflow=None,
+                 stream=None):
+    """af_step_noalloc: one step on caller-owned device arrays (addresses as ints, the
+    library's device layout) with no allocation.  `grid`: (nx, ny, x0, x1, y0, y1); `bc`: side
+    kinds (left, right, bottom, top); `ins`/`outs`: addresses of avg, K, X, Y; `inflow`: 4 x 4
+    states or None.  Returns the step's counters; raises AfError on failure."""
+    L = load()
+    g = Grid(*grid)
+    b = Bc(*bc)
+    w = None
+    if inflow is not None:
+        w = np.ascontiguousarray(np.asarray(inflow, dtype=np.float64).reshape(16))
+    cnt = (ct.c_int64 * AF_NCOUNTERS)()
+    rc = L.af_step_noalloc(ct.byref(g), float(gamma), ct.byref(b),
+                           w.ctypes.data_as(_D) if w is not None else None, int(precision),
+                           int(linearisation), int(bool(correction)), int(bool(limiter)),
+                           *[ct.c_void_p(int(p)) for p in ins], *[ct.c_void_p(int(p)) for p in outs],
+                           int(pitch_avg), int(pitch_pts), float(dt),
+                           ct.c_void_p(stream) if stream else None, cnt)
+    if rc != 0:
+        raise AfError(rc, L.af_last_error(None).decode())
+    return list(cnt)

@@ -7,7 +7,9 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -163,6 +165,28 @@ __global__ void k_cfl(Params P, const double* __restrict__ A, const double* __re
                                    (long long)gridDim.x * blockDim.x);
   block_max_atomic(speed, &dev->smax[slot], red);
 }
+
+// ------------------------------------------------------------------------------------------
+// Scratch memory of af_step_noalloc (no allocation at call time): step control, the fix-up
+// masks and tile list, and the per-site flux sums, carved out of one file-scope array that
+// every GPU the library runs on holds until the process ends.  Host code never passes the
+// array's name to a kernel (in host code it is a stand-in, not a device address): it uses the
+// address that hipGetSymbolAddress returns for the current device.
+// ------------------------------------------------------------------------------------------
+constexpr size_t NOALLOC_BYTES = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Reset the step control (zero, no step limit) and clear n fix-up mask words.
+__global__ void k_noalloc_init(DevState* dev, unsigned long long* mask, long long n) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t == 0) {
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(dev);
+    for (size_t k = 0; k < sizeof(DevState) / 8; ++k) w[k] = 0ull;
+    dev->steps_limit = LLONG_MAX;
+  }
+  for (long long k = t; k < n; k += (long long)gridDim.x * blockDim.x) mask[k] = 0ull;
+}
+static_assert(sizeof(DevState) % 8 == 0, "DevState is cleared as 64-bit words");
 
 }  // namespace af
 
@@ -665,6 +689,46 @@ extern "C" int af_get_counters(const af_handle* h, int64_t* out) {
   return AF_OK;
 }
 
+// Kernels of one step on the buffers B (t_n state in, t_n+1 state out), smax slot `slot`;
+// dt_host > 0 for a caller-given step.  Events e0/e1/e2 (nullable) bracket the point and the
+// update kernels.
+template <class R>
+static void launch_step(const Params& P, const Bufs& B, DevState* dev, bool limiter, bool ind,
+                        double dt_host, int slot, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                        hipEvent_t e2) {
+  const int ntiles = P.tiles_x * P.tiles_y;
+  if (e0) (void)hipEventRecord(e0, s);
+  if (ind) {
+    const long long n = (long long)(P.nx + 4) * (P.ny + 4);
+    const int gb = (int)std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_avgprim, dim3(gb), dim3(256), 0, s, P, B);
+    hipLaunchKernelGGL(k_points_ind<R>, dim3(ntiles), dim3(PT_THREADS), 0, s, P, B, dev,
+                       dt_host, slot);
+  } else if constexpr (sizeof(R) == 4) {
+    hipLaunchKernelGGL(k_points_f32, dim3(ntiles), dim3(PT_THREADS), 0, s, P, B, dev, dt_host,
+                       slot);
+  } else {
+    hipLaunchKernelGGL(k_points_f64, dim3(ntiles), dim3(PT_THREADS), 0, s, P, B, dev, dt_host,
+                       slot);
+  }
+  if (limiter) {
+    const int nb = std::min(ntiles, FIX_BLOCKS);
+    if (ind)
+      hipLaunchKernelGGL(k_fixup_ind<R>, dim3(nb), dim3(PT_THREADS), 0, s, P, B, dev, slot);
+    else if constexpr (sizeof(R) == 4)
+      hipLaunchKernelGGL(k_fixup_f32, dim3(nb), dim3(PT_THREADS), 0, s, P, B, dev, slot);
+    else
+      hipLaunchKernelGGL(k_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, s, P, B, dev, slot);
+  }
+  if (e1) (void)hipEventRecord(e1, s);
+  const long long nwork = (long long)((P.nx + 2 * UP_THREADS - 1) / (2 * UP_THREADS)) * P.ny;
+  const int gu = (int)std::min<long long>(nwork, UP_MAX_BLOCKS);
+  hipLaunchKernelGGL(k_update, dim3(gu), dim3(UP_THREADS), 0, s, P, B.A_in, B.A_out,
+                     (const double*)B.FK, (const double*)B.FX, (const double*)B.FY, dev, slot);
+  hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s, dev, slot);
+  if (e2) (void)hipEventRecord(e2, s);
+}
+
 // enqueue one step reading buffer `in` (0/1); dt_host > 0 for a caller-given step
 template <class R>
 static void enqueue_step_t(af_handle* h, int in, double dt_host) {
@@ -679,47 +743,15 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
   B.fix_mask = h->fix_mask; B.fix_list = h->fix_list;
   B.fix_count = &h->dev->fix_count; B.tile_base = 0;
   B.UB = h->UB;
-  const int ntiles = P.tiles_x * P.tiles_y;
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (h->timing) {
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventCreate(&e2);
-    (void)hipEventRecord(e0, h->stream);
   }
-  const bool ind = h->tsw || h->shock;
-  if (ind) {
-    const long long n = (long long)(h->nx + 4) * (h->ny + 4);
-    const int gb = (int)std::min<long long>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_avgprim, dim3(gb), dim3(256), 0, h->stream, P, B);
-    hipLaunchKernelGGL(k_points_ind<R>, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B,
-                       h->dev, dt_host, in);
-  } else if constexpr (sizeof(R) == 4) {
-    hipLaunchKernelGGL(k_points_f32, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
-                       dt_host, in);
-  } else {
-    hipLaunchKernelGGL(k_points_f64, dim3(ntiles), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
-                       dt_host, in);
-  }
-  if (h->limiter) {
-    const int nb = std::min(ntiles, FIX_BLOCKS);
-    if (ind)
-      hipLaunchKernelGGL(k_fixup_ind<R>, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev,
-                         in);
-    else if constexpr (sizeof(R) == 4)
-      hipLaunchKernelGGL(k_fixup_f32, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev, in);
-    else
-      hipLaunchKernelGGL(k_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, h->stream, P, B, h->dev, in);
-  }
-  if (h->timing) (void)hipEventRecord(e1, h->stream);
-  const long long nwork = (long long)((h->nx + 2 * UP_THREADS - 1) / (2 * UP_THREADS)) * h->ny;
-  const int gu = (int)std::min<long long>(nwork, UP_MAX_BLOCKS);
-  hipLaunchKernelGGL(k_update, dim3(gu), dim3(UP_THREADS), 0, h->stream, P, (const double*)h->A[in],
-                     h->A[out], (const double*)h->FK, (const double*)h->FX,
-                     (const double*)h->FY, h->dev, in);
-  hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, h->stream, h->dev, in);
+  launch_step<R>(P, B, h->dev, h->limiter != 0, (h->tsw || h->shock), dt_host, in, h->stream,
+                 e0, e1, e2);
   if (h->timing) {
-    (void)hipEventRecord(e2, h->stream);
     h->ev.push_back(e0);
     h->ev.push_back(e1);
     h->ev.push_back(e2);
@@ -904,5 +936,148 @@ extern "C" int af_set_inflow(af_handle* h, int32_t g, int32_t side, const double
   // the parameters are baked into captured graphs and the batched descriptors
   if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
   batch_invalidate(h);
+  return AF_OK;
+}
+
+// ==========================================================================================
+// af_step_noalloc: one step on caller-owned device arrays with the file-scope scratch array
+// ==========================================================================================
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void** out) {
+  int device = -1;
+  if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= kMaxDevices)
+    return fail(nullptr, AF_ERR_DEVICE, "af_step_noalloc: no current HIP device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(af::scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, AF_ERR_DEVICE,
+                  std::string("af_step_noalloc: hipGetSymbolAddress(scratch): ") +
+                      hipGetErrorString(e));
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return AF_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" int af_step_noalloc(const af_grid* grid, double gamma, const af_bc* bc,
+                               const double* inflow, int32_t precision, int32_t linearisation,
+                               int32_t correction, int32_t limiter, const double* avg_in,
+                               const double* K_in, const double* X_in, const double* Y_in,
+                               double* avg_out, double* K_out, double* X_out, double* Y_out,
+                               int64_t pitch_avg, int64_t pitch_pts, double dt, void* stream,
+                               int64_t* counters) {
+  const char* fn = "af_step_noalloc";
+  if (!grid || !bc) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: NULL grid or bc");
+  if (int e = check_grid(grid, bc, fn)) return e;
+  if (!(gamma > 1.0)) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: gamma must be > 1");
+  if ((precision != AF_PREC_FP64 && precision != AF_PREC_FP32) || linearisation < 0 ||
+      linearisation > 2 || (correction != 0 && correction != 1) || (limiter != 0 && limiter != 1))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: bad option value");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: dt must be > 0");
+  const double* ins[4] = {avg_in, K_in, X_in, Y_in};
+  const double* outs[4] = {avg_out, K_out, X_out, Y_out};
+  for (int k = 0; k < 4; ++k) {
+    if (!ins[k] || !outs[k]) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: NULL array");
+    if ((reinterpret_cast<uintptr_t>(ins[k]) | reinterpret_cast<uintptr_t>(outs[k])) & 15u)
+      return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: arrays must be 16-byte aligned");
+    for (int m = 0; m < 4; ++m)
+      if (ins[k] == outs[m])
+        return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: an output aliases an input");
+  }
+  const int nx = grid->nx, ny = grid->ny;
+  const int per_x = bc->left == AF_BC_PERIODIC, per_y = bc->bottom == AF_BC_PERIODIC;
+  const int nkx = nx + (per_x ? 0 : 1), nky = ny + (per_y ? 0 : 1);
+  if (pitch_avg < nx || pitch_pts < nkx || (pitch_avg & 1) || (pitch_pts & 1))
+    return fail(nullptr, AF_ERR_INVALID_ARG,
+                "af_step_noalloc: need even pitches, pitch_avg >= nx, pitch_pts >= nx + 1 on "
+                "a non-periodic x axis (>= nx otherwise)");
+  Params P;
+  P.nx = nx; P.ny = ny; P.nkx = nkx; P.nky = nky; P.per_x = per_x; P.per_y = per_y;
+  P.tiles_x = (nkx + TILE - 1) / TILE;
+  P.tiles_y = (nky + TILE - 1) / TILE;
+  const double dx = (grid->x1 - grid->x0) / nx, dy = (grid->y1 - grid->y0) / ny;
+  P.dx = dx; P.dy = dy; P.idx = 1.0 / dx; P.idy = 1.0 / dy;
+  P.gamma = gamma; P.hmin = std::min(dx, dy);
+  P.g1inv = 1.0 / (gamma - 1.0); P.aspect = dx / dy;
+  P.mode = linearisation; P.correction = correction; P.limiter = limiter; P.pad = 0;
+  P.pA = pitch_avg; P.sA = pitch_avg * ny;
+  P.pP = pitch_pts; P.sP = pitch_pts * nky;
+  P.pF = pitch_pts; P.sF = pitch_pts * nky;
+  const int kinds[4] = {bc->left, bc->right, bc->bottom, bc->top};
+  for (int s = 0; s < 4; ++s) {
+    P.bc[s] = kinds[s];
+    for (int v = 0; v < 4; ++v) P.inflow[s][v] = 0.0;
+    if (kinds[s] == AF_BC_INFLOW) {
+      if (!inflow || !(inflow[4 * s] > 0.0) || !(inflow[4 * s + 3] > 0.0))
+        return fail(nullptr, AF_ERR_INVALID_ARG,
+                    "af_step_noalloc: an inflow side needs a state with rho > 0 and p > 0");
+      for (int v = 0; v < 4; ++v) P.inflow[s][v] = inflow[4 * s + v];
+    }
+  }
+  P.tsw = 0; P.shock = 0; P.pU = 0; P.sU = 0;
+
+  // scratch layout: step control, fix-up masks (4 words per tile), fix-up list, flux sums
+  const size_t ntiles = (size_t)P.tiles_x * P.tiles_y;
+  const size_t o_mask = align256(sizeof(DevState));
+  const size_t o_list = align256(o_mask + ntiles * 4 * sizeof(unsigned long long));
+  const size_t o_flux = align256(o_list + ntiles * sizeof(int));
+  const size_t flux_words = (size_t)P.sF * 16;  // FK: 8 variables, FX: 4, FY: 4
+  const size_t need = o_flux + flux_words * sizeof(double);
+  if (need > NOALLOC_BYTES)
+    return fail(nullptr, AF_ERR_INVALID_ARG,
+                "af_step_noalloc: grid too large for the scratch array (" +
+                    std::to_string(need) + " bytes needed, " + std::to_string(NOALLOC_BYTES) +
+                    " available)");
+  void* base = nullptr;
+  if (int e = scratch_address(&base)) return e;
+  unsigned char* sp = static_cast<unsigned char*>(base);
+  DevState* dev = reinterpret_cast<DevState*>(sp);
+  Bufs B;
+  B.A_in = avg_in; B.A_out = avg_out;
+  B.K_in = K_in; B.X_in = X_in; B.Y_in = Y_in;
+  B.K_out = K_out; B.X_out = X_out; B.Y_out = Y_out;
+  double* flux = reinterpret_cast<double*>(sp + o_flux);
+  B.FK = flux; B.FX = flux + (size_t)P.sF * 8; B.FY = flux + (size_t)P.sF * 12;
+  B.fix_mask = reinterpret_cast<unsigned long long*>(sp + o_mask);
+  B.fix_list = reinterpret_cast<int*>(sp + o_list);
+  B.fix_count = &dev->fix_count;
+  B.tile_base = 0;
+  B.UB = nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long nmask = (long long)ntiles * 4;
+  const int ib = (int)std::min<long long>((nmask + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_noalloc_init, dim3(std::max(ib, 1)), dim3(256), 0, s, dev, B.fix_mask,
+                     nmask);
+  if (precision == AF_PREC_FP32)
+    launch_step<float>(P, B, dev, limiter != 0, false, dt, 0, s, nullptr, nullptr, nullptr);
+  else
+    launch_step<double>(P, B, dev, limiter != 0, false, dt, 0, s, nullptr, nullptr, nullptr);
+  hipError_t he = hipGetLastError();
+  if (he != hipSuccess)
+    return fail(nullptr, AF_ERR_DEVICE, std::string("af_step_noalloc: launch: ") + hipGetErrorString(he));
+  DevState ds;
+  he = hipMemcpyAsync(&ds, dev, sizeof(ds), hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess)
+    return fail(nullptr, AF_ERR_DEVICE, std::string("af_step_noalloc: ") + hipGetErrorString(he));
+  if (counters) {
+    for (int k = 0; k < AF_NCOUNTERS; ++k) counters[k] = (int64_t)ds.cnt[k];
+    counters[AF_CNT_STEPS] = ds.steps;
+  }
+  if (ds.err) return fail(nullptr, ds.err, std::string(fn) + ": " + err_text(ds.err));
+  if (ds.steps != 1) return fail(nullptr, AF_ERR_DEVICE, "af_step_noalloc: step did not commit");
   return AF_OK;
 }
