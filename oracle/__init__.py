@@ -39,7 +39,7 @@ class Cfg(ct.Structure):
                 ("per_x", ct.c_int), ("per_y", ct.c_int), ("mode", ct.c_int),
                 ("correction", ct.c_int), ("limiter", ct.c_int), ("gl_n", ct.c_int),
                 ("nthreads", ct.c_int), ("bc", ct.c_int * 4), ("inflow", (ct.c_double * 4) * 4),
-                ("tsw", ct.c_int), ("shock", ct.c_int)]
+                ("tsw", ct.c_int), ("shock", ct.c_int), ("flux_limiter", ct.c_int)]
 
 
 FIELD_CB = ct.CFUNCTYPE(None, ct.c_double, ct.c_double, ct.POINTER(ct.c_double))
@@ -88,6 +88,8 @@ def lib():
             L.or_eg_cb.argtypes = [ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.c_int, _D,
                                    ct.c_double, ct.c_double, FIELD_CB, ct.c_int, _D]
             L.or_eg_cb.restype = ct.c_int
+            L.or_flux_theta.argtypes = [_D, _D, ct.c_double]
+            L.or_flux_theta.restype = ct.c_double
             _lib = L
     return _lib
 
@@ -102,8 +104,9 @@ def _v(x) -> np.ndarray:
 
 
 def cfg_for(state, mode=MODE_AF3, correction=True, limiter=False, gl_n=10, nthreads=0,
-            tsw=False, shock=False) -> Cfg:
-    """tsw: Algorithm 2; shock: the shock-indicator blend of Sec. 3.4."""
+            tsw=False, shock=False, flux_limiter=False) -> Cfg:
+    """tsw: Algorithm 2; shock: the shock-indicator blend of Sec. 3.4; flux_limiter: flux
+    limiting of the cell averages (Sec. 3.5)."""
     g = state.grid
     c = Cfg(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy, state.gamma, int(g.bc_x == 0),
             int(g.bc_y == 0), mode, int(correction), int(limiter), gl_n, nthreads)
@@ -115,6 +118,7 @@ def cfg_for(state, mode=MODE_AF3, correction=True, limiter=False, gl_n=10, nthre
                 c.inflow[s][v] = float(w[v])
     c.tsw = int(bool(tsw))
     c.shock = int(bool(shock))
+    c.flux_limiter = int(bool(flux_limiter))
     return c
 
 
@@ -253,3 +257,8 @@ def eg_field(order, xb, yb, vline, hline, lin, tau, field, gamma=1.4, gl_n=10):
     e = lib().or_eg_cb(order, xb, yb, int(vline), int(hline), _p(_v(lin)), float(tau), gamma,
                        f, gl_n, _p(o))
     return e, o
+
+
+def flux_theta(Qlo, d, gamma=1.4):
+    """Sec. 3.5: largest theta in [0, 1] with Qlo + theta d above the density/pressure floors."""
+    return lib().or_flux_theta(_p(_v(Qlo)), _p(_v(d)), gamma)

@@ -825,6 +825,143 @@ static void ctx_free(ctx* C) {
 /* ------------------------------------------------------------------------------------ */
 /* One time step                                                                         */
 /* ------------------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------------------ */
+/* Sec. 3.5: flux limiting of the cell averages.  Each face flux becomes                  */
+/*   F_lim = gamma F_ho + (1 - gamma) F_lo,  gamma in [0, 1],                            */
+/* with F_ho the Simpson flux (eq. F) and F_lo the local Lax-Friedrichs (Rusanov) flux of */
+/* the t_n averages of the two cells.  gamma is chosen, following the positivity-         */
+/* preserving flux limiting of Hu, Adams and Shu (J. Comput. Phys. 242, 2013) built on   */
+/* Zhang and Shu, so that the averages of both cells stay admissible: the new average of  */
+/* a cell is the mean of the four states Q_lo - 4 lambda_f s_f gamma_f (F_ho - F_lo)_f    */
+/* (Q_lo: the cell's low-order update; s_f = +1 on the east and north faces, -1 on the    */
+/* west and south faces; lambda_f = dt/dx or dt/dy), and gamma_f is the smallest over the */
+/* face's two cells of the largest theta in [0, 1] for which that state has density and  */
+/* pressure at least min(1e-13, the low-order update's).  The admissible theta of one     */
+/* state form an interval containing 0 (density is linear and pressure concave along the */
+/* segment), found by bisection.                                                          */
+/* ------------------------------------------------------------------------------------ */
+static void rusanov(const double QL[4], const double QR[4], int dir, double gamma, double o[4]) {
+  double UL[4], UR[4], fL[4], fR[4];
+  or_c2p(QL, gamma, UL);
+  or_c2p(QR, gamma, UR);
+  if (dir == 0) { flux_f(UL, gamma, fL); flux_f(UR, gamma, fR); }
+  else { flux_g(UL, gamma, fL); flux_g(UR, gamma, fR); }
+  const double aL = fabs(UL[1 + dir]) + sound(UL, gamma);
+  const double aR = fabs(UR[1 + dir]) + sound(UR, gamma);
+  const double al = aL > aR ? aL : aR;
+  for (int v = 0; v < 4; ++v) o[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * al * (QR[v] - QL[v]);
+}
+
+/* density >= er and pressure >= ep */
+static int above(const double Q[4], double gamma, double er, double ep) {
+  if (!(Q[0] >= er)) return 0;
+  const double p = (gamma - 1.0) * (Q[3] - 0.5 * (Q[1] * Q[1] + Q[2] * Q[2]) / Q[0]);
+  return p >= ep;
+}
+
+/* largest theta in [0, 1] with Qlo + theta d above the floors (bisection, 60 halvings) */
+static double flux_theta(const double Qlo[4], const double d[4], double gamma) {
+  double Ulo[4];
+  or_c2p(Qlo, gamma, Ulo);
+  const double er = Qlo[0] < 1e-13 ? Qlo[0] : 1e-13;
+  const double ep = Ulo[3] < 1e-13 ? Ulo[3] : 1e-13;
+  double Q[4];
+  for (int v = 0; v < 4; ++v) Q[v] = Qlo[v] + d[v];
+  if (above(Q, gamma, er, ep)) return 1.0;
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    const double m = 0.5 * (lo + hi);
+    for (int v = 0; v < 4; ++v) Q[v] = Qlo[v] + m * d[v];
+    if (above(Q, gamma, er, ep)) lo = m;
+    else hi = m;
+  }
+  return lo;
+}
+
+double or_flux_theta(const double Qlo[4], const double d[4], double gamma) {
+  return flux_theta(Qlo, d, gamma);
+}
+
+/* Limit the faces of all cells in place.  F[cell][face][v]: face 0 west, 1 east, 2 south,
+ * 3 north (the high-order fluxes on entry, the limited ones on return; a face shared by two
+ * cells holds the same value in both).  Returns the number of limited faces, or -1 if a
+ * low-order update is not admissible. */
+static long long limit_fluxes(const ctx* C, double dt, double* F) {
+  const or_cfg* c = C->c;
+  const int nx = c->nx, ny = c->ny;
+  const double g = c->gamma, lam[2] = {dt / c->dx, dt / c->dy};
+  const size_t ncell = (size_t)nx * ny;
+  double* FL = (double*)malloc(sizeof(double) * 16 * ncell); /* low-order fluxes, same layout */
+  double* TH = (double*)malloc(sizeof(double) * 4 * ncell);  /* theta per cell and face */
+  int bad = 0;
+#pragma omp parallel for reduction(+ : bad) schedule(static)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t cell = (size_t)j * nx + i;
+      double Q[4], Qw[4], Qe[4], Qs[4], Qn[4];
+      getA(C, i, j, Q);
+      getA(C, i - 1, j, Qw);
+      getA(C, i + 1, j, Qe);
+      getA(C, i, j - 1, Qs);
+      getA(C, i, j + 1, Qn);
+      double* fl = FL + 16 * cell;
+      rusanov(Qw, Q, 0, g, fl + 0);
+      rusanov(Q, Qe, 0, g, fl + 4);
+      rusanov(Qs, Q, 1, g, fl + 8);
+      rusanov(Q, Qn, 1, g, fl + 12);
+      double Qlo[4], Ulo[4];
+      for (int v = 0; v < 4; ++v)
+        Qlo[v] = Q[v] - lam[0] * (fl[4 + v] - fl[v]) - lam[1] * (fl[12 + v] - fl[8 + v]);
+      or_c2p(Qlo, g, Ulo);
+      if (!admissible(Ulo)) { bad++; continue; }
+      const double* fh = F + 16 * cell;
+      for (int face = 0; face < 4; ++face) {
+        const double sgn = (face == 1 || face == 3) ? 1.0 : -1.0;
+        double d[4];
+        for (int v = 0; v < 4; ++v)
+          d[v] = -4.0 * lam[face / 2] * sgn * (fh[4 * face + v] - fl[4 * face + v]);
+        TH[4 * cell + face] = flux_theta(Qlo, d, g);
+      }
+    }
+  long long nlim = -1;
+  if (!bad) {
+    nlim = 0;
+    double* out = (double*)malloc(sizeof(double) * 16 * ncell);
+#pragma omp parallel for reduction(+ : nlim) schedule(static)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t cell = (size_t)j * nx + i;
+        for (int face = 0; face < 4; ++face) {
+          /* the neighbour across the face and its face index; none beyond a non-periodic side */
+          int ni = i + (face == 1) - (face == 0), nj = j + (face == 3) - (face == 2);
+          const int per = face < 2 ? c->per_x : c->per_y;
+          const int n = face < 2 ? nx : ny;
+          const int k = face < 2 ? ni : nj;
+          double gam = TH[4 * cell + face];
+          if (per || (k >= 0 && k < n)) {
+            ni = ((ni % nx) + nx) % nx;
+            nj = ((nj % ny) + ny) % ny;
+            const double t = TH[4 * ((size_t)nj * nx + ni) + (face ^ 1)];
+            if (t < gam) gam = t;
+          }
+          for (int v = 0; v < 4; ++v) {
+            const double fh = F[16 * cell + 4 * face + v], flo = FL[16 * cell + 4 * face + v];
+            out[16 * cell + 4 * face + v] = gam < 1.0 ? gam * fh + (1.0 - gam) * flo : fh;
+          }
+          /* count each face once: west and south faces, and east / north at a closed side */
+          if (gam < 1.0 && (face == 0 || face == 2 || (face == 1 && !c->per_x && i == nx - 1) ||
+                            (face == 3 && !c->per_y && j == ny - 1)))
+            nlim++;
+        }
+      }
+    memcpy(F, out, sizeof(double) * 16 * ncell);
+    free(out);
+  }
+  free(FL);
+  free(TH);
+  return nlim;
+}
+
 int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double dt,
             long long* counters) {
   if (!c || c->nx < 1 || c->ny < 1 || !(dt >= 0.0)) return OR_ERR_ARG;
@@ -873,6 +1010,7 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
   if (err == OR_OK) {
     /* Simpson space-time fluxes (eq. F) and the finite volume update (eq. 2dfvm) */
     double* Anew = (double*)malloc(sizeof(double) * 4 * nx * ny);
+    double* FF = (double*)malloc(sizeof(double) * 16 * (size_t)nx * ny); /* [cell][face][v] */
     const double* lvl[3][3];
     for (int k = 0; k < 3; ++k) {
       lvl[k][1] = half[k];
@@ -880,10 +1018,11 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
     }
     lvl[0][0] = K; lvl[1][0] = X; lvl[2][0] = Y;
     int bad = 0;
-#pragma omp parallel for reduction(+ : bad) schedule(static)
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j) {
       for (int i = 0; i < nx; ++i) {
-        double Fw[4] = {0}, Fe[4] = {0}, Gs[4] = {0}, Gn[4] = {0};
+        double* Fc = FF + 16 * ((size_t)j * nx + i);
+        for (int q = 0; q < 16; ++q) Fc[q] = 0.0;
         const double wt[3] = {1.0, 4.0, 1.0};
         for (int t = 0; t < 3; ++t) {
           for (int face = 0; face < 4; ++face) {
@@ -902,10 +1041,21 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
             }
             if (face < 2) { flux_f(Ua, g, fa); flux_f(Um, g, fm); flux_f(Ub, g, fb); }
             else { flux_g(Ua, g, fa); flux_g(Um, g, fm); flux_g(Ub, g, fb); }
-            double* acc = face == 0 ? Fw : face == 1 ? Fe : face == 2 ? Gs : Gn;
-            for (int v = 0; v < 4; ++v) acc[v] += wt[t] * (fa[v] + 4.0 * fm[v] + fb[v]) / 36.0;
+            for (int v = 0; v < 4; ++v) Fc[4 * face + v] += wt[t] * (fa[v] + 4.0 * fm[v] + fb[v]) / 36.0;
           }
         }
+      }
+    }
+    if (c->flux_limiter) {
+      const long long nlim = limit_fluxes(&C, dt, FF);
+      if (nlim < 0) bad = 1;
+      else cnt[6] += nlim;
+    }
+#pragma omp parallel for reduction(+ : bad) schedule(static)
+    for (int j = 0; j < ny; ++j) {
+      for (int i = 0; i < nx; ++i) {
+        const double* Fc = FF + 16 * ((size_t)j * nx + i);
+        const double *Fw = Fc, *Fe = Fc + 4, *Gs = Fc + 8, *Gn = Fc + 12;
         double Q[4];
         for (int v = 0; v < 4; ++v) {
           size_t idx = (size_t)v * nx * ny + (size_t)j * nx + i;
@@ -917,6 +1067,7 @@ int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double 
         if (!admissible(U)) bad++;
       }
     }
+    free(FF);
     if (bad) err = OR_ERR_NONPHYSICAL;
     if (err == OR_OK) {
       memcpy(A, Anew, sizeof(double) * 4 * nx * ny);

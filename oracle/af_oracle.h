@@ -34,6 +34,7 @@ typedef struct {
   double inflow[4][4];
   int tsw;             /* 1: Algorithm 2 (full step linearised at averages near transonic shocks) */
   int shock;           /* 1: shock-indicator blend of high- and low-order point values (Sec. 3.4) */
+  int flux_limiter;    /* 1: flux limiting of the cell averages (Sec. 3.5) */
 } or_cfg;
 enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_WALL = 2, OR_BC_INFLOW = 3 };
 
@@ -41,7 +42,8 @@ enum { OR_OK = 0, OR_ERR_ARG = -1, OR_ERR_NONPHYSICAL = -2, OR_ERR_CFL = -3 };
 enum { OR_KIND_K = 0, OR_KIND_X = 1, OR_KIND_Y = 2 };
 /* counters[0] EG1 fallbacks, [1] LF fallbacks, [2] centre-value fallbacks,
  * [3] Algorithm 1 inner-state fallbacks, [4] unused, [5] DOFs whose full step took the
- * transonic-shock linearisation (Algorithm 2), [6..7] unused */
+ * transonic-shock linearisation (Algorithm 2), [6] faces whose flux was limited (Sec. 3.5),
+ * [7] unused */
 #define OR_NCOUNTERS 8
 
 int or_step(const or_cfg* c, double* A, double* K, double* X, double* Y, double dt,
@@ -74,6 +76,9 @@ int or_indicators(const or_cfg* c, const double* A, const double* K, const doubl
                   const double* Y, int kind, int ci, int cj, double* theta, int* tsw);
 int or_lf_point(const or_cfg* c, const double* A, const double* K, const double* X,
                 const double* Y, int kind, int ci, int cj, double tau, double out[4]);
+/* Sec. 3.5: largest theta in [0, 1] for which Qlo + theta d keeps density and pressure at
+ * least min(1e-13, those of Qlo) (conserved variables). */
+double or_flux_theta(const double Qlo[4], const double d[4], double gamma);
 typedef void (*or_field_cb)(double x, double y, double* out4);
 int or_eg_cb(int order, double xb, double yb, int vline, int hline, const double lin[4],
              double tau, double gamma, or_field_cb cb, int gl_n, double out[4]);
