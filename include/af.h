@@ -10,7 +10,8 @@
  *   - cell averages are updated conservatively with Simpson space-time fluxes
  *     (Sec. 2, eqs. 2dfvm and F);
  *   - optionally, point values with negative density or pressure are replaced by EG1 on
- *     piecewise constant data and, failing that, by a Lax-Friedrichs update (Algorithm 3);
+ *     piecewise constant data and, failing that, by a Lax-Friedrichs update (Algorithm 3),
+ *     and face fluxes are limited so that the cell averages stay admissible (Sec. 3.5);
  *   - boundaries are periodic, outflow (piecewise constant extrapolation, Sec. 4), solid wall
  *     or inflow (Sec. 4.3), chosen per side.
  *
@@ -103,7 +104,7 @@ enum {
                                corner, linearises its new time level at the mean of the
                                adjacent primitive averages instead of U^{n+1/2}.  Meant
                                with AF_LIN_AVG (Sec. 3.1).  0 (default): off.              */
-  AF_OPT_SHOCK_LIMITER = 11 /* 1: shock-indicator limiting of point values (Sec. 3.4): the
+  AF_OPT_SHOCK_LIMITER = 11,/* 1: shock-indicator limiting of point values (Sec. 3.4): the
                                intermediate and the new value become theta U + (1 - theta)
                                U_lo, U_lo being EG1 on piecewise constant data linearised at
                                the mean of the adjacent primitive averages (as in
@@ -117,6 +118,17 @@ enum {
                                averages is not admissible the value is not blended.
                                Algorithm 3 (AF_OPT_LIMITER) then runs on the blended value.
                                0 (default): off.                                          */
+  AF_OPT_FLUX_LIMITER = 12  /* 1: flux limiting of the cell averages (Sec. 3.5): every face
+                               flux becomes gamma F + (1 - gamma) F_lo, F the Simpson flux,
+                               F_lo the Rusanov flux of the t_n averages of the two cells,
+                               gamma in [0, 1] the smaller over the two cells of the largest
+                               theta that keeps the cell's share Q_lo - 4 (dt/h) s theta
+                               (F - F_lo) of its new average at density and pressure of at
+                               least min(1e-13, those of its low-order update Q_lo) (after
+                               Hu, Adams and Shu, 2013).  The new averages are then
+                               admissible whenever the low-order updates are.  Faces need
+                               no limiting in smooth flow (gamma = 1: the unlimited step,
+                               bit for bit).  Single-grid handles.  0 (default): off.      */
 };
 /* Tile orders of the batched point kernel.  Workgroups are dealt to the GPU's 8 XCDs in turn;
  * AF_ORDER_XCD gives each XCD a contiguous range of the global tile index, AF_ORDER_LINEAR
@@ -146,6 +158,7 @@ enum {
   AF_CNT_STEPS = 4,      /* steps taken                                               */
   AF_CNT_TSW = 5,        /* DOFs whose new time level took the transonic-shock
                             linearisation (AF_OPT_TRANSONIC)                           */
+  AF_CNT_FLUX = 6,       /* faces whose flux was limited (AF_OPT_FLUX_LIMITER)        */
   AF_NCOUNTERS = 8
 };
 

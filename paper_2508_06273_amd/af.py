@@ -20,13 +20,13 @@ AF_BC_PERIODIC, AF_BC_OUTFLOW, AF_BC_WALL, AF_BC_INFLOW = 0, 1, 2, 3
 AF_SIDE_LEFT, AF_SIDE_RIGHT, AF_SIDE_BOTTOM, AF_SIDE_TOP = 0, 1, 2, 3
 AF_OPT_PRECISION, AF_OPT_LINEARISATION, AF_OPT_CORRECTION, AF_OPT_LIMITER, \
     AF_OPT_GRAPH_STEPS, AF_OPT_TIMING, AF_OPT_AUTOTUNE, AF_OPT_TILE_ORDER, \
-    AF_OPT_UPDATE_THREADS, AF_OPT_TRANSONIC, AF_OPT_SHOCK_LIMITER = \
-    1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+    AF_OPT_UPDATE_THREADS, AF_OPT_TRANSONIC, AF_OPT_SHOCK_LIMITER, AF_OPT_FLUX_LIMITER = \
+    1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
 AF_ORDER_XCD, AF_ORDER_LINEAR, AF_ORDER_GRIDS = 0, 1, 2
 AF_PREC_FP64, AF_PREC_FP32 = 0, 1
 AF_LIN_AF3, AF_LIN_AVG, AF_LIN_SIMPLE = 0, 1, 2
-AF_CNT_EG1, AF_CNT_LF, AF_CNT_CENTRE, AF_CNT_INNER, AF_CNT_STEPS, AF_CNT_TSW = \
-    0, 1, 2, 3, 4, 5
+AF_CNT_EG1, AF_CNT_LF, AF_CNT_CENTRE, AF_CNT_INNER, AF_CNT_STEPS, AF_CNT_TSW, AF_CNT_FLUX = \
+    0, 1, 2, 3, 4, 5, 6
 AF_NCOUNTERS = 8
 
 # every symbol include/af.h declares
@@ -141,7 +141,7 @@ class _Handle:
     h = None
 
     def _options(self, precision, linearisation, correction, limiter, graph_steps,
-                 transonic=False, shock_limiter=False):
+                 transonic=False, shock_limiter=False, flux_limiter=False):
         self.set_option(AF_OPT_PRECISION, precision)
         self.set_option(AF_OPT_LINEARISATION, linearisation)
         self.set_option(AF_OPT_CORRECTION, int(bool(correction)))
@@ -152,6 +152,8 @@ class _Handle:
             self.set_option(AF_OPT_TRANSONIC, 1)
         if shock_limiter:
             self.set_option(AF_OPT_SHOCK_LIMITER, 1)
+        if flux_limiter:
+            self.set_option(AF_OPT_FLUX_LIMITER, 1)
 
     def _check(self, rc, create=False):
         if rc != AF_OK:
@@ -260,10 +262,11 @@ class Solver(_Handle):
     def __init__(self, nx, ny, x0, x1, y0, y1, gamma=1.4, bc_x=AF_BC_PERIODIC,
                  bc_y=AF_BC_PERIODIC, precision=AF_PREC_FP64, linearisation=AF_LIN_AF3,
                  correction=True, limiter=False, graph_steps=None, sides=None, inflow=None,
-                 transonic=False, shock_limiter=False):
+                 transonic=False, shock_limiter=False, flux_limiter=False):
         """sides: optional kinds (left, right, bottom, top) instead of bc_x / bc_y;
         inflow: optional {side: (rho, u, v, p)} for the inflow sides;
-        transonic: Algorithm 2; shock_limiter: the shock-indicator blend (Sec. 3.4)."""
+        transonic: Algorithm 2; shock_limiter: the shock-indicator blend (Sec. 3.4);
+        flux_limiter: flux limiting of the cell averages (Sec. 3.5)."""
         self.L = load()
         self.nx, self.ny = int(nx), int(ny)
         k = _sides(bc_x, bc_y, sides)
@@ -275,7 +278,7 @@ class Solver(_Handle):
         self._check(self.L.af_create(ct.byref(g), gamma, ct.byref(bc), ct.byref(self.h)),
                     create=True)
         self._options(precision, linearisation, correction, limiter, graph_steps, transonic,
-                      shock_limiter)
+                      shock_limiter, flux_limiter)
         for side, W in (inflow or {}).items():
             self.set_inflow(side, W)
 

@@ -56,6 +56,8 @@ struct af_handle {
   int* d_flag = nullptr;     // device flag of check_avg_device
   int tsw = 0, shock = 0;    // Algorithm 2; the shock-indicator blend
   double* UB = nullptr;      // padded primitive averages for the indicators
+  int flux_limiter = 0;      // flux limiting of the averages (Sec. 3.5)
+  double* TH = nullptr;      // its face weights: 4 planes of ny x pA
   long long pU = 0;
   std::string err;
 };

@@ -135,6 +135,61 @@ void k_update(Params P, const double* __restrict__ A_in, double* __restrict__ A_
   }
 }
 
+// Flux limiting of the averages (Sec. 3.5), two passes replacing k_update: the face weights
+// theta of every cell, then the limited update.  One thread per cell, rows of cells in order.
+__global__ __launch_bounds__(256) void k_flux_theta(Params P, const double* __restrict__ A_in,
+                                                    const double* __restrict__ FK,
+                                                    const double* __restrict__ FX,
+                                                    const double* __restrict__ FY,
+                                                    double* __restrict__ TH, DevState* dev) {
+  if (dev->err || !dev->active) return;
+  const double dt = dev->dt;
+  const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
+  const long long n = (long long)P.nx * P.ny, st = (long long)P.ny * P.pA;
+  bool bad = false;
+  for (long long c = blockIdx.x * 256ll + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
+    const int i = (int)(c % P.nx), j = (int)(c / P.nx);
+    double th[4];
+    if (!cell_thetas(P, A_in, FK, FX, FY, lx, ly, i, j, th)) {
+      bad = true;
+      continue;
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) TH[f * st + (long long)j * P.pA + i] = th[f];
+  }
+  if (bad) set_err(dev, ERR_NONPHYS);
+}
+
+__global__ __launch_bounds__(256) void k_update_lim(Params P, const double* __restrict__ A_in,
+                                                    double* __restrict__ A_out,
+                                                    const double* __restrict__ FK,
+                                                    const double* __restrict__ FX,
+                                                    const double* __restrict__ FY,
+                                                    const double* __restrict__ TH,
+                                                    DevState* dev, int slot) {
+  __shared__ double red[4];
+  __shared__ unsigned int s_lim;
+  if (threadIdx.x == 0) s_lim = 0u;
+  __syncthreads();
+  const bool run = !dev->err && dev->active;
+  const double dt = dev->dt;
+  const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
+  const long long n = (long long)P.nx * P.ny;
+  double speed = 0.0;
+  bool bad = false;
+  unsigned nlim = 0;
+  if (run) {
+    for (long long c = blockIdx.x * 256ll + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
+      const int i = (int)(c % P.nx), j = (int)(c / P.nx);
+      if (!update_limited(P, A_in, A_out, FK, FX, FY, TH, lx, ly, i, j, speed, nlim)) bad = true;
+    }
+  }
+  if (bad) set_err(dev, ERR_NONPHYS);
+  if (nlim) atomicAdd(&s_lim, nlim);
+  block_max_atomic(speed, &dev->smax[slot ^ 1], red);
+  if (threadIdx.x == 0 && s_lim) atomicAdd(&dev->cnt[AF_CNT_FLUX], (unsigned long long)s_lim);
+}
+
 // Commit of a step (one thread): a step that ran without error advances t and the step
 // counter and clears the wave-speed slot of the old state.
 __global__ void k_commit(DevState* dev, int slot) {
@@ -313,6 +368,7 @@ static void destroy_handle(af_handle* h) {
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->dev) (void)hipFree(h->dev);
   if (h->UB) (void)hipFree(h->UB);
+  if (h->TH) (void)hipFree(h->TH);
   if (h->d_flag) (void)hipFree(h->d_flag);
   if (h->stage) (void)hipHostFree(h->stage);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
@@ -455,6 +511,15 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
       if (key == AF_OPT_TRANSONIC) h->tsw = (int)value;
       else h->shock = (int)value;
       break;
+    case AF_OPT_FLUX_LIMITER:
+      if (value != 0 && value != 1) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: 0 or 1");
+      if (value && h->batch)
+        return fail(h, AF_ERR_INVALID_ARG,
+                    "af_set_option: flux limiting is available on single-grid handles");
+      if (value && !h->TH)
+        HIP_OK(hipMalloc(&h->TH, (size_t)4 * h->pA * h->ny * sizeof(double)), h);
+      h->flux_limiter = (int)value;
+      break;
     case AF_OPT_TILE_ORDER:
     case AF_OPT_UPDATE_THREADS: {
       if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: batched handles only");
@@ -487,6 +552,7 @@ extern "C" int af_get_option(const af_handle* h, int key, int64_t* value) {
     case AF_OPT_AUTOTUNE: *value = h->autotune == 1; return AF_OK;
     case AF_OPT_TRANSONIC: *value = h->tsw; return AF_OK;
     case AF_OPT_SHOCK_LIMITER: *value = h->shock; return AF_OK;
+    case AF_OPT_FLUX_LIMITER: *value = h->flux_limiter; return AF_OK;
     case AF_OPT_TILE_ORDER:
     case AF_OPT_UPDATE_THREADS:
       if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_get_option: batched handles only");
@@ -695,7 +761,7 @@ extern "C" int af_get_counters(const af_handle* h, int64_t* out) {
 template <class R>
 static void launch_step(const Params& P, const Bufs& B, DevState* dev, bool limiter, bool ind,
                         double dt_host, int slot, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                        hipEvent_t e2) {
+                        hipEvent_t e2, double* TH = nullptr) {
   const int ntiles = P.tiles_x * P.tiles_y;
   if (e0) (void)hipEventRecord(e0, s);
   if (ind) {
@@ -721,10 +787,20 @@ static void launch_step(const Params& P, const Bufs& B, DevState* dev, bool limi
       hipLaunchKernelGGL(k_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, s, P, B, dev, slot);
   }
   if (e1) (void)hipEventRecord(e1, s);
-  const long long nwork = (long long)((P.nx + 2 * UP_THREADS - 1) / (2 * UP_THREADS)) * P.ny;
-  const int gu = (int)std::min<long long>(nwork, UP_MAX_BLOCKS);
-  hipLaunchKernelGGL(k_update, dim3(gu), dim3(UP_THREADS), 0, s, P, B.A_in, B.A_out,
-                     (const double*)B.FK, (const double*)B.FX, (const double*)B.FY, dev, slot);
+  if (TH) {
+    const long long n = (long long)P.nx * P.ny;
+    const int gb = (int)std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_flux_theta, dim3(gb), dim3(256), 0, s, P, B.A_in, (const double*)B.FK,
+                       (const double*)B.FX, (const double*)B.FY, TH, dev);
+    hipLaunchKernelGGL(k_update_lim, dim3(gb), dim3(256), 0, s, P, B.A_in, B.A_out,
+                       (const double*)B.FK, (const double*)B.FX, (const double*)B.FY,
+                       (const double*)TH, dev, slot);
+  } else {
+    const long long nwork = (long long)((P.nx + 2 * UP_THREADS - 1) / (2 * UP_THREADS)) * P.ny;
+    const int gu = (int)std::min<long long>(nwork, UP_MAX_BLOCKS);
+    hipLaunchKernelGGL(k_update, dim3(gu), dim3(UP_THREADS), 0, s, P, B.A_in, B.A_out,
+                       (const double*)B.FK, (const double*)B.FX, (const double*)B.FY, dev, slot);
+  }
   hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s, dev, slot);
   if (e2) (void)hipEventRecord(e2, s);
 }
@@ -750,7 +826,7 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
     (void)hipEventCreate(&e2);
   }
   launch_step<R>(P, B, h->dev, h->limiter != 0, (h->tsw || h->shock), dt_host, in, h->stream,
-                 e0, e1, e2);
+                 e0, e1, e2, h->flux_limiter ? h->TH : nullptr);
   if (h->timing) {
     h->ev.push_back(e0);
     h->ev.push_back(e1);

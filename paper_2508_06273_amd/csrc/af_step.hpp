@@ -878,3 +878,209 @@ __device__ __forceinline__ double state_speed(const Params& P, const double* __r
 }
 
 }  // namespace af
+
+namespace af {
+
+// ------------------------------------------------------------------------------------------
+// Flux limiting of the cell averages (Sec. 3.5).  Each face flux becomes
+// gamma F_ho + (1 - gamma) F_lo with F_lo the Rusanov flux of the t_n averages of the two
+// cells; gamma is the smaller over the face's two cells of the largest theta in [0, 1] that
+// keeps the cell's share Q_lo - 4 lambda s theta (F_ho - F_lo) of the new average above the
+// density and pressure floors min(1e-13, those of Q_lo), Q_lo being the cell's low-order
+// update (positivity-preserving limiting after Hu, Adams and Shu on Zhang and Shu).  The new
+// average is the mean of the four shares, hence admissible.
+// ------------------------------------------------------------------------------------------
+// t_n average of the possibly ghost cell (i, j), one layer beyond the grid, by the side rules
+// (periodic wrap, outflow copy, wall mirror with the normal momentum negated, inflow state).
+__device__ __forceinline__ void ghost_avg(const Params& P, const double* __restrict__ A, int i,
+                                          int j, double Q[4]) {
+  int sx, sy;
+  const int gi = map_axis<false>(i, P.nx, P.per_x, P.bc[0], P.bc[1], sx);
+  const int gj = map_axis<false>(j, P.ny, P.per_y, P.bc[2], P.bc[3], sy);
+  const long long o = (long long)gj * P.pA + gi;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Q[v] = A[v * P.sA + o];
+  if (sx >= 0 && side_kind(P, sx) == BC_WALL) Q[1] = -Q[1];
+  if (sy >= 0 && side_kind(P, 2 + sy) == BC_WALL) Q[2] = -Q[2];
+  if (sx >= 0 && side_kind(P, sx) == BC_INFLOW) {
+    double W[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) W[v] = side_inflow(P, sx, v);
+    p2c(W, P.g1inv, Q);
+  }
+  if (sy >= 0 && side_kind(P, 2 + sy) == BC_INFLOW) {
+    double W[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) W[v] = side_inflow(P, 2 + sy, v);
+    p2c(W, P.g1inv, Q);
+  }
+}
+
+// Rusanov flux between the conserved states QL, QR in direction dir (0: x, 1: y), scaled by
+// 36 (the scale of the Simpson site sums the update works with).
+__device__ __forceinline__ void rusanov36(const Params& P, const double QL[4], const double QR[4],
+                                          int dir, double o[4]) {
+  double UL[4], UR[4], FL[4], GL[4], FR[4], GR[4];
+  const double gm1 = P.gamma - 1.0;
+  c2p_plain(QL, gm1, UL);
+  c2p_plain(QR, gm1, UR);
+  flux_fg(UL, P.g1inv, FL, GL);
+  flux_fg(UR, P.g1inv, FR, GR);
+  const double aL = __builtin_fabs(UL[1 + dir]) + __builtin_sqrt(P.gamma * UL[3] / UL[0]);
+  const double aR = __builtin_fabs(UR[1 + dir]) + __builtin_sqrt(P.gamma * UR[3] / UR[0]);
+  const double al = mx(aL, aR);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double fl = dir ? GL[v] : FL[v], fr = dir ? GR[v] : FR[v];
+    o[v] = 36.0 * (0.5 * (fl + fr) - 0.5 * al * (QR[v] - QL[v]));
+  }
+}
+
+// density >= er and pressure >= ep
+__device__ __forceinline__ bool above_floor(const double Q[4], double gm1, double er, double ep) {
+  if (!(Q[0] >= er)) return false;
+  const double p = gm1 * (Q[3] - 0.5 * (Q[1] * Q[1] + Q[2] * Q[2]) / Q[0]);
+  return p >= ep;
+}
+
+// Largest theta in [0, 1] with Qlo + theta d above the floors: theta = 1 if that state is,
+// else bisection (60 halvings; the admissible theta form an interval containing 0).
+__device__ __forceinline__ double flux_theta(const double Qlo[4], const double d[4], double gm1,
+                                             double plo) {
+  const double er = mn(1e-13, Qlo[0]), ep = mn(1e-13, plo);
+  double Q[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Q[v] = Qlo[v] + d[v];
+  if (above_floor(Q, gm1, er, ep)) return 1.0;
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    const double m = 0.5 * (lo + hi);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Q[v] = Qlo[v] + m * d[v];
+    if (above_floor(Q, gm1, er, ep)) lo = m;
+    else hi = m;
+  }
+  return lo;
+}
+
+// Site sums of the four faces of cell (i, j), Simpson in space (F = f_K + 4 f_X + f_K'):
+// S[0] west, S[1] east, S[2] south, S[3] north.
+__device__ __forceinline__ void face_sums(const Params& P, const double* __restrict__ FK,
+                                          const double* __restrict__ FX,
+                                          const double* __restrict__ FY, int i, int j,
+                                          double S[4][4]) {
+  const int jp = wrap_line(j + 1, P.ny, P.per_y);
+  const int ip = wrap_line(i + 1, P.nx, P.per_x);
+  const long long r0 = (long long)j * P.pF, r1 = (long long)jp * P.pF;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double* fk = FK + v * P.sF;
+    const double* gk = FK + (4 + v) * P.sF;
+    const double* fx = FX + v * P.sF;
+    const double* fy = FY + v * P.sF;
+    S[0][v] = fk[r0 + i] + 4.0 * fx[r0 + i] + fk[r1 + i];
+    S[1][v] = fk[r0 + ip] + 4.0 * fx[r0 + ip] + fk[r1 + ip];
+    S[2][v] = gk[r0 + i] + 4.0 * fy[r0 + i] + gk[r0 + ip];
+    S[3][v] = gk[r1 + i] + 4.0 * fy[r1 + i] + gk[r1 + ip];
+  }
+}
+
+// Rusanov fluxes (x36) of the four faces of cell (i, j), same face order, and its average.
+__device__ __forceinline__ void face_low(const Params& P, const double* __restrict__ A, int i,
+                                         int j, double Q[4], double L[4][4]) {
+  double Qw[4], Qe[4], Qs[4], Qn[4];
+  ghost_avg(P, A, i, j, Q);
+  ghost_avg(P, A, i - 1, j, Qw);
+  ghost_avg(P, A, i + 1, j, Qe);
+  ghost_avg(P, A, i, j - 1, Qs);
+  ghost_avg(P, A, i, j + 1, Qn);
+  rusanov36(P, Qw, Q, 0, L[0]);
+  rusanov36(P, Q, Qe, 0, L[1]);
+  rusanov36(P, Qs, Q, 1, L[2]);
+  rusanov36(P, Q, Qn, 1, L[3]);
+}
+
+// theta of the four faces of cell (i, j); false if its low-order update is not admissible.
+__device__ __forceinline__ bool cell_thetas(const Params& P, const double* __restrict__ A,
+                                            const double* __restrict__ FK,
+                                            const double* __restrict__ FX,
+                                            const double* __restrict__ FY, double lx, double ly,
+                                            int i, int j, double th[4]) {
+  double S[4][4], L[4][4], Q[4], Qlo[4], Ulo[4];
+  face_sums(P, FK, FX, FY, i, j, S);
+  face_low(P, A, i, j, Q, L);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Qlo[v] = Q[v] - lx * (L[1][v] - L[0][v]) - ly * (L[3][v] - L[2][v]);
+  c2p_plain(Qlo, P.gamma - 1.0, Ulo);
+  if (!admissible(Ulo[0], Ulo[3])) return false;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const double sl = (f == 1 || f == 3) ? -4.0 : 4.0;  // -4 s_f
+    const double lam = f < 2 ? lx : ly;
+    double d[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = sl * lam * (S[f][v] - L[f][v]);
+    th[f] = flux_theta(Qlo, d, P.gamma - 1.0, Ulo[3]);
+  }
+  return true;
+}
+
+// Limited update of cell (i, j) from the thetas (4 planes of the cell layout).  Counts its west
+// and south faces (and east / north at a closed side) in *nlim when limited.  Returns false if
+// the new average is not admissible; else raises `speed`.
+__device__ __forceinline__ bool update_limited(const Params& P, const double* __restrict__ A_in,
+                                               double* __restrict__ A_out,
+                                               const double* __restrict__ FK,
+                                               const double* __restrict__ FX,
+                                               const double* __restrict__ FY,
+                                               const double* __restrict__ TH, double lx,
+                                               double ly, int i, int j, double& speed,
+                                               unsigned& nlim) {
+  const long long st = (long long)P.ny * P.pA;  // theta plane stride
+  auto th = [&](int f, int ci, int cj) { return TH[f * st + (long long)cj * P.pA + ci]; };
+  double S[4][4], g[4];
+  face_sums(P, FK, FX, FY, i, j, S);
+  bool any = false;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    double t = th(f, i, j);
+    const int ni = i + (f == 1) - (f == 0), nj = j + (f == 3) - (f == 2);
+    const bool xf = f < 2;
+    const int k = xf ? ni : nj, n = xf ? P.nx : P.ny;
+    if ((xf ? P.per_x : P.per_y) || (k >= 0 && k < n)) {
+      const int wi = wrap_per(ni < 0 ? ni + P.nx : ni, P.nx);
+      const int wj = wrap_per(nj < 0 ? nj + P.ny : nj, P.ny);
+      t = mn(t, th(f ^ 1, wi, wj));
+    }
+    g[f] = t;
+    if (t < 1.0) {
+      any = true;
+      if (f == 0 || f == 2 || (f == 1 && !P.per_x && i == P.nx - 1) ||
+          (f == 3 && !P.per_y && j == P.ny - 1))
+        ++nlim;
+    }
+  }
+  if (any) {
+    double L[4][4], Q[4];
+    face_low(P, A_in, i, j, Q, L);
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      if (g[f] < 1.0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) S[f][v] = g[f] * S[f][v] + (1.0 - g[f]) * L[f][v];
+      }
+  }
+  const long long oa = (long long)j * P.pA + i;
+  double Qn[4], U[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    Qn[v] = A_in[v * P.sA + oa] - lx * (S[1][v] - S[0][v]) - ly * (S[3][v] - S[2][v]);
+    A_out[v * P.sA + oa] = Qn[v];
+  }
+  c2p_plain(Qn, P.gamma - 1.0, U);
+  if (!admissible(U[0], U[3])) return false;
+  speed = mx(speed, wave_speed(U, P.gamma));
+  return true;
+}
+
+}  // namespace af
