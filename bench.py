@@ -372,11 +372,28 @@ def shock_reflection(stream):
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(seconds: float, n_cpu: int):
+    """The FP64 oracle on the host: as many OpenMP threads as the process may use (its CPU
+    affinity), bounded by OMP_NUM_THREADS when the environment sets it (the host's share of
+    cores for this GPU)."""
     import oracle
     from paper_2508_06273_amd import inputs as I
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    threads = max(1, min(threads, os.cpu_count() or 1, 16))
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = avail
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    threads = max(1, threads)
     st = I.shu_vortex(n_cpu, n_gl=3)
     oracle.run(st, 1e9, 0.3, max_steps=1, nthreads=threads)  # warm-up step
     steps = 0
@@ -388,7 +405,8 @@ def cpu_baseline(seconds: float, n_cpu: int):
     el = time.perf_counter() - t0
     dofs = 4 * n_cpu * n_cpu
     return {"value": dofs * steps / el, "unit": "DOF-updates/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "nproc": os.cpu_count(), "affinity_cpus": avail,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"), "cpu_model": _cpu_model(),
             "sample": f"isentropic vortex {n_cpu}x{n_cpu} (same per-DOF work as the GPU "
                       f"workload), Algorithm 1, CFL 0.3, {steps} steps after 1 warm-up step, "
                       f"{el:.1f} s"}

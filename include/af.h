@@ -163,7 +163,12 @@ enum {
 };
 
 /* Create a solver for `grid` with ratio of specific heats `gamma` (> 1) and boundary
- * conditions `bc`.  Allocates the device state (uninitialised until af_set_state). */
+ * conditions `bc` (Sec. 2: the Cartesian grid of cells with averages at the centres and point
+ * values at the corners and edge midpoints; the ideal gas law with gamma; Sec. 4 and 4.3: the
+ * boundary kinds).  Allocates the device state (uninitialised until af_set_state).  `out`
+ * receives the handle, owned by the caller until af_destroy.  Errors: AF_ERR_INVALID_ARG for
+ * nx or ny outside [2, 65536], an empty domain, gamma <= 1, an unknown boundary kind or a
+ * periodic side without its partner; AF_ERR_DEVICE without a usable GPU; AF_ERR_OOM. */
 int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_handle** out);
 
 /* Set an option (keys and values above). */
@@ -178,25 +183,35 @@ int af_get_option(const af_handle* h, int key, int64_t* value);
  * device work of this handle.  NULL selects the handle's own (non-blocking) stream. */
 int af_set_stream(af_handle* h, void* hip_stream);
 
-/* Copy a state in (host FP64 arrays, layout above) at time t.  Resets the counters. */
+/* Copy a state in (host FP64 arrays, layout above) at time t: the conserved cell averages and
+ * the primitive point values that are the method's degrees of freedom (Sec. 2, the start of a
+ * step t_n).  Resets the counters.  The arrays stay the caller's.  Errors: AF_ERR_INVALID_ARG
+ * (NULL array, t not finite), AF_ERR_NONPHYSICAL if an average has rho <= 0 or p <= 0 (the
+ * state is then not set). */
 int af_set_state(af_handle* h, const double* avg, const double* K, const double* X,
                  const double* Y, double t);
 
-/* Copy the current state out (any output pointer may be NULL). */
+/* Copy the current state out (the degrees of freedom of Sec. 2 at the current time; any output
+ * pointer may be NULL).  Errors: AF_ERR_INVALID_ARG if no state was set. */
 int af_get_state(const af_handle* h, double* avg, double* K, double* X, double* Y,
                  double* t);
 
 /* One time step of size dt > 0 (Algorithm 1 steps 1-3 with the chosen options). */
 int af_step(af_handle* h, double dt);
 
-/* Advance to t_end with dt = cfl * min(dx,dy) / max over all DOFs of (max(|u|,|v|) + c),
+/* Advance to t_end with dt = cfl * min(dx,dy) / max over all DOFs of (max(|u|,|v|) + c)
+ * (the CFL number of Sec. 2, which states stability of the linear schemes up to 0.279),
  * computed on the device from the current state before every step; the last step is cut
  * to land on t_end.  max_steps > 0 bounds the number of steps.  t_reached and steps_taken
- * (nullable) report where the run stopped. */
+ * (nullable) report where the run stopped.  Errors: AF_ERR_INVALID_ARG for cfl outside
+ * (0, 0.5) or a NaN t_end; a failing step ends the run with its code (the state is then the
+ * one before that step, t_reached and steps_taken say where). */
 int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double* t_reached,
            int64_t* steps_taken);
 
-/* Counters (AF_NCOUNTERS values). */
+/* Counters (AF_NCOUNTERS values, indices AF_CNT_*): how often Algorithm 3's low-order
+ * branches, the centre-value fallback, the Algorithm 1 inner-state fallback, Algorithm 2 and
+ * the flux limiting of Sec. 3.5 acted, and the steps taken.  `out` is the caller's. */
 int af_get_counters(const af_handle* h, int64_t* out);
 
 /* Free the handle and its device memory (NULL is ignored). */

@@ -1,0 +1,30 @@
+"""The oracle under the address and undefined-behaviour sanitizers (host code only): build
+oracle/af_oracle.c with oracle/sanitize_main.c and run the driver, which steps small grids
+through every boundary kind, mode and limiter option and checks uniform-state preservation and
+conservation."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_oracle_clean_under_asan_and_ubsan(tmp_path):
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    exe = str(tmp_path / "oracle_sanitize")
+    src = os.path.join(ROOT, "oracle")
+    cmd = [gcc, "-O1", "-g", "-std=c11", "-fopenmp", "-ffp-contract=off",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           os.path.join(src, "af_oracle.c"), os.path.join(src, "sanitize_main.c"), "-I", src,
+           "-o", exe, "-lm"]
+    subprocess.check_call(cmd)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1", OMP_NUM_THREADS="2")
+    env.pop("LD_PRELOAD", None)
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-3000:])
+    assert "0 failures" in r.stdout
