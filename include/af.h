@@ -226,7 +226,9 @@ int64_t af_dof_count(const af_handle* h);
 
 /* Kernel times gathered while AF_OPT_TIMING is on, summed since the option was last set:
  * out[0] = milliseconds in the point-value kernel, out[1] = milliseconds in the flux/update
- * kernel, out[2] = number of steps timed.  Both kernels run on the handle's stream. */
+ * kernel, out[2] = number of steps timed: those in which a grid advanced (launches that a
+ * batched run enqueues after all its grids have stopped are not counted).  Both kernels run on
+ * the handle's stream. */
 int af_get_timing(const af_handle* h, double* out);
 
 /* ---------------------------------------------------------------------------------------
@@ -293,7 +295,8 @@ int af_set_inflow(af_handle* h, int32_t g, int32_t side, const double* W);
  * AF_OPT_LINEARISATION, AF_OPT_CORRECTION and AF_OPT_LIMITER.  Work is enqueued on `stream`
  * (a hipStream_t; NULL: the null stream) and the call waits for it; `counters` (host, nullable,
  * AF_NCOUNTERS values) receives this step's counters.
- * Scratch: step control, fix-up masks and the per-site flux sums live in a static device array
+ * Scratch: step control, the grid descriptor, fix-up masks and the per-site flux sums live in a
+ * static device array
  * of 32 MiB per GPU (held until the process ends): grids whose flux sums (128 bytes per
  * nky * pitch_pts site) and tile masks do not fit, about 500 x 500 cells, are rejected with
  * AF_ERR_INVALID_ARG.  Every call on one GPU uses that GPU's array: calls that overlap on one

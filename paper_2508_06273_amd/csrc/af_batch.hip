@@ -22,16 +22,6 @@
 
 namespace af {
 
-// Per-grid device descriptor: geometry and options, and the buffers for each of the two
-// buffer indices (t_n state in buffer `cur`, t_n+1 in `cur ^ 1`).
-struct GridDesc {
-  Params P;
-  Bufs B[2];
-  int tile_base;  // first global tile of the grid
-  int row_base;   // first global row of cells of the grid
-};
-
-
 // Point kernel over the tiles of all grids.  Workgroup b evolves tile block_tile[b] (a
 // permutation of the global tiles: the schedule, see set_order).
 template <class R>
@@ -740,8 +730,10 @@ static int autotune(af_handle* h, int per) {
   return batch_set_schedule(h, best_order, best_threads);
 }
 
-static void collect_batch_timing(af_handle* h) {
-  for (size_t k = 0; k + 2 < h->ev.size(); k += 3) {
+// Add the event times of the first `used` enqueued steps (those in which some grid advanced;
+// the launches after every grid has stopped return at once and are not counted).
+static void collect_batch_timing(af_handle* h, long long used) {
+  for (size_t k = 0; k + 2 < h->ev.size() && (long long)(k / 3) < used; k += 3) {
     float a = 0.f, c = 0.f;
     if (hipEventElapsedTime(&a, h->ev[k], h->ev[k + 1]) == hipSuccess &&
         hipEventElapsedTime(&c, h->ev[k + 1], h->ev[k + 2]) == hipSuccess) {
@@ -789,8 +781,14 @@ int batch_step(af_handle* h, double dt) {
   if (int e = write_devs(h, ds)) return e;
   enqueue_batch(h, dt);
   HIP_OK(hipGetLastError(), h);
+  std::vector<long long> before((size_t)h->batch->n);
+  for (size_t k = 0; k < ds.size(); ++k) before[k] = ds[k].steps;
   if (int e = read_devs(h, ds)) return e;
-  if (h->timing) collect_batch_timing(h);
+  if (h->timing) {
+    long long used = 0;
+    for (size_t k = 0; k < ds.size(); ++k) used = std::max(used, ds[k].steps - before[k]);
+    collect_batch_timing(h, used);
+  }
   int g = 0;
   if (int e = first_error(ds, &g))
     return fail(h, e, "af_step: grid " + std::to_string(g) + ": " + batch_err_text(e));
@@ -824,9 +822,12 @@ int batch_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double*
   if (h->autotune == 1) {
     if (int e = autotune(h, 2)) return e;
     h->autotune = 2;  // done; the chosen schedule stays
+    if (int e = read_devs(h, ds)) return e;
   }
   const long long chunk = h->graph_steps > 0 ? h->graph_steps : 8;
+  std::vector<long long> before((size_t)b->n);
   while (true) {
+    for (int k = 0; k < b->n; ++k) before[k] = ds[k].steps;
     // every grid stops by itself at t_end or at its step limit; the host only checks between
     // chunks whether any grid is still running or has failed
     if (h->timing) {
@@ -846,7 +847,11 @@ int batch_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double*
     }
     HIP_OK(hipGetLastError(), h);
     if (int e = read_devs(h, ds)) return e;
-    if (h->timing) collect_batch_timing(h);
+    if (h->timing) {
+      long long used = 0;
+      for (int k = 0; k < b->n; ++k) used = std::max(used, ds[k].steps - before[k]);
+      collect_batch_timing(h, used);
+    }
     double tmin = INFINITY;
     long long smax = 0;
     bool running = false;

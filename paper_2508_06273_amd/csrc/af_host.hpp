@@ -39,6 +39,8 @@ struct af_handle {
   unsigned long long* fix_mask = nullptr;
   int* fix_list = nullptr;
   DevState* dev = nullptr;
+  GridDesc* d_desc = nullptr;  // device copy of the parameters and buffers (point kernels)
+  bool desc_valid = false;
   int cur = 0;
   bool has_state = false;
   long long steps_base = 0;

@@ -93,6 +93,16 @@ struct Bufs {
   double* UB;
 };
 
+// Device-resident descriptor of a grid: geometry and options, and the buffers for each of the
+// two buffer indices (t_n state in buffer `cur`, t_n+1 in `cur ^ 1`).  The point kernels read it
+// through a pointer: passed by value, the parameters fill the scalar registers and spill.
+struct GridDesc {
+  Params P;
+  Bufs B[2];
+  int tile_base;  // batched grids: first global tile of the grid
+  int row_base;   // batched grids: first global row of cells of the grid
+};
+
 // Periodic index of a (possibly ghost) cell or grid line, i >= -n.  The common case needs no
 // integer division.
 __device__ __forceinline__ int wrap_per(int i, int n) {

@@ -24,24 +24,34 @@ namespace af {
 // variants add the indicators of Algorithm 2 and Sec. 3.4.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
-void k_points_f32(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
+void k_points_f32(const GridDesc* __restrict__ d, DevState* dev, double dt_host, int slot) {
   __shared__ Smem<float> S;
+  const Params& P = d->P;
+  const Bufs& B = d->B[slot];
   points_body<float>(S, nullptr, P, B, dev, dt_host, slot,
-                     tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y), blockIdx.x == 0);
+                     tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y),
+                     blockIdx.x == 0);
 }
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
-void k_points_f64(Params P, Bufs B, DevState* dev, double dt_host, int slot) {
+void k_points_f64(const GridDesc* __restrict__ d, DevState* dev, double dt_host, int slot) {
   __shared__ Smem<double> S;
+  const Params& P = d->P;
+  const Bufs& B = d->B[slot];
   points_body<double>(S, nullptr, P, B, dev, dt_host, slot,
-                      tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y), blockIdx.x == 0);
+                      tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y),
+                      blockIdx.x == 0);
 }
 template <class R>
-__global__ __launch_bounds__(PT_THREADS) void k_points_ind(Params P, Bufs B, DevState* dev,
-                                                           double dt_host, int slot) {
+__global__ __launch_bounds__(PT_THREADS) void k_points_ind(const GridDesc* __restrict__ d,
+                                                           DevState* dev, double dt_host,
+                                                           int slot) {
   __shared__ Smem<R> S;
   __shared__ Ind I;
+  const Params& P = d->P;
+  const Bufs& B = d->B[slot];
   points_body<R, true>(S, &I, P, B, dev, dt_host, slot,
-                       tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y), blockIdx.x == 0);
+                       tile_of_block(blockIdx.x, P.tiles_x * P.tiles_y),
+                       blockIdx.x == 0);
 }
 
 // Primitive Simpson averages of the cells -2 .. nx+1 x -2 .. ny+1 for the indicators, one
@@ -79,22 +89,22 @@ __device__ __forceinline__ void fixup_body(Smem<R>& S, Ind* I, const Params& P, 
     fixup_tile<R, IND>(S, I, P, B, dev, B.fix_list[k], s_dt, s_run != 0, mask, speed);
   if (n > blockIdx.x) block_max_atomic(speed, &dev->smax[slot ^ 1], S.red);
 }
-__global__ __launch_bounds__(PT_THREADS) void k_fixup_f32(Params P, Bufs B, DevState* dev,
-                                                         int slot) {
+__global__ __launch_bounds__(PT_THREADS) void k_fixup_f32(const GridDesc* __restrict__ d,
+                                                         DevState* dev, int slot) {
   __shared__ Smem<float> S;
-  fixup_body<float, false>(S, nullptr, P, B, dev, slot);
+  fixup_body<float, false>(S, nullptr, d->P, d->B[slot], dev, slot);
 }
-__global__ __launch_bounds__(PT_THREADS) void k_fixup_f64(Params P, Bufs B, DevState* dev,
-                                                         int slot) {
+__global__ __launch_bounds__(PT_THREADS) void k_fixup_f64(const GridDesc* __restrict__ d,
+                                                         DevState* dev, int slot) {
   __shared__ Smem<double> S;
-  fixup_body<double, false>(S, nullptr, P, B, dev, slot);
+  fixup_body<double, false>(S, nullptr, d->P, d->B[slot], dev, slot);
 }
 template <class R>
-__global__ __launch_bounds__(PT_THREADS) void k_fixup_ind(Params P, Bufs B, DevState* dev,
-                                                          int slot) {
+__global__ __launch_bounds__(PT_THREADS) void k_fixup_ind(const GridDesc* __restrict__ d,
+                                                          DevState* dev, int slot) {
   __shared__ Smem<R> S;
   __shared__ Ind I;
-  fixup_body<R, true>(S, &I, P, B, dev, slot);
+  fixup_body<R, true>(S, &I, d->P, d->B[slot], dev, slot);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -222,14 +232,26 @@ __global__ void k_cfl(Params P, const double* __restrict__ A, const double* __re
 }
 
 // ------------------------------------------------------------------------------------------
-// Scratch memory of af_step_noalloc (no allocation at call time): step control, the fix-up
-// masks and tile list, and the per-site flux sums, carved out of one file-scope array that
+// Scratch memory of af_step_noalloc (no allocation at call time): step control, the grid
+// descriptor, the fix-up masks and tile list, and the per-site flux sums, carved out of one file-scope array that
 // every GPU the library runs on holds until the process ends.  Host code never passes the
 // array's name to a kernel (in host code it is a stand-in, not a device address): it uses the
 // address that hipGetSymbolAddress returns for the current device.
 // ------------------------------------------------------------------------------------------
 constexpr size_t NOALLOC_BYTES = size_t(32) << 20;
 __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Write the device descriptor of a single grid (its parameters and the buffers of both buffer
+// indices) from kernel arguments: no host copy, so it may be enqueued anywhere on a stream.
+__global__ void k_write_desc(GridDesc* d, Params P, Bufs B0, Bufs B1) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    d->P = P;
+    d->B[0] = B0;
+    d->B[1] = B1;
+    d->tile_base = 0;
+    d->row_base = 0;
+  }
+}
 
 // Reset the step control (zero, no step limit) and clear n fix-up mask words.
 __global__ void k_noalloc_init(DevState* dev, unsigned long long* mask, long long n) {
@@ -367,6 +389,7 @@ static void destroy_handle(af_handle* h) {
   batch_destroy(h);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->dev) (void)hipFree(h->dev);
+  if (h->d_desc) (void)hipFree(h->d_desc);
   if (h->UB) (void)hipFree(h->UB);
   if (h->TH) (void)hipFree(h->TH);
   if (h->d_flag) (void)hipFree(h->d_flag);
@@ -403,6 +426,8 @@ extern "C" int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_
     else if (hipMemset(h->dev, 0, sizeof(DevState)) != hipSuccess)
       e = fail(h, AF_ERR_DEVICE, "af_create: hipMemset");
   }
+  if (e == AF_OK && hipMalloc(&h->d_desc, sizeof(GridDesc)) != hipSuccess)
+    e = fail(h, AF_ERR_OOM, "af_create: hipMalloc(desc)");
   if (e != AF_OK) {
     g_create_error = h->err;
     destroy_handle(h);
@@ -535,6 +560,7 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
       return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown key");
   }
   if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
+  h->desc_valid = false;
   batch_invalidate(h);
   return AF_OK;
 }
@@ -568,6 +594,7 @@ extern "C" int af_set_stream(af_handle* h, void* s) {
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_stream: NULL handle");
   (void)hipStreamSynchronize(h->stream);
   h->stream = s ? (hipStream_t)s : h->own_stream;
+  h->desc_valid = false;  // rewritten on the new stream before its first step
   if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
   batch_invalidate(h);
   return AF_OK;
@@ -756,35 +783,36 @@ extern "C" int af_get_counters(const af_handle* h, int64_t* out) {
 }
 
 // Kernels of one step on the buffers B (t_n state in, t_n+1 state out), smax slot `slot`;
-// dt_host > 0 for a caller-given step.  Events e0/e1/e2 (nullable) bracket the point and the
-// update kernels.
+// dt_host > 0 for a caller-given step.  `desc` is the device copy of P with B as its buffers
+// B[slot] (the point and fix-up kernels read it there).  Events e0/e1/e2 (nullable) bracket the
+// point and the update kernels.
 template <class R>
-static void launch_step(const Params& P, const Bufs& B, DevState* dev, bool limiter, bool ind,
-                        double dt_host, int slot, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                        hipEvent_t e2, double* TH = nullptr) {
+static void launch_step(const Params& P, const Bufs& B, const GridDesc* desc, DevState* dev,
+                        bool limiter, bool ind, double dt_host, int slot, hipStream_t s,
+                        hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, double* TH = nullptr) {
   const int ntiles = P.tiles_x * P.tiles_y;
   if (e0) (void)hipEventRecord(e0, s);
   if (ind) {
     const long long n = (long long)(P.nx + 4) * (P.ny + 4);
     const int gb = (int)std::min<long long>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(k_avgprim, dim3(gb), dim3(256), 0, s, P, B);
-    hipLaunchKernelGGL(k_points_ind<R>, dim3(ntiles), dim3(PT_THREADS), 0, s, P, B, dev,
+    hipLaunchKernelGGL(k_points_ind<R>, dim3(ntiles), dim3(PT_THREADS), 0, s, desc, dev,
                        dt_host, slot);
   } else if constexpr (sizeof(R) == 4) {
-    hipLaunchKernelGGL(k_points_f32, dim3(ntiles), dim3(PT_THREADS), 0, s, P, B, dev, dt_host,
+    hipLaunchKernelGGL(k_points_f32, dim3(ntiles), dim3(PT_THREADS), 0, s, desc, dev, dt_host,
                        slot);
   } else {
-    hipLaunchKernelGGL(k_points_f64, dim3(ntiles), dim3(PT_THREADS), 0, s, P, B, dev, dt_host,
+    hipLaunchKernelGGL(k_points_f64, dim3(ntiles), dim3(PT_THREADS), 0, s, desc, dev, dt_host,
                        slot);
   }
   if (limiter) {
     const int nb = std::min(ntiles, FIX_BLOCKS);
     if (ind)
-      hipLaunchKernelGGL(k_fixup_ind<R>, dim3(nb), dim3(PT_THREADS), 0, s, P, B, dev, slot);
+      hipLaunchKernelGGL(k_fixup_ind<R>, dim3(nb), dim3(PT_THREADS), 0, s, desc, dev, slot);
     else if constexpr (sizeof(R) == 4)
-      hipLaunchKernelGGL(k_fixup_f32, dim3(nb), dim3(PT_THREADS), 0, s, P, B, dev, slot);
+      hipLaunchKernelGGL(k_fixup_f32, dim3(nb), dim3(PT_THREADS), 0, s, desc, dev, slot);
     else
-      hipLaunchKernelGGL(k_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, s, P, B, dev, slot);
+      hipLaunchKernelGGL(k_fixup_f64, dim3(nb), dim3(PT_THREADS), 0, s, desc, dev, slot);
   }
   if (e1) (void)hipEventRecord(e1, s);
   if (TH) {
@@ -805,10 +833,8 @@ static void launch_step(const Params& P, const Bufs& B, DevState* dev, bool limi
   if (e2) (void)hipEventRecord(e2, s);
 }
 
-// enqueue one step reading buffer `in` (0/1); dt_host > 0 for a caller-given step
-template <class R>
-static void enqueue_step_t(af_handle* h, int in, double dt_host) {
-  const Params P = make_params(h);
+// Buffers of a step that reads buffer `in` (0/1) and writes the other.
+static Bufs handle_bufs(const af_handle* h, int in) {
   const int out = in ^ 1;
   Bufs B;
   B.A_in = h->A[in]; B.A_out = h->A[out];
@@ -819,14 +845,33 @@ static void enqueue_step_t(af_handle* h, int in, double dt_host) {
   B.fix_mask = h->fix_mask; B.fix_list = h->fix_list;
   B.fix_count = &h->dev->fix_count; B.tile_base = 0;
   B.UB = h->UB;
+  return B;
+}
+
+// Bring the device descriptor up to date (enqueued on the handle's stream before the steps that
+// read it; af_run calls this before it captures a graph).
+static int ensure_desc(af_handle* h) {
+  if (h->desc_valid) return AF_OK;
+  hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, h->stream, h->d_desc, make_params(h),
+                     handle_bufs(h, 0), handle_bufs(h, 1));
+  HIP_OK(hipGetLastError(), h);
+  h->desc_valid = true;
+  return AF_OK;
+}
+
+// enqueue one step reading buffer `in` (0/1); dt_host > 0 for a caller-given step
+template <class R>
+static void enqueue_step_t(af_handle* h, int in, double dt_host) {
+  const Params P = make_params(h);
+  const Bufs B = handle_bufs(h, in);
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
   if (h->timing) {
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     (void)hipEventCreate(&e2);
   }
-  launch_step<R>(P, B, h->dev, h->limiter != 0, (h->tsw || h->shock), dt_host, in, h->stream,
-                 e0, e1, e2, h->flux_limiter ? h->TH : nullptr);
+  launch_step<R>(P, B, h->d_desc, h->dev, h->limiter != 0, (h->tsw || h->shock), dt_host, in,
+                 h->stream, e0, e1, e2, h->flux_limiter ? h->TH : nullptr);
   if (h->timing) {
     h->ev.push_back(e0);
     h->ev.push_back(e1);
@@ -882,6 +927,7 @@ extern "C" int af_step(af_handle* h, double dt) {
   ds.steps_limit = LLONG_MAX;
   HIP_OK(hipMemcpyAsync(h->dev, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
   const long long before = ds.steps;
+  if ((e = ensure_desc(h))) return e;
   enqueue_step(h, h->cur, dt);
   HIP_OK(hipGetLastError(), h);
   if ((e = read_dev(h, &ds))) return e;
@@ -910,6 +956,7 @@ extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
   ds.smax[0] = ds.smax[1] = 0ull;
   ds.steps_limit = max_steps > 0 ? steps0 + max_steps : LLONG_MAX;
   HIP_OK(hipMemcpyAsync(h->dev, &ds, sizeof(ds), hipMemcpyHostToDevice, h->stream), h);
+  if ((e = ensure_desc(h))) return e;
   {
     const Params P = make_params(h);
     const int c = h->cur;
@@ -1009,8 +1056,9 @@ extern "C" int af_set_inflow(af_handle* h, int32_t g, int32_t side, const double
     return fail(h, AF_ERR_INVALID_ARG, "af_set_inflow: need finite W with rho > 0 and p > 0");
   for (int v = 0; v < 4; ++v) h->sides[g].inflow[side][v] = W[v];
   h->sides[g].set |= 1u << side;
-  // the parameters are baked into captured graphs and the batched descriptors
+  // the parameters are baked into captured graphs and the device descriptors
   if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; h->gexec_steps = 0; }
+  h->desc_valid = false;
   batch_invalidate(h);
   return AF_OK;
 }
@@ -1105,9 +1153,11 @@ extern "C" int af_step_noalloc(const af_grid* grid, double gamma, const af_bc* b
   }
   P.tsw = 0; P.shock = 0; P.pU = 0; P.sU = 0;
 
-  // scratch layout: step control, fix-up masks (4 words per tile), fix-up list, flux sums
+  // scratch layout: step control, grid descriptor, fix-up masks (4 words per tile), fix-up
+  // list, flux sums
   const size_t ntiles = (size_t)P.tiles_x * P.tiles_y;
-  const size_t o_mask = align256(sizeof(DevState));
+  const size_t o_desc = align256(sizeof(DevState));
+  const size_t o_mask = align256(o_desc + sizeof(GridDesc));
   const size_t o_list = align256(o_mask + ntiles * 4 * sizeof(unsigned long long));
   const size_t o_flux = align256(o_list + ntiles * sizeof(int));
   const size_t flux_words = (size_t)P.sF * 16;  // FK: 8 variables, FX: 4, FY: 4
@@ -1135,12 +1185,16 @@ extern "C" int af_step_noalloc(const af_grid* grid, double gamma, const af_bc* b
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long nmask = (long long)ntiles * 4;
   const int ib = (int)std::min<long long>((nmask + 255) / 256, 1024);
+  GridDesc* desc = reinterpret_cast<GridDesc*>(sp + o_desc);
   hipLaunchKernelGGL(k_noalloc_init, dim3(std::max(ib, 1)), dim3(256), 0, s, dev, B.fix_mask,
                      nmask);
+  hipLaunchKernelGGL(k_write_desc, dim3(1), dim3(64), 0, s, desc, P, B, B);
   if (precision == AF_PREC_FP32)
-    launch_step<float>(P, B, dev, limiter != 0, false, dt, 0, s, nullptr, nullptr, nullptr);
+    launch_step<float>(P, B, desc, dev, limiter != 0, false, dt, 0, s, nullptr, nullptr,
+                       nullptr);
   else
-    launch_step<double>(P, B, dev, limiter != 0, false, dt, 0, s, nullptr, nullptr, nullptr);
+    launch_step<double>(P, B, desc, dev, limiter != 0, false, dt, 0, s, nullptr, nullptr,
+                        nullptr);
   hipError_t he = hipGetLastError();
   if (he != hipSuccess)
     return fail(nullptr, AF_ERR_DEVICE, std::string("af_step_noalloc: launch: ") + hipGetErrorString(he));

@@ -234,3 +234,27 @@ def test_batch_schedules_give_identical_results():
         s.set_option(af.AF_OPT_TILE_ORDER, 0)
     s.close()
 
+
+
+def test_timing_counts_only_steps_that_ran():
+    """With AF_OPT_TIMING the batched run still enqueues whole chunks of steps; the launches
+    after every grid has reached its step limit or t_end return at once and must not enter the
+    mean kernel times.  The count that af_get_timing reports is the number of steps taken,
+    for single and batched handles alike, and a real step is not shorter than a third of the
+    single-grid step on the same grid (a mean over no-op launches would be)."""
+    _flush("[gpu] timing counts only executed steps")
+    st = I.fourier_state(1, I.Grid(512, 512, 0.0, 1.0, 0.0, 1.0), I.GAMMA, 2)
+    s = af.Solver.for_state(st, precision=1)
+    s.set_option(af.AF_OPT_TIMING, 1)
+    t, n = s.run(1e9, 0.3, 3)
+    mp_s, mu_s, n_s = s.timing()
+    s.close()
+    assert n == 3 and n_s == 3
+    b = af.BatchSolver.for_states([st], precision=1)
+    b.set_option(af.AF_OPT_TIMING, 1)
+    t, n = b.run(1e9, 0.3, 3)  # one chunk of 16 launches, 13 of them no-ops
+    mp_b, mu_b, n_b = b.timing()
+    b.close()
+    _flush(f"  single {mp_s / n_s:.4f} ms, batched {mp_b / n_b:.4f} ms per point kernel")
+    assert n == 3 and n_b == 3
+    assert mp_b / n_b > (mp_s / n_s) / 3.0
