@@ -22,40 +22,34 @@
 
 namespace af {
 
-// Point kernel over the tiles of all grids.  Workgroup b evolves tile block_tile[b] (a
-// permutation of the global tiles: the schedule, see set_order).
-template <class R>
-__device__ __forceinline__ void batch_points(Smem<R>& S, const GridDesc* __restrict__ desc,
-                                             const int* __restrict__ tile_grid,
-                                             const int* __restrict__ block_tile,
+// Point kernel over the tiles of all grids.  Workgroup b evolves the tile block_tile[b] =
+// (grid, tile within the grid): a permutation of the global tiles (the schedule, see
+// set_order).  One table read names the grid, so the grid's descriptor and step control are
+// the next loads and the first staging loads the ones after.
+template <class R, bool IND = false>
+__device__ __forceinline__ void batch_points(Smem<R>& S, Ind* I, const GridDesc* __restrict__ desc,
+                                             const int2* __restrict__ block_tile,
                                              DevState* devs, double dt_host) {
-  __shared__ int s_g, s_cur;
-  const int t = block_tile[blockIdx.x];
-  if (threadIdx.x == 0) {
-    const int g = tile_grid[t];
-    s_g = g;
-    s_cur = devs[g].cur;
-  }
-  __syncthreads();
-  const int g = __builtin_amdgcn_readfirstlane(s_g);
-  const int cur = __builtin_amdgcn_readfirstlane(s_cur);
+  const int2 gt = block_tile[blockIdx.x];
+  const int g = __builtin_amdgcn_readfirstlane(gt.x);
+  const int local = __builtin_amdgcn_readfirstlane(gt.y);
+  const int cur = __builtin_amdgcn_readfirstlane(devs[g].cur);
   const Params& P = desc[g].P;
   const Bufs& B = desc[g].B[cur];
-  const int local = t - desc[g].tile_base;
-  points_body<R>(S, nullptr, P, B, devs + g, dt_host, cur, local, local == 0);
+  points_body<R, IND>(S, I, P, B, devs + g, dt_host, cur, local, local == 0);
 }
 
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
-void kb_points_f32(const GridDesc* desc, const int* tile_grid, const int* block_tile,
+void kb_points_f32(const GridDesc* __restrict__ desc, const int2* __restrict__ block_tile,
                    DevState* devs, double dt_host) {
   __shared__ Smem<float> S;
-  batch_points<float>(S, desc, tile_grid, block_tile, devs, dt_host);
+  batch_points<float>(S, nullptr, desc, block_tile, devs, dt_host);
 }
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
-void kb_points_f64(const GridDesc* desc, const int* tile_grid, const int* block_tile,
+void kb_points_f64(const GridDesc* __restrict__ desc, const int2* __restrict__ block_tile,
                    DevState* devs, double dt_host) {
   __shared__ Smem<double> S;
-  batch_points<double>(S, desc, tile_grid, block_tile, devs, dt_host);
+  batch_points<double>(S, nullptr, desc, block_tile, devs, dt_host);
 }
 
 // With the shock indicators (Algorithm 2, Sec. 3.4): the point kernel's indicator variant.  At
@@ -63,24 +57,11 @@ void kb_points_f64(const GridDesc* desc, const int* tile_grid, const int* block_
 // allows and runs one wave per SIMD.
 template <class R>
 __global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
-void kb_points_ind(const GridDesc* desc, const int* tile_grid, const int* block_tile,
+void kb_points_ind(const GridDesc* __restrict__ desc, const int2* __restrict__ block_tile,
                    DevState* devs, double dt_host) {
   __shared__ Smem<R> S;
   __shared__ Ind I;
-  __shared__ int s_g, s_cur;
-  const int t = block_tile[blockIdx.x];
-  if (threadIdx.x == 0) {
-    const int g = tile_grid[t];
-    s_g = g;
-    s_cur = devs[g].cur;
-  }
-  __syncthreads();
-  const int g = __builtin_amdgcn_readfirstlane(s_g);
-  const int cur = __builtin_amdgcn_readfirstlane(s_cur);
-  const Params& P = desc[g].P;
-  const Bufs& B = desc[g].B[cur];
-  const int local = t - desc[g].tile_base;
-  points_body<R, true>(S, &I, P, B, devs + g, dt_host, cur, local, local == 0);
+  batch_points<R, true>(S, &I, desc, block_tile, devs, dt_host);
 }
 
 // Primitive Simpson averages of every grid's padded cells (-2 .. nx+1 x -2 .. ny+1) from its
@@ -135,53 +116,63 @@ __device__ __forceinline__ void batch_fixup(Smem<R>& S, Ind* I, const GridDesc* 
     __syncthreads();  // the next entry overwrites the shared values
   }
 }
-__global__ __launch_bounds__(PT_THREADS) void kb_fixup_f32(const GridDesc* desc,
-                                                          const int* tile_grid, DevState* devs,
-                                                          const int* fix_list,
-                                                          const unsigned int* fix_count) {
+__global__ __launch_bounds__(PT_THREADS)
+void kb_fixup_f32(const GridDesc* __restrict__ desc, const int* __restrict__ tile_grid,
+                  DevState* devs, const int* __restrict__ fix_list,
+                  const unsigned int* fix_count) {
   __shared__ Smem<float> S;
   batch_fixup<float>(S, nullptr, desc, tile_grid, devs, fix_list, fix_count);
 }
-__global__ __launch_bounds__(PT_THREADS) void kb_fixup_f64(const GridDesc* desc,
-                                                          const int* tile_grid, DevState* devs,
-                                                          const int* fix_list,
-                                                          const unsigned int* fix_count) {
+__global__ __launch_bounds__(PT_THREADS)
+void kb_fixup_f64(const GridDesc* __restrict__ desc, const int* __restrict__ tile_grid,
+                  DevState* devs, const int* __restrict__ fix_list,
+                  const unsigned int* fix_count) {
   __shared__ Smem<double> S;
   batch_fixup<double>(S, nullptr, desc, tile_grid, devs, fix_list, fix_count);
 }
 
 template <class R>
-__global__ __launch_bounds__(PT_THREADS) void kb_fixup_ind(const GridDesc* desc,
-                                                           const int* tile_grid, DevState* devs,
-                                                           const int* fix_list,
-                                                           const unsigned int* fix_count) {
+__global__ __launch_bounds__(PT_THREADS)
+void kb_fixup_ind(const GridDesc* __restrict__ desc, const int* __restrict__ tile_grid,
+                  DevState* devs, const int* __restrict__ fix_list,
+                  const unsigned int* fix_count) {
   __shared__ Smem<R> S;
   __shared__ Ind I;
   batch_fixup<R, true>(S, &I, desc, tile_grid, devs, fix_list, fix_count);
 }
 
-// Update kernel: one workgroup of T threads per row of cells of any grid (XCD-aware row
-// order), the grid's largest new wave speed by one atomic per row.
+// Update kernel.  The cells of a grid are taken as pairs of neighbours in a row (the last pair of
+// a row of odd length is one cell), numbered row by row, and cut into chunks of T pairs; a work
+// item is one chunk of one grid ((grid, chunk) in `items`), one workgroup per item in an
+// XCD-aware order.  Lanes stay busy across the ends of short rows, and neighbouring workgroups
+// read neighbouring memory.  The grid's largest new wave speed goes out by one atomic per item.
+// Two waves per SIMD, as the single-grid update: the register budget lets every load of a cell
+// pair be in flight before its first use (left alone, the compiler takes 116 registers for four
+// waves and the loads go out in groups).
 template <int T>
-__global__ __launch_bounds__(T) void kb_update(const GridDesc* __restrict__ desc,
-                                              const int* __restrict__ row_grid, int total_rows,
-                                              DevState* devs) {
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void kb_update(const GridDesc* __restrict__ desc, const int2* __restrict__ items,
+               int total_items, DevState* devs) {
   __shared__ double red[(T + 63) / 64];
-  const int r = tile_of_block(blockIdx.x, total_rows);
-  const int g = __builtin_amdgcn_readfirstlane(row_grid[r]);
+  const int2 it = items[tile_of_block(blockIdx.x, total_items)];
+  const int g = __builtin_amdgcn_readfirstlane(it.x);
   const Params& P = desc[g].P;
   DevState* dev = devs + g;
-  const int cur = dev->cur;
+  const int cur = __builtin_amdgcn_readfirstlane(dev->cur);
   const Bufs& B = desc[g].B[cur];
   const bool run = !dev->err && dev->active;
   const double dt = dev->dt;
   const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
-  const int j = r - desc[g].row_base;
+  // pairs per row and this thread's pair (below 2^31: at most 65536 rows of 32768 pairs)
+  const unsigned ppr = (unsigned)(P.nx + 1) >> 1;
+  const unsigned pair = (unsigned)it.y * T + threadIdx.x;
   double speed = 0.0;
   bool bad = false;
-  if (run)
-    for (int i = 2 * threadIdx.x; i < P.nx; i += 2 * T)
-      if (!update_pair(P, B.A_in, B.A_out, B.FK, B.FX, B.FY, lx, ly, i, j, speed)) bad = true;
+  if (run && pair < ppr * (unsigned)P.ny) {
+    const unsigned j = pair / ppr;
+    const int i = 2 * (int)(pair - j * ppr);
+    if (!update_pair(P, B.A_in, B.A_out, B.FK, B.FX, B.FY, lx, ly, i, (int)j, speed)) bad = true;
+  }
   if (bad) set_err(dev, ERR_NONPHYS);
   for (int off = 32; off > 0; off >>= 1) speed = mx(speed, __shfl_xor(speed, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = speed;
@@ -234,7 +225,7 @@ struct BatchGrid {
   size_t oA, oP, oF;       // element offsets of the grid in the packed arrays
   long long pU;            // row pitch of the padded primitive averages (indicators)
   size_t oU;               // element offset of those
-  int tile_base, tiles_x, tiles_y, row_base;
+  int tile_base, tiles_x, tiles_y;
   bool has_state;
 };
 
@@ -253,24 +244,42 @@ struct Batch {
   unsigned int* fix_count = nullptr;
   GridDesc* d_desc = nullptr;
   int* d_tile_grid = nullptr;
-  int* d_row_grid = nullptr;
+  int2* d_items = nullptr;       // update work items (grid, chunk of bu_threads cell pairs)
+  int total_items = 0;           // for the current bu_threads
   double* UB = nullptr;          // padded primitive averages (allocated with the indicators)
   int* d_prow_grid = nullptr;    // grid of every padded row
   int* d_prow_base = nullptr;    // first padded row of every grid
   int total_prows = 0;
   DevState* d_devs = nullptr;
-  int total_tiles = 0, total_rows = 0;
+  int total_tiles = 0;
   bool desc_valid = false;
   // schedule: tile order of the point kernel (AF_ORDER_*), workgroup size of the update kernel
   int order = -1;
   int bu_threads = 128;
-  int* d_block_tile = nullptr;
+  int2* d_block_tile = nullptr;       // (grid, tile within the grid) of every workgroup
   std::vector<long long> grid_tiles;  // tiles per grid (host copy for the orders)
+  std::vector<int> tile_grid;         // grid of every global tile (host copy)
   hipGraphExec_t gexec = nullptr;
   int gexec_steps = 0;
 };
 
 static size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+// Update work items for chunks of `pairs` cell pairs: their number, and (with `out`) the table
+// (grid, chunk) grid after grid.
+static long long update_items(const Batch* b, int pairs, std::vector<int2>* out = nullptr) {
+  long long total = 0;
+  if (out) out->clear();
+  for (int g = 0; g < b->n; ++g) {
+    const BatchGrid& q = b->g[g];
+    const long long cells = (long long)((q.nx + 1) / 2) * q.ny;
+    const long long m = (cells + pairs - 1) / pairs;
+    if (out)
+      for (long long c = 0; c < m; ++c) out->push_back(make_int2(g, (int)c));
+    total += m;
+  }
+  return total;
+}
 
 static void batch_free(Batch* b) {
   for (int k = 0; k < 2; ++k) {
@@ -279,7 +288,7 @@ static void batch_free(Batch* b) {
   }
   for (void* p : {(void*)b->FK, (void*)b->FX, (void*)b->FY, (void*)b->fix_mask,
                   (void*)b->fix_list, (void*)b->fix_count, (void*)b->d_desc,
-                  (void*)b->d_tile_grid, (void*)b->d_row_grid, (void*)b->d_devs,
+                  (void*)b->d_tile_grid, (void*)b->d_items, (void*)b->d_devs,
                   (void*)b->UB, (void*)b->d_prow_grid, (void*)b->d_prow_base,
                   (void*)b->d_block_tile})
     if (p) (void)hipFree(p);
@@ -334,7 +343,7 @@ int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af
   b->n = n;
   b->g.resize(n);
   size_t nA = 0, nP = 0, nF = 0;
-  long long tiles = 0, rows = 0;
+  long long tiles = 0;
   for (int k = 0; k < n; ++k) {
     const af_grid& G = grids[k];
     const af_bc& bc = bcs[k];
@@ -353,17 +362,14 @@ int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af
     q.tiles_x = (q.nkx + TILE - 1) / TILE;
     q.tiles_y = (q.nky + TILE - 1) / TILE;
     q.tile_base = (int)tiles;
-    q.row_base = (int)rows;
     q.pU = 0;
     q.oU = 0;
     tiles += (long long)q.tiles_x * q.tiles_y;
-    rows += q.ny;
     q.has_state = false;
   }
-  if (tiles > INT_MAX / 2 || rows > INT_MAX / 2)
+  if (tiles > INT_MAX / 2)
     return fail(h, AF_ERR_INVALID_ARG, "af_create_batch: too many tiles");
   b->total_tiles = (int)tiles;
-  b->total_rows = (int)rows;
   for (int k = 0; k < 2; ++k) {
     HIP_OK(hipMalloc(&b->A[k], nA * 8), h);
     HIP_OK(hipMalloc(&b->K[k], nP * 8), h);
@@ -381,20 +387,22 @@ int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af
   HIP_OK(hipMalloc(&b->d_desc, (size_t)n * sizeof(GridDesc)), h);
   HIP_OK(hipMalloc(&b->d_devs, (size_t)n * sizeof(DevState)), h);
   HIP_OK(hipMemset(b->d_devs, 0, (size_t)n * sizeof(DevState)), h);
-  // the grid of every tile and of every row
-  std::vector<int> tg((size_t)tiles), rg((size_t)rows);
+  // the grid of every tile
+  std::vector<int> tg((size_t)tiles);
   for (int k = 0; k < n; ++k) {
     const BatchGrid& q = b->g[k];
     std::fill(tg.begin() + q.tile_base, tg.begin() + q.tile_base + q.tiles_x * q.tiles_y, k);
-    std::fill(rg.begin() + q.row_base, rg.begin() + q.row_base + q.ny, k);
   }
   b->grid_tiles.resize(n);
   for (int k = 0; k < n; ++k) b->grid_tiles[k] = (long long)b->g[k].tiles_x * b->g[k].tiles_y;
-  HIP_OK(hipMalloc(&b->d_block_tile, tg.size() * sizeof(int)), h);
+  HIP_OK(hipMalloc(&b->d_block_tile, tg.size() * sizeof(int2)), h);
   HIP_OK(hipMalloc(&b->d_tile_grid, tg.size() * sizeof(int)), h);
-  HIP_OK(hipMalloc(&b->d_row_grid, rg.size() * sizeof(int)), h);
   HIP_OK(hipMemcpy(b->d_tile_grid, tg.data(), tg.size() * sizeof(int), hipMemcpyHostToDevice), h);
-  HIP_OK(hipMemcpy(b->d_row_grid, rg.data(), rg.size() * sizeof(int), hipMemcpyHostToDevice), h);
+  b->tile_grid = tg;
+  // update work items: room for the smallest chunk (64 pairs), which gives the most items
+  if (update_items(b, 64) > INT_MAX / 2)
+    return fail(h, AF_ERR_INVALID_ARG, "af_create_batch: too many cells");
+  HIP_OK(hipMalloc(&b->d_items, (size_t)update_items(b, 64) * sizeof(int2)), h);
   (void)gamma;
   return batch_set_schedule(h, AF_ORDER_XCD, 128);
 }
@@ -449,9 +457,20 @@ int batch_set_schedule(af_handle* h, int order, int bu_threads) {
     return fail(h, AF_ERR_INVALID_ARG, "af_set_option: update threads must be 64, 128 or 256");
   if (order != b->order) {
     const std::vector<int> tab = block_tile_table(b, order);
-    HIP_OK(hipMemcpy(b->d_block_tile, tab.data(), tab.size() * sizeof(int),
+    std::vector<int2> gt(tab.size());
+    for (size_t k = 0; k < tab.size(); ++k) {
+      const int g = b->tile_grid[tab[k]];
+      gt[k] = make_int2(g, tab[k] - b->g[g].tile_base);
+    }
+    HIP_OK(hipMemcpy(b->d_block_tile, gt.data(), gt.size() * sizeof(int2),
                      hipMemcpyHostToDevice), h);
     b->order = order;
+  }
+  if (bu_threads != b->bu_threads || b->total_items == 0) {
+    std::vector<int2> items;
+    b->total_items = (int)update_items(b, bu_threads, &items);
+    HIP_OK(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int2),
+                     hipMemcpyHostToDevice), h);
   }
   b->bu_threads = bu_threads;
   if (b->gexec) {
@@ -503,7 +522,6 @@ static int upload_desc(af_handle* h) {
       B.tile_base = q.tile_base;
     }
     d[k].tile_base = q.tile_base;
-    d[k].row_base = q.row_base;
   }
   HIP_OK(hipMemcpyAsync(b->d_desc, d.data(), d.size() * sizeof(GridDesc), hipMemcpyHostToDevice,
                         h->stream), h);
@@ -636,13 +654,13 @@ static void enqueue_batch_step(af_handle* h, double dt_host, hipEvent_t* ev) {
     hipLaunchKernelGGL(kb_avgprim, dim3(b->total_prows), dim3(256), 0, h->stream, b->d_desc,
                        b->d_prow_grid, b->d_prow_base, b->d_devs);
     hipLaunchKernelGGL(kb_points_ind<R>, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
-                       b->d_desc, b->d_tile_grid, b->d_block_tile, b->d_devs, dt_host);
+                       b->d_desc, b->d_block_tile, b->d_devs, dt_host);
   } else if constexpr (sizeof(R) == 4) {
     hipLaunchKernelGGL(kb_points_f32, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
-                       b->d_desc, b->d_tile_grid, b->d_block_tile, b->d_devs, dt_host);
+                       b->d_desc, b->d_block_tile, b->d_devs, dt_host);
   } else {
     hipLaunchKernelGGL(kb_points_f64, dim3(b->total_tiles), dim3(PT_THREADS), 0, h->stream,
-                       b->d_desc, b->d_tile_grid, b->d_block_tile, b->d_devs, dt_host);
+                       b->d_desc, b->d_block_tile, b->d_devs, dt_host);
   }
   if (h->limiter) {
     const int nb = std::min(b->total_tiles, FIX_BLOCKS);
@@ -658,14 +676,14 @@ static void enqueue_batch_step(af_handle* h, double dt_host, hipEvent_t* ev) {
   }
   if (ev) (void)hipEventRecord(ev[1], h->stream);
   if (b->bu_threads == 64)
-    hipLaunchKernelGGL(kb_update<64>, dim3(b->total_rows), dim3(64), 0, h->stream, b->d_desc,
-                       b->d_row_grid, b->total_rows, b->d_devs);
+    hipLaunchKernelGGL(kb_update<64>, dim3(b->total_items), dim3(64), 0, h->stream, b->d_desc,
+                       b->d_items, b->total_items, b->d_devs);
   else if (b->bu_threads == 256)
-    hipLaunchKernelGGL(kb_update<256>, dim3(b->total_rows), dim3(256), 0, h->stream, b->d_desc,
-                       b->d_row_grid, b->total_rows, b->d_devs);
+    hipLaunchKernelGGL(kb_update<256>, dim3(b->total_items), dim3(256), 0, h->stream, b->d_desc,
+                       b->d_items, b->total_items, b->d_devs);
   else
-    hipLaunchKernelGGL(kb_update<128>, dim3(b->total_rows), dim3(128), 0, h->stream, b->d_desc,
-                       b->d_row_grid, b->total_rows, b->d_devs);
+    hipLaunchKernelGGL(kb_update<128>, dim3(b->total_items), dim3(128), 0, h->stream, b->d_desc,
+                       b->d_items, b->total_items, b->d_devs);
   hipLaunchKernelGGL(kb_commit, dim3((b->n + 63) / 64), dim3(64), 0, h->stream, b->d_devs, b->n,
                      b->fix_count);
   if (ev) (void)hipEventRecord(ev[2], h->stream);

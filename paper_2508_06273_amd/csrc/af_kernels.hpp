@@ -100,7 +100,6 @@ struct GridDesc {
   Params P;
   Bufs B[2];
   int tile_base;  // batched grids: first global tile of the grid
-  int row_base;   // batched grids: first global row of cells of the grid
 };
 
 // Periodic index of a (possibly ghost) cell or grid line, i >= -n.  The common case needs no

@@ -249,7 +249,6 @@ __global__ void k_write_desc(GridDesc* d, Params P, Bufs B0, Bufs B1) {
     d->B[0] = B0;
     d->B[1] = B1;
     d->tile_base = 0;
-    d->row_base = 0;
   }
 }
 
