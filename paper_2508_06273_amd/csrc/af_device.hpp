@@ -44,6 +44,9 @@ template <> struct Math<float> {
 template <class T> __device__ __forceinline__ T mx(T a, T b) { return a > b ? a : b; }
 template <class T> __device__ __forceinline__ T mn(T a, T b) { return a < b ? a : b; }
 template <class T> __device__ __forceinline__ T clamp1(T a) { return mn(mx(a, T(-1)), T(1)); }
+// |x| in the precision of x (__builtin_fabs alone would widen a float to double)
+__device__ __forceinline__ float absr(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double absr(double x) { return __builtin_fabs(x); }
 
 // ------------------------------------------------------------------------------------------
 // Ideal gas (paper Sec. 2).  P2C is written without FMA contraction so that a host that

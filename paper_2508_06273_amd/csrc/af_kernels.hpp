@@ -292,7 +292,7 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const R rp = R(lin64[0]), up = R(lin64[1]), vp = R(lin64[2]), pp = R(lin64[3]);
   if (!admissible(rp, pp)) return ERR_NONPHYS;
   const R c = MA::sqrt_(qdiv(G.gamma * pp, rp));
-  if ((mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * tau >= G.half_h) return ERR_CFL;
+  if ((mx(absr(up), absr(vp)) + c) * tau >= G.half_h) return ERR_CFL;
   const R ic = qdiv(R(1), c);
   // foot point offset and circle radius in units of dx
   const R px = -up * tau * G.idx, py = -vp * tau * G.idx;
@@ -462,7 +462,7 @@ __device__ __forceinline__ int eg1_pc(const double* __restrict__ ub, int cb, con
   const R rp = R(lin64[0]), up = R(lin64[1]), vp = R(lin64[2]), pp = R(lin64[3]);
   if (!admissible(rp, pp)) return ERR_NONPHYS;
   const R c = MA::sqrt_(G.gamma * pp / rp);
-  if ((mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * tau >= G.half_h) return ERR_CFL;
+  if ((mx(absr(up), absr(vp)) + c) * tau >= G.half_h) return ERR_CFL;
   const R ic = R(1) / c;
   const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
   const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));

@@ -94,7 +94,7 @@ template <class R>
 __device__ __forceinline__ bool eg1_cfl_fails(const Geo<R>& G, const double Ut[4], double tau) {
   const R rp = R(Ut[0]), up = R(Ut[1]), vp = R(Ut[2]), pp = R(Ut[3]);
   const R c = Math<R>::sqrt_(G.gamma * pp / rp);
-  return (mx(__builtin_fabs(up), __builtin_fabs(vp)) + c) * R(tau) >= G.half_h;
+  return (mx(absr(up), absr(vp)) + c) * R(tau) >= G.half_h;
 }
 
 template <class R, int KIND, bool FIX, bool IND>

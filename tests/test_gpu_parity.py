@@ -485,7 +485,8 @@ def test_vortex_error_matches_oracle(golden_dir):
     """The vortex accuracy gate: after t = 0.25 at 128^2 and 256^2 (Algorithm 1, CFL 0.3), the
     FP64 path's L1 error against the exact translated vortex equals the FP64 oracle's error
     (tests/golden/vortex_t025_oracle.txt, written by make_vortex_t025.py from the oracle) to
-    1e-5 relative; the FP32-bulk path's error equals it to 1e-2 relative."""
+    1e-5 relative; the FP32-bulk path's error equals it to 2e-4 relative (measured: a few
+    1e-5; the FP32 rounding of the EG2 deviations is far below the truncation error here)."""
     from conftest import load_table
     tab = {int(r[0]): r for r in load_table(f"{golden_dir}/vortex_t025_oracle.txt")}
     for n in (128, 256):
@@ -502,7 +503,7 @@ def test_vortex_error_matches_oracle(golden_dir):
             rel = np.abs(l1 - ref_l1) / ref_l1
             _flush(f"    L1 {l1.tolist()} oracle {ref_l1.tolist()} relative difference "
                    f"{rel.tolist()}")
-            assert np.all(rel <= (1e-5 if prec == 0 else 1e-2)), (n, prec, l1, ref_l1)
+            assert np.all(rel <= (1e-5 if prec == 0 else 2e-4)), (n, prec, l1, ref_l1)
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
