@@ -615,8 +615,8 @@ __device__ __forceinline__ void prep_cell(Smem<R>& S, const Params& P, const Buf
     if (owned && count) atomicAdd(&dev->cnt[AF_CNT_CENTRE], 1ull);
   }
   const double rho = P.aspect, rho2 = rho * rho;
-  // primitive Simpson average and monomial coefficients, one variable at a time
-#pragma unroll 1
+  // primitive Simpson average and monomial coefficients, variable by variable
+#pragma unroll
   for (int v = 0; v < 4; ++v) {
     double w[8];
 #pragma unroll
@@ -654,27 +654,31 @@ __device__ __forceinline__ void stage_and_prep(Smem<R>& S, const Params& P, cons
   // a tile whose halo (sites i0-1 .. i0+TILE, cells i0-1 .. i0+TILE-1, likewise in y) lies
   // inside the grid needs no boundary rule: the same for the whole block
   const bool inner = i0 >= 1 && j0 >= 1 && i0 + TILE <= P.nx - 1 && j0 + TILE <= P.ny - 1;
-  // the three source arrays as opaque values: a select among the fields of the kernel
-  // arguments would otherwise become an indexed load from a scratch copy of them
-  const double *srcK = B.K_in, *srcX = B.X_in, *srcY = B.Y_in;
-  asm("" : "+v"(srcK), "+v"(srcX), "+v"(srcY));
-
-  // 1. stage the t_n point values of the halo (local sites -1 .. TILE) in LDS
-  for (int e = tid; e < 3 * NS; e += PT_THREADS) {
-    const int kind = e / NS, s = e % NS;
-    const int a = s % HS - 1, b = s / HS - 1;
-    double W[4];
+  // 1. stage the t_n point values of the halo (local sites -1 .. TILE) in LDS: one site per
+  // thread, its K, X and Y values together (one index computation, twelve loads from the three
+  // arrays at one offset)
+  static_assert(NS <= PT_THREADS, "one halo site per thread");
+  if (tid < NS) {
+    const int a = tid % HS - 1, b = tid / HS - 1;
+    double W[3][4];
     if (inner) {
-      const double* src = kind == 0 ? srcK : (kind == 1 ? srcX : srcY);
       const long long o = (long long)(j0 + b) * P.pP + (i0 + a);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) W[v] = src[v * P.sP + o];
+      for (int v = 0; v < 4; ++v) {
+        W[0][v] = B.K_in[v * P.sP + o];
+        W[1][v] = B.X_in[v * P.sP + o];
+        W[2][v] = B.Y_in[v * P.sP + o];
+      }
     } else {
-      fetch_site(P, B, kind, i0 + a, j0 + b, W);
-    }
-    double* dst = kind == 0 ? S.sk : (kind == 1 ? S.sx : S.sy);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) dst[v * NS + s] = W[v];
+      for (int kind = 0; kind < 3; ++kind) fetch_site(P, B, kind, i0 + a, j0 + b, W[kind]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      S.sk[v * NS + tid] = W[0][v];
+      S.sx[v * NS + tid] = W[1][v];
+      S.sy[v * NS + tid] = W[2][v];
+    }
   }
   __syncthreads();
 
