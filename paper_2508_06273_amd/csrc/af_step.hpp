@@ -575,33 +575,26 @@ __device__ __forceinline__ void prep_cell(Smem<R>& S, const Params& P, const Buf
   const long long oa = (long long)gj * P.pA + gi;
 #pragma unroll
   for (int v = 0; v < 4; ++v) Qb[v] = B.A_in[v * P.sA + oa];
-  // reference state: mean of the eight nodes (exact for equal nodes)
-  double Wr[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    Wr[v] = ((((double)nptr[0][v * NS] + (double)nptr[1][v * NS]) +
-              ((double)nptr[2][v * NS] + (double)nptr[3][v * NS])) +
-             (((double)nptr[4][v * NS] + (double)nptr[5][v * NS]) +
-              ((double)nptr[6][v * NS] + (double)nptr[7][v * NS]))) * 0.125;
-  }
   // inverse Simpson for the centre value: Q_c = Q-bar + [sum_K (Q-bar - Q_k)
-  //                                          + 4 sum_E (Q-bar - Q_e)] / 16
-  double dQ[4], Uc[4];
+  //                                          + 4 sum_E (Q-bar - Q_e)] / 16,
+  // converted to primitive variables by deviation from the lower-left corner node Wr (so that
+  // equal nodes give the centre value Wr exactly)
+  double dQ[4], Uc[4], Wr[4];
   {
-    double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, W[4], Q[4];
+    double sK[4] = {0, 0, 0, 0}, sE[4] = {0, 0, 0, 0}, W[4], Q[4], Qr[4];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       node(k, W);
       p2c(W, g1inv, Q);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        if (k == 0) { Wr[v] = W[v]; Qr[v] = Q[v]; }
         if (k < 4) sK[v] += Qb[v] - Q[v];
         else sE[v] += Qb[v] - Q[v];
       }
     }
-    p2c(Wr, g1inv, Q);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Q[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
+    for (int v = 0; v < 4; ++v) dQ[v] = (Qb[v] - Qr[v]) + (sK[v] + 4.0 * sE[v]) * 0.0625;
   }
   c2p_dev(Wr, dQ, gm1, Uc);
   if (inflow) {
