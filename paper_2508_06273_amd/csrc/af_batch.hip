@@ -141,11 +141,13 @@ void kb_fixup_ind(const GridDesc* __restrict__ desc, const int* __restrict__ til
   batch_fixup<R, true>(S, &I, desc, tile_grid, devs, fix_list, fix_count);
 }
 
-// Update kernel.  The cells of a grid are taken as pairs of neighbours in a row (the last pair of
-// a row of odd length is one cell), numbered row by row, and cut into chunks of T pairs; a work
-// item is one chunk of one grid ((grid, chunk) in `items`), one workgroup per item in an
-// XCD-aware order.  Lanes stay busy across the ends of short rows, and neighbouring workgroups
-// read neighbouring memory.  The grid's largest new wave speed goes out by one atomic per item.
+// Update kernel.  The cells of a grid are taken as pairs of neighbours in a row, numbered row by
+// row, and cut into chunks of T pairs; in a grid of odd width the last cell of every row is left
+// out of the pairs, and these cells form chunks of T rows of their own after the pair chunks (so
+// that no wave mixes the paired and the single-cell code).  A work item is one chunk of one grid
+// ((grid, chunk) in `items`), one workgroup per item in an XCD-aware order.  Lanes stay busy
+// across the ends of short rows, and neighbouring workgroups read neighbouring memory.  The
+// grid's largest new wave speed goes out by one atomic per item.
 // Two waves per SIMD, as the single-grid update: the register budget lets every load of a cell
 // pair be in flight before its first use (left alone, the compiler takes 116 registers for four
 // waves and the loads go out in groups).
@@ -163,15 +165,26 @@ void kb_update(const GridDesc* __restrict__ desc, const int2* __restrict__ items
   const bool run = !dev->err && dev->active;
   const double dt = dev->dt;
   const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
-  // pairs per row and this thread's pair (below 2^31: at most 65536 rows of 32768 pairs)
-  const unsigned ppr = (unsigned)(P.nx + 1) >> 1;
-  const unsigned pair = (unsigned)it.y * T + threadIdx.x;
+  // full pairs per row, their number and chunks (below 2^31: at most 65536 rows of 32768 pairs)
+  const unsigned ppr = (unsigned)P.nx >> 1;
+  const unsigned npair = ppr * (unsigned)P.ny;
+  const unsigned nchunk = (npair + T - 1) / T;
   double speed = 0.0;
   bool bad = false;
-  if (run && pair < ppr * (unsigned)P.ny) {
-    const unsigned j = pair / ppr;
-    const int i = 2 * (int)(pair - j * ppr);
-    if (!update_pair(P, B.A_in, B.A_out, B.FK, B.FX, B.FY, lx, ly, i, (int)j, speed)) bad = true;
+  if (run) {
+    int i = -1, j = 0;
+    if ((unsigned)it.y < nchunk) {
+      const unsigned pair = (unsigned)it.y * T + threadIdx.x;
+      if (pair < npair) {
+        j = (int)(pair / ppr);
+        i = 2 * (int)(pair - (unsigned)j * ppr);
+      }
+    } else {  // the last cell of each row of a grid of odd width
+      j = (int)(((unsigned)it.y - nchunk) * T + threadIdx.x);
+      if (j < P.ny) i = P.nx - 1;
+    }
+    if (i >= 0 && !update_pair(P, B.A_in, B.A_out, B.FK, B.FX, B.FY, lx, ly, i, j, speed))
+      bad = true;
   }
   if (bad) set_err(dev, ERR_NONPHYS);
   for (int off = 32; off > 0; off >>= 1) speed = mx(speed, __shfl_xor(speed, off, 64));
@@ -265,15 +278,16 @@ struct Batch {
 
 static size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
 
-// Update work items for chunks of `pairs` cell pairs: their number, and (with `out`) the table
+// Update work items for chunks of `pairs` cell pairs (and, in a grid of odd width, chunks of
+// `pairs` rows for the last cell of each row): their number, and (with `out`) the table
 // (grid, chunk) grid after grid.
 static long long update_items(const Batch* b, int pairs, std::vector<int2>* out = nullptr) {
   long long total = 0;
   if (out) out->clear();
   for (int g = 0; g < b->n; ++g) {
     const BatchGrid& q = b->g[g];
-    const long long cells = (long long)((q.nx + 1) / 2) * q.ny;
-    const long long m = (cells + pairs - 1) / pairs;
+    const long long npair = (long long)(q.nx / 2) * q.ny;
+    const long long m = (npair + pairs - 1) / pairs + ((q.nx & 1) ? (q.ny + pairs - 1) / pairs : 0);
     if (out)
       for (long long c = 0; c < m; ++c) out->push_back(make_int2(g, (int)c));
     total += m;
