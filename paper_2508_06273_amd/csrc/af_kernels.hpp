@@ -267,7 +267,7 @@ template <class T> __device__ __forceinline__ const T* lds_base(const T* p) {
 }
 
 template <class R> struct Geo {
-  R idx, hy, gamma, half_h;
+  R idx, hy, gamma, half_h, dx;
 };
 
 // a / b in the bulk precision: IEEE division in FP64, hardware reciprocal (1 ulp) in FP32
@@ -278,11 +278,12 @@ template <> __device__ __forceinline__ float qdiv<float>(float a, float b) {
 
 // ------------------------------------------------------------------------------------------
 // EG2 at one DOF.  cb: LDS index of the lower-left cell around the DOF (K: cell (a-1,b-1);
-// X: cell (a-1,b); Y: cell (a,b-1)).  Returns the deviation dU = EG2[U] - lin.
+// X: cell (a-1,b); Y: cell (a,b-1)); tau: the evolution time, itau = 1 / tau (the FP64 path
+// forms 1 / (c' tau / dx) from it without a division).  Returns the deviation dU = EG2[U] - lin.
 // ------------------------------------------------------------------------------------------
 template <class R, int KIND>
 __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[4], R tau,
-                                   const Geo<R>& G, R dU[4]) {
+                                   R itau, const Geo<R>& G, R dU[4]) {
   using MA = Math<R>;
   // the coefficients of the lower-left cell and of the cell above it; their right neighbours
   // are constant offsets from them
@@ -291,7 +292,8 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const double* __restrict__ c0 = S.c0;
   const R rp = R(lin64[0]), up = R(lin64[1]), vp = R(lin64[2]), pp = R(lin64[3]);
   if (!admissible(rp, pp)) return ERR_NONPHYS;
-  const R c = MA::sqrt_(qdiv(G.gamma * pp, rp));
+  const R irho = qdiv(R(1), rp);
+  const R c = MA::sqrt_(G.gamma * pp * irho);
   if ((mx(absr(up), absr(vp)) + c) * tau >= G.half_h) return ERR_CFL;
   const R ic = qdiv(R(1), c);
   // foot point offset and circle radius in units of dx
@@ -410,13 +412,15 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const R dpP = poly_eval(dev0(3, cellP), chP + 3 * 8, 1, xiP, etaP);
 
   // undo the moment scaling: first-order integrals carry a factor ar, second-order ar^2
-  const R ia = qdiv(R(1), ar), ia2 = ia * ia;
+  // 1 / ar: in FP64 from 1/c and the caller's 1/tau (no division), in FP32 by the hardware
+  // reciprocal
+  const R ia = (sizeof(R) == 8) ? ic * itau * G.dx : qdiv(R(1), ar), ia2 = ia * ia;
   const R IpC = A.IpC * ia, IpS = A.IpS * ia, Jr = A.Jr * ia;
   const R Ju = R(2) * A.Ua * ia2 - R(0.5) * A.Ub;
   const R Jv = R(2) * A.Va * ia2 - R(0.5) * A.Vb;
   const R ipi = R(1.0 / kPi);
   const R ic2 = ic * ic;
-  const R irc = qdiv(ic, rp);
+  const R irc = ic * irho;
   const R rc = rp * c;
   dU[0] = drP - R(2) * dpP * ic2 + ipi * (A.Ip * ic2 - rp * ic * Jr);
   dU[1] = ipi * (Ju - IpC * irc);

@@ -101,7 +101,9 @@ template <class R, int KIND, bool FIX, bool IND>
 __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Params& P,
                                            const Bufs& B, DevState* dev, int tile, int a, int b,
                                            int gi, int gj, double dt, double& speed) {
-  const Geo<R> G = {R(P.idx), R(0.5 * P.dy * P.idx), R(P.gamma), R(0.5 * P.hmin)};
+  const Geo<R> G = {R(P.idx), R(0.5 * P.dy * P.idx), R(P.gamma), R(0.5 * P.hmin), R(P.dx)};
+  // 1 / tau of the three evaluations (tau = dt/4, dt/2, dt): powers of two times 1 / dt
+  const double idt = 1.0 / dt;
   const double* site = (KIND == KIND_K) ? S.sk : (KIND == KIND_X ? S.sx : S.sy);
   const int s0 = sidx(a, b);
   double U0[4];
@@ -155,7 +157,7 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Param
   double lin[4];
   if (P.mode == LIN_AF3) {
     R dq[4];
-    e = eg2<R, KIND>(S, cb, U0, R(0.25 * dt), G, dq);
+    e = eg2<R, KIND>(S, cb, U0, R(0.25 * dt), R(4.0 * idt), G, dq);
     if (e) { set_err(dev, e); return; }
     double q[4];
 #pragma unroll
@@ -201,7 +203,7 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Param
   double Uh[4], U1[4];
   {
     R d[4];
-    e = eg2<R, KIND>(S, cb, lin, R(0.5 * dt), G, d);
+    e = eg2<R, KIND>(S, cb, lin, R(0.5 * dt), R(2.0 * idt), G, d);
     if (e) { set_err(dev, e); return; }
 #pragma unroll
     for (int v = 0; v < 4; ++v) Uh[v] = lin[v] + (double)d[v] + h2 * (double)Cv[v];
@@ -242,7 +244,7 @@ __device__ __forceinline__ void evolve_dof(Smem<R>& S, const Ind* I, const Param
       for (int v = 0; v < 4; ++v) lf[v] = Uh[v];
     }
     R d[4];
-    e = eg2<R, KIND>(S, cb, lf, R(dt), G, d);
+    e = eg2<R, KIND>(S, cb, lf, R(dt), R(idt), G, d);
     if (e) { set_err(dev, e); return; }
 #pragma unroll
     for (int v = 0; v < 4; ++v) U1[v] = lf[v] + (double)d[v] + f2 * (double)Cv[v];
