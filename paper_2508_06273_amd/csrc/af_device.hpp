@@ -110,7 +110,10 @@ __device__ __forceinline__ void flux_fg(const double U[4], double g1inv, double 
 }
 
 __device__ __forceinline__ double wave_speed(const double U[4], double gamma) {
-  double c = __builtin_sqrt(gamma * U[3] / U[0]);
+  // c = sqrt(gamma p / rho) = gamma p / sqrt(gamma p rho): one reciprocal square root instead
+  // of a division and a square root
+  const double gp = gamma * U[3];
+  const double c = gp * ::rsqrt(gp * U[0]);
   return mx(__builtin_fabs(U[1]), __builtin_fabs(U[2])) + c;
 }
 

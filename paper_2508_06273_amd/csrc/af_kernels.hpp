@@ -293,9 +293,16 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
   const R rp = R(lin64[0]), up = R(lin64[1]), vp = R(lin64[2]), pp = R(lin64[3]);
   if (!admissible(rp, pp)) return ERR_NONPHYS;
   const R irho = qdiv(R(1), rp);
-  const R c = MA::sqrt_(G.gamma * pp * irho);
+  const R c2 = G.gamma * pp * irho;
+  R c, ic;
+  if constexpr (sizeof(R) == 8) {
+    ic = ::rsqrt(c2);  // 1/c without a square root and a division
+    c = c2 * ic;
+  } else {
+    c = MA::sqrt_(c2);
+    ic = qdiv(R(1), c);
+  }
   if ((mx(absr(up), absr(vp)) + c) * tau >= G.half_h) return ERR_CFL;
-  const R ic = qdiv(R(1), c);
   // foot point offset and circle radius in units of dx
   const R px = -up * tau * G.idx, py = -vp * tau * G.idx;
   const R ar = c * tau * G.idx;
