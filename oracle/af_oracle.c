@@ -342,20 +342,22 @@ static void field_arc(const field_t* F, int right, int top, double x, double y, 
   else memcpy(o, F->C->Ub + 4 * ghost_index(F->C, i, j), sizeof(double) * 4);
 }
 
-/* Value at the foot point P' = (x - u' tau, y - v' tau).  The cpq data are continuous, so
- * on a grid line either side gives the value.  For pc data a foot point on a grid line
- * takes the mean of the cells whose closure contains it (reading of the paper). */
+/* Value at the foot point P' = (x, y) = (xb - u' tau, yb - v' tau).  The cpq data are
+ * continuous, so on a grid line either side gives the value.  For pc data a foot point on a
+ * grid line takes the mean of the cells whose closure contains it (reading of the paper).
+ * P' - (xb, yb) = -tau (u', v') exactly, so the side of P' is read from the signs of u' and
+ * v' (tau > 0): the rounded coordinates can equal xb or yb while P' lies off the line. */
 static void field_point(const field_t* F, double xb, double yb, int vline, int hline,
-                        double x, double y, double o[4]) {
+                        double x, double y, double up, double vp, double o[4]) {
   if (F->cb || F->rec == 0) {
     field_arc(F, x >= xb, y >= yb, x, y, o);
     return;
   }
   int xs[2], ys[2], nxs = 1, nys = 1;
-  xs[0] = x > xb;
-  ys[0] = y > yb;
-  if (vline && x == xb) { xs[0] = 0; xs[1] = 1; nxs = 2; }
-  if (hline && y == yb) { ys[0] = 0; ys[1] = 1; nys = 2; }
+  xs[0] = up < 0.0;
+  ys[0] = vp < 0.0;
+  if (vline && up == 0.0) { xs[0] = 0; xs[1] = 1; nxs = 2; }
+  if (hline && vp == 0.0) { ys[0] = 0; ys[1] = 1; nys = 2; }
   double acc[4] = {0, 0, 0, 0}, t[4];
   for (int a = 0; a < nxs; ++a)
     for (int b = 0; b < nys; ++b) {
@@ -450,7 +452,7 @@ static int eg_generic(const field_t* F, int order, double xb, double yb, int vli
     }
   }
   double P[4];
-  field_point(F, xb, yb, vline, hline, Px, Py, P);
+  field_point(F, xb, yb, vline, hline, Px, Py, up, vp, P);
   if (order == 2) {
     out[0] = P[0] - 2.0 * P[3] / (cp * cp) + I[0] / PI;
     out[1] = I[1] / PI;
@@ -527,7 +529,10 @@ static void dof_avg_lin(const ctx* C, int kind, int i, int j, double o[4]) {
   if (kind == OR_KIND_K) {
     const double *a = Ubcell(C, i - 1, j - 1), *b = Ubcell(C, i, j - 1),
                  *d = Ubcell(C, i - 1, j), *e = Ubcell(C, i, j);
-    for (int v = 0; v < 4; ++v) o[v] = 0.25 * (a[v] + b[v] + d[v] + e[v]);
+    /* summed by rows: on a solid wall the ghost row (or the ghost cell of each row) is the
+     * mirror image of the interior one, and this order gives the exact mean, whose normal
+     * velocity is zero, so that EG1's foot point lies on the wall line (Sec. 4.3) */
+    for (int v = 0; v < 4; ++v) o[v] = 0.25 * ((a[v] + b[v]) + (d[v] + e[v]));
   } else if (kind == OR_KIND_X) {
     const double *a = Ubcell(C, i - 1, j), *b = Ubcell(C, i, j);
     for (int v = 0; v < 4; ++v) o[v] = 0.5 * (a[v] + b[v]);
