@@ -3,7 +3,12 @@ from 2 to 45 cells per side (one tile to six, ragged edges, cells from 3x as wid
 as high as wide), every kind of side on each side (periodic pairs, outflow, solid wall, inflow),
 the three linearisations, with and without the correction, with and without the positivity
 limiter, in both precisions.  Each case runs three steps on the GPU and in the FP64 oracle;
-tolerances as in the other parity tests (FP64 1e-12 * scale, FP32 bulk 1e-6 * scale)."""
+tolerances as in the other parity tests (FP64 1e-12 * scale, FP32 bulk 1e-6 * scale).
+
+A second sweep runs four-state Riemann data (transonic shocks along the dividing lines) through
+the indicators: Algorithm 2's linearisation switch, the Sec. 3.4 blend or both, with and without
+the positivity limiter, over random grids and sides.  It compares the error code, the method's
+counters (EG1 and LF fallbacks, transonic DOFs, ...) and the states after four steps."""
 import sys
 
 import numpy as np
@@ -82,4 +87,95 @@ def test_sweep_matches_oracle(k):
         out, t, n = outs[prec]
         assert n == 3, (prec, n)
         assert abs(t - st.t) <= tol * abs(st.t), (prec, t, st.t)
+        _assert_close(out, st, tol, f"prec {prec}")
+
+
+# Four constant states (lower left, lower right, upper left, upper right) whose flows collide,
+# so that the dividing lines carry transonic shocks (Algorithm 2) and jumps (Sec. 3.4).
+QUADRANTS = (np.array([1.0, 1.3, 1.3, 0.7]), np.array([1.8, -0.1, 1.3, 2.0]),
+             np.array([1.8, 1.3, -0.1, 2.0]), np.array([2.5, -0.2, -0.2, 3.0]))
+
+
+def _riemann(grid, xs, ys):
+    """QUADRANTS meeting at (xs, ys); point values on a dividing line take the mean of the
+    states on either side."""
+    def prim(x, y, sites):
+        W = np.zeros((4,) + x.shape)
+        for q, (r, t) in enumerate(((0, 0), (1, 0), (0, 1), (1, 1))):
+            wx = np.where(x > xs, 1.0, 0.0) if r else np.where(x < xs, 1.0, 0.0)
+            wy = np.where(y > ys, 1.0, 0.0) if t else np.where(y < ys, 1.0, 0.0)
+            if sites:
+                wx = wx + 0.5 * (x == xs)
+                wy = wy + 0.5 * (y == ys)
+            W += QUADRANTS[q][:, None] * (wx * wy).reshape(-1)[None, :] if x.ndim == 1 else \
+                QUADRANTS[q][(slice(None),) + (None,) * x.ndim] * (wx * wy)[None]
+        return W
+
+    avg = I.cell_average(lambda x, y: prim(x, y, False), grid, I.GAMMA, 4)
+    return I.State(grid, I.GAMMA, avg, prim(*grid.k_sites(), True),
+                   prim(*grid.x_sites(), True), prim(*grid.y_sites(), True))
+
+
+def _indicator_cases(n=12, seed=I.SEED_BASE + 9200):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        nx, ny = int(rng.integers(6, 40)), int(rng.integers(6, 40))
+        aspect = float(np.exp(rng.uniform(np.log(1 / 2), np.log(2))))
+        lx, ly = 1.0, aspect * ny / nx
+        sides = []
+        for axis in range(2):
+            if rng.random() < 0.25:
+                sides += [PER, PER]
+            else:
+                sides += [int(rng.choice([OUT, WALL, INFLOW])) for _ in range(2)]
+        inflow = tuple((float(rng.uniform(1.0, 2.0)), float(rng.uniform(-0.3, 0.3)),
+                        float(rng.uniform(-0.3, 0.3)), float(rng.uniform(1.0, 2.5)))
+                       if s == INFLOW else None for s in sides)
+        grid = I.Grid(nx, ny, 0.0, lx, 0.0, ly, sides=tuple(sides),
+                      inflow=inflow if INFLOW in sides else None)
+        opt = int(rng.integers(1, 4))  # 1: Algorithm 2, 2: Sec. 3.4 blend, 3: both
+        out.append(dict(grid=grid, xs=float(rng.uniform(0.3, 0.7)) * lx,
+                        ys=float(rng.uniform(0.3, 0.7)) * ly, mode=int(rng.integers(0, 3)),
+                        tsw=bool(opt & 1), shock=bool(opt & 2), limiter=bool(rng.random() < 0.5)))
+    return out
+
+
+IND_CASES = _indicator_cases()
+
+
+@pytest.mark.parametrize("k", range(len(IND_CASES)))
+def test_sweep_indicators_match_oracle(k):
+    c = IND_CASES[k]
+    g = c["grid"]
+    label = (f"indicator case {k}: {g.nx}x{g.ny} sides {g.side_kinds()} mode {c['mode']} "
+             f"transonic {c['tsw']} shock {c['shock']} limiter {c['limiter']}")
+    _flush(f"[gpu] sweep {label}")
+    st = _riemann(g, c["xs"], c["ys"])
+    outs = {}
+    for prec in (0, 1):
+        s = af.Solver.for_state(st, precision=prec, linearisation=c["mode"], limiter=c["limiter"],
+                                transonic=c["tsw"], shock_limiter=c["shock"])
+        try:
+            t, n = s.run(1e9, 0.3, 4)
+            outs[prec] = (0, s.get_state(), t, n, s.counters())
+        except af.AfError as err:
+            outs[prec] = (err.code, None, None, None, None)
+        s.close()
+    e, n2, cnt = oracle.run(st, 1e9, 0.3, max_steps=4, mode=c["mode"], limiter=c["limiter"],
+                            tsw=c["tsw"], shock=c["shock"])
+    assert outs[0][0] == e, (outs[0][0], e)
+    if e != 0:
+        return
+    for prec, tol in ((0, 1e-12), (1, 1e-6)):
+        code, out, t, n, gcnt = outs[prec]
+        assert code == 0 and n == 4, (prec, code, n)
+        assert abs(t - st.t) <= tol * abs(st.t), (prec, t, st.t)
+        if prec == 0:
+            # the method's counters (EG1, LF, centre, inner, transonic, limited faces) equal
+            # the oracle's; the library also counts the steps taken (AF_CNT_STEPS)
+            keep = [af.AF_CNT_EG1, af.AF_CNT_LF, af.AF_CNT_CENTRE, af.AF_CNT_INNER,
+                    af.AF_CNT_TSW, af.AF_CNT_FLUX]
+            assert [int(gcnt[i]) for i in keep] == [int(cnt[i]) for i in keep], (gcnt, cnt)
+            assert int(gcnt[af.AF_CNT_STEPS]) == 4
         _assert_close(out, st, tol, f"prec {prec}")
