@@ -182,7 +182,8 @@ def run_batched(prec, steps, warmup, stream, n_gl=2):
     b.set_option(af.AF_OPT_AUTOTUNE, 1)  # the warm-up run picks the schedule
     b.run(1e9, 0.3, warmup)
     schedule = {"tile_order": ["xcd", "linear", "grids"][b.get_option(af.AF_OPT_TILE_ORDER)],
-                "update_threads": b.get_option(af.AF_OPT_UPDATE_THREADS)}
+                "update_threads": b.get_option(af.AF_OPT_UPDATE_THREADS),
+                "step_kernel": ["split", "persistent"][b.get_option(af.AF_OPT_STEP_KERNEL)]}
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)

@@ -88,11 +88,12 @@ enum {
   AF_OPT_GRAPH_STEPS = 5,   /* steps per captured HIP graph in af_run (even, 0 = no graph) */
   AF_OPT_TIMING = 6,        /* 1: launch eagerly and time every kernel with HIP events on the
                                handle's stream (af_get_timing); 0 (default): off           */
-  AF_OPT_AUTOTUNE = 7,      /* batched handles: 1 = the next af_run times every tile order
-                               and update workgroup size on its first steps (2 steps each)
-                               and keeps the fastest; the results do not depend on the
-                               schedule.  0 (default): keep the current schedule.  No effect
-                               on single-grid handles.                                    */
+  AF_OPT_AUTOTUNE = 7,      /* batched handles: 1 = the next af_run times, on its first
+                               steps (2 steps each), every tile order and update workgroup
+                               size with separate kernels and every tile order with the
+                               persistent step kernel, and keeps the fastest schedule; the
+                               results do not depend on the schedule.  0 (default): keep the
+                               current schedule.  No effect on single-grid handles.       */
   AF_OPT_TILE_ORDER = 8,    /* batched handles: order in which the point kernel's workgroups
                                take the tiles of all grids (AF_ORDER_*; default XCD)      */
   AF_OPT_UPDATE_THREADS = 9, /* batched handles: workgroup size of the update kernel, one
@@ -118,7 +119,7 @@ enum {
                                averages is not admissible the value is not blended.
                                Algorithm 3 (AF_OPT_LIMITER) then runs on the blended value.
                                0 (default): off.                                          */
-  AF_OPT_FLUX_LIMITER = 12  /* 1: flux limiting of the cell averages (Sec. 3.5): every face
+  AF_OPT_FLUX_LIMITER = 12, /* 1: flux limiting of the cell averages (Sec. 3.5): every face
                                flux becomes gamma F + (1 - gamma) F_lo, F the Simpson flux,
                                F_lo the Rusanov flux of the t_n averages of the two cells,
                                gamma in [0, 1] the smaller over the two cells of the largest
@@ -129,11 +130,23 @@ enum {
                                admissible whenever the low-order updates are.  Faces need
                                no limiting in smooth flow (gamma = 1: the unlimited step,
                                bit for bit).  Single-grid handles.  0 (default): off.      */
+  AF_OPT_STEP_KERNEL = 13   /* batched handles: AF_STEP_SPLIT (default) launches the point,
+                               fix-up, update and commit kernels in turn; AF_STEP_PERSISTENT
+                               runs the whole step in one launch of a persistent kernel: as
+                               many workgroups as the GPU holds at once take the step's work
+                               (indicator rows, tiles, listed tiles, update chunks) from
+                               device-side queues, phase after phase, with grid-wide barriers
+                               between the phases, and the last to finish commits every grid.
+                               A barrier not reached within 2 s (workgroups not all resident,
+                               e.g. another kernel sharing the GPU) ends the step of every
+                               running grid with AF_ERR_DEVICE, the state kept at t_n.     */
 };
 /* Tile orders of the batched point kernel.  Workgroups are dealt to the GPU's 8 XCDs in turn;
  * AF_ORDER_XCD gives each XCD a contiguous range of the global tile index, AF_ORDER_LINEAR
  * takes the tiles in index order, AF_ORDER_GRIDS packs whole grids onto the XCDs. */
 enum { AF_ORDER_XCD = 0, AF_ORDER_LINEAR = 1, AF_ORDER_GRIDS = 2 };
+/* Step kernels of batched handles (AF_OPT_STEP_KERNEL). */
+enum { AF_STEP_SPLIT = 0, AF_STEP_PERSISTENT = 1 };
 /* AF_PREC_FP64: every operation in FP64.  AF_PREC_FP32 (FP32 bulk): the evolution operators
  * (moment recurrences, circle shifts and contractions of EG2 and EG1) and the correction term
  * run in FP32 on deviations from the linearisation state; point values and cell averages are
@@ -233,7 +246,8 @@ int af_get_timing(const af_handle* h, double* out);
 
 /* ---------------------------------------------------------------------------------------
  * Batched grids: many independent grids (own sizes, domains, boundaries, time steps) in one
- * handle, advanced together with one launch of each kernel per step for all grids.  This is
+ * handle, advanced together with one launch of each kernel per step for all grids, or with one
+ * launch of a persistent kernel per step (AF_OPT_STEP_KERNEL).  This is
  * the method of Sec. 2 applied to each grid independently; nothing couples the grids.
  * Options, af_set_stream, af_step, af_run, af_get_counters, af_get_timing, af_dof_count,
  * af_last_error and af_destroy work on batched handles as on single ones:

@@ -22,6 +22,15 @@
 
 namespace af {
 
+// Agent-scope load of a value another workgroup may have written earlier in the same launch.
+__device__ __forceinline__ int ld_agent(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __longlong_as_double(__hip_atomic_load(reinterpret_cast<const long long*>(p),
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 // Point kernel over the tiles of all grids.  Workgroup b evolves the tile block_tile[b] =
 // (grid, tile within the grid): a permutation of the global tiles (the schedule, see
 // set_order).  One table read names the grid, so the grid's descriptor and step control are
@@ -29,8 +38,8 @@ namespace af {
 template <class R, bool IND = false>
 __device__ __forceinline__ void batch_points(Smem<R>& S, Ind* I, const GridDesc* __restrict__ desc,
                                              const int2* __restrict__ block_tile,
-                                             DevState* devs, double dt_host) {
-  const int2 gt = block_tile[blockIdx.x];
+                                             DevState* devs, double dt_host, int k) {
+  const int2 gt = block_tile[k];
   const int g = __builtin_amdgcn_readfirstlane(gt.x);
   const int local = __builtin_amdgcn_readfirstlane(gt.y);
   const int cur = __builtin_amdgcn_readfirstlane(devs[g].cur);
@@ -43,13 +52,13 @@ __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
 void kb_points_f32(const GridDesc* __restrict__ desc, const int2* __restrict__ block_tile,
                    DevState* devs, double dt_host) {
   __shared__ Smem<float> S;
-  batch_points<float>(S, nullptr, desc, block_tile, devs, dt_host);
+  batch_points<float>(S, nullptr, desc, block_tile, devs, dt_host, blockIdx.x);
 }
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F64
 void kb_points_f64(const GridDesc* __restrict__ desc, const int2* __restrict__ block_tile,
                    DevState* devs, double dt_host) {
   __shared__ Smem<double> S;
-  batch_points<double>(S, nullptr, desc, block_tile, devs, dt_host);
+  batch_points<double>(S, nullptr, desc, block_tile, devs, dt_host, blockIdx.x);
 }
 
 // With the shock indicators (Algorithm 2, Sec. 3.4): the point kernel's indicator variant.  At
@@ -61,20 +70,20 @@ void kb_points_ind(const GridDesc* __restrict__ desc, const int2* __restrict__ b
                    DevState* devs, double dt_host) {
   __shared__ Smem<R> S;
   __shared__ Ind I;
-  batch_points<R, true>(S, &I, desc, block_tile, devs, dt_host);
+  batch_points<R, true>(S, &I, desc, block_tile, devs, dt_host, blockIdx.x);
 }
 
 // Primitive Simpson averages of every grid's padded cells (-2 .. nx+1 x -2 .. ny+1) from its
 // current state: one workgroup per padded row (prow_grid: the grid of each padded row).
-__global__ __launch_bounds__(256) void kb_avgprim(const GridDesc* __restrict__ desc,
-                                                  const int* __restrict__ prow_grid,
-                                                  const int* __restrict__ prow_base,
-                                                  DevState* devs) {
-  const int g = prow_grid[blockIdx.x];
+__device__ __forceinline__ void avgprim_row(const GridDesc* __restrict__ desc,
+                                            const int* __restrict__ prow_grid,
+                                            const int* __restrict__ prow_base, DevState* devs,
+                                            int row) {
+  const int g = prow_grid[row];
   const Params& P = desc[g].P;
   const Bufs& B = desc[g].B[devs[g].cur];
-  const int j = blockIdx.x - prow_base[g] - 2;
-  for (int i = (int)threadIdx.x - 2; i < P.nx + 2; i += 256) {
+  const int j = row - prow_base[g] - 2;
+  for (int i = (int)threadIdx.x - 2; i < P.nx + 2; i += (int)blockDim.x) {
     double ub[4];
     prim_average(P, B, i, j, ub);
     const long long o = (long long)(j + 2) * P.pU + (i + 2);
@@ -82,39 +91,51 @@ __global__ __launch_bounds__(256) void kb_avgprim(const GridDesc* __restrict__ d
     for (int v = 0; v < 4; ++v) B.UB[v * P.sU + o] = ub[v];
   }
 }
+__global__ __launch_bounds__(256) void kb_avgprim(const GridDesc* __restrict__ desc,
+                                                  const int* __restrict__ prow_grid,
+                                                  const int* __restrict__ prow_base,
+                                                  DevState* devs) {
+  avgprim_row(desc, prow_grid, prow_base, devs, blockIdx.x);
+}
 
 // Positivity fix-up over the global list of flagged tiles (entries are global tile indices).
+// Entry k of the list: the tile's grid, buffers and step from the device state.
+template <class R, bool IND = false>
+__device__ __forceinline__ void fixup_entry(Smem<R>& S, Ind* I, const GridDesc* __restrict__ desc,
+                                            const int* __restrict__ tile_grid, DevState* devs,
+                                            const int* fix_list, unsigned int k) {
+  __shared__ unsigned long long mask[3];
+  __shared__ int s_g, s_cur, s_run, s_tile;
+  __shared__ double s_dt;
+  if (threadIdx.x == 0) {
+    const int t = fix_list[k];
+    const int g = tile_grid[t];
+    s_g = g;
+    s_tile = t - desc[g].tile_base;
+    s_cur = devs[g].cur;
+    s_run = !ld_agent(&devs[g].err) && ld_agent(&devs[g].active);
+    s_dt = ld_agent(&devs[g].dt);
+  }
+  __syncthreads();
+  const int g = __builtin_amdgcn_readfirstlane(s_g);
+  const int cur = __builtin_amdgcn_readfirstlane(s_cur);
+  const Params& P = desc[g].P;
+  const Bufs& B = desc[g].B[cur];
+  double speed = 0.0;
+  fixup_tile<R, IND>(S, I, P, B, devs + g, s_tile, s_dt, s_run != 0, mask, speed);
+  block_max_atomic(speed, &devs[g].smax[cur ^ 1], S.red);
+  __syncthreads();  // the next entry overwrites the shared values
+}
 template <class R, bool IND = false>
 __device__ __forceinline__ void batch_fixup(Smem<R>& S, Ind* I, const GridDesc* __restrict__ desc,
                                             const int* __restrict__ tile_grid, DevState* devs,
                                             const int* fix_list, const unsigned int* fix_count) {
-  __shared__ unsigned long long mask[3];
   __shared__ unsigned int s_n;
-  __shared__ int s_g, s_cur, s_run, s_tile;
-  __shared__ double s_dt;
   if (threadIdx.x == 0) s_n = *fix_count;
   __syncthreads();
   const unsigned int n = s_n;
-  for (unsigned int k = blockIdx.x; k < n; k += gridDim.x) {
-    if (threadIdx.x == 0) {
-      const int t = fix_list[k];
-      const int g = tile_grid[t];
-      s_g = g;
-      s_tile = t - desc[g].tile_base;
-      s_cur = devs[g].cur;
-      s_run = !devs[g].err && devs[g].active;
-      s_dt = devs[g].dt;
-    }
-    __syncthreads();
-    const int g = __builtin_amdgcn_readfirstlane(s_g);
-    const int cur = __builtin_amdgcn_readfirstlane(s_cur);
-    const Params& P = desc[g].P;
-    const Bufs& B = desc[g].B[cur];
-    double speed = 0.0;
-    fixup_tile<R, IND>(S, I, P, B, devs + g, s_tile, s_dt, s_run != 0, mask, speed);
-    block_max_atomic(speed, &devs[g].smax[cur ^ 1], S.red);
-    __syncthreads();  // the next entry overwrites the shared values
-  }
+  for (unsigned int k = blockIdx.x; k < n; k += gridDim.x)
+    fixup_entry<R, IND>(S, I, desc, tile_grid, devs, fix_list, k);
 }
 __global__ __launch_bounds__(PT_THREADS)
 void kb_fixup_f32(const GridDesc* __restrict__ desc, const int* __restrict__ tile_grid,
@@ -152,18 +173,16 @@ void kb_fixup_ind(const GridDesc* __restrict__ desc, const int* __restrict__ til
 // pair be in flight before its first use (left alone, the compiler takes 116 registers for four
 // waves and the loads go out in groups).
 template <int T>
-__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void kb_update(const GridDesc* __restrict__ desc, const int2* __restrict__ items,
-               int total_items, DevState* devs) {
-  __shared__ double red[(T + 63) / 64];
-  const int2 it = items[tile_of_block(blockIdx.x, total_items)];
+__device__ __forceinline__ void update_item(const GridDesc* __restrict__ desc, int2 it,
+                                            DevState* devs, double* red) {
   const int g = __builtin_amdgcn_readfirstlane(it.x);
   const Params& P = desc[g].P;
   DevState* dev = devs + g;
   const int cur = __builtin_amdgcn_readfirstlane(dev->cur);
   const Bufs& B = desc[g].B[cur];
-  const bool run = !dev->err && dev->active;
-  const double dt = dev->dt;
+  // written by another workgroup earlier in the step (persistent kernel): agent-scope loads
+  const bool run = !ld_agent(&dev->err) && ld_agent(&dev->active);
+  const double dt = ld_agent(&dev->dt);
   const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
   // full pairs per row, their number and chunks (below 2^31: at most 65536 rows of 32768 pairs)
   const unsigned ppr = (unsigned)P.nx >> 1;
@@ -196,20 +215,28 @@ void kb_update(const GridDesc* __restrict__ desc, const int2* __restrict__ items
     atomic_max_pos(&dev->smax[cur ^ 1], m);
   }
 }
+template <int T>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void kb_update(const GridDesc* __restrict__ desc, const int2* __restrict__ items,
+               int total_items, DevState* devs) {
+  __shared__ double red[(T + 63) / 64];
+  update_item<T>(desc, items[tile_of_block(blockIdx.x, total_items)], devs, red);
+}
 
 // Commit: every grid whose step ran without error advances t and its step counter, clears the
 // wave-speed slot of the old state and switches to the other buffer.
-__global__ void kb_commit(DevState* devs, int n, unsigned int* fix_count) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g == 0) *fix_count = 0u;
-  if (g >= n) return;
-  DevState* d = devs + g;
+__device__ __forceinline__ void commit_grid(DevState* d) {
   if (!d->err && d->active) {
     d->t = d->last ? d->t_end : d->t + d->dt;
     d->steps += 1;
     d->smax[d->cur] = 0ull;
     d->cur ^= 1;
   }
+}
+__global__ void kb_commit(DevState* devs, int n, unsigned int* fix_count) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) *fix_count = 0u;
+  if (g < n) commit_grid(devs + g);
 }
 
 // Wave speed of every grid's current state into its smax[cur], before a run: `per` workgroups
@@ -224,6 +251,235 @@ __global__ void kb_cfl(const GridDesc* __restrict__ desc, DevState* devs, int pe
                                    (long long)part * blockDim.x + threadIdx.x,
                                    (long long)per * blockDim.x);
   block_max_atomic(speed, &devs[g].smax[cur], red);
+}
+
+// ------------------------------------------------------------------------------------------
+// The whole step in one persistent launch (AF_STEP_PERSISTENT).
+//
+// A fixed grid of workgroups, no more than can be resident on the GPU at once, takes the step's
+// work from device-side queues, phase after phase: the padded primitive averages (with the
+// indicators), the tiles of the point kernel, the tiles listed for the positivity fix-up (with
+// the limiter), the update items.  A grid-wide barrier separates the phases; the last workgroup
+// to finish commits every grid and leaves the queues empty for the next launch.  Each phase's
+// items are split over 8 queues, one per XCD (workgroup b runs on XCD b mod 8, and queue x
+// holds items x, x + 8, x + 16, ...), so that the tile orders keep their meaning (see
+// next_item).  The grid is a multiple of 8 workgroups.  Every wait is bounded: a
+// barrier not reached within SYNC_TIMEOUT_TICKS of the 100 MHz wall clock (workgroups that
+// were not all resident) flags `timeout`, and the step then ends every running grid with
+// ERR_SYNC instead of committing it.
+struct StepSync {
+  unsigned int head[8 * 16];  // queue heads, 64 bytes apart
+  unsigned int arrive, pad0[15];
+  unsigned int gen, pad1[15];
+  unsigned int done, pad2[15];
+  unsigned int timeout, pad3[15];
+};
+constexpr unsigned long long SYNC_TIMEOUT_TICKS = 200000000ull;  // 2 s
+constexpr unsigned int SYNC_MAX_POLLS = 1u << 26;  // a second bound, independent of the clock
+
+// Relaxed agent-scope load of a counter: no cache invalidation (an acquire would invalidate the
+// caches at every queue pop and every poll, and the tiles would lose their L2 halo reuse); the
+// barrier orders the data with fences of its own.
+__device__ __forceinline__ unsigned int ld_relaxed(const unsigned int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(unsigned int* p, unsigned int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Items of a phase with m items: queue x holds items x, x + 8, x + 16, ... below m (queue-local
+// index j: item x + 8 j); the workgroups of XCD x (b mod 8 = x, wpq = nb / 8 of them) take the
+// queue's first items by a fixed stride -- workgroup b takes j = b / 8, b / 8 + wpq, ... -- so
+// that together they walk the queue in order, as the hardware dispatches a kernel's workgroups,
+// with no atomic per item.  The last 2 wpq items of every queue are handed out one by one by
+// its head counter, to the queue's own workgroups first and then to those whose queues are
+// done.
+__device__ __forceinline__ int queue_len(int m, int x) { return x < m ? (m - x + 7) >> 3 : 0; }
+__device__ __forceinline__ int queue_tail(int m, int x, int wpq) {
+  return min(queue_len(m, x), 2 * wpq);
+}
+// A tail item for a workgroup on XCD `xcd` (thread 0 only): an index in [0, m), or -1 once
+// every tail is empty.
+__device__ __forceinline__ int pop_tail(StepSync* s, int m, int xcd, int wpq) {
+  for (int k = 0; k < 8; ++k) {
+    const int x = (xcd + k) & 7;
+    const unsigned int t = (unsigned int)queue_tail(m, x, wpq);
+    if (t == 0u || ld_relaxed(&s->head[16 * x]) >= t) continue;
+    const unsigned int p = atomicAdd(&s->head[16 * x], 1u);
+    if (p < t) return x + 8 * (queue_len(m, x) - (int)t + (int)p);
+  }
+  return -1;
+}
+
+// The workgroup's next item of a phase with m items, the same for all its threads; `j` (thread
+// 0's) is the workgroup's next fixed-stride index, b / 8 at the start of the phase, -1 once
+// they are done.
+__device__ __forceinline__ int next_item(StepSync* s, int m, int* s_item, int& j) {
+  if (threadIdx.x == 0) {
+    const int x = (int)(blockIdx.x & 7), wpq = (int)(gridDim.x >> 3);
+    int k = -1;
+    if (j >= 0) {
+      if (j < queue_len(m, x) - queue_tail(m, x, wpq)) {
+        k = x + 8 * j;
+        j += wpq;
+      } else {
+        j = -1;
+      }
+    }
+    if (k < 0) k = pop_tail(s, m, x, wpq);
+    *s_item = k;
+  }
+  __syncthreads();
+  const int k = *s_item;
+  __syncthreads();  // read by all before thread 0 overwrites it
+  return k;
+}
+
+// Grid-wide barrier of the `nb` workgroups; the last to arrive empties the queues for the
+// next phase.  Every wave releases its writes (agent scope) before the workgroup arrives and
+// acquires the other workgroups' after it leaves.
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void grid_barrier(StepSync* s, unsigned int nb) {
+  fence_release();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int g = ld_relaxed(&s->gen);
+    fence_release();  // the read of gen comes before the arrival
+    if (atomicAdd(&s->arrive, 1u) == nb - 1) {
+      for (int x = 0; x < 8; ++x) st_relaxed(&s->head[16 * x], 0u);
+      st_relaxed(&s->arrive, 0u);
+      __hip_atomic_fetch_add(&s->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned long long t0 = (unsigned long long)wall_clock64();
+      for (unsigned int it = 0; ld_relaxed(&s->gen) == g; ++it) {
+        __builtin_amdgcn_s_sleep(4);
+        if ((unsigned long long)wall_clock64() - t0 > SYNC_TIMEOUT_TICKS ||
+            it >= SYNC_MAX_POLLS) {
+          st_relaxed(&s->timeout, 1u);
+          break;
+        }
+      }
+    }
+    fence_acquire();
+  }
+  __syncthreads();
+  fence_acquire();
+}
+
+template <class R, bool LIM, bool IND>
+__device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __restrict__ desc,
+                                          const int2* __restrict__ block_tile, int n_tiles,
+                                          const int2* __restrict__ items, int n_items,
+                                          const int* __restrict__ tile_grid,
+                                          const int* __restrict__ prow_grid,
+                                          const int* __restrict__ prow_base, int n_prows,
+                                          DevState* devs, int n_grids, int* fix_list,
+                                          unsigned int* fix_count, StepSync* sync,
+                                          double dt_host) {
+  __shared__ int s_item;
+  __shared__ unsigned int s_n;
+  __shared__ int s_last;
+  // the later phases' arguments wait in LDS: kept in registers, they would stay live through
+  // the point phase and push its registers into spills
+  __shared__ const int2* s_items;
+  __shared__ const int* s_tile_grid;
+  __shared__ int* s_fix_list;
+  __shared__ unsigned int* s_fix_count;
+  __shared__ int s_n_items, s_n_grids;
+  if (threadIdx.x == 0) {
+    s_items = items;
+    s_tile_grid = tile_grid;
+    s_fix_list = fix_list;
+    s_fix_count = fix_count;
+    s_n_items = n_items;
+    s_n_grids = n_grids;
+  }
+  const unsigned int nb = gridDim.x;
+  const int j0 = (int)(blockIdx.x >> 3);
+  if constexpr (IND) {
+    for (int k, j = j0; (k = next_item(sync, n_prows, &s_item, j)) >= 0;)
+      avgprim_row(desc, prow_grid, prow_base, devs, k);
+    grid_barrier(sync, nb);
+  }
+  for (int k, j = j0; (k = next_item(sync, n_tiles, &s_item, j)) >= 0;)
+    batch_points<R, IND>(S, I, desc, block_tile, devs, dt_host, k);
+  grid_barrier(sync, nb);
+  if constexpr (LIM) {
+    if (threadIdx.x == 0) s_n = __hip_atomic_load(s_fix_count, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int nfix = (int)s_n;
+    const int* tg = s_tile_grid;
+    const int* fl = s_fix_list;
+    for (int k, j = j0; (k = next_item(sync, nfix, &s_item, j)) >= 0;)
+      fixup_entry<R, IND>(S, I, desc, tg, devs, fl, (unsigned int)k);
+    grid_barrier(sync, nb);
+  }
+  const int2* its = s_items;
+  const int nit = s_n_items;
+  for (int k, j = j0; (k = next_item(sync, nit, &s_item, j)) >= 0;)
+    update_item<PT_THREADS>(desc, its[tile_of_block(k, nit)], devs, S.red);
+  // the last workgroup to finish commits the step of every grid
+  fence_release();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_last = atomicAdd(&sync->done, 1u) == nb - 1;
+    fence_acquire();
+  }
+  __syncthreads();
+  if (!s_last) return;
+  fence_acquire();
+  const bool timed_out = ld_relaxed(&sync->timeout) != 0u;
+  const int ng = s_n_grids;
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    DevState* d = devs + g;
+    if (timed_out) {
+      if (!d->err && d->active) set_err(d, ERR_SYNC);
+    } else {
+      commit_grid(d);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int x = 0; x < 8; ++x) st_relaxed(&sync->head[16 * x], 0u);
+    st_relaxed(&sync->arrive, 0u);  // already 0 unless a barrier timed out
+    st_relaxed(&sync->done, 0u);
+    st_relaxed(&sync->timeout, 0u);
+    st_relaxed(s_fix_count, 0u);
+  }
+}
+
+#define AF_STEP_ARGS                                                                          \
+  const GridDesc *__restrict__ desc, const int2 *__restrict__ block_tile, int n_tiles,       \
+      const int2 *__restrict__ items, int n_items, const int *__restrict__ tile_grid,        \
+      const int *__restrict__ prow_grid, const int *__restrict__ prow_base, int n_prows,     \
+      DevState *devs, int n_grids, int *fix_list, unsigned int *fix_count, StepSync *sync,   \
+      double dt_host
+#define AF_STEP_PASS                                                                          \
+  desc, block_tile, n_tiles, items, n_items, tile_grid, prow_grid, prow_base, n_prows, devs, \
+      n_grids, fix_list, fix_count, sync, dt_host
+
+// At least as many waves per SIMD as the point kernels get (left alone, the update phase's
+// register budget lowers them: 3 -> 2 in FP32, 2 -> 1 in FP64).
+template <bool LIM>
+__global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+void kb_step_f32(AF_STEP_ARGS) {
+  __shared__ Smem<float> S;
+  step_body<float, LIM, false>(S, nullptr, AF_STEP_PASS);
+}
+template <bool LIM>
+__global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+void kb_step_f64(AF_STEP_ARGS) {
+  __shared__ Smem<double> S;
+  step_body<double, LIM, false>(S, nullptr, AF_STEP_PASS);
+}
+template <class R, bool LIM>
+__global__ __launch_bounds__(PT_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+void kb_step_ind(AF_STEP_ARGS) {
+  __shared__ Smem<R> S;
+  __shared__ Ind I;
+  step_body<R, LIM, true>(S, &I, AF_STEP_PASS);
 }
 
 }  // namespace af
@@ -269,6 +525,12 @@ struct Batch {
   // schedule: tile order of the point kernel (AF_ORDER_*), workgroup size of the update kernel
   int order = -1;
   int bu_threads = 128;
+  int step_kernel = AF_STEP_SPLIT;    // AF_STEP_SPLIT or AF_STEP_PERSISTENT
+  af::StepSync* d_sync = nullptr;     // queues and barrier of the persistent step kernel
+  int2* d_items_p = nullptr;          // its update items (chunks of PT_THREADS cell pairs)
+  int total_items_p = 0;
+  int step_cap[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // resident workgroups per step-kernel variant
+  int step_nb = 0;                              // workgroups of its next launches
   int2* d_block_tile = nullptr;       // (grid, tile within the grid) of every workgroup
   std::vector<long long> grid_tiles;  // tiles per grid (host copy for the orders)
   std::vector<int> tile_grid;         // grid of every global tile (host copy)
@@ -304,7 +566,7 @@ static void batch_free(Batch* b) {
                   (void*)b->fix_list, (void*)b->fix_count, (void*)b->d_desc,
                   (void*)b->d_tile_grid, (void*)b->d_items, (void*)b->d_devs,
                   (void*)b->UB, (void*)b->d_prow_grid, (void*)b->d_prow_base,
-                  (void*)b->d_block_tile})
+                  (void*)b->d_block_tile, (void*)b->d_sync, (void*)b->d_items_p})
     if (p) (void)hipFree(p);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   delete b;
@@ -417,8 +679,17 @@ int batch_create(int n, const af_grid* grids, double gamma, const af_bc* bcs, af
   if (update_items(b, 64) > INT_MAX / 2)
     return fail(h, AF_ERR_INVALID_ARG, "af_create_batch: too many cells");
   HIP_OK(hipMalloc(&b->d_items, (size_t)update_items(b, 64) * sizeof(int2)), h);
+  {
+    std::vector<int2> items;
+    b->total_items_p = (int)update_items(b, PT_THREADS, &items);
+    HIP_OK(hipMalloc(&b->d_items_p, items.size() * sizeof(int2)), h);
+    HIP_OK(hipMemcpy(b->d_items_p, items.data(), items.size() * sizeof(int2),
+                     hipMemcpyHostToDevice), h);
+  }
+  HIP_OK(hipMalloc(&b->d_sync, sizeof(StepSync)), h);
+  HIP_OK(hipMemset(b->d_sync, 0, sizeof(StepSync)), h);
   (void)gamma;
-  return batch_set_schedule(h, AF_ORDER_XCD, 128);
+  return batch_set_schedule(h, AF_ORDER_XCD, 128, AF_STEP_SPLIT);
 }
 
 // Workgroup-to-tile table of the point kernel for a tile order:
@@ -463,12 +734,15 @@ static std::vector<int> block_tile_table(const Batch* b, int order) {
   return tab;
 }
 
-int batch_set_schedule(af_handle* h, int order, int bu_threads) {
+int batch_set_schedule(af_handle* h, int order, int bu_threads, int step_kernel) {
   Batch* b = h->batch;
   if (order != AF_ORDER_XCD && order != AF_ORDER_LINEAR && order != AF_ORDER_GRIDS)
     return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown tile order");
   if (bu_threads != 64 && bu_threads != 128 && bu_threads != 256)
     return fail(h, AF_ERR_INVALID_ARG, "af_set_option: update threads must be 64, 128 or 256");
+  if (step_kernel != AF_STEP_SPLIT && step_kernel != AF_STEP_PERSISTENT)
+    return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown step kernel");
+  b->step_kernel = step_kernel;
   if (order != b->order) {
     const std::vector<int> tab = block_tile_table(b, order);
     std::vector<int2> gt(tab.size());
@@ -495,9 +769,10 @@ int batch_set_schedule(af_handle* h, int order, int bu_threads) {
   return AF_OK;
 }
 
-int batch_get_schedule(const af_handle* h, int* order, int* bu_threads) {
+int batch_get_schedule(const af_handle* h, int* order, int* bu_threads, int* step_kernel) {
   *order = h->batch->order;
   *bu_threads = h->batch->bu_threads;
+  *step_kernel = h->batch->step_kernel;
   return AF_OK;
 }
 
@@ -656,14 +931,82 @@ int batch_get_counters(const af_handle* h, int64_t* out) {
   return AF_OK;
 }
 
-// One step of every grid: point kernel, fix-up (limiter on), update, commit.
+// Launch of one persistent step-kernel variant with nb workgroups.
+template <class K>
+static void launch_step(K kernel, const Batch* b, hipStream_t st, int nb, double dt_host) {
+  hipLaunchKernelGGL(kernel, dim3(nb), dim3(PT_THREADS), 0, st, b->d_desc, b->d_block_tile,
+                     b->total_tiles, b->d_items_p, b->total_items_p, b->d_tile_grid,
+                     b->d_prow_grid, b->d_prow_base, b->total_prows, b->d_devs, b->n,
+                     b->fix_list, b->fix_count, b->d_sync, dt_host);
+}
+template <class R>
+static void launch_step(const af_handle* h, int nb, double dt_host) {
+  const Batch* b = h->batch;
+  const bool lim = h->limiter != 0, ind = h->tsw || h->shock;
+  if (ind) {
+    if (lim) launch_step(kb_step_ind<R, true>, b, h->stream, nb, dt_host);
+    else launch_step(kb_step_ind<R, false>, b, h->stream, nb, dt_host);
+  } else if constexpr (sizeof(R) == 4) {
+    if (lim) launch_step(kb_step_f32<true>, b, h->stream, nb, dt_host);
+    else launch_step(kb_step_f32<false>, b, h->stream, nb, dt_host);
+  } else {
+    if (lim) launch_step(kb_step_f64<true>, b, h->stream, nb, dt_host);
+    else launch_step(kb_step_f64<false>, b, h->stream, nb, dt_host);
+  }
+}
+
+// Workgroups of the persistent step kernel for the handle's options (into b->step_nb): as many
+// as the GPU holds at once -- every workgroup must be resident for the kernel's barriers -- or
+// fewer if the step has fewer items.
+template <class K>
+static int resident_blocks(K kernel, int* per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, PT_THREADS, 0) ==
+                 hipSuccess
+             ? AF_OK
+             : AF_ERR_DEVICE;
+}
+static int prepare_step_kernel(af_handle* h) {
+  Batch* b = h->batch;
+  if (b->step_kernel != AF_STEP_PERSISTENT) return AF_OK;
+  const bool lim = h->limiter != 0, ind = h->tsw || h->shock, f32 = h->prec == AF_PREC_FP32;
+  int& cap = b->step_cap[(f32 ? 4 : 0) + (lim ? 2 : 0) + (ind ? 1 : 0)];
+  if (cap == 0) {
+    int dev = 0, ncu = 0, per = 0, e = AF_OK;
+    HIP_OK(hipGetDevice(&dev), h);
+    HIP_OK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), h);
+    if (ind && f32) e = lim ? resident_blocks(kb_step_ind<float, true>, &per)
+                            : resident_blocks(kb_step_ind<float, false>, &per);
+    else if (ind) e = lim ? resident_blocks(kb_step_ind<double, true>, &per)
+                          : resident_blocks(kb_step_ind<double, false>, &per);
+    else if (f32) e = lim ? resident_blocks(kb_step_f32<true>, &per)
+                          : resident_blocks(kb_step_f32<false>, &per);
+    else e = lim ? resident_blocks(kb_step_f64<true>, &per) : resident_blocks(kb_step_f64<false>, &per);
+    if (e != AF_OK || per < 1 || ncu < 1 || per * ncu < 8)
+      return fail(h, AF_ERR_DEVICE, "persistent step kernel: occupancy query failed");
+    cap = per * ncu / 8 * 8;
+  }
+  const int work = std::max({b->total_tiles, b->total_items_p, ind ? b->total_prows : 0});
+  b->step_nb = std::max(1, std::min(cap, (work + 7) / 8 * 8));
+  return AF_OK;
+}
+
+// One step of every grid: point kernel, fix-up (limiter on), update, commit; or all of it in
+// one launch of the persistent step kernel.
 // `ev` (nullable): three events recorded before the point kernel, between the fix-up and the
-// update, and after the commit.
+// update, and after the commit (with the persistent kernel: before it, and twice after it).
 template <class R>
 static void enqueue_batch_step(af_handle* h, double dt_host, hipEvent_t* ev) {
   Batch* b = h->batch;
   if (ev) (void)hipEventRecord(ev[0], h->stream);
   const bool ind = h->tsw || h->shock;
+  if (b->step_kernel == AF_STEP_PERSISTENT) {
+    launch_step<R>(h, b->step_nb, dt_host);
+    if (ev) {
+      (void)hipEventRecord(ev[1], h->stream);
+      (void)hipEventRecord(ev[2], h->stream);
+    }
+    return;
+  }
   if (ind) {
     hipLaunchKernelGGL(kb_avgprim, dim3(b->total_prows), dim3(256), 0, h->stream, b->d_desc,
                        b->d_prow_grid, b->d_prow_base, b->d_devs);
@@ -736,30 +1079,44 @@ static int time_steps(af_handle* h, int steps, double* ms_points, double* ms_upd
   return AF_OK;
 }
 
-// Autotuner: time each tile order of the point kernel, then each workgroup size of the update
-// kernel, on `per` steps of the run each (every schedule computes the same values), and keep
-// the fastest.
+// Autotuner, on `per` steps of the run per trial (every schedule computes the same values):
+// with separate kernels, time each tile order of the point kernel, then each workgroup size of
+// the update kernel; then the persistent step kernel with each tile order.  Keeps the schedule
+// with the shortest step.
 static int autotune(af_handle* h, int per) {
   Batch* b = h->batch;
   const int orders[3] = {AF_ORDER_XCD, AF_ORDER_LINEAR, AF_ORDER_GRIDS};
   const int threads[3] = {64, 128, 256};
   double best = INFINITY, mp = 0.0, mu = 0.0;
   int best_order = b->order;
+  if (int e = batch_set_schedule(h, b->order, b->bu_threads, AF_STEP_SPLIT)) return e;
   if (int e = time_steps(h, 1, &mp, &mu)) return e;  // warm-up
   for (int o : orders) {
-    if (int e = batch_set_schedule(h, o, b->bu_threads)) return e;
+    if (int e = batch_set_schedule(h, o, b->bu_threads, AF_STEP_SPLIT)) return e;
     if (int e = time_steps(h, per, &mp, &mu)) return e;
     if (mp < best) { best = mp; best_order = o; }
   }
-  if (int e = batch_set_schedule(h, best_order, b->bu_threads)) return e;
-  best = INFINITY;
+  double split = INFINITY;
   int best_threads = b->bu_threads;
   for (int t : threads) {
-    if (int e = batch_set_schedule(h, best_order, t)) return e;
+    if (int e = batch_set_schedule(h, best_order, t, AF_STEP_SPLIT)) return e;
     if (int e = time_steps(h, per, &mp, &mu)) return e;
-    if (mu < best) { best = mu; best_threads = t; }
+    if (mp + mu < split) { split = mp + mu; best_threads = t; }
   }
-  return batch_set_schedule(h, best_order, best_threads);
+  double fused = INFINITY;
+  int fused_order = best_order, e_warm = AF_OK;
+  for (int o : orders) {
+    if (int e = batch_set_schedule(h, o, best_threads, AF_STEP_PERSISTENT)) return e;
+    if (int e = prepare_step_kernel(h)) return e;
+    if (o == orders[0] && (e_warm = time_steps(h, 1, &mp, &mu))) return e_warm;
+    if (int e = time_steps(h, per, &mp, &mu)) return e;
+    if (mp + mu < fused) { fused = mp + mu; fused_order = o; }
+  }
+  if (fused < split) {
+    if (int e = batch_set_schedule(h, fused_order, best_threads, AF_STEP_PERSISTENT)) return e;
+    return prepare_step_kernel(h);
+  }
+  return batch_set_schedule(h, best_order, best_threads, AF_STEP_SPLIT);
 }
 
 // Add the event times of the first `used` enqueued steps (those in which some grid advanced;
@@ -782,6 +1139,8 @@ static const char* batch_err_text(int code) {
   switch (code) {
     case ERR_NONPHYS: return "non-positive density or pressure";
     case ERR_CFL: return "time step too large: an evolution circle leaves its cells";
+    case ERR_SYNC: return "persistent step kernel: a grid barrier timed out (not all workgroups "
+                          "were resident); the step was not committed";
     default: return "device error";
   }
 }
@@ -804,6 +1163,7 @@ int batch_step(af_handle* h, double dt) {
   if (int e = check_all_state(h, "af_step")) return e;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(h, AF_ERR_INVALID_ARG, "af_step: dt must be > 0");
   if (int e = upload_desc(h)) return e;
+  if (int e = prepare_step_kernel(h)) return e;
   std::vector<DevState> ds;
   if (int e = read_devs(h, ds)) return e;
   for (DevState& d : ds) {
@@ -834,6 +1194,7 @@ int batch_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double*
   if (std::isnan(t_end)) return fail(h, AF_ERR_INVALID_ARG, "af_run: t_end is NaN");
   Batch* b = h->batch;
   if (int e = upload_desc(h)) return e;
+  if (int e = prepare_step_kernel(h)) return e;
   std::vector<DevState> ds;
   if (int e = read_devs(h, ds)) return e;
   std::vector<long long> steps0((size_t)b->n);

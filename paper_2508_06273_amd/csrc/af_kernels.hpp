@@ -19,7 +19,7 @@
 
 namespace af {
 
-enum { ERR_NONPHYS = -2, ERR_CFL = -3 };
+enum { ERR_NONPHYS = -2, ERR_CFL = -3, ERR_SYNC = -4 };
 enum { KIND_K = 0, KIND_X = 1, KIND_Y = 2 };
 enum { LIN_AF3 = 0, LIN_AVG = 1, LIN_SIMPLE = 2 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_WALL = 2, BC_INFLOW = 3 };

@@ -545,15 +545,17 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
       h->flux_limiter = (int)value;
       break;
     case AF_OPT_TILE_ORDER:
-    case AF_OPT_UPDATE_THREADS: {
+    case AF_OPT_UPDATE_THREADS:
+    case AF_OPT_STEP_KERNEL: {
       if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: batched handles only");
-      int order = 0, threads = 0;
-      batch_get_schedule(h, &order, &threads);
-      if (key == AF_OPT_TILE_ORDER) order = (int)value;
-      else threads = (int)value;
+      int order = 0, threads = 0, kernel = 0;
+      batch_get_schedule(h, &order, &threads, &kernel);
       if (value < 0 || value > 4096)
         return fail(h, AF_ERR_INVALID_ARG, "af_set_option: bad schedule value");
-      return batch_set_schedule(h, order, threads);
+      if (key == AF_OPT_TILE_ORDER) order = (int)value;
+      else if (key == AF_OPT_UPDATE_THREADS) threads = (int)value;
+      else kernel = (int)value;
+      return batch_set_schedule(h, order, threads, kernel);
     }
     default:
       return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown key");
@@ -566,7 +568,7 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
 
 extern "C" int af_get_option(const af_handle* h, int key, int64_t* value) {
   if (!h || !value) return fail(h, AF_ERR_INVALID_ARG, "af_get_option: NULL argument");
-  int order = 0, threads = 0;
+  int order = 0, threads = 0, kernel = 0;
   switch (key) {
     case AF_OPT_PRECISION: *value = h->prec; return AF_OK;
     case AF_OPT_LINEARISATION: *value = h->mode; return AF_OK;
@@ -580,9 +582,10 @@ extern "C" int af_get_option(const af_handle* h, int key, int64_t* value) {
     case AF_OPT_FLUX_LIMITER: *value = h->flux_limiter; return AF_OK;
     case AF_OPT_TILE_ORDER:
     case AF_OPT_UPDATE_THREADS:
+    case AF_OPT_STEP_KERNEL:
       if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_get_option: batched handles only");
-      batch_get_schedule(h, &order, &threads);
-      *value = key == AF_OPT_TILE_ORDER ? order : threads;
+      batch_get_schedule(h, &order, &threads, &kernel);
+      *value = key == AF_OPT_TILE_ORDER ? order : (key == AF_OPT_UPDATE_THREADS ? threads : kernel);
       return AF_OK;
     default:
       return fail(h, AF_ERR_INVALID_ARG, "af_get_option: unknown key");
