@@ -17,8 +17,8 @@
 // cell's biquadratic becomes a polynomial sum d_kl C^k S^l (k, l <= 2) and the integrals are
 // exact combinations of the trigonometric moments  M_ab = int C^a S^b dtheta  over the arcs
 // that lie in that cell.  The moments follow from the arc end points and the arc length by
-// the standard reduction formulas, so the only transcendental functions are one acos and one
-// asin per evaluation.  The arc set of a cell is the intersection of the circular interval
+// the standard reduction formulas, so the only transcendental functions are the two arc
+// angles per evaluation (an acos and an asin).  The arc set of a cell is the intersection of the circular interval
 // where Q is on that side of the vertical line with the one for the horizontal line.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -28,17 +28,58 @@ namespace af {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// FP64 arc angles.  The circle crosses a grid line at a point (c, s) of the unit circle whose
+// both coordinates the evolution operators form anyway (c = u'/c' or v'/c', s = sqrt(1 - c^2)),
+// and the smaller of |c| and s is at most 1/sqrt(2): the angle is an arcsine of it, plus or
+// minus a multiple of pi/2.  On 0 <= x <= 1/sqrt(2), asin(x) = x + x^3 g(x^2), g taken as its
+// interpolant of degree 18 at the Chebyshev points of [0, 1/2] (coefficients from
+// csrc/asin_coeffs.py; at most 0.09 ulp from asin with exact evaluation), evaluated by Estrin's
+// scheme: 22 operations of dependency depth 6, against about 100 for the library's acos or
+// asin with its long Horner chains.
+constexpr double kAsinC[19] = {
+    0.16666666666666669,    0.07499999999998412,   0.04464285714665563,
+    0.030381944084994415,   0.0223721770065477,    0.017352221539201188,
+    0.013975730180211136,   0.01139924601483468,   0.011310924828955462,
+    -0.0032941927380090922, 0.07377343868679113,   -0.2809947932275328,
+    0.952265420570822,      -2.3535297860232123,   4.3847119392409954,
+    -5.883233416999023,     5.436384462318588,     -3.0948547605199717,
+    0.8387674099544927};
+__device__ __forceinline__ double asin_small(double x) {
+  constexpr const double* a = kAsinC;  // constant subscripts below: folded to immediates
+  const double t = x * x, t2 = t * t, t4 = t2 * t2, t8 = t4 * t4, t16 = t8 * t8;
+  const double q0 = __builtin_fma(a[1], t, a[0]), q1 = __builtin_fma(a[3], t, a[2]);
+  const double q2 = __builtin_fma(a[5], t, a[4]), q3 = __builtin_fma(a[7], t, a[6]);
+  const double q4 = __builtin_fma(a[9], t, a[8]), q5 = __builtin_fma(a[11], t, a[10]);
+  const double q6 = __builtin_fma(a[13], t, a[12]), q7 = __builtin_fma(a[15], t, a[14]);
+  const double q8 = __builtin_fma(a[17], t, a[16]);
+  const double r0 = __builtin_fma(q1, t2, q0), r1 = __builtin_fma(q3, t2, q2);
+  const double r2 = __builtin_fma(q5, t2, q4), r3 = __builtin_fma(q7, t2, q6);
+  const double r4 = __builtin_fma(a[18], t2, q8);
+  const double s0 = __builtin_fma(r1, t4, r0), s1 = __builtin_fma(r3, t4, r2);
+  const double p = __builtin_fma(r4, t16, __builtin_fma(s1, t8, s0));
+  return __builtin_fma(x * t, p, x);
+}
+
 template <class R> struct Math;
 template <> struct Math<double> {
   static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
-  static __device__ __forceinline__ double acos_(double x) { return ::acos(x); }
-  static __device__ __forceinline__ double asin_(double x) { return ::asin(x); }
+  // acos(c) and asin(c) given s = sqrt(1 - c^2), |c| <= 1
+  static __device__ __forceinline__ double acos_cs(double c, double s) {
+    const bool mid = __builtin_fabs(c) <= s;  // the angle lies in [pi/4, 3pi/4]
+    const double r = asin_small(mid ? c : s);
+    return mid ? 0.5 * kPi - r : (c > 0.0 ? r : kPi - r);
+  }
+  static __device__ __forceinline__ double asin_cs(double c, double s) {
+    const bool mid = __builtin_fabs(c) <= s;  // |asin c| <= pi/4
+    const double r = asin_small(mid ? c : s);
+    return mid ? r : __builtin_copysign(0.5 * kPi - r, c);
+  }
 };
 template <> struct Math<float> {
   // hardware square root (1 ulp) rather than the correctly rounded expansion
   static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-  static __device__ __forceinline__ float acos_(float x) { return ::acosf(x); }
-  static __device__ __forceinline__ float asin_(float x) { return ::asinf(x); }
+  static __device__ __forceinline__ float acos_cs(float c, float) { return ::acosf(c); }
+  static __device__ __forceinline__ float asin_cs(float c, float) { return ::asinf(c); }
 };
 
 template <class T> __device__ __forceinline__ T mx(T a, T b) { return a > b ? a : b; }

@@ -323,7 +323,7 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
     // only the upper-right arc set needs the general moments.
     const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
     const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
-    const R al = MA::acos_(cMx), be = MA::asin_(cMy);
+    const R al = MA::acos_cs(cMx, sxx), be = MA::asin_cs(cMy, syy);
     const R Ly = pi - R(2) * be;
     // end points of the arcs on the circle of radius ar (the moments are those of that circle)
     const R cxa = ar * cMx, sxa = ar * sxx, sya = ar * syy, cya = ar * cMy, a2 = ar * ar;
@@ -383,10 +383,10 @@ __device__ __forceinline__ int eg2(const Smem<R>& S, int cb, const double lin64[
     Mom<R> M;
     if constexpr (KIND == KIND_X) {
       const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
-      moments_sym_x(ar * cMx, ar * sxx, MA::acos_(cMx), ar * ar, M);
+      moments_sym_x(ar * cMx, ar * sxx, MA::acos_cs(cMx, sxx), ar * ar, M);
     } else {
       const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
-      moments_sym_y(ar * syy, ar * cMy, pi - R(2) * MA::asin_(cMy), ar * ar, M);
+      moments_sym_y(ar * syy, ar * cMy, pi - R(2) * MA::asin_cs(cMy, syy), ar * ar, M);
     }
     const int cl = cb, chh = cb + (KIND == KIND_X ? 1 : HC);
     const R xl = (KIND == KIND_X) ? px + R(0.5) : px;
@@ -478,7 +478,7 @@ __device__ __forceinline__ int eg1_pc(const double* __restrict__ ub, int cb, con
   const R cMx = clamp1(up * ic), cMy = clamp1(vp * ic);
   const R sxx = MA::sqrt_(mx(R(0), R(1) - cMx * cMx));
   const R syy = MA::sqrt_(mx(R(0), R(1) - cMy * cMy));
-  const R al = MA::acos_(cMx), be = MA::asin_(cMy);
+  const R al = MA::acos_cs(cMx, sxx), be = MA::asin_cs(cMy, syy);
   R Ip = 0, IpC = 0, IpS = 0, Jr = 0, Ku = 0, Kv = 0;
   // The data are constant on the quadrants (K) or halves (X, Y) around the DOF.  As for EG2,
   // split them into the low-side value on the full circle plus differences on the right half,
