@@ -367,60 +367,72 @@ __device__ __forceinline__ void grid_barrier(StepSync* s, unsigned int nb) {
   fence_acquire();
 }
 
+// The kernel's arguments, kept in LDS.  Read back inside every phase loop (after its barrier,
+// so that the reads cannot be hoisted out of the loop) they are not live through the point
+// phase: as kernel-argument registers held across the whole kernel they pushed the point
+// phase into SGPR spills (v_readlane/v_writelane, VALU instructions in the hot code).
+struct StepArgs {
+  const GridDesc* desc;
+  const int2* block_tile;
+  const int2* items;
+  const int* tile_grid;
+  const int* prow_grid;
+  const int* prow_base;
+  DevState* devs;
+  int* fix_list;
+  unsigned int* fix_count;
+  StepSync* sync;
+  double dt_host;
+  int n_tiles, n_items, n_prows, n_grids;
+};
+// A pointer read from LDS, made wave-uniform (scalar loads through it stay possible).
+template <class T> __device__ __forceinline__ T* uni(T* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)v);
+  const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(v >> 32));
+  return (T*)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// `desc` and `block_tile` stay kernel arguments: read-only and __restrict__, the descriptors and
+// the tile table are then read with scalar loads (through a pointer read back from LDS the
+// compiler cannot tell that nothing writes them, and loads them with vector instructions).
 template <class R, bool LIM, bool IND>
 __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __restrict__ desc,
-                                          const int2* __restrict__ block_tile, int n_tiles,
-                                          const int2* __restrict__ items, int n_items,
-                                          const int* __restrict__ tile_grid,
-                                          const int* __restrict__ prow_grid,
-                                          const int* __restrict__ prow_base, int n_prows,
-                                          DevState* devs, int n_grids, int* fix_list,
-                                          unsigned int* fix_count, StepSync* sync,
-                                          double dt_host) {
+                                          const int2* __restrict__ block_tile,
+                                          const StepArgs& arg) {
+  __shared__ StepArgs A;
   __shared__ int s_item;
   __shared__ unsigned int s_n;
   __shared__ int s_last;
-  // the later phases' arguments wait in LDS: kept in registers, they would stay live through
-  // the point phase and push its registers into spills
-  __shared__ const int2* s_items;
-  __shared__ const int* s_tile_grid;
-  __shared__ int* s_fix_list;
-  __shared__ unsigned int* s_fix_count;
-  __shared__ int s_n_items, s_n_grids;
-  if (threadIdx.x == 0) {
-    s_items = items;
-    s_tile_grid = tile_grid;
-    s_fix_list = fix_list;
-    s_fix_count = fix_count;
-    s_n_items = n_items;
-    s_n_grids = n_grids;
-  }
+  if (threadIdx.x == 0) A = arg;
+  __syncthreads();
   const unsigned int nb = gridDim.x;
   const int j0 = (int)(blockIdx.x >> 3);
   if constexpr (IND) {
-    for (int k, j = j0; (k = next_item(sync, n_prows, &s_item, j)) >= 0;)
-      avgprim_row(desc, prow_grid, prow_base, devs, k);
-    grid_barrier(sync, nb);
+    for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_prows), &s_item, j)) >= 0;)
+      avgprim_row(desc, uni(A.prow_grid), uni(A.prow_base), uni(A.devs), k);
+    grid_barrier(uni(A.sync), nb);
   }
-  for (int k, j = j0; (k = next_item(sync, n_tiles, &s_item, j)) >= 0;)
-    batch_points<R, IND>(S, I, desc, block_tile, devs, dt_host, k);
-  grid_barrier(sync, nb);
+  for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_tiles), &s_item, j)) >= 0;)
+    batch_points<R, IND>(S, I, desc, block_tile, uni(A.devs), A.dt_host, k);
+  grid_barrier(uni(A.sync), nb);
   if constexpr (LIM) {
-    if (threadIdx.x == 0) s_n = __hip_atomic_load(s_fix_count, __ATOMIC_RELAXED,
+    if (threadIdx.x == 0) s_n = __hip_atomic_load(A.fix_count, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int nfix = (int)s_n;
-    const int* tg = s_tile_grid;
-    const int* fl = s_fix_list;
-    for (int k, j = j0; (k = next_item(sync, nfix, &s_item, j)) >= 0;)
-      fixup_entry<R, IND>(S, I, desc, tg, devs, fl, (unsigned int)k);
-    grid_barrier(sync, nb);
+    for (int k, j = j0; (k = next_item(uni(A.sync), nfix, &s_item, j)) >= 0;)
+      fixup_entry<R, IND>(S, I, desc, uni(A.tile_grid), uni(A.devs), uni(A.fix_list),
+                          (unsigned int)k);
+    grid_barrier(uni(A.sync), nb);
   }
-  const int2* its = s_items;
-  const int nit = s_n_items;
-  for (int k, j = j0; (k = next_item(sync, nit, &s_item, j)) >= 0;)
-    update_item<PT_THREADS>(desc, its[tile_of_block(k, nit)], devs, S.red);
+  for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_items), &s_item, j)) >= 0;) {
+    const int n = uni(A.n_items);
+    update_item<PT_THREADS>(desc, uni(A.items)[tile_of_block(k, n)], uni(A.devs), S.red);
+  }
   // the last workgroup to finish commits the step of every grid
+  StepSync* sync = uni(A.sync);
   fence_release();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -431,7 +443,8 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
   if (!s_last) return;
   fence_acquire();
   const bool timed_out = ld_relaxed(&sync->timeout) != 0u;
-  const int ng = s_n_grids;
+  DevState* devs = uni(A.devs);
+  const int ng = uni(A.n_grids);
   for (int g = threadIdx.x; g < ng; g += blockDim.x) {
     DevState* d = devs + g;
     if (timed_out) {
@@ -446,7 +459,7 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
     st_relaxed(&sync->arrive, 0u);  // already 0 unless a barrier timed out
     st_relaxed(&sync->done, 0u);
     st_relaxed(&sync->timeout, 0u);
-    st_relaxed(s_fix_count, 0u);
+    st_relaxed(A.fix_count, 0u);
   }
 }
 
@@ -457,8 +470,9 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
       DevState *devs, int n_grids, int *fix_list, unsigned int *fix_count, StepSync *sync,   \
       double dt_host
 #define AF_STEP_PASS                                                                          \
-  desc, block_tile, n_tiles, items, n_items, tile_grid, prow_grid, prow_base, n_prows, devs, \
-      n_grids, fix_list, fix_count, sync, dt_host
+  desc, block_tile,                                                                           \
+      StepArgs{desc, block_tile, items, tile_grid, prow_grid, prow_base, devs, fix_list,     \
+               fix_count, sync, dt_host, n_tiles, n_items, n_prows, n_grids}
 
 // At least as many waves per SIMD as the point kernels get (left alone, the update phase's
 // register budget lowers them: 3 -> 2 in FP32, 2 -> 1 in FP64).
