@@ -130,7 +130,7 @@ enum {
                                admissible whenever the low-order updates are.  Faces need
                                no limiting in smooth flow (gamma = 1: the unlimited step,
                                bit for bit).  Single-grid handles.  0 (default): off.      */
-  AF_OPT_STEP_KERNEL = 13   /* batched handles: AF_STEP_SPLIT (default) launches the point,
+  AF_OPT_STEP_KERNEL = 13,  /* batched handles: AF_STEP_SPLIT (default) launches the point,
                                fix-up, update and commit kernels in turn; AF_STEP_PERSISTENT
                                runs the whole step in one launch of a persistent kernel: as
                                many workgroups as the GPU holds at once take the step's work
@@ -139,7 +139,13 @@ enum {
                                between the phases, and the last to finish commits every grid.
                                A barrier not reached within 2 s (workgroups not all resident,
                                e.g. another kernel sharing the GPU) ends the step of every
-                               running grid with AF_ERR_DEVICE, the state kept at t_n.     */
+                               running grid with AF_ERR_DEVICE, the state kept at t_n
+                               (the limit: AF_OPT_SYNC_TIMEOUT_US).                       */
+  AF_OPT_SYNC_TIMEOUT_US = 14 /* batched handles: how long a workgroup of the persistent step
+                               kernel waits at a barrier before the step is abandoned, in
+                               microseconds of the GPU's wall clock, 0 .. 1e8 (default 2e6;
+                               0: the step ends with AF_ERR_DEVICE unless every workgroup
+                               is already there).                                          */
 };
 /* Tile orders of the batched point kernel.  Workgroups are dealt to the GPU's 8 XCDs in turn;
  * AF_ORDER_XCD gives each XCD a contiguous range of the global tile index, AF_ORDER_LINEAR

@@ -21,7 +21,7 @@ AF_SIDE_LEFT, AF_SIDE_RIGHT, AF_SIDE_BOTTOM, AF_SIDE_TOP = 0, 1, 2, 3
 AF_OPT_PRECISION, AF_OPT_LINEARISATION, AF_OPT_CORRECTION, AF_OPT_LIMITER, \
     AF_OPT_GRAPH_STEPS, AF_OPT_TIMING, AF_OPT_AUTOTUNE, AF_OPT_TILE_ORDER, \
     AF_OPT_UPDATE_THREADS, AF_OPT_TRANSONIC, AF_OPT_SHOCK_LIMITER, AF_OPT_FLUX_LIMITER, \
-    AF_OPT_STEP_KERNEL = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13
+    AF_OPT_STEP_KERNEL, AF_OPT_SYNC_TIMEOUT_US = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14
 AF_ORDER_XCD, AF_ORDER_LINEAR, AF_ORDER_GRIDS = 0, 1, 2
 AF_STEP_SPLIT, AF_STEP_PERSISTENT = 0, 1
 AF_PREC_FP64, AF_PREC_FP32 = 0, 1

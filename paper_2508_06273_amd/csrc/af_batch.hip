@@ -264,7 +264,7 @@ __global__ void kb_cfl(const GridDesc* __restrict__ desc, DevState* devs, int pe
 // items are split over 8 queues, one per XCD (workgroup b runs on XCD b mod 8, and queue x
 // holds items x, x + 8, x + 16, ...), so that the tile orders keep their meaning (see
 // next_item).  The grid is a multiple of 8 workgroups.  Every wait is bounded: a
-// barrier not reached within SYNC_TIMEOUT_TICKS of the 100 MHz wall clock (workgroups that
+// barrier not reached within the handle's limit on the 100 MHz wall clock (workgroups that
 // were not all resident) flags `timeout`, and the step then ends every running grid with
 // ERR_SYNC instead of committing it.
 struct StepSync {
@@ -274,7 +274,6 @@ struct StepSync {
   unsigned int done, pad2[15];
   unsigned int timeout, pad3[15];
 };
-constexpr unsigned long long SYNC_TIMEOUT_TICKS = 200000000ull;  // 2 s
 constexpr unsigned int SYNC_MAX_POLLS = 1u << 26;  // a second bound, independent of the clock
 
 // Relaxed agent-scope load of a counter: no cache invalidation (an acquire would invalidate the
@@ -340,7 +339,8 @@ __device__ __forceinline__ int next_item(StepSync* s, int m, int* s_item, int& j
 // acquires the other workgroups' after it leaves.
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-__device__ __forceinline__ void grid_barrier(StepSync* s, unsigned int nb) {
+__device__ __forceinline__ void grid_barrier(StepSync* s, unsigned int nb,
+                                             unsigned long long limit_ticks) {
   fence_release();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -354,7 +354,7 @@ __device__ __forceinline__ void grid_barrier(StepSync* s, unsigned int nb) {
       const unsigned long long t0 = (unsigned long long)wall_clock64();
       for (unsigned int it = 0; ld_relaxed(&s->gen) == g; ++it) {
         __builtin_amdgcn_s_sleep(4);
-        if ((unsigned long long)wall_clock64() - t0 > SYNC_TIMEOUT_TICKS ||
+        if ((unsigned long long)wall_clock64() - t0 > limit_ticks ||
             it >= SYNC_MAX_POLLS) {
           st_relaxed(&s->timeout, 1u);
           break;
@@ -383,6 +383,7 @@ struct StepArgs {
   unsigned int* fix_count;
   StepSync* sync;
   double dt_host;
+  unsigned long long sync_ticks;  // barrier wait limit (100 MHz wall-clock ticks)
   int n_tiles, n_items, n_prows, n_grids;
 };
 // A pointer read from LDS, made wave-uniform (scalar loads through it stay possible).
@@ -412,11 +413,11 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
   if constexpr (IND) {
     for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_prows), &s_item, j)) >= 0;)
       avgprim_row(desc, uni(A.prow_grid), uni(A.prow_base), uni(A.devs), k);
-    grid_barrier(uni(A.sync), nb);
+    grid_barrier(uni(A.sync), nb, A.sync_ticks);
   }
   for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_tiles), &s_item, j)) >= 0;)
     batch_points<R, IND>(S, I, desc, block_tile, uni(A.devs), A.dt_host, k);
-  grid_barrier(uni(A.sync), nb);
+  grid_barrier(uni(A.sync), nb, A.sync_ticks);
   if constexpr (LIM) {
     if (threadIdx.x == 0) s_n = __hip_atomic_load(A.fix_count, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
@@ -425,7 +426,7 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
     for (int k, j = j0; (k = next_item(uni(A.sync), nfix, &s_item, j)) >= 0;)
       fixup_entry<R, IND>(S, I, desc, uni(A.tile_grid), uni(A.devs), uni(A.fix_list),
                           (unsigned int)k);
-    grid_barrier(uni(A.sync), nb);
+    grid_barrier(uni(A.sync), nb, A.sync_ticks);
   }
   for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_items), &s_item, j)) >= 0;) {
     const int n = uni(A.n_items);
@@ -448,7 +449,8 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
   for (int g = threadIdx.x; g < ng; g += blockDim.x) {
     DevState* d = devs + g;
     if (timed_out) {
-      if (!d->err && d->active) set_err(d, ERR_SYNC);
+      // every running grid: an abandoned step may also have flagged other errors on the way
+      if (d->active) set_err(d, ERR_SYNC);
     } else {
       commit_grid(d);
     }
@@ -468,11 +470,11 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
       const int2 *__restrict__ items, int n_items, const int *__restrict__ tile_grid,        \
       const int *__restrict__ prow_grid, const int *__restrict__ prow_base, int n_prows,     \
       DevState *devs, int n_grids, int *fix_list, unsigned int *fix_count, StepSync *sync,   \
-      double dt_host
+      double dt_host, unsigned long long sync_ticks
 #define AF_STEP_PASS                                                                          \
   desc, block_tile,                                                                           \
       StepArgs{desc, block_tile, items, tile_grid, prow_grid, prow_base, devs, fix_list,     \
-               fix_count, sync, dt_host, n_tiles, n_items, n_prows, n_grids}
+               fix_count, sync, dt_host, sync_ticks, n_tiles, n_items, n_prows, n_grids}
 
 // At least as many waves per SIMD as the point kernels get (left alone, the update phase's
 // register budget lowers them: 3 -> 2 in FP32, 2 -> 1 in FP64).
@@ -545,6 +547,7 @@ struct Batch {
   int total_items_p = 0;
   int step_cap[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // resident workgroups per step-kernel variant
   int step_nb = 0;                              // workgroups of its next launches
+  unsigned long long sync_ticks = 200000000ull;  // its barrier wait limit: 2 s at 100 MHz
   int2* d_block_tile = nullptr;       // (grid, tile within the grid) of every workgroup
   std::vector<long long> grid_tiles;  // tiles per grid (host copy for the orders)
   std::vector<int> tile_grid;         // grid of every global tile (host copy)
@@ -783,6 +786,16 @@ int batch_set_schedule(af_handle* h, int order, int bu_threads, int step_kernel)
   return AF_OK;
 }
 
+int batch_set_sync_timeout(af_handle* h, int64_t us) {
+  if (us < 0 || us > 100000000)
+    return fail(h, AF_ERR_INVALID_ARG, "af_set_option: sync timeout must be 0 .. 1e8 us");
+  h->batch->sync_ticks = (unsigned long long)us * 100ull;
+  return AF_OK;
+}
+int64_t batch_get_sync_timeout(const af_handle* h) {
+  return (int64_t)(h->batch->sync_ticks / 100ull);
+}
+
 int batch_get_schedule(const af_handle* h, int* order, int* bu_threads, int* step_kernel) {
   *order = h->batch->order;
   *bu_threads = h->batch->bu_threads;
@@ -951,7 +964,7 @@ static void launch_step(K kernel, const Batch* b, hipStream_t st, int nb, double
   hipLaunchKernelGGL(kernel, dim3(nb), dim3(PT_THREADS), 0, st, b->d_desc, b->d_block_tile,
                      b->total_tiles, b->d_items_p, b->total_items_p, b->d_tile_grid,
                      b->d_prow_grid, b->d_prow_base, b->total_prows, b->d_devs, b->n,
-                     b->fix_list, b->fix_count, b->d_sync, dt_host);
+                     b->fix_list, b->fix_count, b->d_sync, dt_host, b->sync_ticks);
 }
 template <class R>
 static void launch_step(const af_handle* h, int nb, double dt_host) {

@@ -107,5 +107,7 @@ int batch_get_counters(const af_handle* h, int64_t* out);
 int batch_step(af_handle* h, double dt);
 int batch_set_schedule(af_handle* h, int order, int bu_threads, int step_kernel);
 int batch_get_schedule(const af_handle* h, int* order, int* bu_threads, int* step_kernel);
+int batch_set_sync_timeout(af_handle* h, int64_t us);
+int64_t batch_get_sync_timeout(const af_handle* h);
 int batch_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double* t_reached,
               int64_t* steps_taken);

@@ -557,6 +557,11 @@ extern "C" int af_set_option(af_handle* h, int key, int64_t value) {
       else kernel = (int)value;
       return batch_set_schedule(h, order, threads, kernel);
     }
+    case AF_OPT_SYNC_TIMEOUT_US: {
+      if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_set_option: batched handles only");
+      if (int e = batch_set_sync_timeout(h, value)) return e;
+      break;  // a captured graph holds the old limit: rebuilt below
+    }
     default:
       return fail(h, AF_ERR_INVALID_ARG, "af_set_option: unknown key");
   }
@@ -580,6 +585,10 @@ extern "C" int af_get_option(const af_handle* h, int key, int64_t* value) {
     case AF_OPT_TRANSONIC: *value = h->tsw; return AF_OK;
     case AF_OPT_SHOCK_LIMITER: *value = h->shock; return AF_OK;
     case AF_OPT_FLUX_LIMITER: *value = h->flux_limiter; return AF_OK;
+    case AF_OPT_SYNC_TIMEOUT_US:
+      if (!h->batch) return fail(h, AF_ERR_INVALID_ARG, "af_get_option: batched handles only");
+      *value = batch_get_sync_timeout(h);
+      return AF_OK;
     case AF_OPT_TILE_ORDER:
     case AF_OPT_UPDATE_THREADS:
     case AF_OPT_STEP_KERNEL:

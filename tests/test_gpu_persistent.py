@@ -179,3 +179,43 @@ def test_persistent_option_and_autotuner():
     with pytest.raises(af.AfError):
         s.set_option(af.AF_OPT_STEP_KERNEL, af.AF_STEP_PERSISTENT)
     s.close()
+
+
+def test_persistent_barrier_timeout_keeps_the_state():
+    """The persistent kernel's barrier waits are bounded.  With the limit set to 0 from the host
+    (AF_OPT_SYNC_TIMEOUT_US) the workgroups that reach a barrier first stop waiting at once: the
+    step is abandoned with AF_ERR_DEVICE, every kernel still ends, and each grid keeps its t_n
+    state (the step writes only the other buffer).  With the default limit restored the next
+    steps equal the separate kernels' bit for bit.  Limiter and indicators off: their phases
+    read lists that an abandoned barrier would leave half written."""
+    _flush("[gpu] persistent barrier timeout")
+    states = _mixed_states()
+    dt = 2e-4
+    ref = af.BatchSolver.for_states(states, precision=1)
+    for _ in range(3):
+        ref.step(dt)
+    want = [ref.get_state(g) for g in range(len(states))]
+    ref.close()
+    b = af.BatchSolver.for_states(states, precision=1)
+    b.set_option(af.AF_OPT_STEP_KERNEL, af.AF_STEP_PERSISTENT)
+    assert b.get_option(af.AF_OPT_SYNC_TIMEOUT_US) == 2000000
+    b.set_option(af.AF_OPT_SYNC_TIMEOUT_US, 0)
+    with pytest.raises(af.AfError) as ei:
+        b.step(dt)
+    assert ei.value.code == af.AF_ERR_DEVICE and "barrier" in str(ei.value)
+    for g, st in enumerate(states):
+        assert b.grid_info(g) == (0.0, 0)
+        out = b.get_state(g)
+        for k in ("avg", "K", "X", "Y"):
+            assert np.array_equal(out[k], getattr(st, k)), (g, k)
+    b.set_option(af.AF_OPT_SYNC_TIMEOUT_US, 2000000)
+    for _ in range(3):
+        b.step(dt)
+    _same([b.get_state(g) for g in range(len(states))], want, "after timeout")
+    with pytest.raises(af.AfError):
+        b.set_option(af.AF_OPT_SYNC_TIMEOUT_US, -1)
+    b.close()
+    s = af.Solver.for_state(states[0])
+    with pytest.raises(af.AfError):
+        s.set_option(af.AF_OPT_SYNC_TIMEOUT_US, 10)
+    s.close()
