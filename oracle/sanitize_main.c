@@ -1,5 +1,5 @@
 /*
- * sanitize_main.c -- TEST INFRASTRUCTURE ONLY: a driver that runs the oracle's whole step
+ * sanitize_main.c -- TEST INFRASTRUCTURE ONLY: a program that runs the oracle's whole step
  * under the address and undefined-behaviour sanitizers (built and run by
  * tests/test_oracle_sanitize.py with gcc).  It steps small grids through every boundary kind,
  * linearisation mode and limiter option, and checks two invariants as it goes: a uniform

@@ -1,5 +1,5 @@
 """The oracle under the address and undefined-behaviour sanitizers (host code only): build
-oracle/af_oracle.c with oracle/sanitize_main.c and run the driver, which steps small grids
+oracle/af_oracle.c with oracle/sanitize_main.c and run that program, which steps small grids
 through every boundary kind, mode and limiter option and checks uniform-state preservation and
 conservation."""
 import os
