@@ -258,3 +258,58 @@ def test_timing_counts_only_steps_that_ran():
     _flush(f"  single {mp_s / n_s:.4f} ms, batched {mp_b / n_b:.4f} ms per point kernel")
     assert n == 3 and n_b == 3
     assert mp_b / n_b > (mp_s / n_s) / 3.0
+
+
+def _batch_sweep_cases(n=20, seed=I.SEED_BASE + 39400):
+    PER, OUT, WALL, INFLOW = I.BC_PERIODIC, I.BC_OUTFLOW, I.BC_WALL, I.BC_INFLOW
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        ng = int(rng.integers(2, 7))
+        states = []
+        for g in range(ng):
+            nx, ny = int(rng.integers(3, 70)), int(rng.integers(3, 70))
+            sides = []
+            for axis in range(2):
+                if rng.random() < 0.4:
+                    sides += [PER, PER]
+                else:
+                    sides += [int(rng.choice([OUT, WALL, INFLOW])) for _ in range(2)]
+            inflow = tuple((float(rng.uniform(0.9, 1.1)), float(rng.uniform(-0.2, 0.2)),
+                            float(rng.uniform(-0.2, 0.2)), float(rng.uniform(0.9, 1.1)))
+                           if s == INFLOW else None for s in sides)
+            dx = float(rng.uniform(0.02, 0.1))
+            grid = I.Grid(nx, ny, 0.0, nx * dx, 0.0, ny * dx * float(rng.uniform(0.5, 2.0)),
+                          sides=tuple(sides), inflow=inflow if INFLOW in sides else None)
+            states.append(I.fourier_state(int(rng.integers(1, 10 ** 6)), grid, I.GAMMA, 3))
+        opts = dict(precision=int(rng.integers(0, 2)), linearisation=int(rng.integers(0, 3)),
+                    limiter=bool(rng.random() < 0.5), transonic=bool(rng.random() < 0.3),
+                    shock_limiter=bool(rng.random() < 0.3))
+        out.append((states, opts, int(rng.integers(0, 2))))
+    return out
+
+
+BATCH_SWEEP = _batch_sweep_cases()
+
+
+@pytest.mark.parametrize("k", range(len(BATCH_SWEEP)))
+def test_batch_sweep_equals_single_handles(k):
+    """Random batches: 2 to 6 grids of 3 to 69 cells per side, every kind of side (inflow
+    states per grid), random options (precision, linearisation, limiter, Algorithm 2, the
+    Sec. 3.4 blend) and either step kernel: 5 steps of the batch equal separate single-grid
+    handles bit for bit, each grid with its own time step."""
+    states, opts, kernel = BATCH_SWEEP[k]
+    _flush(f"[gpu] batch sweep case {k}: {len(states)} grids, {opts}, step kernel {kernel}")
+    b = af.BatchSolver.for_states(states, **opts)
+    b.set_option(af.AF_OPT_STEP_KERNEL, kernel)
+    t, n = b.run(1e9, 0.3, 5)
+    assert n == 5
+    outs = [b.get_state(g) for g in range(len(states))]
+    b.close()
+    for g, st in enumerate(states):
+        s = af.Solver.for_state(st, **opts)
+        s.run(1e9, 0.3, 5)
+        ref = s.get_state()
+        s.close()
+        for key in ("avg", "K", "X", "Y"):
+            assert np.array_equal(outs[g][key], ref[key]), (g, key)
