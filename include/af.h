@@ -186,8 +186,10 @@ enum {
  * values at the corners and edge midpoints; the ideal gas law with gamma; Sec. 4 and 4.3: the
  * boundary kinds).  Allocates the device state (uninitialised until af_set_state).  `out`
  * receives the handle, owned by the caller until af_destroy.  Errors: AF_ERR_INVALID_ARG for
- * nx or ny outside [2, 65536], an empty domain, gamma <= 1, an unknown boundary kind or a
- * periodic side without its partner; AF_ERR_DEVICE without a usable GPU; AF_ERR_OOM. */
+ * nx or ny outside [2, 65536], non-finite or empty domain bounds, a cell size that is not a
+ * finite positive number (below 1e-150), gamma not finite or <= 1, an unknown boundary kind
+ * or a periodic side without its partner (all checked before any HIP call);
+ * AF_ERR_DEVICE without a usable GPU; AF_ERR_OOM. */
 int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_handle** out);
 
 /* Set an option (keys and values above). */

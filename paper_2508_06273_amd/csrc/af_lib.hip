@@ -372,8 +372,14 @@ static int check_grid(const af_grid* grid, const af_bc* bc, const char* fn) {
   const std::string f(fn);
   if (grid->nx < 2 || grid->ny < 2 || grid->nx > (1 << 16) || grid->ny > (1 << 16))
     return fail(nullptr, AF_ERR_INVALID_ARG, f + ": nx, ny must be in [2, 65536]");
+  if (!std::isfinite(grid->x0) || !std::isfinite(grid->x1) || !std::isfinite(grid->y0) ||
+      !std::isfinite(grid->y1))
+    return fail(nullptr, AF_ERR_INVALID_ARG, f + ": domain bounds must be finite");
   if (!(grid->x1 > grid->x0) || !(grid->y1 > grid->y0))
     return fail(nullptr, AF_ERR_INVALID_ARG, f + ": empty domain");
+  const double dx = (grid->x1 - grid->x0) / grid->nx, dy = (grid->y1 - grid->y0) / grid->ny;
+  if (!std::isfinite(dx) || !std::isfinite(dy) || !(dx >= 1e-150) || !(dy >= 1e-150))
+    return fail(nullptr, AF_ERR_INVALID_ARG, f + ": cell size not finite and positive");
   auto okbc = [](int k) { return k >= AF_BC_PERIODIC && k <= AF_BC_INFLOW; };
   if (!okbc(bc->left) || !okbc(bc->right) || !okbc(bc->bottom) || !okbc(bc->top))
     return fail(nullptr, AF_ERR_INVALID_ARG, f + ": unknown boundary kind");
@@ -402,7 +408,8 @@ extern "C" int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_
   *out = nullptr;
   if (!grid || !bc) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: NULL grid or bc");
   if (int e = check_grid(grid, bc, "af_create")) return e;
-  if (!(gamma > 1.0)) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: gamma must be > 1");
+  if (!(gamma > 1.0) || !std::isfinite(gamma))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create: gamma must be finite and > 1");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail(nullptr, AF_ERR_DEVICE, "af_create: no HIP device");
@@ -444,7 +451,8 @@ extern "C" int af_create_batch(int32_t n, const af_grid* grids, double gamma, co
     return fail(nullptr, AF_ERR_INVALID_ARG, "af_create_batch: need n >= 1 grids and bcs");
   for (int k = 0; k < n; ++k)
     if (int e = check_grid(&grids[k], &bcs[k], "af_create_batch")) return e;
-  if (!(gamma > 1.0)) return fail(nullptr, AF_ERR_INVALID_ARG, "af_create_batch: gamma must be > 1");
+  if (!(gamma > 1.0) || !std::isfinite(gamma))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_create_batch: gamma must be finite and > 1");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail(nullptr, AF_ERR_DEVICE, "af_create_batch: no HIP device");
@@ -1116,7 +1124,8 @@ extern "C" int af_step_noalloc(const af_grid* grid, double gamma, const af_bc* b
   const char* fn = "af_step_noalloc";
   if (!grid || !bc) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: NULL grid or bc");
   if (int e = check_grid(grid, bc, fn)) return e;
-  if (!(gamma > 1.0)) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: gamma must be > 1");
+  if (!(gamma > 1.0) || !std::isfinite(gamma))
+    return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: gamma must be finite and > 1");
   if ((precision != AF_PREC_FP64 && precision != AF_PREC_FP32) || linearisation < 0 ||
       linearisation > 2 || (correction != 0 && correction != 1) || (limiter != 0 && limiter != 1))
     return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: bad option value");

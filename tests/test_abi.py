@@ -46,3 +46,32 @@ def test_binding_fails_loudly_without_library(tmp_path):
         af._lib = None
         af.load(str(tmp_path / "missing.so"))
     af._lib = None
+
+
+@pytest.mark.parametrize("grid,gamma,bc,what", [
+    ((8, 8, 0.0, float("inf"), 0.0, 1.0), 1.4, (0, 0, 0, 0), "finite"),
+    ((8, 8, float("nan"), 1.0, 0.0, 1.0), 1.4, (0, 0, 0, 0), "finite"),
+    ((8, 8, 0.0, 1.0, 1.0, 1.0), 1.4, (0, 0, 0, 0), "empty domain"),
+    ((8, 8, 0.0, 1e-300, 0.0, 1.0), 1.4, (0, 0, 0, 0), "cell size"),
+    ((1, 8, 0.0, 1.0, 0.0, 1.0), 1.4, (0, 0, 0, 0), "nx, ny"),
+    ((8, 8, 0.0, 1.0, 0.0, 1.0), float("inf"), (0, 0, 0, 0), "gamma"),
+    ((8, 8, 0.0, 1.0, 0.0, 1.0), 1.0, (0, 0, 0, 0), "gamma"),
+    ((8, 8, 0.0, 1.0, 0.0, 1.0), 1.4, (0, 1, 0, 0), "periodic"),
+    ((8, 8, 0.0, 1.0, 0.0, 1.0), 1.4, (7, 7, 0, 0), "boundary kind"),
+])
+def test_create_rejects_bad_arguments(grid, gamma, bc, what):
+    """Argument checks of af_create and af_create_batch come before any HIP call: a bad grid,
+    gamma or side set is refused with AF_ERR_INVALID_ARG and a message naming the problem."""
+    if not os.path.exists(af.LIB_PATH):
+        pytest.skip("libaf.so not built")
+    af._lib = None
+    L = af.load()
+    G = af.Grid(*grid)
+    B = af.Bc(*bc)
+    h = ct.c_void_p()
+    assert L.af_create(ct.byref(G), gamma, ct.byref(B), ct.byref(h)) == af.AF_ERR_INVALID_ARG
+    assert not h.value
+    assert what in L.af_last_error(None).decode()
+    assert L.af_create_batch(1, ct.byref(G), gamma, ct.byref(B), ct.byref(h)) == \
+        af.AF_ERR_INVALID_ARG
+    assert what in L.af_last_error(None).decode()
