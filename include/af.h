@@ -238,6 +238,15 @@ int af_get_counters(const af_handle* h, int64_t* out);
 /* Free the handle and its device memory (NULL is ignored). */
 void af_destroy(af_handle* h);
 
+/* Domain totals of the conserved variables of the current state of grid g (0 on a single-grid
+ * handle): out[0..3] = the sums over the grid's cells of the averages of rho, rho u, rho v and
+ * E, times the cell area -- the quantities the conservative update (eq. 2dfvm) keeps on a
+ * periodic grid.  Computed on the device in FP64 by a reduction in a fixed order (the same
+ * bits for the same state), synchronous on the handle's stream; out is the caller's (4
+ * doubles).  For conservation checks and per-step monitoring between af_step calls.  Errors:
+ * AF_ERR_INVALID_ARG (NULL argument, bad grid index, no state set). */
+int af_get_totals(const af_handle* h, int32_t g, double* out);
+
 /* Text of the last error on this handle (or of the last failed af_create if h is NULL). */
 const char* af_last_error(const af_handle* h);
 

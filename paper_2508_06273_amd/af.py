@@ -36,7 +36,7 @@ EXPORTS = ["af_create", "af_set_option", "af_set_stream", "af_set_state", "af_ge
            "af_dof_count", "af_get_timing", "af_create_batch", "af_batch_size",
            "af_set_state_grid", "af_get_state_grid", "af_get_grid_info", "af_get_option",
            "af_set_inflow", "af_set_state_device", "af_get_state_device",
-           "af_step_noalloc"]
+           "af_step_noalloc", "af_get_totals"]
 
 
 class AfError(RuntimeError):
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
     L.af_run.argtypes = [_H, ct.c_double, ct.c_double, ct.c_int64, _D,
                          ct.POINTER(ct.c_int64)]
     L.af_get_counters.argtypes = [_H, ct.POINTER(ct.c_int64)]
+    L.af_get_totals.argtypes = [_H, ct.c_int32, _D]
     L.af_destroy.argtypes = [_H]
     L.af_destroy.restype = None
     L.af_last_error.argtypes = [_H]
@@ -199,6 +200,12 @@ class _Handle:
         c = (ct.c_int64 * AF_NCOUNTERS)()
         self._check(self.L.af_get_counters(self.h, c))
         return np.array(list(c), dtype=np.int64)
+
+    def totals(self, g=0):
+        """Domain totals of rho, rho u, rho v, E of grid g's current state (af_get_totals)."""
+        o = np.zeros(4)
+        self._check(self.L.af_get_totals(self.h, int(g), o.ctypes.data_as(_D)))
+        return o
 
     def timing(self):
         """(ms in the point kernel, ms in the update kernel, steps) while timing is on."""

@@ -26,7 +26,8 @@ def hipcc() -> str:
 
 def build(verbose: bool = False, extra=None) -> str:
     cmd = [hipcc()] + FLAGS + list(extra or []) + ["-I", os.path.join(ROOT, "include"),
-                                                   "-I", CSRC] + SOURCES + ["-o", LIB + ".tmp"]
+                                                   "-I", CSRC] + SOURCES + \
+        ["-lrocprofiler-sdk-roctx", "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=HERE)

@@ -935,6 +935,18 @@ int batch_get_state(const af_handle* h, int g, double* avg, double* K, double* X
   return AF_OK;
 }
 
+int batch_totals(const af_handle* h, int g, double* out) {
+  const Batch* b = h->batch;
+  if (g < 0 || g >= b->n) return fail(h, AF_ERR_INVALID_ARG, "af_get_totals: bad grid index");
+  const BatchGrid& q = b->g[g];
+  if (!q.has_state) return fail(h, AF_ERR_INVALID_ARG, "af_get_totals: no state set");
+  DevState ds;
+  HIP_OK(hipMemcpyAsync(&ds, b->d_devs + g, sizeof(ds), hipMemcpyDeviceToHost, h->stream), h);
+  HIP_OK(hipStreamSynchronize(h->stream), h);
+  return reduce_totals(h, h->stream, b->A[ds.cur] + q.oA, q.pA, q.pA * q.ny, q.nx, q.ny,
+                       q.dx * q.dy, h->d_totals, out);
+}
+
 int batch_grid_info(const af_handle* h, int g, double* t, int64_t* steps) {
   const Batch* b = h->batch;
   if (g < 0 || g >= b->n) return fail(h, AF_ERR_INVALID_ARG, "af_get_grid_info: bad grid index");

@@ -2,6 +2,7 @@
 // batched runtime.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
 #include <vector>
@@ -10,6 +11,16 @@
 #include "af_kernels.hpp"
 
 using namespace af;
+
+// A roctx range over a scope: the library's calls appear by name on the host timeline of
+// `rocprofv3 --marker-trace`, around the kernels they enqueue; next to no cost without a
+// profiler.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 struct Batch;  // batched grids (af_batch.hip)
 
@@ -40,6 +51,7 @@ struct af_handle {
   int* fix_list = nullptr;
   DevState* dev = nullptr;
   GridDesc* d_desc = nullptr;  // device copy of the parameters and buffers (point kernels)
+  double* d_totals = nullptr;  // partial sums and result of af_get_totals (allocated on first use)
   bool desc_valid = false;
   int cur = 0;
   bool has_state = false;
@@ -108,6 +120,14 @@ int batch_step(af_handle* h, double dt);
 int batch_set_schedule(af_handle* h, int order, int bu_threads, int step_kernel);
 int batch_get_schedule(const af_handle* h, int* order, int* bu_threads, int* step_kernel);
 int batch_set_sync_timeout(af_handle* h, int64_t us);
+int batch_totals(const af_handle* h, int g, double* out);
 int64_t batch_get_sync_timeout(const af_handle* h);
 int batch_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double* t_reached,
               int64_t* steps_taken);
+
+// Domain totals (sum over cells of the conserved averages, times the cell area) of one grid's
+// averages A (4 variables at stride sA, rows at pitch pA), by the deterministic two-pass
+// reduction of af_lib.hip; synchronous on `stream`.  `scratch`: TOTAL_BLOCKS * 4 + 4 doubles.
+constexpr int TOTAL_BLOCKS = 256;
+int reduce_totals(const af_handle* h, hipStream_t stream, const double* A, long long pA,
+                  long long sA, int nx, int ny, double area, double* scratch, double* out);

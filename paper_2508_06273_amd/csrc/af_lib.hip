@@ -273,6 +273,61 @@ using namespace af;
 
 std::string g_create_error;
 
+// ------------------------------------------------------------------------------------------
+// Domain totals of the conserved variables (af_get_totals): two passes in a fixed order, so
+// that the result does not depend on the scheduling: TOTAL_BLOCKS workgroups sum the cells
+// b, b + TOTAL_BLOCKS * 256, ... of the row-major cell index (each of its 256 threads a
+// strided share, then a fixed-order tree over the workgroup), one workgroup adds the partial
+// sums in block order.  FP64 throughout.
+namespace {
+__global__ __launch_bounds__(256) void k_totals_partial(const double* __restrict__ A, long long pA,
+                                                        long long sA, int nx, int ny,
+                                                        double* __restrict__ partial) {
+  __shared__ double red[4][256];
+  const long long n = (long long)nx * ny;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long c = (long long)blockIdx.x * 256 + threadIdx.x; c < n;
+       c += (long long)gridDim.x * 256) {
+    const long long j = c / nx, i = c - j * nx;
+    const long long o = j * pA + i;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s[v] += A[v * sA + o];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[v][threadIdx.x] = s[v];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+__global__ void k_totals_final(const double* __restrict__ partial, int nblocks, double area,
+                               double* __restrict__ out) {
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[4 * b + threadIdx.x];
+    out[threadIdx.x] = s * area;
+  }
+}
+}  // namespace
+
+int reduce_totals(const af_handle* h, hipStream_t stream, const double* A, long long pA,
+                  long long sA, int nx, int ny, double area, double* scratch, double* out) {
+  hipLaunchKernelGGL(k_totals_partial, dim3(TOTAL_BLOCKS), dim3(256), 0, stream, A, pA, sA, nx,
+                     ny, scratch);
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, stream, (const double*)scratch,
+                     TOTAL_BLOCKS, area, scratch + 4 * TOTAL_BLOCKS);
+  HIP_OK(hipGetLastError(), h);
+  HIP_OK(hipMemcpyAsync(out, scratch + 4 * TOTAL_BLOCKS, 4 * sizeof(double),
+                        hipMemcpyDeviceToHost, stream), h);
+  HIP_OK(hipStreamSynchronize(stream), h);
+  return AF_OK;
+}
+
 int fail(const af_handle* h, int code, const std::string& msg) {
   if (h) const_cast<af_handle*>(h)->err = msg;
   else g_create_error = msg;
@@ -395,6 +450,7 @@ static void destroy_handle(af_handle* h) {
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->dev) (void)hipFree(h->dev);
   if (h->d_desc) (void)hipFree(h->d_desc);
+  if (h->d_totals) (void)hipFree(h->d_totals);
   if (h->UB) (void)hipFree(h->UB);
   if (h->TH) (void)hipFree(h->TH);
   if (h->d_flag) (void)hipFree(h->d_flag);
@@ -768,6 +824,7 @@ static int get_state_impl(const af_handle* h, int g, double* avg, double* K, dou
 
 extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, const double* X,
                             const double* Y, double t) {
+  Range range("af_set_state");
   if (h && h->batch && batch_count(h) != 1)
     return fail(h, AF_ERR_INVALID_ARG, "af_set_state: batched handle, use af_set_state_grid");
   return set_state_impl(h, 0, avg, K, X, Y, t, false, "af_set_state");
@@ -775,6 +832,7 @@ extern "C" int af_set_state(af_handle* h, const double* avg, const double* K, co
 
 extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* X, double* Y,
                             double* t) {
+  Range range("af_get_state");
   if (h && h->batch && batch_count(h) != 1)
     return fail(h, AF_ERR_INVALID_ARG, "af_get_state: batched handle, use af_get_state_grid");
   return get_state_impl(h, 0, avg, K, X, Y, t, false, "af_get_state");
@@ -782,11 +840,13 @@ extern "C" int af_get_state(const af_handle* h, double* avg, double* K, double* 
 
 extern "C" int af_set_state_device(af_handle* h, int32_t g, const double* avg, const double* K,
                                    const double* X, const double* Y, double t) {
+  Range range("af_set_state_device");
   return set_state_impl(h, g, avg, K, X, Y, t, true, "af_set_state_device");
 }
 
 extern "C" int af_get_state_device(const af_handle* h, int32_t g, double* avg, double* K,
                                    double* X, double* Y, double* t) {
+  Range range("af_get_state_device");
   return get_state_impl(h, g, avg, K, X, Y, t, true, "af_get_state_device");
 }
 
@@ -934,6 +994,7 @@ static const char* err_text(int code) {
 }
 
 extern "C" int af_step(af_handle* h, double dt) {
+  Range range("af_step");
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step: NULL handle");
   if (int e = check_inflow(h, "af_step")) return e;
   if (h->batch) return batch_step(h, dt);
@@ -959,6 +1020,7 @@ extern "C" int af_step(af_handle* h, double dt) {
 
 extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
                       double* t_reached, int64_t* steps_taken) {
+  Range range("af_run");
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_run: NULL handle");
   if (int e = check_inflow(h, "af_run")) return e;
   if (h->batch) return batch_run(h, t_end, cfl, max_steps, t_reached, steps_taken);
@@ -986,6 +1048,7 @@ extern "C" int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps,
   }
   long long done = 0;
   while (true) {
+    Range chunk("af_run: chunk of steps");
     if ((e = read_dev(h, &ds))) return e;
     const long long executed = ds.steps - steps0;
     if (h->timing) collect_timing(h, executed - done);
@@ -1032,6 +1095,7 @@ extern "C" int af_get_timing(const af_handle* h, double* out) {
 
 extern "C" int af_set_state_grid(af_handle* h, int32_t g, const double* avg, const double* K,
                                  const double* X, const double* Y, double t) {
+  Range range("af_set_state_grid");
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_set_state_grid: NULL handle");
   if (!h->batch) {
     if (g != 0) return fail(h, AF_ERR_INVALID_ARG, "af_set_state_grid: bad grid index");
@@ -1042,6 +1106,7 @@ extern "C" int af_set_state_grid(af_handle* h, int32_t g, const double* avg, con
 
 extern "C" int af_get_state_grid(const af_handle* h, int32_t g, double* avg, double* K, double* X,
                                  double* Y, double* t) {
+  Range range("af_get_state_grid");
   if (!h) return fail(nullptr, AF_ERR_INVALID_ARG, "af_get_state_grid: NULL handle");
   if (!h->batch) {
     if (g != 0) return fail(h, AF_ERR_INVALID_ARG, "af_get_state_grid: bad grid index");
@@ -1121,6 +1186,7 @@ extern "C" int af_step_noalloc(const af_grid* grid, double gamma, const af_bc* b
                                double* avg_out, double* K_out, double* X_out, double* Y_out,
                                int64_t pitch_avg, int64_t pitch_pts, double dt, void* stream,
                                int64_t* counters) {
+  Range range("af_step_noalloc");
   const char* fn = "af_step_noalloc";
   if (!grid || !bc) return fail(nullptr, AF_ERR_INVALID_ARG, "af_step_noalloc: NULL grid or bc");
   if (int e = check_grid(grid, bc, fn)) return e;
@@ -1230,4 +1296,19 @@ extern "C" int af_step_noalloc(const af_grid* grid, double gamma, const af_bc* b
   if (ds.err) return fail(nullptr, ds.err, std::string(fn) + ": " + err_text(ds.err));
   if (ds.steps != 1) return fail(nullptr, AF_ERR_DEVICE, "af_step_noalloc: step did not commit");
   return AF_OK;
+}
+
+// Domain totals of the conserved variables of the current state: out[0..3] = the sums over the
+// grid's cells of rho, rho u, rho v and E times the cell area (deterministic; synchronous).
+extern "C" int af_get_totals(const af_handle* h, int32_t g, double* out) {
+  Range range("af_get_totals");
+  if (!h || !out) return fail(h, AF_ERR_INVALID_ARG, "af_get_totals: NULL argument");
+  af_handle* hm = const_cast<af_handle*>(h);
+  if (!hm->d_totals)
+    HIP_OK(hipMalloc(&hm->d_totals, (4 * TOTAL_BLOCKS + 4) * sizeof(double)), h);
+  if (h->batch) return batch_totals(h, g, out);
+  if (g != 0) return fail(h, AF_ERR_INVALID_ARG, "af_get_totals: grid index must be 0");
+  if (!h->has_state) return fail(h, AF_ERR_INVALID_ARG, "af_get_totals: no state set");
+  return reduce_totals(h, h->stream, h->A[h->cur], h->pA, h->pA * h->ny, h->nx, h->ny,
+                       h->dx * h->dy, h->d_totals, out);
 }
