@@ -192,16 +192,19 @@ enum {
  * AF_ERR_DEVICE without a usable GPU; AF_ERR_OOM. */
 int af_create(const af_grid* grid, double gamma, const af_bc* bc, af_handle** out);
 
-/* Set an option (keys and values above). */
+/* Set an option (keys and values above; each key names the passage whose variant it selects:
+ * Algorithm 1/eq. Un+1/2/eq. 1stStep, Corollary 1, Algorithms 2 and 3, Secs. 3.4 and 3.5).
+ * Errors: AF_ERR_INVALID_ARG for an unknown key or value. */
 int af_set_option(af_handle* h, int key, int64_t value);
 
 /* Current value of an option (for AF_OPT_TILE_ORDER and AF_OPT_UPDATE_THREADS after an
  * autotuned run: the schedule the tuner kept).  The tile order and update threads are
- * AF_ERR_INVALID_ARG on single-grid handles. */
+ * AF_ERR_INVALID_ARG on single-grid handles.  Runtime control; no passage of the paper. */
 int af_get_option(const af_handle* h, int key, int64_t* value);
 
 /* Use `hip_stream` (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) for all
- * device work of this handle.  NULL selects the handle's own (non-blocking) stream. */
+ * device work of this handle.  NULL selects the handle's own (non-blocking) stream.  Runtime
+ * plumbing; no passage of the paper. */
 int af_set_stream(af_handle* h, void* hip_stream);
 
 /* Copy a state in (host FP64 arrays, layout above) at time t: the conserved cell averages and
@@ -235,7 +238,7 @@ int af_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double* t_
  * the flux limiting of Sec. 3.5 acted, and the steps taken.  `out` is the caller's. */
 int af_get_counters(const af_handle* h, int64_t* out);
 
-/* Free the handle and its device memory (NULL is ignored). */
+/* Free the handle and its device memory (NULL is ignored).  Runtime plumbing. */
 void af_destroy(af_handle* h);
 
 /* Domain totals of the conserved variables of the current state of grid g (0 on a single-grid
@@ -247,14 +250,18 @@ void af_destroy(af_handle* h);
  * AF_ERR_INVALID_ARG (NULL argument, bad grid index, no state set). */
 int af_get_totals(const af_handle* h, int32_t g, double* out);
 
-/* Text of the last error on this handle (or of the last failed af_create if h is NULL). */
+/* Text of the last error on this handle (or of the last failed af_create if h is NULL).
+ * Runtime plumbing; the errors of the method are those of Algorithm 3 and of the CFL
+ * condition of Sec. 2 (AF_ERR_NONPHYSICAL, AF_ERR_CFL). */
 const char* af_last_error(const af_handle* h);
 
-/* Number of DOF sites (averages + K + X + Y) of the handle's grid: the unit of the
- * DOF-updates/s throughput figure. */
+/* Number of DOF sites (averages + K + X + Y) of the handle's grid -- the degrees of freedom of
+ * Sec. 2: a cell average per cell, point values at the corners and edge midpoints -- the unit
+ * of the DOF-updates/s throughput figure. */
 int64_t af_dof_count(const af_handle* h);
 
-/* Kernel times gathered while AF_OPT_TIMING is on, summed since the option was last set:
+/* Measurement, no passage of the paper.  Kernel times gathered while AF_OPT_TIMING is on,
+ * summed since the option was last set:
  * out[0] = milliseconds in the point-value kernel, out[1] = milliseconds in the flux/update
  * kernel, out[2] = number of steps timed: those in which a grid advanced (launches that a
  * batched run enqueues after all its grids have stopped are not counted).  Both kernels run on
@@ -278,24 +285,30 @@ int af_get_timing(const af_handle* h, double* out);
  * af_set_state / af_get_state work only when n == 1; use the _grid variants.
  * --------------------------------------------------------------------------------------- */
 
-/* Create a handle for n >= 1 grids: grids[g], bcs[g] as for af_create, one gamma. */
+/* Create a handle for n >= 1 grids: grids[g], bcs[g] as for af_create (Sec. 2's grid and
+ * DOFs, Sec. 4.3's sides, per grid), one gamma.  Errors as for af_create. */
 int af_create_batch(int32_t n, const af_grid* grids, double gamma, const af_bc* bcs,
                     af_handle** out);
 
-/* Number of grids of the handle (1 for af_create handles; 0 for NULL). */
+/* Number of grids of the handle (1 for af_create handles; 0 for NULL).  Runtime plumbing. */
 int32_t af_batch_size(const af_handle* h);
 
-/* af_set_state / af_get_state for grid g (0 <= g < n; g = 0 on single handles).  Arrays as
- * for one grid of grids[g]'s sizes.  Every grid needs a state before af_step or af_run. */
+/* af_set_state / af_get_state for grid g (0 <= g < n; g = 0 on single handles): the DOFs of
+ * Sec. 2 of that grid at its t_n.  Arrays as for one grid of grids[g]'s sizes.  Every grid
+ * needs a state before af_step or af_run.  Errors as for af_set_state / af_get_state, and
+ * AF_ERR_INVALID_ARG for a bad grid index. */
 int af_set_state_grid(af_handle* h, int32_t g, const double* avg, const double* K,
                       const double* X, const double* Y, double t);
 int af_get_state_grid(const af_handle* h, int32_t g, double* avg, double* K, double* X,
                       double* Y, double* t);
 
-/* Time and steps taken (since af_set_state_grid) of grid g (nullable outputs). */
+/* Time t_n and steps taken (since af_set_state_grid) of grid g in its own time stepping
+ * (Sec. 2: dt from the CFL condition of its own state); nullable outputs.  Errors:
+ * AF_ERR_INVALID_ARG for a bad grid index. */
 int af_get_grid_info(const af_handle* h, int32_t g, double* t, int64_t* steps);
 
-/* af_set_state_grid / af_get_state_grid for arrays in device memory of the handle's GPU (for
+/* The DOFs of Sec. 2, as af_set_state_grid / af_get_state_grid, for arrays in device memory
+ * of the handle's GPU (for
  * instance torch tensors), in the host layout above (FP64, variable-major, unpadded): copied
  * device to device on the handle's stream, synchronously, with no host staging; the caller
  * keeps ownership.  The averages are checked on the device (AF_ERR_NONPHYSICAL if one is not
