@@ -48,6 +48,35 @@ __device__ __forceinline__ void batch_points(Smem<R>& S, Ind* I, const GridDesc*
   points_body<R, IND>(S, I, P, B, devs + g, dt_host, cur, local, local == 0);
 }
 
+// The persistent kernel's point item: the grid's descriptor is copied into LDS by the
+// workgroup and the tile works from that copy.  Read from global memory inside the persistent
+// loop, the descriptor is loaded with vector instructions at every tile (the compiler cannot
+// prove that the loop's stores leave it alone), a chain of global-memory latencies at the start
+// of every tile; from LDS it is a few LDS reads.
+template <class T>
+__device__ __forceinline__ void copy_to_lds(const T& src, T& dst) {
+  static_assert(sizeof(T) % 8 == 0, "8-byte words");
+  const unsigned long long* a = reinterpret_cast<const unsigned long long*>(&src);
+  unsigned long long* b = reinterpret_cast<unsigned long long*>(&dst);
+  for (int w = threadIdx.x; w < (int)(sizeof(T) / 8); w += blockDim.x) b[w] = a[w];
+}
+template <class R, bool IND = false>
+__device__ __forceinline__ void batch_points_staged(Smem<R>& S, Ind* I,
+                                                    const GridDesc* __restrict__ desc,
+                                                    const int2* __restrict__ block_tile,
+                                                    DevState* devs, double dt_host, int k,
+                                                    Params& sP, Bufs& sB) {
+  const int2 gt = block_tile[k];
+  const int g = __builtin_amdgcn_readfirstlane(gt.x);
+  const int local = __builtin_amdgcn_readfirstlane(gt.y);
+  const int cur = __builtin_amdgcn_readfirstlane(devs[g].cur);
+  copy_to_lds(desc[g].P, sP);
+  copy_to_lds(desc[g].B[cur], sB);
+  __syncthreads();
+  points_body<R, IND>(S, I, sP, sB, devs + g, dt_host, cur, local, local == 0);
+  __syncthreads();  // every read of the copy is done before the next item overwrites it
+}
+
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
 void kb_points_f32(const GridDesc* __restrict__ desc, const int2* __restrict__ block_tile,
                    DevState* devs, double dt_host) {
@@ -173,13 +202,8 @@ void kb_fixup_ind(const GridDesc* __restrict__ desc, const int* __restrict__ til
 // pair be in flight before its first use (left alone, the compiler takes 116 registers for four
 // waves and the loads go out in groups).
 template <int T>
-__device__ __forceinline__ void update_item(const GridDesc* __restrict__ desc, int2 it,
-                                            DevState* devs, double* red) {
-  const int g = __builtin_amdgcn_readfirstlane(it.x);
-  const Params& P = desc[g].P;
-  DevState* dev = devs + g;
-  const int cur = __builtin_amdgcn_readfirstlane(dev->cur);
-  const Bufs& B = desc[g].B[cur];
+__device__ __forceinline__ void update_body(const Params& P, const Bufs& B, int2 it,
+                                            DevState* dev, int cur, double* red) {
   // written by another workgroup earlier in the step (persistent kernel): agent-scope loads
   const bool run = !ld_agent(&dev->err) && ld_agent(&dev->active);
   const double dt = ld_agent(&dev->dt);
@@ -214,6 +238,29 @@ __device__ __forceinline__ void update_item(const GridDesc* __restrict__ desc, i
     for (int k = 1; k < (T + 63) / 64; ++k) m = mx(m, red[k]);
     atomic_max_pos(&dev->smax[cur ^ 1], m);
   }
+}
+template <int T>
+__device__ __forceinline__ void update_item(const GridDesc* __restrict__ desc, int2 it,
+                                            DevState* devs, double* red) {
+  const int g = __builtin_amdgcn_readfirstlane(it.x);
+  DevState* dev = devs + g;
+  const int cur = __builtin_amdgcn_readfirstlane(dev->cur);
+  update_body<T>(desc[g].P, desc[g].B[cur], it, dev, cur, red);
+}
+// The persistent kernel's update item, from an LDS copy of the descriptor (as
+// batch_points_staged).
+template <int T>
+__device__ __forceinline__ void update_item_staged(const GridDesc* __restrict__ desc, int2 it,
+                                                   DevState* devs, double* red, Params& sP,
+                                                   Bufs& sB) {
+  const int g = __builtin_amdgcn_readfirstlane(it.x);
+  DevState* dev = devs + g;
+  const int cur = __builtin_amdgcn_readfirstlane(dev->cur);
+  copy_to_lds(desc[g].P, sP);
+  copy_to_lds(desc[g].B[cur], sB);
+  __syncthreads();
+  update_body<T>(sP, sB, it, dev, cur, red);
+  __syncthreads();
 }
 template <int T>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(2, 2)))
@@ -415,8 +462,10 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
       avgprim_row(desc, uni(A.prow_grid), uni(A.prow_base), uni(A.devs), k);
     grid_barrier(uni(A.sync), nb, A.sync_ticks);
   }
+  __shared__ Params sP;
+  __shared__ Bufs sB;
   for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_tiles), &s_item, j)) >= 0;)
-    batch_points<R, IND>(S, I, desc, block_tile, uni(A.devs), A.dt_host, k);
+    batch_points_staged<R, IND>(S, I, desc, block_tile, uni(A.devs), A.dt_host, k, sP, sB);
   grid_barrier(uni(A.sync), nb, A.sync_ticks);
   if constexpr (LIM) {
     if (threadIdx.x == 0) s_n = __hip_atomic_load(A.fix_count, __ATOMIC_RELAXED,
@@ -430,7 +479,8 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
   }
   for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_items), &s_item, j)) >= 0;) {
     const int n = uni(A.n_items);
-    update_item<PT_THREADS>(desc, uni(A.items)[tile_of_block(k, n)], uni(A.devs), S.red);
+    update_item_staged<PT_THREADS>(desc, uni(A.items)[tile_of_block(k, n)], uni(A.devs), S.red,
+                                   sP, sB);
   }
   // the last workgroup to finish commits the step of every grid
   StepSync* sync = uni(A.sync);
