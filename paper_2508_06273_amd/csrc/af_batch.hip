@@ -60,12 +60,17 @@ __device__ __forceinline__ void copy_to_lds(const T& src, T& dst) {
   unsigned long long* b = reinterpret_cast<unsigned long long*>(&dst);
   for (int w = threadIdx.x; w < (int)(sizeof(T) / 8); w += blockDim.x) b[w] = a[w];
 }
-template <class R, bool IND = false>
-__device__ __forceinline__ void batch_points_staged(Smem<R>& S, Ind* I,
+// The tile is the split kernel's points_body with one addition: `pop` (a functor called by
+// every thread) takes the workgroup's next item from its queue once the tile's sites are staged
+// and prepared, so that the atomic's round trip overlaps the tile's arithmetic.  A grid that
+// takes no step does no work and no pop; the caller then pops after the item.  Returns whether
+// `pop` was called (uniform over the workgroup).
+template <class R, bool IND, class Pop>
+__device__ __forceinline__ bool batch_points_staged(Smem<R>& S, Ind* I,
                                                     const GridDesc* __restrict__ desc,
                                                     const int2* __restrict__ block_tile,
                                                     DevState* devs, double dt_host, int k,
-                                                    Params& sP, Bufs& sB) {
+                                                    Params& sP, Bufs& sB, Pop& pop) {
   const int2 gt = block_tile[k];
   const int g = __builtin_amdgcn_readfirstlane(gt.x);
   const int local = __builtin_amdgcn_readfirstlane(gt.y);
@@ -73,8 +78,20 @@ __device__ __forceinline__ void batch_points_staged(Smem<R>& S, Ind* I,
   copy_to_lds(desc[g].P, sP);
   copy_to_lds(desc[g].B[cur], sB);
   __syncthreads();
-  points_body<R, IND>(S, I, sP, sB, devs + g, dt_host, cur, local, local == 0);
+  DevState* dev = devs + g;
+  double dt;
+  bool popped = false;
+  if (step_dt(sP, dev, dt_host, cur, local == 0, &dt)) {
+    stage_and_prep(S, sP, sB, dev, local, true);
+    if constexpr (IND) stage_indicators(S, *I, sP, sB, local);
+    pop();
+    popped = true;
+    double speed = 0.0;
+    evolve_tile<R, false, IND>(S, I, sP, sB, dev, local, dt, nullptr, speed);
+    block_max_atomic(speed, &dev->smax[cur ^ 1], S.red);
+  }
   __syncthreads();  // every read of the copy is done before the next item overwrites it
+  return popped;
 }
 
 __global__ __launch_bounds__(PT_THREADS) AF_ATTR_F32
@@ -309,8 +326,10 @@ __global__ void kb_cfl(const GridDesc* __restrict__ desc, DevState* devs, int pe
 // the limiter), the update items.  A grid-wide barrier separates the phases; the last workgroup
 // to finish commits every grid and leaves the queues empty for the next launch.  Each phase's
 // items are split over 8 queues, one per XCD (workgroup b runs on XCD b mod 8, and queue x
-// holds items x, x + 8, x + 16, ...), so that the tile orders keep their meaning (see
-// next_item).  The grid is a multiple of 8 workgroups.  Every wait is bounded: a
+// holds items x, x + 8, x + 16, ...), so that the tile orders keep their meaning.  The point
+// phase hands out every tile by the queue's head counter, in order (resolve_pop); the other
+// phases take most items by a fixed stride (next_item).  The grid is a multiple of 8
+// workgroups.  Every wait is bounded: a
 // barrier not reached within the handle's limit on the 100 MHz wall clock (workgroups that
 // were not all resident) flags `timeout`, and the step then ends every running grid with
 // ERR_SYNC instead of committing it.
@@ -333,13 +352,13 @@ __device__ __forceinline__ void st_relaxed(unsigned int* p, unsigned int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Items of a phase with m items: queue x holds items x, x + 8, x + 16, ... below m (queue-local
-// index j: item x + 8 j); the workgroups of XCD x (b mod 8 = x, wpq = nb / 8 of them) take the
-// queue's first items by a fixed stride -- workgroup b takes j = b / 8, b / 8 + wpq, ... -- so
-// that together they walk the queue in order, as the hardware dispatches a kernel's workgroups,
-// with no atomic per item.  The last 2 wpq items of every queue are handed out one by one by
-// its head counter, to the queue's own workgroups first and then to those whose queues are
-// done.
+// Items of the other phases, m of them: queue x holds items x, x + 8, x + 16, ... below m
+// (queue-local index j: item x + 8 j); the workgroups of XCD x (b mod 8 = x, wpq = nb / 8 of
+// them) take the queue's first items by a fixed stride -- workgroup b takes j = b / 8,
+// b / 8 + wpq, ... -- so that together they walk the queue in order, as the hardware
+// dispatches a kernel's workgroups, with no atomic per item.  The last 2 wpq items of every
+// queue are handed out one by one by its head counter, to the queue's own workgroups first and
+// then to those whose queues are done.
 __device__ __forceinline__ int queue_len(int m, int x) { return x < m ? (m - x + 7) >> 3 : 0; }
 __device__ __forceinline__ int queue_tail(int m, int x, int wpq) {
   return min(queue_len(m, x), 2 * wpq);
@@ -379,6 +398,24 @@ __device__ __forceinline__ int next_item(StepSync* s, int m, int* s_item, int& j
   const int k = *s_item;
   __syncthreads();  // read by all before thread 0 overwrites it
   return k;
+}
+
+// The point phase takes every tile through its queue's head counter: the p-th pop of queue x
+// is item x + 8 p, so each XCD's tiles go out strictly in order, as the hardware dispatcher
+// hands out a kernel's workgroups, and the tiles in flight on an XCD stay a narrow window of
+// its range (the fixed stride lets the workgroups drift apart, and the tiles that share a halo
+// are then no longer in L2 together).  `p` is the value the workgroup's atomic on its own head
+// returned; once its queue is empty it takes items from the others.  -1 when all are empty.
+__device__ __forceinline__ int resolve_pop(StepSync* s, int m, int xcd, unsigned int p) {
+  if ((int)p < queue_len(m, xcd)) return xcd + 8 * (int)p;
+  for (int k = 1; k < 8; ++k) {
+    const int x = (xcd + k) & 7;
+    const unsigned int t = (unsigned int)queue_len(m, x);
+    if (t == 0u || ld_relaxed(&s->head[16 * x]) >= t) continue;
+    const unsigned int q = atomicAdd(&s->head[16 * x], 1u);
+    if (q < t) return x + 8 * (int)q;
+  }
+  return -1;
 }
 
 // Grid-wide barrier of the `nb` workgroups; the last to arrive empties the queues for the
@@ -464,8 +501,29 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
   }
   __shared__ Params sP;
   __shared__ Bufs sB;
-  for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_tiles), &s_item, j)) >= 0;)
-    batch_points_staged<R, IND>(S, I, desc, block_tile, uni(A.devs), A.dt_host, k, sP, sB);
+  {
+    StepSync* sy = uni(A.sync);
+    const int m = uni(A.n_tiles), xcd = (int)(blockIdx.x & 7);
+    if (threadIdx.x == 0) s_item = resolve_pop(sy, m, xcd, atomicAdd(&sy->head[16 * xcd], 1u));
+    __syncthreads();
+    int k = s_item;
+    __syncthreads();
+    while (k >= 0) {
+      unsigned int p = 0u;  // thread 0's
+      auto pop = [&]() {
+        if (threadIdx.x == 0) p = atomicAdd(&sy->head[16 * xcd], 1u);
+      };
+      const bool popped = batch_points_staged<R, IND>(S, I, desc, block_tile, uni(A.devs),
+                                                      A.dt_host, k, sP, sB, pop);
+      if (threadIdx.x == 0) {
+        if (!popped) p = atomicAdd(&sy->head[16 * xcd], 1u);
+        s_item = resolve_pop(sy, m, xcd, p);
+      }
+      __syncthreads();
+      k = s_item;
+      __syncthreads();
+    }
+  }
   grid_barrier(uni(A.sync), nb, A.sync_ticks);
   if constexpr (LIM) {
     if (threadIdx.x == 0) s_n = __hip_atomic_load(A.fix_count, __ATOMIC_RELAXED,
