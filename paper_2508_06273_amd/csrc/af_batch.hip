@@ -492,6 +492,17 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
   __shared__ int s_last;
   if (threadIdx.x == 0) A = arg;
   __syncthreads();
+  // A launch in which no grid can step (every grid stopped or failed: the rest of a run's last
+  // graph chunk) leaves at once, instead of handing out every tile to find that out.  The test
+  // is step_dt's, which would only clear the stopped grids' `active` flags, and the next launch
+  // that steps sets every flag again before anything reads it.  All workgroups read the same
+  // states, written by earlier launches, so they all leave or all stay.
+  int can_step = 0;
+  for (int g = threadIdx.x; g < uni(A.n_grids); g += blockDim.x) {
+    const DevState* d = uni(A.devs) + g;
+    can_step |= !d->err && d->steps < d->steps_limit && (A.dt_host > 0.0 || d->t < d->t_end);
+  }
+  if (!__syncthreads_or(can_step)) return;
   const unsigned int nb = gridDim.x;
   const int j0 = (int)(blockIdx.x >> 3);
   if constexpr (IND) {
@@ -1369,9 +1380,17 @@ int batch_run(af_handle* h, double t_end, double cfl, int64_t max_steps, double*
   while (true) {
     for (int k = 0; k < b->n; ++k) before[k] = ds[k].steps;
     // every grid stops by itself at t_end or at its step limit; the host only checks between
-    // chunks whether any grid is still running or has failed
-    if (h->timing) {
-      for (long long s = 0; s < chunk; ++s) enqueue_batch(h, 0.0);
+    // chunks whether any grid is still running or has failed.  No more steps are launched
+    // than the step limit leaves to any running grid: a shorter rest goes out without a graph.
+    long long n_launch = chunk;
+    if (max_steps > 0) {
+      long long rest = 0;
+      for (int k = 0; k < b->n; ++k)
+        if (!ds[k].err && ds[k].t < t_end) rest = std::max(rest, ds[k].steps_limit - ds[k].steps);
+      n_launch = std::min(chunk, rest);
+    }
+    if (h->timing || n_launch < chunk) {
+      for (long long s = 0; s < n_launch; ++s) enqueue_batch(h, 0.0);
     } else {
       if (!b->gexec || b->gexec_steps != chunk) {
         if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }

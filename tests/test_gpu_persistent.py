@@ -147,6 +147,33 @@ def test_persistent_host_dt_and_error_isolation():
     _same(res[af.AF_STEP_PERSISTENT], res[af.AF_STEP_SPLIT], "af_step")
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_persistent_runs_that_stop_inside_a_chunk(prec):
+    """Grids that reach t_end at different steps, so that the last launches of the graph chunk
+    find no grid that can step (the persistent kernel then leaves at once); then one af_step
+    with a host dt past t_end, and a run cut by its step limit (launched without a graph).
+    Every state, time and step count equals the separate kernels'."""
+    _flush(f"[gpu] persistent runs stopping inside a chunk, prec={prec}")
+    states = _mixed_states()
+    res = {}
+    for kernel in (af.AF_STEP_SPLIT, af.AF_STEP_PERSISTENT):
+        b = af.BatchSolver.for_states(states, precision=prec)
+        b.set_option(af.AF_OPT_STEP_KERNEL, kernel)
+        t, n = b.run(0.05, 0.3)
+        assert t == 0.05 and 1 < n < 16  # the chunk ends with launches that step no grid
+        steps = [b.grid_info(g)[1] for g in range(len(states))]
+        assert len(set(steps)) > 1
+        b.step(1e-3)
+        t2, n2 = b.run(0.2, 0.3, 5)
+        assert n2 == 5
+        res[kernel] = ([b.get_state(g) for g in range(len(states))],
+                       [b.grid_info(g) for g in range(len(states))], b.counters())
+        b.close()
+    _same(res[af.AF_STEP_PERSISTENT][0], res[af.AF_STEP_SPLIT][0], "stop inside a chunk")
+    assert res[af.AF_STEP_PERSISTENT][1] == res[af.AF_STEP_SPLIT][1]
+    assert np.array_equal(res[af.AF_STEP_PERSISTENT][2], res[af.AF_STEP_SPLIT][2])
+
+
 @pytest.mark.parametrize("prec", [1, 0])
 def test_persistent_full_size_workload(prec):
     """The batched workload at full size (256 periodic grids, N ~ U{64..512}): more tiles than
