@@ -221,9 +221,13 @@ void kb_fixup_ind(const GridDesc* __restrict__ desc, const int* __restrict__ til
 template <int T>
 __device__ __forceinline__ void update_body(const Params& P, const Bufs& B, int2 it,
                                             DevState* dev, int cur, double* red) {
-  // written by another workgroup earlier in the step (persistent kernel): agent-scope loads
-  const bool run = !ld_agent(&dev->err) && ld_agent(&dev->active);
-  const double dt = ld_agent(&dev->dt);
+  // Set in the point phase, which a kernel boundary or (persistent kernel) a grid barrier
+  // separates from this one: the barrier's acquire makes plain loads current, and they hit L2,
+  // where agent-scope atomic loads would go to memory at every item.  An error flagged by
+  // another update item meanwhile may be missed; the item then updates a state that is not
+  // committed, and the codes combine by a minimum (set_err), whichever item came first.
+  const bool run = !dev->err && dev->active;
+  const double dt = dev->dt;
   const double lx = dt * P.idx * (1.0 / 36.0), ly = dt * P.idy * (1.0 / 36.0);
   // full pairs per row, their number and chunks (below 2^31: at most 65536 rows of 32768 pairs)
   const unsigned ppr = (unsigned)P.nx >> 1;
