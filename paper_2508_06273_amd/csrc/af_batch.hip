@@ -331,9 +331,9 @@ __global__ void kb_cfl(const GridDesc* __restrict__ desc, DevState* devs, int pe
 // to finish commits every grid and leaves the queues empty for the next launch.  Each phase's
 // items are split over 8 queues, one per XCD (workgroup b runs on XCD b mod 8, and queue x
 // holds items x, x + 8, x + 16, ...), so that the tile orders keep their meaning.  The point
-// phase hands out every tile by the queue's head counter, in order (resolve_pop); the other
-// phases take most items by a fixed stride (next_item).  The grid is a multiple of 8
-// workgroups.  Every wait is bounded: a
+// and update phases hand out every item by the queue's head counter, in order (resolve_pop);
+// the indicator rows and the listed tiles go mostly by a fixed stride (next_item).  The grid
+// is a multiple of 8 workgroups.  Every wait is bounded: a
 // barrier not reached within the handle's limit on the 100 MHz wall clock (workgroups that
 // were not all resident) flags `timeout`, and the step then ends every running grid with
 // ERR_SYNC instead of committing it.
@@ -404,12 +404,13 @@ __device__ __forceinline__ int next_item(StepSync* s, int m, int* s_item, int& j
   return k;
 }
 
-// The point phase takes every tile through its queue's head counter: the p-th pop of queue x
-// is item x + 8 p, so each XCD's tiles go out strictly in order, as the hardware dispatcher
-// hands out a kernel's workgroups, and the tiles in flight on an XCD stay a narrow window of
-// its range (the fixed stride lets the workgroups drift apart, and the tiles that share a halo
-// are then no longer in L2 together).  `p` is the value the workgroup's atomic on its own head
-// returned; once its queue is empty it takes items from the others.  -1 when all are empty.
+// The point and update phases take every item through its queue's head counter: the p-th pop
+// of queue x is item x + 8 p, so each XCD's items go out strictly in order, as the hardware
+// dispatcher hands out a kernel's workgroups, and the items in flight on an XCD stay a narrow
+// window of its range (the fixed stride lets the workgroups drift apart, and the tiles that
+// share a halo are then no longer in L2 together).  `p` is the value the workgroup's atomic on
+// its own head returned; once its queue is empty it takes items from the others.  -1 when all
+// are empty.
 __device__ __forceinline__ int resolve_pop(StepSync* s, int m, int xcd, unsigned int p) {
   if ((int)p < queue_len(m, xcd)) return xcd + 8 * (int)p;
   for (int k = 1; k < 8; ++k) {
@@ -550,10 +551,25 @@ __device__ __forceinline__ void step_body(Smem<R>& S, Ind* I, const GridDesc* __
                           (unsigned int)k);
     grid_barrier(uni(A.sync), nb, A.sync_ticks);
   }
-  for (int k, j = j0; (k = next_item(uni(A.sync), uni(A.n_items), &s_item, j)) >= 0;) {
-    const int n = uni(A.n_items);
-    update_item_staged<PT_THREADS>(desc, uni(A.items)[tile_of_block(k, n)], uni(A.devs), S.red,
-                                   sP, sB);
+  // update items, in order like the tiles (neighbouring rows share the flux sums of their
+  // common sites); the next pop goes out before the item's loads
+  {
+    StepSync* sy = uni(A.sync);
+    const int m = uni(A.n_items), xcd = (int)(blockIdx.x & 7);
+    if (threadIdx.x == 0) s_item = resolve_pop(sy, m, xcd, atomicAdd(&sy->head[16 * xcd], 1u));
+    __syncthreads();
+    int k = s_item;
+    __syncthreads();
+    while (k >= 0) {
+      unsigned int p = 0u;
+      if (threadIdx.x == 0) p = atomicAdd(&sy->head[16 * xcd], 1u);
+      update_item_staged<PT_THREADS>(desc, uni(A.items)[tile_of_block(k, m)], uni(A.devs), S.red,
+                                     sP, sB);
+      if (threadIdx.x == 0) s_item = resolve_pop(sy, m, xcd, p);
+      __syncthreads();
+      k = s_item;
+      __syncthreads();
+    }
   }
   // the last workgroup to finish commits the step of every grid
   StepSync* sync = uni(A.sync);
