@@ -168,10 +168,12 @@ def run_gpu(st, prec, steps, warmup, stream):
                 dofs=dofs, state=out)
 
 
-def run_batched(prec, steps, warmup, stream, n_gl=2):
+def run_batched(prec, steps, warmup, stream, n_gl=2, step_kernel=None):
     """The batched workload (256 periodic grids, N ~ U{64..512}, own dt per grid): DOF-updates/s
     of one graph-captured launch sequence per step for all grids, on the schedule the
-    autotuner picks during the warm-up run."""
+    autotuner picks during the warm-up run.  With `step_kernel` (AF_STEP_SPLIT or
+    AF_STEP_PERSISTENT) the autotuner is off and that step kernel runs on the default tile
+    order and update size; with the persistent kernel `ms_points` is the whole step."""
     from paper_2508_06273_amd import af, inputs as I
     import torch
     states = run_batched.states
@@ -179,7 +181,10 @@ def run_batched(prec, steps, warmup, stream, n_gl=2):
         states = run_batched.states = I.batched_states(n_gl=n_gl)
     b = af.BatchSolver.for_states(states, precision=prec)
     b.set_stream(stream)
-    b.set_option(af.AF_OPT_AUTOTUNE, 1)  # the warm-up run picks the schedule
+    if step_kernel is None:
+        b.set_option(af.AF_OPT_AUTOTUNE, 1)  # the warm-up run picks the schedule
+    else:
+        b.set_option(af.AF_OPT_STEP_KERNEL, step_kernel)
     b.run(1e9, 0.3, warmup)
     schedule = {"tile_order": ["xcd", "linear", "grids"][b.get_option(af.AF_OPT_TILE_ORDER)],
                 "update_threads": b.get_option(af.AF_OPT_UPDATE_THREADS),
@@ -426,6 +431,12 @@ def main():
                     help="skip the batched-grids leg (256 uneven grids)")
     ap.add_argument("--batched-steps", type=int, default=32,
                     help="timed steps of the batched leg (a multiple of 16: whole graphs)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="profiling aid: run only the batched leg, printed as JSON instead of "
+                         "the benchmark line")
+    ap.add_argument("--step-kernel", choices=("auto", "split", "persistent"), default="auto",
+                    help="step kernel of the batched leg: chosen by the autotuner (auto), or "
+                         "fixed on the default schedule")
     ap.add_argument("--prec", choices=("both", "fp32", "fp64"), default="both",
                     help="profiling aid: run one precision only (no JSON line)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -481,6 +492,17 @@ def main():
         return
     if args.ladder:
         print(json.dumps(accuracy_ladder([256, 1024, 4096], 0.1, stream)), flush=True)
+        return
+    step_kernel = {"auto": None, "split": af.AF_STEP_SPLIT,
+                   "persistent": af.AF_STEP_PERSISTENT}[args.step_kernel]
+    if args.batched_only:
+        out = {}
+        for prec, name in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64")):
+            print(f"[bench] batched workload, {name}", file=sys.stderr, flush=True)
+            r = run_batched(prec, args.batched_steps, 32, stream, step_kernel=step_kernel)
+            out[name] = {k: r[k] for k in ("value", "ms_per_step", "ms_points", "ms_update",
+                                           "schedule")}
+        print(json.dumps({"batched": out, "steps": args.batched_steps}), flush=True)
         return
 
     n = args.n
@@ -560,7 +582,7 @@ def main():
     }
     if not args.no_batched:
         print("[bench] batched workload: 256 grids", file=sys.stderr, flush=True)
-        bres = {name: run_batched(prec, args.batched_steps, 32, stream)
+        bres = {name: run_batched(prec, args.batched_steps, 32, stream, step_kernel=step_kernel)
                 for prec, name in ((af.AF_PREC_FP32, "fp32"), (af.AF_PREC_FP64, "fp64"))}
         line["batched"] = {
             "workload": "256 periodic grids N x N on [0,1]^2, N ~ U{64..512} (seeded), random "
