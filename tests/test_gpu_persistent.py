@@ -187,6 +187,22 @@ def test_persistent_full_size_workload(prec):
     _same(out[2], ref[2], "workload")
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_persistent_full_size_workload_with_indicators(prec):
+    """The same workload with Algorithm 2, the Sec. 3.4 blend and Algorithm 3 on: the
+    persistent kernel's indicator variant, with its padded-average phase over every row of the
+    256 grids, equals the separate kernels on every grid, counters included."""
+    _flush(f"[gpu] persistent, 256-grid workload with indicators and limiter, prec={prec}")
+    states = I.batched_states(n_gl=2)
+    kw = dict(precision=prec, linearisation=1, limiter=True, transonic=True,
+              shock_limiter=True)
+    ref = _run(states, af.AF_STEP_SPLIT, 3, **kw)
+    out = _run(states, af.AF_STEP_PERSISTENT, 3, **kw)
+    assert out[1] == ref[1] == 3 and out[3] == ref[3]
+    assert list(out[4]) == list(ref[4])
+    _same(out[2], ref[2], "workload with indicators")
+
+
 def test_persistent_option_and_autotuner():
     _flush("[gpu] persistent option, autotuner")
     states = _mixed_states()
